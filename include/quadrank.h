@@ -1,0 +1,190 @@
+/*
+ * quadrank.h — C ABI of the MI355X (gfx950) rank structures and FM-index.
+ *
+ * Implements the data structures of "QuadRank: Engineering a High Throughput
+ * Rank" (Groot Koerkamp, arXiv 2602.04103) as GPU kernels:
+ *   BiRank    — binary rank(q)                       (paper Section 3)
+ *   QuadRank  — DNA rank(q, c) and rank4(q)           (paper Section 4)
+ *   QuadFm    — count-only FM-index backward search   (paper Appendix D)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named d_* are device pointers (memory of the current HIP device);
+ *   pointers named h_* are host pointers.  The caller owns every buffer it
+ *   passes; no entry point keeps a caller pointer after it returns (builds copy
+ *   the input into the structure's own layout).
+ * - Bit i of a bitvector is bit (i mod 64) of little-endian u64 word i/64.
+ *   DNA codes are A=0, C=1, G=2, T=3; base i occupies bits [2(i mod 32), +2)
+ *   of u64 word i/32.  Bits/bases at positions >= n in the last word are
+ *   ignored (may hold anything).
+ * - Device arrays of u64 must be 8-byte aligned and d_out4 (rank4) 16-byte aligned; a misaligned
+ *   pointer is rejected with QR_EINVAL.
+ * - Positions are zero-based and a query position q ranges over 0 <= q <= n
+ *   (paper Section 1: rank(q, c) counts c among the first q characters).
+ * - Work is enqueued on `stream` (0 = the null stream).  Query entry points
+ *   are asynchronous: they return after enqueuing; results are valid once the
+ *   stream reaches that point.  Build entry points return once the structure
+ *   is complete (they synchronise the stream).
+ * - Handles own their device memory, released by the matching *_free.  A
+ *   handle is bound to the device that was current at build time; calls must
+ *   be made with that device current.  Concurrent queries on one handle
+ *   (from several streams or threads) are allowed; build/free are not
+ *   concurrent with anything else on that handle.
+ * - Errors: argument errors detectable on the host return a negative status
+ *   and change nothing.  Errors that only the device sees (a query with
+ *   q > n, a symbol c > 3) write UINT64_MAX to that output element and set a
+ *   sticky per-handle error word, read and cleared by *_check.
+ * - Every status has a text from qr_status_string; the last failure's
+ *   detail (per thread) is available from qr_last_error.
+ */
+#ifndef QUADRANK_H
+#define QUADRANK_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QR_OK = 0,
+    QR_EINVAL = -1,  /* bad argument (null handle/pointer, wrong device, bad size) */
+    QR_ENOMEM = -2,  /* device or host allocation failed */
+    QR_EHIP = -3,    /* a HIP runtime call failed */
+    QR_ERANGE = -4,  /* input too large for the layout, or a query out of range (from *_check) */
+    QR_EDEVICE = -5  /* a device-side check failed (from *_check) */
+} qr_status;
+
+const char *qr_status_string(int status);
+/* Detail of the most recent failure on this thread ("" if none). */
+const char *qr_last_error(void);
+/* Library version string. */
+const char *qr_version(void);
+
+/* ------------------------------------------------------------------------------------------------
+ * BiRank (paper Section 3).  rank(q) = number of 1 bits among t_0 .. t_{q-1}.
+ * Layout: 128-byte lines, each holding a 16-bit delta to the line's middle and 1008 data bits;
+ * 64 lines form a superblock with a 32-bit offset shifted right by 10 bits.  Inputs up to
+ * 2^42 - 1 bits (QR_ERANGE above that).
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct qr_birank_s *qr_birank;
+
+/* Build from n_bits bits at d_bits (ceil(n_bits/64) u64 words; may be NULL iff n_bits == 0). */
+int birank_build(const uint64_t *d_bits, uint64_t n_bits, hipStream_t stream, qr_birank *out);
+/* d_out[i] = rank(d_q[i]) for i < nq (u64 in, u64 out; d_q and d_out may alias). */
+int birank_rank(qr_birank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t stream);
+/* Synchronise `stream`, return QR_ERANGE if any query since the last check had q > n, and clear. */
+int birank_check(qr_birank h, hipStream_t stream);
+int birank_free(qr_birank h);
+/* n, device bytes of the structure, and raw layout pointers (for structure checks). */
+uint64_t birank_len(qr_birank h);
+uint64_t birank_bytes(qr_birank h);
+int birank_layout(qr_birank h, const void **d_lines, uint64_t *n_lines, const void **d_super, uint64_t *n_super);
+/* Copy the structure to host memory: n_lines*128 bytes to h_lines, n_super*4 bytes to h_super
+ * (synchronous; either pointer may be NULL to skip it). */
+int birank_export(qr_birank h, void *h_lines, void *h_super);
+
+/* ------------------------------------------------------------------------------------------------
+ * QuadRank (paper Section 4).  rank(q, c) = number of c among t_0 .. t_{q-1}, c in {0,1,2,3};
+ * rank4(q) = the four ranks at once.  Layout: 128-byte lines with four 16-bit deltas to the line's
+ * middle and 480 bases in transposed (low-bit plane / high-bit plane) form; 128 lines form a
+ * superblock with four 32-bit offsets shifted right by 12 bits.  Inputs up to 2^44 - 1 bases.
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct qr_quadrank_s *qr_quadrank;
+
+/* Build from n bases, 2-bit packed at d_packed2 (ceil(n/32) u64 words; NULL iff n == 0). */
+int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr_quadrank *out);
+/* d_out[i] = rank(d_q[i], d_c[i]). */
+int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
+                  hipStream_t stream);
+/* d_out4[4*i + c] = rank(d_q[i], c) for c = 0..3 (q-major rows of four u64). */
+int quadrank_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t stream);
+int quadrank_check(qr_quadrank h, hipStream_t stream);
+int quadrank_free(qr_quadrank h);
+uint64_t quadrank_len(qr_quadrank h);
+uint64_t quadrank_bytes(qr_quadrank h);
+int quadrank_layout(qr_quadrank h, const void **d_lines, uint64_t *n_lines, const void **d_super,
+                    uint64_t *n_super);
+/* Copy the structure to host memory: n_lines*128 bytes and n_super*16 bytes (synchronous). */
+int quadrank_export(qr_quadrank h, void *h_lines, void *h_super);
+
+/* ------------------------------------------------------------------------------------------------
+ * QuadFm (paper Appendix D): count-only FM-index over the DNA alphabet, exact single-direction
+ * (backward) search, with QuadRank over the BWT of T$, the sentinel stored by position, and a
+ * lookup table for the first 8 characters searched (the pattern's last 8).  Requires n+1 <= 2^32-1
+ * (intervals and counts are u32).
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct qr_quadfm_s *qr_quadfm;
+
+/* Host helper (input preparation, not the GPU path): suffix array of T$ by induced sorting, then
+ * the BWT of T$ packed 2 bits per symbol into h_bwt_packed2 (ceil((n+1)/32) words, caller-owned),
+ * with '$' stored as A (code 0) and its row returned in *dollar_pos.  h_text holds n codes 0..3.
+ * QR_EINVAL on a code > 3, QR_ERANGE if n+1 > 2^32-1, QR_ENOMEM if host memory runs out. */
+int quadfm_bwt_host(const uint8_t *h_text, uint64_t n, uint64_t *h_bwt_packed2, uint64_t *dollar_pos);
+
+/* Build the index from the packed BWT (n_plus_1 symbols at d_bwt_packed2, '$' stored as A at row
+ * dollar_pos).  Builds QuadRank over the BWT, the C array and the 8-mer interval table. */
+int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,
+                 qr_quadfm *out);
+/* Count occurrences of npat patterns given in CSR form: pattern p is the codes
+ * d_pat[d_off[p] .. d_off[p+1]) (u8 codes 0..3; u64 offsets, npat+1 of them); d_count[p] receives
+ * the size of its BWT interval (u32).  An empty pattern counts n+1; a pattern with a code > 3
+ * counts 0 (it cannot occur in an ACGT text).  Runs the persistent work-queue kernel: resident
+ * wavefronts pull patterns from a device queue until it drains.  Calls on one handle must not
+ * overlap in time (they share the queue head); use one handle per concurrent stream. */
+int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+                 hipStream_t stream);
+/* Same result with one plain launch per batch of `batch` patterns, one lane per pattern
+ * (batch = 0: a single launch over all patterns).  The baseline for the work-queue kernel. */
+int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
+                         uint32_t *d_count, hipStream_t stream);
+/* Synchronise `stream` (counts are then final). */
+int quadfm_check(qr_quadfm h, hipStream_t stream);
+int quadfm_free(qr_quadfm h);
+uint64_t quadfm_len(qr_quadfm h);   /* n (text length, without '$') */
+uint64_t quadfm_bytes(qr_quadfm h); /* device bytes of the index */
+/* Device pointer and entry count (4^8) of the 8-mer table of u32 pairs (sp, ep); an empty interval
+ * is stored as (0, 0).  quadfm_export_table copies the 2*4^8 u32 to host memory. */
+int quadfm_table(qr_quadfm h, const void **d_table, uint64_t *entries);
+int quadfm_export_table(qr_quadfm h, uint32_t *h_pairs);
+/* C[c] = 1 + number of text characters smaller than c, for c = 0..3. */
+int quadfm_c_array(qr_quadfm h, uint64_t *h_C4);
+
+/* ------------------------------------------------------------------------------------------------
+ * Query-kernel tuning (used by the autotuner).  Applies to the handle's subsequent queries.
+ *   block      threads per workgroup (64..1024, multiple of 64; 0 = default)
+ *   per_lane   queries each lane keeps in flight (1, 2, 4 or 8; 0 = default)
+ *   grid_waves resident waves per CU to launch (0 = one lane per query, no grid-stride loop)
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t block;
+    int32_t per_lane;
+    int32_t grid_waves;
+    int32_t reserved;
+} qr_tuning;
+
+int birank_set_tuning(qr_birank h, const qr_tuning *t);
+int quadrank_set_tuning(qr_quadrank h, const qr_tuning *t);
+/* For quadfm_count the fields mean: block = threads per workgroup, per_lane = minimum number of
+ * idle lanes before a wavefront claims new patterns (1..64), grid_waves = resident waves per CU. */
+int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
+
+/* ------------------------------------------------------------------------------------------------
+ * Random-line gather microbenchmark: the achievable ceiling for one random 128-byte line per query.
+ * d_lines (16-byte aligned) holds n_lines 128-byte lines; for each i < nq, line
+ * floor(d_idx[i] * n_lines / 2^64) is read,
+ * bytes_per_query (64 or 128) of it are summed, and the sum is written to d_out[i].
+ * ---------------------------------------------------------------------------------------------- */
+int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
+                    uint32_t bytes_per_query, uint64_t *d_out, hipStream_t stream);
+
+/* Host-side reference of the library's exact division by the line payloads (for tests):
+ * which = 0 -> floor(x / 1008) (BiRank), which = 1 -> floor(x / 480) (QuadRank). */
+uint64_t qr_line_of(uint64_t x, int which);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QUADRANK_H */

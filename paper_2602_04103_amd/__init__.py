@@ -1,0 +1,305 @@
+"""Python binding of the MI355X rank library (include/quadrank.h).
+
+Argument marshalling only: torch supplies device memory (tensor.data_ptr())
+and the HIP stream (torch.cuda.current_stream().cuda_stream); every step runs
+in the HIP kernels of libquadrank.so.  There is no CPU fallback: if the
+library is missing, importing the functions raises.
+
+The functions carry the C names (birank_build, birank_rank, quadrank_rank4,
+quadfm_count, ...).  BiRank / QuadRank / QuadFm wrap a handle and free it when
+collected.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libquadrank.so")
+
+QR_OK, QR_EINVAL, QR_ENOMEM, QR_EHIP, QR_ERANGE, QR_EDEVICE = 0, -1, -2, -3, -4, -5
+
+
+class QRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (status %d): %s" % (msg, status, last_error()))
+        self.status = status
+
+
+class qr_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("per_lane", C.c_int32), ("grid_waves", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+u64, vp, ci = C.c_uint64, C.c_void_p, C.c_int
+
+
+def lib():
+    """Load libquadrank.so (built by __graft_entry__.build() / paper_2602_04103_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libquadrank.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "qr_status_string": (C.c_char_p, [ci]),
+            "qr_last_error": (C.c_char_p, []),
+            "qr_version": (C.c_char_p, []),
+            "qr_line_of": (u64, [u64, ci]),
+            "birank_build": (ci, [vp, u64, vp, C.POINTER(vp)]),
+            "birank_rank": (ci, [vp, vp, u64, vp, vp]),
+            "birank_check": (ci, [vp, vp]),
+            "birank_free": (ci, [vp]),
+            "birank_len": (u64, [vp]),
+            "birank_bytes": (u64, [vp]),
+            "birank_layout": (ci, [vp, C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), C.POINTER(u64)]),
+            "birank_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
+            "birank_export": (ci, [vp, vp, vp]),
+            "quadrank_build": (ci, [vp, u64, vp, C.POINTER(vp)]),
+            "quadrank_rank": (ci, [vp, vp, vp, u64, vp, vp]),
+            "quadrank_rank4": (ci, [vp, vp, u64, vp, vp]),
+            "quadrank_check": (ci, [vp, vp]),
+            "quadrank_free": (ci, [vp]),
+            "quadrank_len": (u64, [vp]),
+            "quadrank_bytes": (u64, [vp]),
+            "quadrank_layout": (ci, [vp, C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), C.POINTER(u64)]),
+            "quadrank_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
+            "quadrank_export": (ci, [vp, vp, vp]),
+            "qr_gather_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
+        }
+        optional = {
+            "quadfm_bwt_host": (ci, [vp, u64, vp, C.POINTER(u64)]),
+            "quadfm_build": (ci, [vp, u64, u64, vp, C.POINTER(vp)]),
+            "quadfm_count": (ci, [vp, vp, vp, u64, vp, vp]),
+            "quadfm_count_batched": (ci, [vp, vp, vp, u64, u64, vp, vp]),
+            "quadfm_check": (ci, [vp, vp]),
+            "quadfm_free": (ci, [vp]),
+            "quadfm_len": (u64, [vp]),
+            "quadfm_bytes": (u64, [vp]),
+            "quadfm_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
+            "quadfm_table": (ci, [vp, C.POINTER(vp), C.POINTER(u64)]),
+            "quadfm_c_array": (ci, [vp, C.POINTER(u64)]),
+        }
+        for name, (res, args) in list(sig.items()) + list(optional.items()):
+            if not hasattr(L, name):
+                if name in sig:
+                    raise ImportError("libquadrank.so lacks %s" % name)
+                continue
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return (lib().qr_last_error() or b"").decode(errors="replace")
+
+
+def version() -> str:
+    return lib().qr_version().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != QR_OK:
+        raise QRError(rc, what)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtypes, numel=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s must have dtype in %s, got %s" % (name, dtypes, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), numel))
+    return t.data_ptr() if t.numel() else 0
+
+
+W64 = (torch.int64, torch.uint64)
+W8 = (torch.uint8,)
+W32 = (torch.int32, torch.uint32)
+
+
+def qr_line_of(x: int, which: int) -> int:
+    return int(lib().qr_line_of(x, which))
+
+
+# ------------------------------------------------------------------------------------------ BiRank
+def birank_build(bits: torch.Tensor, n_bits: int, stream=None) -> int:
+    h = vp()
+    _check(lib().birank_build(_dev(bits, "bits", W64, (n_bits + 63) // 64), n_bits, _stream(stream), C.byref(h)),
+           "birank_build")
+    return h.value
+
+
+def birank_rank(h: int, q: torch.Tensor, out: torch.Tensor, stream=None):
+    nq = q.numel()
+    _check(lib().birank_rank(h, _dev(q, "q", W64), nq, _dev(out, "out", W64, nq), _stream(stream)), "birank_rank")
+    return out
+
+
+def birank_check(h: int, stream=None):
+    _check(lib().birank_check(h, _stream(stream)), "birank_check")
+
+
+def birank_free(h: int):
+    lib().birank_free(h)
+
+
+# ---------------------------------------------------------------------------------------- QuadRank
+def quadrank_build(packed2: torch.Tensor, n: int, stream=None) -> int:
+    h = vp()
+    _check(lib().quadrank_build(_dev(packed2, "packed2", W64, (n + 31) // 32), n, _stream(stream), C.byref(h)),
+           "quadrank_build")
+    return h.value
+
+
+def quadrank_rank(h: int, q: torch.Tensor, c: torch.Tensor, out: torch.Tensor, stream=None):
+    nq = q.numel()
+    _check(lib().quadrank_rank(h, _dev(q, "q", W64), _dev(c, "c", W8, nq), nq, _dev(out, "out", W64, nq),
+                               _stream(stream)), "quadrank_rank")
+    return out
+
+
+def quadrank_rank4(h: int, q: torch.Tensor, out4: torch.Tensor, stream=None):
+    nq = q.numel()
+    _check(lib().quadrank_rank4(h, _dev(q, "q", W64), nq, _dev(out4, "out4", W64, 4 * nq), _stream(stream)),
+           "quadrank_rank4")
+    return out4
+
+
+def quadrank_check(h: int, stream=None):
+    _check(lib().quadrank_check(h, _stream(stream)), "quadrank_check")
+
+
+def quadrank_free(h: int):
+    lib().quadrank_free(h)
+
+
+def qr_gather_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, bytes_per_query: int, out: torch.Tensor,
+                    stream=None):
+    nq = idx.numel()
+    _check(lib().qr_gather_bench(_dev(lines, "lines", W64 + W8 + W32, n_lines * 16 if lines.element_size() == 8 else 1),
+                                 n_lines, _dev(idx, "idx", W64), nq, bytes_per_query, _dev(out, "out", W64, nq),
+                                 _stream(stream)), "qr_gather_bench")
+    return out
+
+
+# ---------------------------------------------------------------------------------------- wrappers
+class _Handle:
+    _free = None
+
+    def __init__(self, h: int):
+        self.h = h
+
+    def free(self):
+        if self.h:
+            type(self)._free(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def _tune(self, fn, block=0, per_lane=0, grid_waves=0):
+        t = qr_tuning(block, per_lane, grid_waves, 0)
+        _check(fn(self.h, C.byref(t)), "set_tuning")
+
+
+def _layout(fn, h):
+    a, b = vp(), vp()
+    na, nb = u64(), u64()
+    _check(fn(h, C.byref(a), C.byref(na), C.byref(b), C.byref(nb)), "layout")
+    return a.value, na.value, b.value, nb.value
+
+
+class BiRank(_Handle):
+    """Binary rank structure built on the current device from n bits (u64 words, LSB first)."""
+    _free = staticmethod(birank_free)
+
+    def __init__(self, bits: torch.Tensor, n_bits: int, stream=None):
+        super().__init__(birank_build(bits, n_bits, stream))
+        self.n = n_bits
+
+    def rank(self, q: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(q.numel(), dtype=torch.int64, device=q.device)
+        return birank_rank(self.h, q, out, stream)
+
+    def check(self, stream=None):
+        birank_check(self.h, stream)
+
+    def set_tuning(self, **kw):
+        self._tune(lib().birank_set_tuning, **kw)
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().birank_bytes(self.h))
+
+    def layout(self):
+        """(lines_ptr, n_lines, super_ptr, n_super) device pointers of the raw layout."""
+        return _layout(lib().birank_layout, self.h)
+
+    def export(self):
+        """Host copies (numpy) of the raw layout: (lines u64[n_lines, 16], super u32[n_super])."""
+        import numpy as np
+        _, nl, _, ns = self.layout()
+        lines = np.empty((nl, 16), dtype=np.uint64)
+        sup = np.empty(ns, dtype=np.uint32)
+        _check(lib().birank_export(self.h, lines.ctypes.data, sup.ctypes.data), "birank_export")
+        return lines, sup
+
+
+class QuadRank(_Handle):
+    """DNA rank structure built from n 2-bit packed bases."""
+    _free = staticmethod(quadrank_free)
+
+    def __init__(self, packed2: torch.Tensor, n: int, stream=None):
+        super().__init__(quadrank_build(packed2, n, stream))
+        self.n = n
+
+    def rank(self, q: torch.Tensor, c: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(q.numel(), dtype=torch.int64, device=q.device)
+        return quadrank_rank(self.h, q, c, out, stream)
+
+    def rank4(self, q: torch.Tensor, out4: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out4 is None:
+            out4 = torch.empty((q.numel(), 4), dtype=torch.int64, device=q.device)
+        return quadrank_rank4(self.h, q, out4, stream)
+
+    def check(self, stream=None):
+        quadrank_check(self.h, stream)
+
+    def set_tuning(self, **kw):
+        self._tune(lib().quadrank_set_tuning, **kw)
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().quadrank_bytes(self.h))
+
+    def layout(self):
+        return _layout(lib().quadrank_layout, self.h)
+
+    def export(self):
+        """Host copies (numpy): (lines u64[n_lines, 16], super u32[n_super, 4])."""
+        import numpy as np
+        _, nl, _, ns = self.layout()
+        lines = np.empty((nl, 16), dtype=np.uint64)
+        sup = np.empty((ns, 4), dtype=np.uint32)
+        _check(lib().quadrank_export(self.h, lines.ctypes.data, sup.ctypes.data), "quadrank_export")
+        return lines, sup

@@ -1,0 +1,51 @@
+// Random-line gather microbenchmark: the achievable throughput of one random 128-byte line (or a
+// 64-byte half of one) per query, with the same per-query index read and result write as a rank
+// query.  This is the measured ceiling the rank kernels are compared against.
+#include <algorithm>
+
+#include "common.hpp"
+
+using namespace qr;
+
+namespace {
+
+template <int SEGS>  // 16-byte segments read per query: 4 (64 B) or 8 (128 B)
+__global__ __launch_bounds__(256) void gather_kernel(const uint4 *__restrict__ lines, uint64_t n_lines,
+                                                     const uint64_t *__restrict__ idx, uint64_t nq,
+                                                     uint64_t *__restrict__ out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const uint64_t l = mulhi64(idx[i], n_lines);  // uniform line in [0, n_lines)
+    const uint4 *L = lines + l * 8;
+    uint4 v[SEGS];
+#pragma unroll
+    for (int k = 0; k < SEGS; ++k) v[k] = L[k];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SEGS; ++k) s += v[k].x + v[k].y + v[k].z + v[k].w;
+    out[i] = s;
+}
+
+}  // namespace
+
+extern "C" int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
+                               uint32_t bytes_per_query, uint64_t *d_out, hipStream_t stream) {
+    if (!d_lines || !n_lines || (nq && (!d_idx || !d_out)) || (bytes_per_query != 64 && bytes_per_query != 128) ||
+        ((uintptr_t)d_lines & 15) || ((uintptr_t)d_idx & 7) || ((uintptr_t)d_out & 7)) {
+        set_error("qr_gather_bench: bad arguments");
+        return QR_EINVAL;
+    }
+    if (!nq) return QR_OK;
+    const uint64_t blocks = (nq + 255) / 256;
+    if (blocks > 0x7fffffffull) {
+        set_error("qr_gather_bench: nq too large");
+        return QR_EINVAL;
+    }
+    const uint4 *L = reinterpret_cast<const uint4 *>(d_lines);
+    if (bytes_per_query == 64)
+        hipLaunchKernelGGL(gather_kernel<4>, dim3((uint32_t)blocks), dim3(256), 0, stream, L, n_lines, d_idx, nq, d_out);
+    else
+        hipLaunchKernelGGL(gather_kernel<8>, dim3((uint32_t)blocks), dim3(256), 0, stream, L, n_lines, d_idx, nq, d_out);
+    QR_HIP(hipGetLastError());
+    return QR_OK;
+}

@@ -1,0 +1,456 @@
+// QuadFm on gfx950 (paper Appendix D): a count-only FM-index over the DNA alphabet whose rank
+// queries run on the QuadRank layout.
+//
+// Index over T$ (length n+1):
+//   - BWT of T$ with the single '$' stored as A at row dollar; rank_B(q, A) = rank(q, A) - [q > dollar]
+//     corrects it (the sentinel handled by storing its position, Appendix D);
+//   - C[c] = 1 + #{text characters < c} ('$' sorts first and occupies row 0's bucket);
+//   - a lookup table of the interval of every 8-mer (the prefix table for the first 8 characters
+//     the backward search processes, i.e. the pattern's last 8), built by 8 backward steps.
+// Count of pattern P (length m): start from table[P[m-8..m)] (or [0, n+1) when m < 8), then for
+// i = m-9 down to 0 (m-1 down to 0): c = P[i], sp = C[c] + rank_B(sp, c), ep = C[c] + rank_B(ep, c),
+// stopping once sp >= ep; the count is ep - sp (0 when empty).  m = 0 counts n+1; a code > 3 counts 0.
+//
+// Two count kernels:
+//   fm_batch_kernel       one lane per pattern; the host launches it once per batch of patterns;
+//   fm_persistent_kernel  CUs x waves resident wavefronts pull patterns from a device queue: when
+//                         lanes finish, the wave claims as many new patterns as it has idle lanes
+//                         with one atomic add on the queue head, so no lane idles while work remains
+//                         (the GPU counterpart of the paper's active list with swap-pop).
+#include <algorithm>
+#include <new>
+
+#include "common.hpp"
+#include "quadrank_dev.hpp"
+
+using namespace qr;
+
+namespace qr {
+int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, uint32_t *super, hipStream_t stream);
+}
+
+struct qr_quadfm_s {
+    int device;
+    uint64_t n1;      // BWT length = n + 1
+    uint64_t dollar;  // row of '$'
+    uint64_t C[4];
+    uint64_t n_lines, n_sb;
+    uint64_t *lines;
+    uint32_t *super;
+    uint2 *table;                // 4^8 intervals (sp, ep)
+    unsigned long long *head;    // device work-queue head
+    uint32_t *err;
+    qr_tuning tune;              // persistent kernel: block, refill threshold (per_lane), waves per CU
+};
+
+namespace {
+
+constexpr int KMER = 8;
+constexpr uint32_t KMER_ENTRIES = 1u << (2 * KMER);
+
+struct FmDev {
+    const uint4 *lines;
+    const uint32_t *super;
+    const uint2 *table;
+    uint64_t n1, dollar;
+    uint64_t C0, C1, C2, C3;
+};
+
+__device__ __forceinline__ uint64_t fm_C(const FmDev &f, uint32_t c) {
+    return c == 0 ? f.C0 : c == 1 ? f.C1 : c == 2 ? f.C2 : f.C3;
+}
+
+// One backward step of the interval [sp, ep) with symbol c.
+__device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint64_t &sp, uint64_t &ep) {
+    HalfLine a, b;
+    load_half(f.lines, f.super, sp, a);
+    load_half(f.lines, f.super, ep, b);
+    uint64_t rs = rank1_from_half(a, c), re = rank1_from_half(b, c);
+    if (c == 0) {
+        rs -= sp > f.dollar;
+        re -= ep > f.dollar;
+    }
+    const uint64_t base = fm_C(f, c);
+    sp = base + rs;
+    ep = base + re;
+}
+
+__global__ __launch_bounds__(256) void fm_table_kernel(FmDev f, uint2 *__restrict__ table) {
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= KMER_ENTRIES) return;
+    uint64_t sp = 0, ep = f.n1;
+    for (int k = 0; k < KMER && sp < ep; ++k) fm_step(f, (w >> (2 * k)) & 3u, sp, ep);
+    if (sp >= ep) sp = ep = 0;
+    table[w] = make_uint2((uint32_t)sp, (uint32_t)ep);
+}
+
+// Totals of each symbol in the BWT (rank at n+1) with '$' removed from A, and out4[4] = 1 iff
+// the row of '$' holds A as the layout requires.
+__global__ void fm_totals_kernel(FmDev f, unsigned long long *__restrict__ out4) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    HalfLine h, d0, d1;
+    load_half(f.lines, f.super, f.n1, h);
+    uint64_t r[4];
+    rank4_from_half(h, r);
+    load_half(f.lines, f.super, f.dollar, d0);
+    load_half(f.lines, f.super, f.dollar + 1, d1);
+    out4[0] = r[0] - 1;
+    out4[1] = r[1];
+    out4[2] = r[2];
+    out4[3] = r[3];
+    out4[4] = rank1_from_half(d1, 0) - rank1_from_half(d0, 0);
+}
+
+// Per-lane search state.
+struct Search {
+    uint64_t sp, ep;
+    const uint8_t *P;  // pattern start
+    uint32_t i;        // characters still to process: P[0..i)
+    uint64_t buf;      // bytes [buf_at, buf_at + 8) of the pattern, holding P[i-1]
+    uintptr_t buf_at;
+    uintptr_t lo, hi;  // the pattern's byte range [lo, hi): no read leaves it
+};
+
+// Initialise the search for a pattern; returns true if its count is already known (written to cnt).
+__device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restrict__ pat, const uint64_t *__restrict__ off,
+                                        uint64_t p, Search &s, uint32_t &cnt) {
+    const uint64_t o = off[p], m = off[p + 1] - o;
+    s.P = pat + o;
+    s.lo = (uintptr_t)s.P;
+    s.hi = s.lo + m;
+    s.buf_at = ~(uintptr_t)0;
+    if (m == 0) {
+        cnt = (uint32_t)f.n1;
+        return true;
+    }
+    if (m >= KMER) {
+        uint32_t w = 0;
+        bool bad = false;
+        for (int t = 0; t < KMER; ++t) {
+            const uint32_t c = s.P[m - KMER + t];
+            bad |= c > 3;
+            w = (w << 2) | (c & 3u);
+        }
+        if (bad) {
+            cnt = 0;
+            return true;
+        }
+        const uint2 iv = f.table[w];
+        s.sp = iv.x;
+        s.ep = iv.y;
+        s.i = (uint32_t)(m - KMER);
+    } else {
+        s.sp = 0;
+        s.ep = f.n1;
+        s.i = (uint32_t)m;
+    }
+    if (s.sp >= s.ep || s.i == 0) {
+        cnt = s.sp < s.ep ? (uint32_t)(s.ep - s.sp) : 0u;
+        return true;
+    }
+    return false;
+}
+
+// Next character P[i-1].  Characters are fetched 8 at a time with one aligned load when the whole
+// aligned 8-byte window lies inside the pattern, else one byte at a time.
+__device__ __forceinline__ uint32_t next_char(Search &s) {
+    const uintptr_t a = (uintptr_t)(s.P + s.i - 1);
+    if (s.buf_at == ~(uintptr_t)0 || a < s.buf_at) {
+        const uintptr_t w = a & ~(uintptr_t)7;
+        if (w >= s.lo && w + 8 <= s.hi) {
+            s.buf_at = w;
+            s.buf = *reinterpret_cast<const uint64_t *>(w);
+        } else {
+            s.buf_at = a;
+            s.buf = *reinterpret_cast<const uint8_t *>(a);
+        }
+    }
+    return (uint32_t)(s.buf >> (8 * (a - s.buf_at))) & 0xffu;
+}
+
+// Advance one character; returns true when the search has finished (count in cnt).
+__device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &cnt) {
+    const uint32_t c = next_char(s);
+    if (c > 3) {
+        cnt = 0;
+        return true;
+    }
+    fm_step(f, c, s.sp, s.ep);
+    --s.i;
+    if (s.sp >= s.ep || s.i == 0) {
+        cnt = s.sp < s.ep ? (uint32_t)(s.ep - s.sp) : 0u;
+        return true;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *__restrict__ pat,
+                                                       const uint64_t *__restrict__ off, uint64_t p0, uint64_t np,
+                                                       uint32_t *__restrict__ count) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const uint64_t p = p0 + k;
+    Search s;
+    uint32_t cnt = 0;
+    if (!fm_init(f, pat, off, p, s, cnt))
+        while (!fm_advance(f, s, cnt)) {
+        }
+    count[p] = cnt;
+}
+
+__global__ void fill_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+__global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8_t *__restrict__ pat,
+                                                            const uint64_t *__restrict__ off, uint64_t npat,
+                                                            uint32_t *__restrict__ count,
+                                                            unsigned long long *__restrict__ head, uint32_t refill_min) {
+    const uint32_t lane = __lane_id();
+    bool active = false, drained = false;
+    uint64_t p = 0;
+    Search s;
+    s.sp = s.ep = 0;
+    s.P = pat;
+    s.i = 0;
+    s.buf = 0;
+    s.buf_at = ~(uintptr_t)0;
+    s.lo = s.hi = 0;
+    while (true) {
+        if (!drained) {
+            const uint64_t idle = __ballot(!active);
+            const uint32_t nidle = __popcll(idle);
+            if (nidle != 0 && (nidle >= refill_min || nidle == 64)) {
+                const uint32_t leader = __ffsll((unsigned long long)idle) - 1;
+                unsigned long long got = 0;
+                if (lane == leader) got = atomicAdd(head, (unsigned long long)nidle);
+                got = __shfl(got, leader, 64);
+                if (got + nidle >= npat) drained = true;
+                if (!active) {
+                    const uint32_t rank = __popcll(idle & ((1ull << lane) - 1ull));
+                    const uint64_t mine = got + rank;
+                    if (mine < npat) {
+                        p = mine;
+                        uint32_t cnt = 0;
+                        if (fm_init(f, pat, off, p, s, cnt)) count[p] = cnt;
+                        else active = true;
+                    }
+                }
+            }
+        }
+        if (!__any(active)) {
+            if (drained) break;
+            continue;
+        }
+        if (active) {
+            uint32_t cnt = 0;
+            if (fm_advance(f, s, cnt)) {
+                count[p] = cnt;
+                active = false;
+            }
+        }
+    }
+}
+
+void release(qr_quadfm_s *h) {
+    if (!h) return;
+    if (h->lines) (void)hipFree(h->lines);
+    if (h->super) (void)hipFree(h->super);
+    if (h->table) (void)hipFree(h->table);
+    if (h->head) (void)hipFree(h->head);
+    if (h->err) (void)hipFree(h->err);
+    delete h;
+}
+
+FmDev dev_view(const qr_quadfm_s *h) {
+    FmDev f;
+    f.lines = reinterpret_cast<const uint4 *>(h->lines);
+    f.super = h->super;
+    f.table = h->table;
+    f.n1 = h->n1;
+    f.dollar = h->dollar;
+    f.C0 = h->C[0], f.C1 = h->C[1], f.C2 = h->C[2], f.C3 = h->C[3];
+    return f;
+}
+
+int count_args(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+               const char *what) {
+    if (!h || (npat && (!d_off || !d_count))) {
+        set_error("%s: null handle or pointer", what);
+        return QR_EINVAL;
+    }
+    if (((uintptr_t)d_off & 7) || ((uintptr_t)d_count & 3)) {
+        set_error("%s: d_off must be 8-byte and d_count 4-byte aligned", what);
+        return QR_EINVAL;
+    }
+    (void)d_pat;  // may be NULL when every pattern is empty
+    return check_device(h->device);
+}
+
+}  // namespace
+
+extern "C" {
+
+int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,
+                 qr_quadfm *out) {
+    if (!out) return QR_EINVAL;
+    *out = nullptr;
+    if (!d_bwt_packed2 || n_plus_1 == 0 || dollar_pos >= n_plus_1 || ((uintptr_t)d_bwt_packed2 & 7)) {
+        set_error("quadfm_build: need a BWT of n+1 >= 1 symbols and dollar_pos < n+1");
+        return QR_EINVAL;
+    }
+    if (n_plus_1 > 0xffffffffull) {
+        set_error("quadfm_build: n+1 = %llu exceeds the u32 interval limit", (unsigned long long)n_plus_1);
+        return QR_ERANGE;
+    }
+    qr_quadfm_s *h = new (std::nothrow) qr_quadfm_s{};
+    if (!h) return QR_ENOMEM;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return QR_EHIP;
+    }
+    h->n1 = n_plus_1;
+    h->dollar = dollar_pos;
+    h->n_lines = n_plus_1 / QR_DATA_BASES + 1;
+    h->n_sb = n_plus_1 / QR_SB_BASES + 1;
+    h->tune = qr_tuning{256, 16, 16, 0};
+    unsigned long long *tot = nullptr;
+    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 16) != hipSuccess ||
+        hipMalloc(&h->table, KMER_ENTRIES * sizeof(uint2)) != hipSuccess || hipMalloc(&h->head, 8) != hipSuccess ||
+        hipMalloc(&h->err, 4) != hipSuccess || hipMalloc(&tot, 40) != hipSuccess) {
+        (void)hipGetLastError();
+        if (tot) (void)hipFree(tot);
+        release(h);
+        set_error("quadfm_build: device allocation failed");
+        return QR_ENOMEM;
+    }
+    int rc = quadrank_build_into(d_bwt_packed2, n_plus_1, h->lines, h->super, stream);
+    if (rc) {
+        (void)hipFree(tot);
+        release(h);
+        return rc;
+    }
+    FmDev f = dev_view(h);
+    hipLaunchKernelGGL(fm_totals_kernel, dim3(1), dim3(64), 0, stream, f, tot);
+    unsigned long long t[5] = {0, 0, 0, 0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(t, tot, 40, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(tot);
+    if (e != hipSuccess) {
+        set_error("quadfm_build: %s", hipGetErrorString(e));
+        release(h);
+        return QR_EHIP;
+    }
+    uint64_t acc = 1;
+    for (int c = 0; c < 4; ++c) {
+        h->C[c] = acc;
+        acc += t[c];
+    }
+    if (acc != n_plus_1 || t[4] != 1) {
+        set_error("quadfm_build: the BWT row dollar_pos must hold A (code 0)");
+        release(h);
+        return QR_EINVAL;
+    }
+    f = dev_view(h);
+    hipLaunchKernelGGL(fm_table_kernel, dim3(KMER_ENTRIES / 256), dim3(256), 0, stream, f, h->table);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemsetAsync(h->err, 0, 4, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        set_error("quadfm_build: %s", hipGetErrorString(e));
+        release(h);
+        return QR_EHIP;
+    }
+    *out = h;
+    return QR_OK;
+}
+
+int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+                 hipStream_t stream) {
+    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count");
+    if (rc) return rc;
+    if (!npat) return QR_OK;
+    const int block = h->tune.block ? h->tune.block : 256;
+    const uint32_t refill = h->tune.per_lane > 0 ? (uint32_t)h->tune.per_lane : 16u;
+    const int wpc = h->tune.grid_waves > 0 ? h->tune.grid_waves : 16;
+    uint64_t blocks = (uint64_t)cu_count() * wpc * 64 / block;
+    const uint64_t need = (npat + block - 1) / block;  // no more waves than patterns need
+    blocks = std::max<uint64_t>(1, std::min(blocks, need));
+    hipLaunchKernelGGL(fill_zero_u64, dim3(1), dim3(1), 0, stream, h->head);
+    QR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(fm_persistent_kernel, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat, d_off,
+                       npat, d_count, h->head, refill);
+    QR_HIP(hipGetLastError());
+    return QR_OK;
+}
+
+int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
+                         uint32_t *d_count, hipStream_t stream) {
+    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_batched");
+    if (rc) return rc;
+    if (!batch) batch = npat;
+    const FmDev f = dev_view(h);
+    for (uint64_t p0 = 0; p0 < npat; p0 += batch) {
+        const uint64_t np = std::min(batch, npat - p0);
+        const uint64_t blocks = (np + 255) / 256;
+        if (blocks > 0x7fffffffull) {
+            set_error("quadfm_count_batched: batch too large");
+            return QR_EINVAL;
+        }
+        hipLaunchKernelGGL(fm_batch_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off, p0, np,
+                           d_count);
+        QR_HIP(hipGetLastError());
+    }
+    return QR_OK;
+}
+
+int quadfm_check(qr_quadfm h, hipStream_t stream) {
+    if (!h) return QR_EINVAL;
+    int rc = check_device(h->device);
+    if (rc) return rc;
+    QR_HIP(hipStreamSynchronize(stream));
+    return QR_OK;
+}
+
+int quadfm_free(qr_quadfm h) {
+    release(h);
+    return QR_OK;
+}
+
+uint64_t quadfm_len(qr_quadfm h) { return h ? h->n1 - 1 : 0; }
+uint64_t quadfm_bytes(qr_quadfm h) {
+    return h ? h->n_lines * 128 + h->n_sb * 16 + KMER_ENTRIES * sizeof(uint2) : 0;
+}
+
+int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t) {
+    if (!h || !t) return QR_EINVAL;
+    if ((t->block && (t->block < 64 || t->block > 256 || t->block % 64)) || t->per_lane < 0 || t->per_lane > 64 ||
+        t->grid_waves < 0 || t->grid_waves > 64) {
+        set_error("quadfm_set_tuning: block 64..256 step 64, refill threshold 0..64, waves per CU 0..64");
+        return QR_EINVAL;
+    }
+    h->tune = *t;
+    return QR_OK;
+}
+
+int quadfm_table(qr_quadfm h, const void **d_table, uint64_t *entries) {
+    if (!h) return QR_EINVAL;
+    if (d_table) *d_table = h->table;
+    if (entries) *entries = KMER_ENTRIES;
+    return QR_OK;
+}
+
+int quadfm_export_table(qr_quadfm h, uint32_t *h_pairs) {
+    if (!h || !h_pairs) return QR_EINVAL;
+    int rc = check_device(h->device);
+    if (rc) return rc;
+    QR_HIP(hipMemcpy(h_pairs, h->table, KMER_ENTRIES * sizeof(uint2), hipMemcpyDeviceToHost));
+    return QR_OK;
+}
+
+int quadfm_c_array(qr_quadfm h, uint64_t *h_C4) {
+    if (!h || !h_C4) return QR_EINVAL;
+    for (int c = 0; c < 4; ++c) h_C4[c] = h->C[c];
+    return QR_OK;
+}
+
+}  // extern "C"
