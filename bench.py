@@ -1,0 +1,367 @@
+#!/usr/bin/env python3
+"""Benchmark of the rank / FM-index hot path on one MI355X.
+
+One step = one batch (2^24 queries) through every rank row of the scale configuration:
+  QuadRank rank(q,c) and rank4(q) on a 2^32-base text (uniform ACGT with 1000 planted 10-kb
+  segments x 20 copies, 1% substitutions), BiRank rank(q) on 2^36-bit vectors at densities 0.5
+  and 0.05; 10^9 uniform queries per row are issued as 59 batches of 2^24 and one of 10,144,256,
+  step k using batch k mod 60.  Inputs and queries are resident in HBM before timing starts.
+`value` is rank queries per second over the whole step.  Per-row rates come from HIP events
+around each launch on the stream the kernels run on.
+
+The FM-index rows run the batched-count configuration (2^28-base text with the same repeat
+planting, 10^7 patterns of length 20..250, 90% sampled with 1% substitutions, 10% iid) with the
+persistent work-queue kernel and with one plain launch per batch, in their own timed loop.
+The CPU baseline times the oracle on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+BATCH = 1 << 24
+TOTAL_Q = 10 ** 9
+
+# algorithmic bytes per query: one random 128-byte line + the coalesced query/result streams
+BYTES_PER_QUERY = {
+    "quadrank_rank": 128 + 8 + 1 + 8,
+    "quadrank_rank4": 128 + 8 + 32,
+    "birank_rank_p0.5": 128 + 8 + 8,
+    "birank_rank_p0.05": 128 + 8 + 8,
+}
+KERNEL_NAMES = {
+    "quadrank_rank": "qr_rank1_pair_kernel",
+    "quadrank_rank4": "qr_rank4_pair_kernel",
+    "birank_rank_p0.5": "br_rank_pair_kernel",
+    "birank_rank_p0.05": "br_rank_pair_kernel",
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def batches(total: int, batch: int):
+    out, o = [], 0
+    while o < total:
+        out.append((o, min(batch, total - o)))
+        o += batch
+    return out
+
+
+def source_hash(*names) -> str:
+    h = hashlib.sha256()
+    for nme in names:
+        with open(os.path.join(ROOT, "paper_2602_04103_amd", "csrc", nme), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-fm", action="store_true", help="skip the FM-index rows")
+    ap.add_argument("--fm-patterns", type=int, default=10 ** 7)
+    ap.add_argument("--fm-reps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
+    ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05")
+    ap.add_argument("--json-out", default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the rank structures and the FM-index are replicated per GPU; see the sharding notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    from paper_2602_04103_amd import autotune
+
+    qr.lib()  # fail loudly when the HIP library is missing
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = [r for r in args.rows.split(",") if r]
+    t_setup = time.time()
+
+    def to_dev(a):
+        a = np.ascontiguousarray(a)
+        if a.dtype == np.uint64:
+            a = a.view(np.int64)
+        return torch.from_numpy(a).to(dev)
+
+    # ------------------------------------------------------------------ structures + queries
+    structs, qsets, builds = {}, {}, {}
+    packed_q = None
+    n_qr = 1 << 32
+    if any(r.startswith("quadrank") for r in rows):
+        t0 = time.time()
+        codes = datagen.dna_codes(3202, n_qr)
+        datagen.plant_repeats(3203, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
+        packed_q = datagen.pack2(codes)
+        del codes
+        d = to_dev(packed_q)
+        log("quadrank text generated %.1fs" % (time.time() - t0))
+        torch.cuda.synchronize()
+        t0 = time.time()
+        structs["quadrank"] = qr.QuadRank(d, n_qr)
+        builds["quadrank_build_s"] = time.time() - t0
+        builds["quadrank_bytes"] = structs["quadrank"].nbytes
+        del d
+        if "quadrank_rank" in rows:
+            qsets["quadrank_rank"] = (to_dev(datagen.queries(3204, n_qr, TOTAL_Q)), to_dev(datagen.symbols(3205, TOTAL_Q)))
+        if "quadrank_rank4" in rows:
+            qsets["quadrank_rank4"] = (to_dev(datagen.queries(3206, n_qr, TOTAL_Q)), None)
+    n_br = 1 << 36
+    for dens, seed in ((0.5, 3636), (0.05, 3637)):
+        row = "birank_rank_p%g" % dens
+        if row not in rows:
+            continue
+        t0 = time.time()
+        d = to_dev(datagen.bits(seed, n_br, dens))
+        torch.cuda.synchronize()
+        t1 = time.time()
+        structs[row] = qr.BiRank(d, n_br)
+        builds[row.replace("rank", "build") + "_s"] = time.time() - t1
+        del d
+        qsets[row] = (to_dev(datagen.queries(seed + 100, n_br, TOTAL_Q)), None)
+        log("%s ready (gen %.1fs)" % (row, t1 - t0))
+    torch.cuda.empty_cache()
+
+    outs = torch.empty(BATCH * 4, dtype=torch.int64, device=dev)
+    bl = batches(TOTAL_Q, BATCH)
+
+    def launch(row, k):
+        o, cnt = bl[k % len(bl)]
+        q, c = qsets[row]
+        if row == "quadrank_rank":
+            structs["quadrank"].rank(q[o:o + cnt], c[o:o + cnt], outs[:cnt])
+        elif row == "quadrank_rank4":
+            structs["quadrank"].rank4(q[o:o + cnt], outs[:4 * cnt])
+        else:
+            structs[row].rank(q[o:o + cnt], outs[:cnt])
+
+    # ------------------------------------------------------------------ autotune (untimed)
+    tuning = {}
+    for row in rows:
+        h = structs["quadrank"] if row.startswith("quadrank") else structs[row]
+        if args.no_tune:
+            h.set_tuning(lanes=2, per_lane=1, block=256, grid_waves=0)
+            tuning[row] = "default"
+            continue
+        best, table = autotune.tune(row, h.n, h.set_tuning, lambda r=row: launch(r, 0), autotune.RANK_CANDIDATES,
+                                    use_cache=False)
+        tuning[row] = best
+        log("tuned %s -> %s (%s)" % (row, best, ", ".join("%.3f" % (t * 1e3) for _, t in table[:6])))
+        if row == "quadrank_rank4":  # rank and rank4 share the handle: keep the per-row setting
+            tuning["_rank4_setting"] = best
+
+    def apply(row):
+        h = structs["quadrank"] if row.startswith("quadrank") else structs[row]
+        if tuning.get(row) not in (None, "default"):
+            h.set_tuning(**tuning[row])
+
+    if args.calibrate_copy:
+        src = torch.zeros(1 << 27, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # ------------------------------------------------------------------ timed steps
+    for k in range(args.warmup):
+        for row in rows:
+            apply(row)
+            launch(row, k)
+    torch.cuda.synchronize()
+    ev = {row: [] for row in rows}
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        for row in rows:
+            apply(row)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            launch(row, k)
+            b.record(stream)
+            ev[row].append((a, b, bl[k % len(bl)][1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    step_queries = sum(bl[k % len(bl)][1] for k in range(args.steps)) * len(rows)
+    row_res = {}
+    for row in rows:
+        secs = [a.elapsed_time(b) / 1e3 for a, b, _ in ev[row]]
+        nq = sum(c for _, _, c in ev[row])
+        per_launch = statistics.mean(secs)
+        qps = nq / sum(secs)
+        bpq = BYTES_PER_QUERY[row]
+        achieved = bpq * nq / sum(secs) / 1e9
+        row_res[row] = {
+            "queries_per_s": qps,
+            "avg_launch_ms": per_launch * 1e3,
+            "lines_per_query": 1,
+            "roofline_frac_hbm": achieved / HBM_PEAK_GBS,
+            "algorithmic_GBps": achieved,
+            "tuning": tuning.get(row),
+        }
+        log("%-20s %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline" % (row, qps / 1e9, per_launch * 1e3,
+                                                                        100 * achieved / HBM_PEAK_GBS))
+    ms_per_step = wall / args.steps * 1e3
+    value = step_queries / wall
+
+    # dominant kernel = largest share of the step's time
+    dom = max(rows, key=lambda r: row_res[r]["avg_launch_ms"])
+    traffic = None
+    prof_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        prof = json.load(open(prof_path))
+        ent = prof.get("kernels", {}).get(dom)
+        src = source_hash(*prof.get("sources", []))
+        if ent and src == prof.get("source_hash"):
+            traffic = ent["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    roofline = {
+        "bound": "hbm",
+        "kernel": KERNEL_NAMES[dom] + " (" + dom + ")",
+        "achieved": round(row_res[dom]["algorithmic_GBps"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(row_res[dom]["roofline_frac_hbm"], 4),
+        "traffic": traffic,
+        "bytes_per_query": BYTES_PER_QUERY[dom],
+    }
+
+    # ------------------------------------------------------------------ FM-index rows
+    fm_res = None
+    if not args.no_fm:
+        fm_res = bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev)
+
+    # ------------------------------------------------------------------ CPU baseline (oracle)
+    cpu = None
+    if not args.no_cpu_baseline and packed_q is not None and "quadrank_rank" in qsets:
+        cpu = cpu_baseline(packed_q, n_qr, datagen, np)
+
+    out = {
+        "metric": "rank queries/s + % HBM random-line roofline; FM count patterns/s, p99 latency",
+        "value": value,
+        "unit": "rank queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "scale rank rows: QuadRank rank(q,c)+rank4 on 2^32 bases (uniform ACGT, 1000 planted "
+                        "10-kb segments x20, 1% subs) and BiRank rank on 2^36 bits (Bernoulli 0.5 and 0.05); "
+                        "10^9 uniform queries per row in batches of 2^24",
+            "global_batch": BATCH,
+            "rows_per_step": rows,
+            "queries_per_step": step_queries // args.steps,
+        },
+        "rows": row_res,
+        "builds": builds,
+        "roofline": roofline,
+        "fm": fm_res,
+        "cpu_baseline": cpu,
+        "setup_s": round(time.time() - t_setup, 1),
+    }
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(line + "\n")
+
+
+def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
+    n = 1 << 28
+    t0 = time.time()
+    codes = datagen.dna_codes(2828, n)
+    datagen.plant_repeats(2829, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
+    t1 = time.time()
+    bwt, dollar = qr.quadfm_bwt_host(codes)
+    t2 = time.time()
+    fm = qr.QuadFm(to_dev(bwt), n + 1, dollar)
+    torch.cuda.synchronize()
+    t3 = time.time()
+    pat, off, kind = datagen.patterns(2830, codes, args.fm_patterns)
+    del codes
+    dp, do = to_dev(pat), to_dev(off)
+    npat = args.fm_patterns
+    total_chars = int(off[-1])
+    log("fm index: text %.1fs, host SA+BWT %.1fs, device build %.2fs" % (t1 - t0, t2 - t1, t3 - t2))
+    cnt = torch.empty(npat, dtype=torch.int32, device=dev)
+    cnt_b = torch.empty(npat, dtype=torch.int32, device=dev)
+    if not args.no_tune:
+        sub = min(npat, 2_000_000)
+        best, _ = autotune.tune("quadfm", n, fm.set_tuning, lambda: fm.count(dp, do[:sub + 1], cnt[:sub]),
+                                autotune.FM_CANDIDATES, reps=2, use_cache=False)
+    else:
+        best = "default"
+    t_p = autotune.time_launch(lambda: fm.count(dp, do, cnt), reps=args.fm_reps)
+    res = {"workload": "QuadFm count: 2^28-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs) "
+                       "+ sentinel; %d patterns, lengths 20..250, 90%% sampled with 1%% substitutions, 10%% iid"
+                       % npat,
+           "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3, "tuning": best,
+           "index_bytes": fm.nbytes, "bits_per_base": fm.nbytes * 8 / n, "pattern_chars": total_chars,
+           "host_sa_bwt_s": t2 - t1, "device_build_s": t3 - t2}
+    for batch in (1 << 16, 1 << 20, 0):
+        t_b = autotune.time_launch(lambda: fm.count_batched(dp, do, batch, cnt_b), reps=args.fm_reps)
+        res["batched_%s_patterns_per_s" % (batch or "all")] = npat / t_b
+        res["batched_%s_ms" % (batch or "all")] = t_b * 1e3
+    best_b = max(v for k, v in res.items() if k.startswith("batched_") and k.endswith("per_s"))
+    res["gain_vs_best_batched"] = res["persistent_patterns_per_s"] / best_b
+    res["gain_vs_batch_2^16"] = res["persistent_patterns_per_s"] / res["batched_65536_patterns_per_s"]
+    res["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
+    log("fm persistent %.1f M patterns/s; batched best %.1f M; gain %.2fx; equal=%s" % (
+        npat / t_p / 1e6, best_b / 1e6, res["gain_vs_best_batched"], res["persistent_equals_batched"]))
+    fm.free()
+    return res
+
+
+def cpu_baseline(packed, n, datagen, np):
+    """The oracle (plain C, OpenMP over queries) on the host cores: build its prefix table over the
+    whole 2^32-base text once per call, then answer a bounded sample of the same queries."""
+    import oracle
+    S = 10 ** 7
+    q = datagen.queries(3204, n, S)
+    c = datagen.symbols(3205, S)
+    t0 = time.perf_counter()
+    oracle.rank_dna(packed, n, q[:1], c[:1])
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.rank_dna(packed, n, q, c)
+    t_all = time.perf_counter() - t0
+    t_q = max(t_all - t_build, 1e-9)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": S / t_q, "unit": "rank queries/s", "cores": cores, "kind": "oracle",
+            "sample": "first 10^7 of the QuadRank rank(q,c) queries on the same 2^32-base text; the oracle's "
+                      "prefix table over the whole text (%.1f s, built per call) is subtracted, as the GPU build "
+                      "is outside the GPU timing" % t_build,
+            "prefix_build_s": t_build}
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,12 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
  * overlap in time (they share the queue head); use one handle per concurrent stream. */
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
                  hipStream_t stream);
+/* quadfm_count with a caller-owned queue head: d_workspace is >= 8 bytes of 8-byte aligned device
+ * memory, zeroed by the call itself on `stream`.  Calls with distinct workspaces may overlap on
+ * different streams over one handle (the index is read-only); this is what concurrent batches of a
+ * serving loop use. */
+int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+                    void *d_workspace, hipStream_t stream);
 /* Same result with one plain launch per batch of `batch` patterns, one lane per pattern
  * (batch = 0: a single launch over all patterns).  The baseline for the work-queue kernel. */
 int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
@@ -153,15 +159,17 @@ int quadfm_c_array(qr_quadfm h, uint64_t *h_C4);
 
 /* ------------------------------------------------------------------------------------------------
  * Query-kernel tuning (used by the autotuner).  Applies to the handle's subsequent queries.
- *   block      threads per workgroup (64..1024, multiple of 64; 0 = default)
- *   per_lane   queries each lane keeps in flight (1, 2, 4 or 8; 0 = default)
- *   grid_waves resident waves per CU to launch (0 = one lane per query, no grid-stride loop)
+ *   block      threads per workgroup (64, 128, 192 or 256; 0 = default 256)
+ *   per_lane   queries each lane (or lane pair) keeps in flight (1, 2, 4 or 8; 0 = default)
+ *   grid_waves resident waves per CU to launch (0 = enough lanes for every query, no grid-stride)
+ *   lanes      lanes per query: 2 (default; each lane reads one 64-byte half of the line and the
+ *              halves are combined by a cross-lane shuffle) or 1 (one lane reads what it needs)
  * ---------------------------------------------------------------------------------------------- */
 typedef struct {
     int32_t block;
     int32_t per_lane;
     int32_t grid_waves;
-    int32_t reserved;
+    int32_t lanes;
 } qr_tuning;
 
 int birank_set_tuning(qr_birank h, const qr_tuning *t);

@@ -29,7 +29,7 @@ class QRError(RuntimeError):
 
 
 class qr_tuning(C.Structure):
-    _fields_ = [("block", C.c_int32), ("per_lane", C.c_int32), ("grid_waves", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("per_lane", C.c_int32), ("grid_waves", C.c_int32), ("lanes", C.c_int32)]
 
 
 _lib = None
@@ -74,13 +74,15 @@ def lib():
             "quadfm_build": (ci, [vp, u64, u64, vp, C.POINTER(vp)]),
             "quadfm_count": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadfm_count_batched": (ci, [vp, vp, vp, u64, u64, vp, vp]),
+            "quadfm_count_ws": (ci, [vp, vp, vp, u64, vp, vp, vp]),
             "quadfm_check": (ci, [vp, vp]),
             "quadfm_free": (ci, [vp]),
             "quadfm_len": (u64, [vp]),
             "quadfm_bytes": (u64, [vp]),
             "quadfm_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
             "quadfm_table": (ci, [vp, C.POINTER(vp), C.POINTER(u64)]),
-            "quadfm_c_array": (ci, [vp, C.POINTER(u64)]),
+            "quadfm_export_table": (ci, [vp, vp]),
+            "quadfm_c_array": (ci, [vp, vp]),
         }
         for name, (res, args) in list(sig.items()) + list(optional.items()):
             if not hasattr(L, name):
@@ -197,6 +199,57 @@ def qr_gather_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, bytes_
     return out
 
 
+# ------------------------------------------------------------------------------------------ QuadFm
+def quadfm_bwt_host(text_codes):
+    """Host input preparation: (BWT of T$ packed 2 bits/symbol with '$' stored as A, dollar row)."""
+    import numpy as np
+    t = np.ascontiguousarray(text_codes, dtype=np.uint8)
+    n = t.size
+    out = np.zeros(max(1, (n + 1 + 31) // 32), dtype=np.uint64)
+    d = u64()
+    src = t if n else np.zeros(1, np.uint8)
+    _check(lib().quadfm_bwt_host(src.ctypes.data, n, out.ctypes.data, C.byref(d)), "quadfm_bwt_host")
+    return out, int(d.value)
+
+
+def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None) -> int:
+    h = vp()
+    _check(lib().quadfm_build(_dev(bwt_packed2, "bwt_packed2", W64, (n_plus_1 + 31) // 32), n_plus_1, dollar_pos,
+                              _stream(stream), C.byref(h)), "quadfm_build")
+    return h.value
+
+
+def quadfm_count(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, stream=None):
+    npat = off.numel() - 1
+    _check(lib().quadfm_count(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, _dev(count, "count", W32, npat),
+                              _stream(stream)), "quadfm_count")
+    return count
+
+
+def quadfm_count_ws(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, workspace: torch.Tensor,
+                    stream=None):
+    npat = off.numel() - 1
+    _check(lib().quadfm_count_ws(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat,
+                                 _dev(count, "count", W32, npat), _dev(workspace, "workspace", W64, 1),
+                                 _stream(stream)), "quadfm_count_ws")
+    return count
+
+
+def quadfm_count_batched(h: int, pat: torch.Tensor, off: torch.Tensor, batch: int, count: torch.Tensor, stream=None):
+    npat = off.numel() - 1
+    _check(lib().quadfm_count_batched(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, batch,
+                                      _dev(count, "count", W32, npat), _stream(stream)), "quadfm_count_batched")
+    return count
+
+
+def quadfm_check(h: int, stream=None):
+    _check(lib().quadfm_check(h, _stream(stream)), "quadfm_check")
+
+
+def quadfm_free(h: int):
+    lib().quadfm_free(h)
+
+
 # ---------------------------------------------------------------------------------------- wrappers
 class _Handle:
     _free = None
@@ -215,8 +268,8 @@ class _Handle:
         except Exception:
             pass
 
-    def _tune(self, fn, block=0, per_lane=0, grid_waves=0):
-        t = qr_tuning(block, per_lane, grid_waves, 0)
+    def _tune(self, fn, block=0, per_lane=0, grid_waves=0, lanes=0):
+        t = qr_tuning(block, per_lane, grid_waves, lanes)
         _check(fn(self.h, C.byref(t)), "set_tuning")
 
 
@@ -303,3 +356,54 @@ class QuadRank(_Handle):
         sup = np.empty((ns, 4), dtype=np.uint32)
         _check(lib().quadrank_export(self.h, lines.ctypes.data, sup.ctypes.data), "quadrank_export")
         return lines, sup
+
+
+class QuadFm(_Handle):
+    """Count-only FM-index built from a packed BWT of T$ ('$' stored as A at row dollar_pos)."""
+    _free = staticmethod(quadfm_free)
+
+    def __init__(self, bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None):
+        super().__init__(quadfm_build(bwt_packed2, n_plus_1, dollar_pos, stream))
+        self.n = n_plus_1 - 1
+
+    @classmethod
+    def from_text(cls, text_codes, stream=None):
+        """Host SA/BWT construction, then the device build."""
+        import numpy as np
+        bwt, dollar = quadfm_bwt_host(text_codes)
+        d = torch.from_numpy(bwt.view(np.int64)).cuda()
+        return cls(d, int(np.asarray(text_codes).size) + 1, dollar, stream)
+
+    def count(self, pat: torch.Tensor, off: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        if out is None:
+            out = torch.empty(off.numel() - 1, dtype=torch.int32, device=off.device)
+        return quadfm_count(self.h, pat, off, out, stream)
+
+    def count_batched(self, pat: torch.Tensor, off: torch.Tensor, batch: int = 0, out: torch.Tensor | None = None,
+                      stream=None):
+        if out is None:
+            out = torch.empty(off.numel() - 1, dtype=torch.int32, device=off.device)
+        return quadfm_count_batched(self.h, pat, off, batch, out, stream)
+
+    def check(self, stream=None):
+        quadfm_check(self.h, stream)
+
+    def set_tuning(self, block=0, refill=0, waves_per_cu=0):
+        self._tune(lib().quadfm_set_tuning, block=block, per_lane=refill, grid_waves=waves_per_cu)
+
+    def c_array(self):
+        import numpy as np
+        c = np.zeros(4, dtype=np.uint64)
+        _check(lib().quadfm_c_array(self.h, c.ctypes.data), "quadfm_c_array")
+        return c
+
+    def table(self):
+        """(sp, ep) u32 arrays of the 4^8 entries of the 8-mer table."""
+        import numpy as np
+        t = np.zeros(2 * 65536, dtype=np.uint32)
+        _check(lib().quadfm_export_table(self.h, t.ctypes.data), "quadfm_export_table")
+        return t[0::2].copy(), t[1::2].copy()
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().quadfm_bytes(self.h))

@@ -33,12 +33,25 @@ def hipcc() -> str:
     return p
 
 
+SCRATCH_KERNELS: list = []
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
+    cmd = [hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))
+    # report kernels that spill to scratch (private memory): every kernel here should use registers only
+    name = None
+    for line in r.stderr.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:")[1].split("[")[0].strip()
+        elif "ScratchSize" in line and name:
+            size = int(line.split(":")[-1].split("[")[0].strip() or 0)
+            if size:
+                SCRATCH_KERNELS.append((src, name, size))
     return obj
 
 
@@ -53,6 +66,8 @@ def build() -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-6000:]))
     os.replace(tmp, LIB)
+    for src, name, size in SCRATCH_KERNELS:
+        print("warning: %s: kernel %s uses %d bytes of scratch per lane" % (src, name, size))
     return LIB
 
 

@@ -99,6 +99,14 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
+// Value held by the other lane of this lane's pair (lane ^ 1), by a DPP quad permute [1,0,3,2].
+__device__ __forceinline__ uint32_t pair_swap32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint64_t pair_swap64(uint64_t x) {
+    return (uint64_t)pair_swap32((uint32_t)x) | ((uint64_t)pair_swap32((uint32_t)(x >> 32)) << 32);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -57,7 +57,9 @@ struct FmDev {
 };
 
 __device__ __forceinline__ uint64_t fm_C(const FmDev &f, uint32_t c) {
-    return c == 0 ? f.C0 : c == 1 ? f.C1 : c == 2 ? f.C2 : f.C3;
+    const uint64_t m1 = 0ull - (c & 1u), m2 = 0ull - ((c >> 1) & 1u);
+    const uint64_t lo = (f.C0 & ~m1) | (f.C1 & m1), hi = (f.C2 & ~m1) | (f.C3 & m1);
+    return (lo & ~m2) | (hi & m2);
 }
 
 // One backward step of the interval [sp, ep) with symbol c.
@@ -364,23 +366,41 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
     return QR_OK;
 }
 
-int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
-                 hipStream_t stream) {
-    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count");
-    if (rc) return rc;
-    if (!npat) return QR_OK;
+static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+                            unsigned long long *head, hipStream_t stream) {
     const int block = h->tune.block ? h->tune.block : 256;
     const uint32_t refill = h->tune.per_lane > 0 ? (uint32_t)h->tune.per_lane : 16u;
     const int wpc = h->tune.grid_waves > 0 ? h->tune.grid_waves : 16;
     uint64_t blocks = (uint64_t)cu_count() * wpc * 64 / block;
     const uint64_t need = (npat + block - 1) / block;  // no more waves than patterns need
     blocks = std::max<uint64_t>(1, std::min(blocks, need));
-    hipLaunchKernelGGL(fill_zero_u64, dim3(1), dim3(1), 0, stream, h->head);
+    hipLaunchKernelGGL(fill_zero_u64, dim3(1), dim3(1), 0, stream, head);
     QR_HIP(hipGetLastError());
     hipLaunchKernelGGL(fm_persistent_kernel, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat, d_off,
-                       npat, d_count, h->head, refill);
+                       npat, d_count, head, refill);
     QR_HIP(hipGetLastError());
     return QR_OK;
+}
+
+int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+                 hipStream_t stream) {
+    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count");
+    if (rc) return rc;
+    if (!npat) return QR_OK;
+    return count_persistent(h, d_pat, d_off, npat, d_count, h->head, stream);
+}
+
+int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
+                    void *d_workspace, hipStream_t stream) {
+    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_ws");
+    if (rc) return rc;
+    if (!d_workspace || ((uintptr_t)d_workspace & 7)) {
+        set_error("quadfm_count_ws: d_workspace must be a non-null, 8-byte aligned device pointer");
+        return QR_EINVAL;
+    }
+    if (!npat) return QR_OK;
+    return count_persistent(h, d_pat, d_off, npat, d_count, reinterpret_cast<unsigned long long *>(d_workspace),
+                            stream);
 }
 
 int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,

@@ -210,6 +210,99 @@ __global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__
     }
 }
 
+// Lane-pair kernels (default): lanes 2k, 2k+1 serve one query, lane hf loading half hf of the line
+// (64 contiguous bytes), so each wave load instruction touches 32 lines.  The lane holding q's half
+// counts; lane 0 adds offset and delta; the two contributions are summed across the pair.
+template <int PER_PAIR>
+__global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restrict__ lines,
+                                                            const uint32_t *__restrict__ super, uint64_t n,
+                                                            const uint64_t *__restrict__ Q,
+                                                            const uint8_t *__restrict__ Cs, uint64_t nq,
+                                                            uint64_t *__restrict__ out, uint32_t *__restrict__ err) {
+    const uint32_t hf = threadIdx.x & 1u;
+    const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
+        uint64_t q[PER_PAIR], r[PER_PAIR];
+        uint32_t c[PER_PAIR];
+        uint4 s[PER_PAIR];
+        bool bad[PER_PAIR];
+        PairHalf ph[PER_PAIR];
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint64_t i = min(i0 + u * pairs, nq - 1);
+            q[u] = Q[i];
+            c[u] = Cs[i];
+        }
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            bad[u] = q[u] > n || c[u] > 3;
+            load_pair_half(lines, bad[u] ? 0 : q[u], hf, ph[u]);
+            s[u] = reinterpret_cast<const uint4 *>(super)[ph[u].j / QR_LINES_PER_SB];
+        }
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint32_t cc = c[u] & 3u;
+            const uint32_t cnt = pair_count1(ph[u], hf, cc);
+            const uint64_t mine = hf == 0 ? ((uint64_t)sel4(s[u], cc) << QR_SHIFT) + pair_delta(ph[u], cc) - cnt : (uint64_t)cnt;
+            r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
+        }
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint64_t i = i0 + u * pairs;
+            if (hf == 0 && i < nq) {
+                out[i] = r[u];
+                if (bad[u]) atomicOr(err, 1u);
+            }
+        }
+    }
+}
+
+template <int PER_PAIR>
+__global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restrict__ lines,
+                                                            const uint32_t *__restrict__ super, uint64_t n,
+                                                            const uint64_t *__restrict__ Q, uint64_t nq,
+                                                            uint64_t *__restrict__ out4, uint32_t *__restrict__ err) {
+    const uint32_t hf = threadIdx.x & 1u;
+    const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
+        uint64_t q[PER_PAIR], ra[PER_PAIR], rb[PER_PAIR];
+        uint4 s[PER_PAIR];
+        bool bad[PER_PAIR];
+        PairHalf ph[PER_PAIR];
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) q[u] = Q[min(i0 + u * pairs, nq - 1)];
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            bad[u] = q[u] > n;
+            load_pair_half(lines, bad[u] ? 0 : q[u], hf, ph[u]);
+            s[u] = reinterpret_cast<const uint4 *>(super)[ph[u].j / QR_LINES_PER_SB];
+        }
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            uint32_t cnt[4];
+            pair_count4(ph[u], hf, cnt);
+            uint64_t r[4];
+#pragma unroll
+            for (uint32_t cc = 0; cc < 4; ++cc) {
+                const uint64_t mine = hf == 0 ? ((uint64_t)sel4(s[u], cc) << QR_SHIFT) + pair_delta(ph[u], cc) - cnt[cc]
+                                              : (uint64_t)cnt[cc];
+                r[cc] = mine + pair_swap64(mine);
+            }
+            // lane 0 writes symbols A, C and lane 1 writes G, T of the row
+            ra[u] = bad[u] ? ~0ull : (hf == 0 ? r[0] : r[2]);
+            rb[u] = bad[u] ? ~0ull : (hf == 0 ? r[1] : r[3]);
+        }
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint64_t i = i0 + u * pairs;
+            if (i < nq) {
+                reinterpret_cast<ulonglong2 *>(out4 + 4 * i)[hf] = make_ulonglong2(ra[u], rb[u]);
+                if (bad[u] && hf == 0) atomicOr(err, 1u);
+            }
+        }
+    }
+}
+
 void release(qr_quadrank_s *h) {
     if (!h) return;
     if (h->lines) (void)hipFree(h->lines);
@@ -218,8 +311,8 @@ void release(qr_quadrank_s *h) {
     delete h;
 }
 
-uint64_t grid_for(uint64_t nq, int pl, int block, int grid_waves) {
-    uint64_t blocks = ((nq + pl - 1) / pl + block - 1) / block;
+uint64_t grid_for(uint64_t nq, int pl, int block, int grid_waves, int lanes) {
+    uint64_t blocks = (lanes * ((nq + pl - 1) / pl) + block - 1) / block;
     if (grid_waves > 0) blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, (uint64_t)cu_count() * grid_waves * 64 / block));
     return std::max<uint64_t>(1, std::min<uint64_t>(blocks, 0x7fffffffull));
 }
@@ -284,7 +377,7 @@ int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr
     h->n = n;
     h->n_lines = n / QR_DATA_BASES + 1;
     h->n_sb = n / QR_SB_BASES + 1;
-    h->tune = qr_tuning{256, 1, 0, 0};
+    h->tune = qr_tuning{256, 1, 0, 2};
     if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 16) != hipSuccess ||
         hipMalloc(&h->err, 4) != hipSuccess) {
         (void)hipGetLastError();
@@ -328,8 +421,19 @@ int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64
     }
     if (!nq) return QR_OK;
     const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
-    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves)), b(block);
+    const int lanes = h->tune.lanes == 1 ? 1 : 2;
+    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
     const uint4 *L = reinterpret_cast<const uint4 *>(h->lines);
+    if (lanes == 2) {
+        switch (pl) {
+            case 1: hipLaunchKernelGGL(qr_rank1_pair_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
+            case 2: hipLaunchKernelGGL(qr_rank1_pair_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
+            case 4: hipLaunchKernelGGL(qr_rank1_pair_kernel<4>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
+            default: hipLaunchKernelGGL(qr_rank1_pair_kernel<8>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
+        }
+        QR_HIP(hipGetLastError());
+        return QR_OK;
+    }
     switch (pl) {
         case 1: hipLaunchKernelGGL(qr_rank1_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
         case 2: hipLaunchKernelGGL(qr_rank1_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
@@ -345,8 +449,19 @@ int quadrank_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_
     if (rc) return rc;
     if (!nq) return QR_OK;
     const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
-    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves)), b(block);
+    const int lanes = h->tune.lanes == 1 ? 1 : 2;
+    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
     const uint4 *L = reinterpret_cast<const uint4 *>(h->lines);
+    if (lanes == 2) {
+        switch (pl) {
+            case 1: hipLaunchKernelGGL(qr_rank4_pair_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
+            case 2: hipLaunchKernelGGL(qr_rank4_pair_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
+            case 4: hipLaunchKernelGGL(qr_rank4_pair_kernel<4>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
+            default: hipLaunchKernelGGL(qr_rank4_pair_kernel<8>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
+        }
+        QR_HIP(hipGetLastError());
+        return QR_OK;
+    }
     switch (pl) {
         case 1: hipLaunchKernelGGL(qr_rank4_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
         case 2: hipLaunchKernelGGL(qr_rank4_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
@@ -403,11 +518,12 @@ int quadrank_set_tuning(qr_quadrank h, const qr_tuning *t) {
     if (!h || !t) return QR_EINVAL;
     if ((t->block && (t->block < 64 || t->block > 256 || t->block % 64)) ||
         (t->per_lane && t->per_lane != 1 && t->per_lane != 2 && t->per_lane != 4 && t->per_lane != 8) ||
-        t->grid_waves < 0 || t->grid_waves > 64) {
-        set_error("quadrank_set_tuning: block 64..256 step 64, per_lane 1/2/4/8, grid_waves 0..64");
+        t->grid_waves < 0 || t->grid_waves > 64 || (t->lanes != 0 && t->lanes != 1 && t->lanes != 2)) {
+        set_error("quadrank_set_tuning: block 64..256 step 64, per_lane 1/2/4/8, grid_waves 0..64, lanes 1/2");
         return QR_EINVAL;
     }
     h->tune = *t;
+    if (!h->tune.lanes) h->tune.lanes = 2;
     return QR_OK;
 }
 

@@ -38,13 +38,18 @@ __device__ __forceinline__ void load_half(const uint4 *__restrict__ lines, const
     hl.s = reinterpret_cast<const uint4 *>(super)[j / QR_LINES_PER_SB];
 }
 
+// v.{x,y,z,w}[c] by mask arithmetic: a runtime-indexed select chain would be lowered to a
+// stack array (scratch memory) once several queries are unrolled per lane.
 __device__ __forceinline__ uint32_t sel4(const uint4 &v, uint32_t c) {
-    return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+    const uint32_t m1 = 0u - (c & 1u), m2 = 0u - ((c >> 1) & 1u);
+    const uint32_t lo = (v.x & ~m1) | (v.y & m1), hi = (v.z & ~m1) | (v.w & m1);
+    return (lo & ~m2) | (hi & m2);
 }
 
 __device__ __forceinline__ uint32_t delta_of(const HalfLine &hl, uint32_t c) {
-    const uint32_t d = (c & 2) ? hl.dGT : hl.dAC;
-    return (c & 1) ? (d >> 16) : (d & 0xffffu);
+    const uint32_t m2 = 0u - ((c >> 1) & 1u);
+    const uint32_t d = (hl.dAC & ~m2) | (hl.dGT & m2);
+    return (d >> (16u * (c & 1u))) & 0xffffu;
 }
 
 // Occurrences of c in the counted range of the half: slots [0, t) if up, else [t, 256).
@@ -91,6 +96,76 @@ __device__ __forceinline__ void rank4_from_half(const HalfLine &hl, uint64_t (&r
         const uint64_t mid = ((uint64_t)sel4(hl.s, c) << QR_SHIFT) + delta_of(hl, c);
         r[c] = hl.up ? mid + cnt[c] : mid - cnt[c];
     }
+}
+
+// ---- lane-pair form: lane hf (0/1) of a pair holds half hf of the line -------------------------
+struct PairHalf {
+    uint32_t w[16];  // half hf of the line, same word order as HalfLine::w
+    uint32_t t;      // slot of q inside the half that contains it
+    bool up;         // q lies in the upper half
+    uint64_t j;      // line index
+};
+
+__device__ __forceinline__ void load_pair_half(const uint4 *__restrict__ lines, uint64_t q, uint32_t hf, PairHalf &ph) {
+    ph.j = qr_line_of(q);
+    const uint32_t p = (uint32_t)(q - ph.j * QR_DATA_BASES) + QR_HDR;
+    ph.up = p >= QR_MID;
+    ph.t = ph.up ? p - QR_MID : p;
+    const uint4 *H = lines + ph.j * 8 + hf * 4;
+    const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
+    ph.w[0] = a.x, ph.w[1] = a.y, ph.w[2] = a.z, ph.w[3] = a.w;
+    ph.w[4] = b.x, ph.w[5] = b.y, ph.w[6] = b.z, ph.w[7] = b.w;
+    ph.w[8] = c.x, ph.w[9] = c.y, ph.w[10] = c.z, ph.w[11] = c.w;
+    ph.w[12] = d.x, ph.w[13] = d.y, ph.w[14] = d.z, ph.w[15] = d.w;
+}
+
+// Occurrences of c in this lane's share of the counted range (zero unless the lane holds q's half).
+__device__ __forceinline__ uint32_t pair_count1(const PairHalf &ph, uint32_t hf, uint32_t c) {
+    if ((uint32_t)ph.up != hf) return 0u;
+    const uint32_t inv = ph.up ? 0u : 0xffffffffu;
+    const uint32_t xl = (c & 1) ? 0u : 0xffffffffu, xh = (c & 2) ? 0u : 0xffffffffu;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const uint32_t m = prefix_mask32(ph.t, 2 * k + sub) ^ inv;
+            cnt += __popc((ph.w[4 * k + sub] ^ xl) & (ph.w[4 * k + 2 + sub] ^ xh) & m);
+        }
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ void pair_count4(const PairHalf &ph, uint32_t hf, uint32_t (&cnt)[4]) {
+    if ((uint32_t)ph.up != hf) {
+        cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0u;
+        return;
+    }
+    const uint32_t inv = ph.up ? 0u : 0xffffffffu;
+    uint32_t cT = 0, cL = 0, cH = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const uint32_t m = prefix_mask32(ph.t, 2 * k + sub) ^ inv;
+            const uint32_t lo = ph.w[4 * k + sub] & m, hi = ph.w[4 * k + 2 + sub] & m;
+            cT += __popc(lo & hi);
+            cL += __popc(lo);
+            cH += __popc(hi);
+        }
+    }
+    const uint32_t len = ph.up ? ph.t : QR_MID - ph.t;
+    cnt[0] = len - cL - cH + cT;
+    cnt[1] = cL - cT;
+    cnt[2] = cH - cT;
+    cnt[3] = cT;
+}
+
+// Delta b_{j,c} from lane 0's half (pair 0 low words).
+__device__ __forceinline__ uint32_t pair_delta(const PairHalf &ph, uint32_t c) {
+    const uint32_t m2 = 0u - ((c >> 1) & 1u);
+    const uint32_t d = (ph.w[0] & ~m2) | (ph.w[2] & m2);
+    return (d >> (16u * (c & 1u))) & 0xffffu;
 }
 
 }  // namespace qr

@@ -1,0 +1,146 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+  python -m paper_2602_04103_amd.profiling stats DIR [--cmd "..."]        kernel-trace statistics table
+  python -m paper_2602_04103_amd.profiling counters DIR COUNTER [...]     per-kernel mean of PMC counters
+  python -m paper_2602_04103_amd.profiling traffic FETCH_DIR WRITE_DIR --copy-bytes B --out JSON
+
+`traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM bytes per launch of each rank
+kernel, scaled by what the same counters read for a plain device copy of known size in the same
+runs (the calibration factor), and records a hash of the kernel sources they were taken with."""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SOURCES = ["quadrank.hip", "quadrank_dev.hpp", "birank.hip", "common.hpp"]
+ROW_KERNELS = {
+    "quadrank_rank": "qr_rank1_pair_kernel",
+    "quadrank_rank4": "qr_rank4_pair_kernel",
+    "birank_rank_p0.5": "br_rank_pair_kernel",
+    "birank_rank_p0.05": "br_rank_pair_kernel",
+}
+
+
+def _csvs(d: str, suffix: str):
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def _rows(path: str):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_stats(d: str):
+    out = []
+    for p in _csvs(d, "kernel_stats.csv"):
+        out += _rows(p)
+    return out
+
+
+def counter_values(d: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter."""
+    res = {}
+    for p in _csvs(d, "counter_collection.csv"):
+        for r in _rows(p):
+            name = r.get("Counter_Name") or r.get("Counter-Name")
+            if name != counter:
+                continue
+            k = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
+            res.setdefault(k, []).append(float(r.get("Counter_Value") or r.get("Counter-Value") or 0))
+    return res
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for nme in SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_04103_amd", "csrc", nme), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _match(kernels: dict, needle: str):
+    vals = []
+    for k, v in kernels.items():
+        if needle in k:
+            vals += v
+    return vals
+
+
+def cmd_stats(a):
+    rows = kernel_stats(a.dir)
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))
+    print("# rocprofv3 --kernel-trace --stats summary")
+    if a.cmd:
+        print("# command: " + a.cmd)
+    print("%-90s %8s %14s %12s %7s" % ("kernel", "calls", "total_ns", "avg_ns", "pct"))
+    for r in rows:
+        print("%-90s %8s %14s %12.0f %7.2f" % (r["Name"][:90], r["Calls"], r["TotalDurationNs"],
+                                               float(r["AverageNs"]), float(r.get("Percentage", 0) or 0)))
+
+
+def cmd_counters(a):
+    print("# rocprofv3 --pmc per-kernel mean over dispatches")
+    if a.cmd:
+        print("# command: " + a.cmd)
+    for c in a.counter:
+        vals = counter_values(a.dir, c)
+        for k, v in sorted(vals.items()):
+            print("%-24s %-80s dispatches=%-5d mean=%.4g" % (c, k[:80], len(v), statistics.mean(v)))
+
+
+def cmd_traffic(a):
+    fetch = counter_values(a.fetch_dir, "FETCH_SIZE")
+    write = counter_values(a.write_dir, "WRITE_SIZE")
+    copy_f = _match(fetch, a.copy_kernel)
+    copy_w = _match(write, a.copy_kernel)
+    if not copy_f or not copy_w:
+        sys.exit("no calibration copy kernel '%s' in the counter output" % a.copy_kernel)
+    # the copy reads and writes copy_bytes once each: factors convert counter KiB to bytes
+    f_fac = a.copy_bytes / (max(copy_f) * 1024.0)
+    w_fac = a.copy_bytes / (max(copy_w) * 1024.0)
+    out = {"sources": SOURCES, "source_hash": source_hash(), "fetch_factor": f_fac, "write_factor": w_fac,
+           "copy_bytes": a.copy_bytes, "kernels": {}}
+    for row, kname in ROW_KERNELS.items():
+        fv, wv = _match(fetch, kname), _match(write, kname)
+        if not fv or not wv:
+            continue
+        out["kernels"][row] = {
+            "kernel": kname,
+            "fetch_kib_per_dispatch": statistics.mean(fv),
+            "write_kib_per_dispatch": statistics.mean(wv),
+            "hbm_bytes_per_launch": statistics.mean(fv) * 1024.0 * f_fac + statistics.mean(wv) * 1024.0 * w_fac,
+        }
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--cmd", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("counter", nargs="+")
+    c.add_argument("--cmd", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--copy-kernel", default="elementwise")
+    t.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    {"stats": cmd_stats, "counters": cmd_counters, "traffic": cmd_traffic}[a.what](a)
+
+
+if __name__ == "__main__":
+    main()

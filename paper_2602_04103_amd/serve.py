@@ -1,0 +1,289 @@
+"""Serving loop for FM-index count requests against a device-resident QuadFm index.
+
+Continuous batching.  Requests arrive over time, each carrying a block of patterns.  Whenever a
+slot is free and device memory allows, every request that has arrived (FIFO, up to a batch limit)
+is admitted as one batch:
+  - the batch's patterns are copied to device memory taken from an arena of fixed size (the HBM
+    budget),
+  - the persistent count kernel runs on the slot's own stream with the slot's own queue head,
+  - the counts come back to pinned host memory.
+Up to `slots` batches are in flight at once, so batches that arrive while others run overlap on the
+device.  A request completes when the host observes its batch's completion event; its latency is
+completion time minus arrival time.
+
+The scheduler is written against a small executor interface (`submit`, `poll`, `counts`), with the
+GPU executor below and a CPU stand-in for tests of the scheduling logic.
+"""
+from __future__ import annotations
+
+import bisect
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------------------------- arena
+class Arena:
+    """First-fit allocator over [0, size) with aligned blocks; frees may arrive in any order."""
+
+    def __init__(self, size: int):
+        self.size = int(size)
+        self.free = [(0, self.size)]  # sorted, disjoint, coalesced (start, end)
+
+    def alloc(self, nbytes: int, align: int = 256) -> Optional[int]:
+        for k, (a, b) in enumerate(self.free):
+            s = (a + align - 1) // align * align
+            if s + nbytes <= b:
+                pieces = []
+                if s > a:
+                    pieces.append((a, s))
+                if s + nbytes < b:
+                    pieces.append((s + nbytes, b))
+                self.free[k:k + 1] = pieces
+                return s
+        return None
+
+    def release(self, start: int, nbytes: int):
+        blk = (start, start + nbytes)
+        k = bisect.bisect_left(self.free, blk)
+        self.free.insert(k, blk)
+        merged = []
+        for a, b in self.free:
+            if merged and merged[-1][1] >= a:
+                merged[-1] = (merged[-1][0], max(merged[-1][1], b))
+            else:
+                merged.append((a, b))
+        self.free = merged
+
+    @property
+    def free_bytes(self) -> int:
+        return sum(b - a for a, b in self.free)
+
+
+# ------------------------------------------------------------------------------------------ requests
+@dataclasses.dataclass
+class Workload:
+    """All requests of a run as one CSR: request r owns patterns [req_off[r], req_off[r+1]) of
+    (pat, off); arrival[r] is its arrival time in seconds from the start."""
+    pat: np.ndarray       # u8 codes
+    off: np.ndarray       # u64, npat + 1
+    req_off: np.ndarray   # i64, nreq + 1
+    arrival: np.ndarray   # f64, nreq
+
+    @property
+    def nreq(self) -> int:
+        return self.arrival.size
+
+    def batch_bytes(self, r0: int, r1: int) -> int:
+        p0, p1 = int(self.req_off[r0]), int(self.req_off[r1])
+        chars = int(self.off[p1] - self.off[p0])
+        return _pad(chars) + _pad(8 * (p1 - p0 + 1)) + _pad(4 * (p1 - p0)) + 256
+
+
+def _pad(x: int, a: int = 256) -> int:
+    return (x + a - 1) // a * a
+
+
+def make_workload(seed: int, text_codes: np.ndarray, rate_patterns_per_s: float, duration_s: float,
+                  max_requests: int = 200_000, max_size: int = 4096) -> Workload:
+    """Poisson arrivals whose request sizes are log-uniform in [1, max_size] patterns; the request rate is
+    the pattern rate divided by the mean request size."""
+    import datagen
+    mean_size = float(np.mean(datagen.request_sizes(seed ^ 0x5EED, 20_000, max_size)))
+    req_rate = rate_patterns_per_s / mean_size
+    nreq = int(min(max_requests, max(8, np.ceil(req_rate * duration_s))))
+    arrival = datagen.arrivals(seed, req_rate, nreq)
+    sizes = datagen.request_sizes(seed, nreq, max_size)
+    npat = int(sizes.sum())
+    pat, off, _ = datagen.patterns(seed + 1, text_codes, npat)
+    req_off = np.zeros(nreq + 1, dtype=np.int64)
+    req_off[1:] = np.cumsum(sizes)
+    return Workload(pat=pat, off=off, req_off=req_off, arrival=arrival - arrival[0])
+
+
+# ------------------------------------------------------------------------------------------ executors
+class GpuExecutor:
+    """Runs batches on the GPU: per slot a stream and an 8-byte queue head; device memory for the
+    batches comes from one arena buffer of `budget_bytes`."""
+
+    def __init__(self, fm, workload: Workload, slots: int, budget_bytes: int):
+        import torch
+
+        import paper_2602_04103_amd as qr
+        self.torch, self.qr, self.fm, self.w = torch, qr, fm, workload
+        dev = torch.device("cuda")
+        self.arena_dev = torch.empty(int(budget_bytes), dtype=torch.uint8, device=dev)
+        self.heads = torch.zeros(slots, dtype=torch.int64, device=dev)
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]  # default priority
+        # pinned host copies of the request stream and of the results
+        self.h_pat = torch.from_numpy(workload.pat).pin_memory()
+        self.h_cnt = torch.empty(int(workload.off.size - 1), dtype=torch.int32).pin_memory()
+        self.events = [None] * slots
+        self.jobs = [None] * slots
+
+    def submit(self, slot: int, r0: int, r1: int, base: int):
+        torch, w = self.torch, self.w
+        p0, p1 = int(w.req_off[r0]), int(w.req_off[r1])
+        c0, c1 = int(w.off[p0]), int(w.off[p1])
+        npat, chars = p1 - p0, c1 - c0
+        o_pat = base
+        o_off = base + _pad(chars)
+        o_cnt = o_off + _pad(8 * (npat + 1))
+        d_pat = self.arena_dev[o_pat:o_pat + max(chars, 1)]
+        d_off = self.arena_dev[o_off:o_off + 8 * (npat + 1)].view(torch.int64)
+        d_cnt = self.arena_dev[o_cnt:o_cnt + 4 * npat].view(torch.int32)
+        h_off = torch.from_numpy((w.off[p0:p1 + 1] - w.off[p0]).astype(np.int64))
+        s = self.streams[slot]
+        with torch.cuda.stream(s):
+            if chars:
+                d_pat[:chars].copy_(self.h_pat[c0:c1], non_blocking=True)
+            d_off.copy_(h_off.pin_memory(), non_blocking=True)
+            self.qr.quadfm_count_ws(self.fm.h, d_pat, d_off, d_cnt, self.heads[slot:slot + 1], stream=s)
+            self.h_cnt[p0:p1].copy_(d_cnt, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.events[slot] = ev
+        self.jobs[slot] = (p0, p1)
+
+    def poll(self, slot: int) -> bool:
+        return self.events[slot].query()
+
+    def counts(self, p0: int, p1: int) -> np.ndarray:
+        return self.h_cnt[p0:p1].numpy()
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+
+class FakeExecutor:
+    """CPU stand-in: counts with `count_fn(pat, off)` and completes a batch once `ready(slot)` says so
+    (tests use it to force out-of-order completion)."""
+
+    def __init__(self, workload: Workload, count_fn: Callable, ready: Optional[Callable] = None):
+        self.w, self.count_fn = workload, count_fn
+        self.ready = ready or (lambda slot: True)
+        self.cnt = np.zeros(int(workload.off.size - 1), dtype=np.uint32)
+        self.submitted: List[tuple] = []
+
+    def submit(self, slot: int, r0: int, r1: int, base: int):
+        w = self.w
+        p0, p1 = int(w.req_off[r0]), int(w.req_off[r1])
+        off = (w.off[p0:p1 + 1] - w.off[p0]).astype(np.uint64)
+        self.cnt[p0:p1] = self.count_fn(w.pat[int(w.off[p0]):int(w.off[p1])], off)
+        self.submitted.append((slot, r0, r1, base))
+
+    def poll(self, slot: int) -> bool:
+        return bool(self.ready(slot))
+
+    def counts(self, p0: int, p1: int) -> np.ndarray:
+        return self.cnt[p0:p1]
+
+    def sync(self):
+        pass
+
+
+# ------------------------------------------------------------------------------------------ scheduler
+@dataclasses.dataclass
+class ServeStats:
+    latency_s: np.ndarray        # per request
+    finish_s: np.ndarray         # per request, from start
+    batches: int
+    max_inflight: int
+    max_reserved_bytes: int
+    patterns: int
+    wall_s: float
+
+    def summary(self) -> dict:
+        lat = self.latency_s
+        span = float(self.finish_s.max() - 0.0) if lat.size else 0.0
+        return {
+            "requests": int(lat.size),
+            "patterns": int(self.patterns),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "mean_ms": float(lat.mean() * 1e3) if lat.size else None,
+            "patterns_per_s": float(self.patterns / span) if span > 0 else None,
+            "batches": self.batches,
+            "max_inflight_batches": self.max_inflight,
+            "max_reserved_bytes": self.max_reserved_bytes,
+        }
+
+
+class Server:
+    def __init__(self, executor, slots: int, budget_bytes: int, max_batch_patterns: int = 1 << 18,
+                 free_bytes_fn: Optional[Callable[[], int]] = None):
+        self.ex = executor
+        self.slots = slots
+        self.arena = Arena(budget_bytes)
+        self.max_batch_patterns = max_batch_patterns
+        self.free_bytes_fn = free_bytes_fn  # optional extra admission limit (device free memory)
+
+    def run(self, w: Workload, clock: Optional[Callable[[], float]] = None, time_scale: float = 1.0,
+            deadline_s: float = 600.0) -> ServeStats:
+        """Serve every request of `w`.  `clock` returns seconds since start (real time by default)."""
+        if clock is None:
+            t0 = time.perf_counter()
+            clock = lambda: (time.perf_counter() - t0) * time_scale
+        nreq = w.nreq
+        finish = np.full(nreq, np.nan)
+        free_slots = list(range(self.slots))
+        inflight = {}  # slot -> (r0, r1, base, nbytes)
+        nxt = 0        # next request not yet admitted (FIFO)
+        batches = max_inflight = max_reserved = 0
+        reserved = 0
+        done = 0
+        start = clock()
+        while done < nreq:
+            now = clock()
+            if now - start > deadline_s:
+                raise TimeoutError("serving run exceeded its deadline with %d of %d requests done" % (done, nreq))
+            progressed = False
+            # completions (any order)
+            for slot in list(inflight):
+                if self.ex.poll(slot):
+                    r0, r1, base, nb = inflight.pop(slot)
+                    t = clock()
+                    finish[r0:r1] = t
+                    done += r1 - r0
+                    self.arena.release(base, nb)
+                    reserved -= nb
+                    free_slots.append(slot)
+                    progressed = True
+            # admissions: all arrived requests, FIFO, as large a batch as slot, arena and limit allow
+            while free_slots and nxt < nreq and w.arrival[nxt] <= now:
+                r1 = nxt + 1
+                arrived = bisect.bisect_right(w.arrival, now, lo=nxt)
+                while r1 < arrived and int(w.req_off[r1 + 1] - w.req_off[nxt]) <= self.max_batch_patterns:
+                    r1 += 1
+                nb = w.batch_bytes(nxt, r1)
+                while r1 > nxt + 1 and nb > self.arena.size:
+                    r1 -= 1
+                    nb = w.batch_bytes(nxt, r1)
+                if nb > self.arena.size:
+                    raise MemoryError("request %d needs %d bytes, more than the whole budget %d" % (nxt, nb,
+                                                                                                  self.arena.size))
+                if self.free_bytes_fn is not None and nb > self.free_bytes_fn():
+                    break
+                base = self.arena.alloc(nb)
+                if base is None:
+                    break  # wait for memory to free up
+                slot = free_slots.pop()
+                self.ex.submit(slot, nxt, r1, base)
+                inflight[slot] = (nxt, r1, base, nb)
+                reserved += nb
+                batches += 1
+                max_inflight = max(max_inflight, len(inflight))
+                max_reserved = max(max_reserved, reserved)
+                nxt = r1
+                progressed = True
+            if not progressed:
+                time.sleep(2e-5)
+        self.ex.sync()
+        lat = finish - w.arrival
+        return ServeStats(latency_s=lat, finish_s=finish, batches=batches, max_inflight=max_inflight,
+                          max_reserved_bytes=max_reserved, patterns=int(w.req_off[-1]), wall_s=clock() - start)
+
+    def counts_of(self, w: Workload, r: int) -> np.ndarray:
+        return self.ex.counts(int(w.req_off[r]), int(w.req_off[r + 1]))

@@ -1,0 +1,158 @@
+"""GPU parity of the QuadFm count-only FM-index: counts from the persistent work-queue kernel and
+from the one-launch-per-batch kernel equal the oracle's counts exactly (u32, tolerance 0); the C
+array and the 8-mer interval table equal the oracle's textbook backward search."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from tests.gpu_util import announce, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def make_text(seed, n, repeats=True):
+    codes = datagen.dna_codes(seed, n)
+    if repeats and n >= 50_000:
+        datagen.plant_repeats(seed + 1, codes, nseg=max(1, n // 100_000), seglen=min(10_000, n // 10), copies=20,
+                              sub=0.01)
+    return codes
+
+
+def edge_patterns(codes, seed):
+    n = codes.size
+    pats = [np.zeros(0, np.uint8), codes[:1], codes[:7], codes[:8], codes[:9], codes[max(0, n - 8):],
+            codes[max(0, n - 20):], codes.copy(), datagen.dna_codes(seed, n + 1), np.array([0, 1, 9, 2], np.uint8),
+            np.array([1, 2, 3, 0, 1, 2, 3, 0, 7], np.uint8), np.array([5] + [0] * 10, np.uint8),
+            np.array([2] * 12, np.uint8)]
+    for k in range(1, 12):
+        pats.append(datagen.dna_codes(seed + k, k))
+    return pats
+
+
+def csr(pats):
+    off = np.zeros(len(pats) + 1, np.uint64)
+    off[1:] = np.cumsum([p.size for p in pats])
+    flat = np.concatenate(pats).astype(np.uint8) if off[-1] else np.zeros(1, np.uint8)
+    return flat, off
+
+
+def gpu_counts(fm, pat, off, batch=None):
+    dp, do = to_dev(pat if pat.size else np.zeros(1, np.uint8)), to_dev(off)
+    if batch is None:
+        c = fm.count(dp, do)
+    else:
+        c = fm.count_batched(dp, do, batch)
+    fm.check()
+    return c.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("n", [1, 2, 9, 100, 1000, 65_537])
+def test_fm_small_texts_all_kernels(n):
+    qr = require_gpu()
+    codes = make_text(40 + n, n)
+    pats = edge_patterns(codes, 7 * n)
+    sp, so, _ = datagen.patterns(n, codes, 2000, minlen=1, maxlen=40, frac_sampled=0.8, sub=0.02)
+    pats += [sp[int(so[i]):int(so[i + 1])] for i in range(so.size - 1)]
+    pat, off = csr(pats)
+    announce("fm-small", n, len(pats))
+    fm = qr.QuadFm.from_text(codes)
+    sa = oracle.suffix_array(codes)
+    want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
+    assert np.array_equal(gpu_counts(fm, pat, off), want)
+    assert np.array_equal(gpu_counts(fm, pat, off, batch=0), want)
+    assert np.array_equal(gpu_counts(fm, pat, off, batch=333), want)
+
+
+def test_fm_c_array_and_kmer_table():
+    qr = require_gpu()
+    n = 200_003
+    codes = make_text(77, n)
+    announce("fm-table", n)
+    fm = qr.QuadFm.from_text(codes)
+    cnt = np.bincount(codes, minlength=4).astype(np.uint64)
+    want_C = 1 + np.concatenate([[0], np.cumsum(cnt)[:3]]).astype(np.uint64)
+    assert np.array_equal(fm.c_array(), want_C)
+    sa = oracle.suffix_array(codes)
+    b, _ = oracle.bwt(codes, sa)
+    lo, hi = oracle.kmer_intervals(b, 8)
+    sp, ep = fm.table()
+    nonempty = hi > lo
+    assert np.array_equal(sp[nonempty], lo[nonempty].astype(np.uint32))
+    assert np.array_equal(ep[nonempty], hi[nonempty].astype(np.uint32))
+    assert np.all(sp[~nonempty] >= ep[~nonempty])
+
+
+def test_fm_medium_random_patterns():
+    """2^20-base text with planted repeats; 10^5 patterns of lengths 20..250 (90% sampled with 1%
+    substitutions, 10% iid) — the batched configuration's distribution at a size the oracle's
+    suffix-array search handles in seconds."""
+    qr = require_gpu()
+    n = 1 << 20
+    codes = make_text(91, n)
+    pat, off, kind = datagen.patterns(92, codes, 100_000)
+    announce("fm-medium", n)
+    fm = qr.QuadFm.from_text(codes)
+    sa = oracle.suffix_array(codes)
+    want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
+    got = gpu_counts(fm, pat, off)
+    assert np.array_equal(got, want)
+    assert np.array_equal(gpu_counts(fm, pat, off, batch=1 << 14), want)
+    assert (want[kind == 1] > 0).mean() > 0.2   # exact copies occur; substituted ones mostly do not
+
+
+@pytest.mark.parametrize("tune", [dict(refill=1), dict(refill=64), dict(refill=8, waves_per_cu=1),
+                                  dict(block=64, refill=32, waves_per_cu=4), dict(waves_per_cu=32)])
+def test_fm_persistent_tunings(tune):
+    qr = require_gpu()
+    n = 300_000
+    codes = make_text(5, n)
+    pat, off, _ = datagen.patterns(6, codes, 30_000)
+    announce("fm-tune", tune)
+    fm = qr.QuadFm.from_text(codes)
+    fm.set_tuning(**tune)
+    sa = oracle.suffix_array(codes)
+    want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
+    for _ in range(2):  # the queue head is reset on every call
+        assert np.array_equal(gpu_counts(fm, pat, off), want)
+
+
+def test_fm_rejects_bad_dollar():
+    qr = require_gpu()
+    codes = datagen.dna_codes(3, 1000)
+    bwt, d = qr.quadfm_bwt_host(codes)
+    # claim '$' is at a row that holds a C/G/T: the build must refuse
+    rows = (bwt[np.arange(1001) // 32] >> (2 * (np.arange(1001) % 32)).astype(np.uint64)) & np.uint64(3)
+    bad = int(np.nonzero(rows != 0)[0][0])
+    announce("fm-bad-dollar")
+    with pytest.raises(qr.QRError):
+        qr.QuadFm(to_dev(bwt), 1001, bad)
+    with pytest.raises(qr.QRError):
+        qr.QuadFm(to_dev(bwt), 1001, 1001)
+
+
+def test_fm_config3_full_sampled():
+    """Text of 2^28 bases with 1000 planted 10-kb repeats x 20 copies; 10^7 patterns (lengths
+    20..250, 90% sampled with 1% substitutions, 10% iid).  All counts come from the persistent
+    kernel; 200 sampled patterns are recounted by the oracle's direct scan, and the per-batch
+    kernel must agree with the persistent one on every pattern."""
+    qr = require_gpu()
+    n = 1 << 28
+    codes = datagen.dna_codes(2028, n)
+    datagen.plant_repeats(2029, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
+    pat, off, kind = datagen.patterns(2030, codes, 10 ** 7)
+    announce("fm-config3 build")
+    fm = qr.QuadFm.from_text(codes)
+    announce("fm-config3 count")
+    dp, do = to_dev(pat), to_dev(off)
+    got = fm.count(dp, do).cpu().numpy().view(np.uint32)
+    got_b = fm.count_batched(dp, do, 1 << 20).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, got_b)
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(10 ** 7, 200, replace=False))
+    sp = [pat[int(off[i]):int(off[i + 1])] for i in sample]
+    spat, soff = csr(sp)
+    want = oracle.count_naive(codes, spat, soff).astype(np.uint32)
+    assert np.array_equal(got[sample], want)
+    assert got.max() <= n

@@ -68,9 +68,12 @@ def test_birank_config0_full():
     assert np.array_equal(got, oracle.rank_bits(bits, n, q))
 
 
-@pytest.mark.parametrize("tune", [dict(per_lane=1), dict(per_lane=2), dict(per_lane=4), dict(per_lane=8),
-                                  dict(block=64, per_lane=2), dict(per_lane=4, grid_waves=8),
-                                  dict(per_lane=1, grid_waves=1)])
+TUNINGS = [dict(per_lane=1), dict(per_lane=2), dict(per_lane=4), dict(per_lane=8), dict(block=64, per_lane=2),
+           dict(per_lane=4, grid_waves=8), dict(per_lane=1, grid_waves=1), dict(lanes=1), dict(lanes=1, per_lane=4),
+           dict(lanes=1, block=128, per_lane=2, grid_waves=4), dict(lanes=2, block=192, per_lane=8, grid_waves=2)]
+
+
+@pytest.mark.parametrize("tune", TUNINGS)
 def test_birank_tunings_agree(tune):
     qr = require_gpu()
     n = 3 * 64512 + 4321
@@ -186,8 +189,7 @@ def test_quadrank_config1_full():
     assert np.array_equal(got4, oracle.rank4_dna(packed, n, q4))
 
 
-@pytest.mark.parametrize("tune", [dict(per_lane=2), dict(per_lane=4), dict(per_lane=8), dict(block=128, per_lane=2),
-                                  dict(per_lane=4, grid_waves=8), dict(per_lane=2, grid_waves=1)])
+@pytest.mark.parametrize("tune", TUNINGS)
 def test_quadrank_tunings_agree(tune):
     qr = require_gpu()
     n = 2 * 61440 + 4321
