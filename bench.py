@@ -75,9 +75,15 @@ def main():
     ap.add_argument("--fm-patterns", type=int, default=10 ** 7)
     ap.add_argument("--fm-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
+    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7", help="offered loads, patterns/s")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
     ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--tuning-from", default=None,
+                    help="apply the launch settings recorded in an earlier bench JSON line instead of tuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -161,8 +167,19 @@ def main():
 
     # ------------------------------------------------------------------ autotune (untimed)
     tuning = {}
+    fixed = None
+    if args.tuning_from:
+        with open(args.tuning_from) as f:
+            prev = json.loads(f.readline())
+        fixed = {r: v.get("tuning") for r, v in prev.get("rows", {}).items()}
+        fixed["_fm"] = (prev.get("fm") or {}).get("tuning")
+        args.fm_tuning = fixed["_fm"]
     for row in rows:
         h = structs["quadrank"] if row.startswith("quadrank") else structs[row]
+        if fixed and isinstance(fixed.get(row), dict):
+            h.set_tuning(**fixed[row])
+            tuning[row] = fixed[row]
+            continue
         if args.no_tune:
             h.set_tuning(lanes=2, per_lane=1, block=256, grid_waves=0)
             tuning[row] = "default"
@@ -255,6 +272,11 @@ def main():
     if not args.no_fm:
         fm_res = bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev)
 
+    # ------------------------------------------------------------------ serving sweep
+    serve_res = None
+    if not args.no_serve:
+        serve_res = bench_serve(args, qr, datagen, np, torch, to_dev)
+
     # ------------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
     if not args.no_cpu_baseline and packed_q is not None and "quadrank_rank" in qsets:
@@ -285,6 +307,7 @@ def main():
         "builds": builds,
         "roofline": roofline,
         "fm": fm_res,
+        "serve": serve_res,
         "cpu_baseline": cpu,
         "setup_s": round(time.time() - t_setup, 1),
     }
@@ -314,7 +337,10 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     log("fm index: text %.1fs, host SA+BWT %.1fs, device build %.2fs" % (t1 - t0, t2 - t1, t3 - t2))
     cnt = torch.empty(npat, dtype=torch.int32, device=dev)
     cnt_b = torch.empty(npat, dtype=torch.int32, device=dev)
-    if not args.no_tune:
+    if isinstance(getattr(args, "fm_tuning", None), dict):
+        best = args.fm_tuning
+        fm.set_tuning(**best)
+    elif not args.no_tune:
         sub = min(npat, 2_000_000)
         best, _ = autotune.tune("quadfm", n, fm.set_tuning, lambda: fm.count(dp, do[:sub + 1], cnt[:sub]),
                                 autotune.FM_CANDIDATES, reps=2, use_cache=False)
@@ -337,6 +363,47 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     res["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
     log("fm persistent %.1f M patterns/s; batched best %.1f M; gain %.2fx; equal=%s" % (
         npat / t_p / 1e6, best_b / 1e6, res["gain_vs_best_batched"], res["persistent_equals_batched"]))
+    fm.free()
+    return res
+
+
+def bench_serve(args, qr, datagen, np, torch, to_dev):
+    """Poisson request arrivals against a device-resident index; each request holds 1..4096 patterns
+    (log-uniform), lengths 20..250; offered loads swept; latency from arrival to counts on the host."""
+    from paper_2602_04103_amd.serve import GpuExecutor, Server, make_workload
+    n = 1 << args.serve_log_n
+    t0 = time.time()
+    text = datagen.dna_codes(3030, n)
+    datagen.plant_repeats(3031, text, nseg=1000, seglen=10_000, copies=20, sub=0.01)
+    bwt, dollar = qr.quadfm_bwt_host(text)
+    t1 = time.time()
+    fm = qr.QuadFm(to_dev(bwt), n + 1, dollar)
+    del bwt
+    fm.set_tuning(block=64, refill=32, waves_per_cu=8)
+    log("serve index 2^%d: host SA+BWT %.1fs" % (args.serve_log_n, t1 - t0))
+    slots, budget = 4, 256 << 20
+    free, total = torch.cuda.mem_get_info()
+    res = {"workload": "QuadFm serving: 2^%d-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs); "
+                       "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
+                       % args.serve_log_n,
+           "slots": slots, "hbm_budget_bytes": budget, "device_free_bytes_at_start": int(free),
+           "host_sa_bwt_s": t1 - t0, "loads": []}
+    for k, load in enumerate(float(x) for x in args.serve_loads.split(",")):
+        w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
+        ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)
+        srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
+                     free_bytes_fn=lambda: torch.cuda.mem_get_info()[0])
+        st = srv.run(w, deadline_s=120.0)
+        summ = st.summary()
+        summ["offered_patterns_per_s"] = load
+        # every served count equals one direct count of all patterns of the run
+        d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
+        summ["equal_to_direct_count"] = bool(np.array_equal(ex.counts(0, int(w.req_off[-1])), d_all))
+        res["loads"].append(summ)
+        log("serve load %.0e: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, %d batches, max in flight %d, equal=%s"
+            % (load, summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6, summ["batches"],
+               summ["max_inflight_batches"], summ["equal_to_direct_count"]))
+        del ex, srv
     fm.free()
     return res
 

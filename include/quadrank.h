@@ -179,6 +179,22 @@ int quadrank_set_tuning(qr_quadrank h, const qr_tuning *t);
 int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
 
 /* ------------------------------------------------------------------------------------------------
+ * HIP graph capture of launch sequences.  Between qr_graph_begin(stream) and qr_graph_end(stream,
+ * &g), calls to the enqueue-only entry points on `stream` (birank_rank, quadrank_rank,
+ * quadrank_rank4, quadfm_count, quadfm_count_ws, quadfm_count_batched) are recorded instead of
+ * run; qr_graph_launch replays the whole sequence with one launch, with the same pointers and sizes.
+ * Build, *_check, *_export and *_free synchronise or allocate and must not be called while
+ * capturing.  stream must not be the null stream.  The graph owns no caller buffer: those must
+ * outlive every replay.
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct qr_graph_s *qr_graph;
+
+int qr_graph_begin(hipStream_t stream);
+int qr_graph_end(hipStream_t stream, qr_graph *out);
+int qr_graph_launch(qr_graph g, hipStream_t stream);
+int qr_graph_free(qr_graph g);
+
+/* ------------------------------------------------------------------------------------------------
  * Random-line gather microbenchmark: the achievable ceiling for one random 128-byte line per query.
  * d_lines (16-byte aligned) holds n_lines 128-byte lines; for each i < nq, line
  * floor(d_idx[i] * n_lines / 2^64) is read,

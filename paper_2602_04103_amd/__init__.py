@@ -68,6 +68,10 @@ def lib():
             "quadrank_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
             "quadrank_export": (ci, [vp, vp, vp]),
             "qr_gather_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
+            "qr_graph_begin": (ci, [vp]),
+            "qr_graph_end": (ci, [vp, C.POINTER(vp)]),
+            "qr_graph_launch": (ci, [vp, vp]),
+            "qr_graph_free": (ci, [vp]),
         }
         optional = {
             "quadfm_bwt_host": (ci, [vp, u64, vp, C.POINTER(u64)]),
@@ -248,6 +252,43 @@ def quadfm_check(h: int, stream=None):
 
 def quadfm_free(h: int):
     lib().quadfm_free(h)
+
+
+# ------------------------------------------------------------------------------------------ graphs
+class Graph:
+    """A captured launch sequence.  Use as:  with qr.Graph(stream) as g: <enqueue-only calls on stream>
+    then g.launch() replays it (same pointers, sizes and stream order)."""
+
+    def __init__(self, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.g = None
+
+    def __enter__(self):
+        _check(lib().qr_graph_begin(_stream(self.stream)), "qr_graph_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        g = vp()
+        rc = lib().qr_graph_end(_stream(self.stream), C.byref(g))
+        if exc_type is None:
+            _check(rc, "qr_graph_end")
+            self.g = g.value
+        return False
+
+    def launch(self, stream=None):
+        _check(lib().qr_graph_launch(self.g, _stream(stream if stream is not None else self.stream)),
+               "qr_graph_launch")
+
+    def free(self):
+        if self.g:
+            lib().qr_graph_free(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------------------- wrappers

@@ -1,0 +1,76 @@
+"""Microbenchmarks behind the query-kernel design choices (run on the GPU; print one line per point).
+
+  python -m paper_2602_04103_amd.microbench gather   random 64/128-byte line gathers vs working set
+  python -m paper_2602_04103_amd.microbench lanes    BiRank rank on 2^36 bits: one lane per query
+                                                     (several 16-byte loads per lane) vs lane pairs
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _time(fn, reps=5):
+    from paper_2602_04103_amd.autotune import time_launch
+    return time_launch(fn, reps)
+
+
+def gather(args):
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    nq = 1 << 24
+    idx = torch.from_numpy(datagen.bits(7, nq * 64).view(np.int64)).cuda()  # raw 64-bit draws
+    out = torch.empty(nq, dtype=torch.int64, device="cuda")
+    for gib in args.gib:
+        nl = int(gib * (1 << 30)) // 128
+        buf = torch.ones(nl * 16, dtype=torch.int64, device="cuda")
+        for b in (64, 128):
+            t = _time(lambda: qr.qr_gather_bench(buf, nl, idx, b, out))
+            print("gather ws=%.3f GiB bytes=%d: %.2f G lines/s (%.0f GB/s of 128-byte lines)"
+                  % (gib, b, nq / t / 1e9, nq * 128 / t / 1e9), flush=True)
+        del buf
+        torch.cuda.empty_cache()
+
+
+def lanes(args):
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    n = 1 << args.log_n
+    bits = torch.from_numpy(datagen.bits(3636, n, 0.5).view(np.int64)).cuda()
+    h = qr.BiRank(bits, n)
+    del bits
+    torch.cuda.empty_cache()
+    nq = 1 << 24
+    q = torch.from_numpy(datagen.queries(3736, n, nq).view(np.int64)).cuda()
+    out = torch.empty(nq, dtype=torch.int64, device="cuda")
+    for lanes_, pl in ((1, 1), (1, 2), (2, 1), (2, 2)):
+        h.set_tuning(lanes=lanes_, per_lane=pl, block=256, grid_waves=0)
+        t = _time(lambda: h.rank(q, out))
+        print("birank n=2^%d lanes_per_query=%d queries_per_lane=%d: %.2f G q/s" % (args.log_n, lanes_, pl,
+                                                                                    nq / t / 1e9), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    g = sub.add_parser("gather")
+    g.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 2, 3, 4, 8])
+    l = sub.add_parser("lanes")
+    l.add_argument("--log-n", type=int, default=36)
+    a = ap.parse_args(argv)
+    {"gather": gather, "lanes": lanes}[a.what](a)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,82 @@
+"""GPU serving: continuous batching over a device-resident QuadFm index.  Each request's counts
+must be identical when served inside the concurrent mix and when counted alone, and must equal
+the oracle's counts; batches must actually overlap on the device."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_util import announce, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def index():
+    qr = require_gpu()
+    n = 1 << 20
+    text = datagen.dna_codes(4040, n)
+    datagen.plant_repeats(4041, text, nseg=10, seglen=5000, copies=20, sub=0.01)
+    announce("serve index", n)
+    fm = qr.QuadFm.from_text(text)
+    sa = oracle.suffix_array(text)
+    return qr, text, fm, sa
+
+
+def serve(fm, w, slots, budget, max_batch):
+    from paper_2602_04103_amd.serve import GpuExecutor, Server
+    ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)
+    srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=max_batch)
+    st = srv.run(w, deadline_s=120.0)
+    return srv, st
+
+
+def alone_counts(qr, fm, w, r):
+    p0, p1 = int(w.req_off[r]), int(w.req_off[r + 1])
+    pat = w.pat[int(w.off[p0]):int(w.off[p1])]
+    off = (w.off[p0:p1 + 1] - w.off[p0]).astype(np.uint64)
+    return fm.count(to_dev(pat if pat.size else np.zeros(1, np.uint8)), to_dev(off)).cpu().numpy().view(np.uint32)
+
+
+def test_serve_poisson_mix_equals_alone_and_oracle(index):
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import make_workload
+    w = make_workload(77, text, rate_patterns_per_s=4e6, duration_s=0.25, max_size=4096)
+    announce("serve poisson", w.nreq)
+    srv, st = serve(fm, w, slots=4, budget=32 << 20, max_batch=1 << 15)
+    assert not np.isnan(st.finish_s).any() and np.all(st.latency_s >= 0)
+    served = np.concatenate([srv.counts_of(w, r) for r in range(w.nreq)])
+    want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
+    assert np.array_equal(served, want)
+    rng = np.random.default_rng(3)
+    for r in rng.choice(w.nreq, min(200, w.nreq), replace=False):
+        assert np.array_equal(srv.counts_of(w, int(r)), alone_counts(qr, fm, w, int(r)))
+
+
+def test_serve_burst_overlaps_batches(index):
+    """All requests arrive at once and batches are capped small, so several batches must be in
+    flight together; results still equal the oracle."""
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import make_workload
+    w = make_workload(78, text, rate_patterns_per_s=1e8, duration_s=0.01, max_size=512)
+    w.arrival[:] = 0.0
+    announce("serve burst", w.nreq)
+    srv, st = serve(fm, w, slots=4, budget=16 << 20, max_batch=2048)
+    assert st.max_inflight >= 2
+    assert st.max_reserved_bytes <= 16 << 20
+    served = np.concatenate([srv.counts_of(w, r) for r in range(w.nreq)])
+    assert np.array_equal(served, oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
+
+
+def test_serve_tight_budget_still_exact(index):
+    """A budget that holds only about one batch forces admission to wait for memory."""
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import make_workload
+    w = make_workload(79, text, rate_patterns_per_s=2e7, duration_s=0.02, max_size=256)
+    one = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
+    budget = 2 * one
+    announce("serve tight budget", w.nreq, budget)
+    srv, st = serve(fm, w, slots=4, budget=budget, max_batch=256)
+    assert st.max_reserved_bytes <= budget
+    served = np.concatenate([srv.counts_of(w, r) for r in range(w.nreq)])
+    assert np.array_equal(served, oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
