@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
-    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7", help="offered loads, patterns/s")
+    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8", help="offered loads, patterns/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
     ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05")
@@ -242,13 +242,15 @@ def main():
         log("%-20s %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline" % (row, qps / 1e9, per_launch * 1e3,
                                                                         100 * achieved / HBM_PEAK_GBS))
     ms_per_step = wall / args.steps * 1e3
-    value = step_queries / wall
+    value = step_queries / wall if rows else None
 
     # dominant kernel = largest share of the step's time
-    dom = max(rows, key=lambda r: row_res[r]["avg_launch_ms"])
+    dom = max(rows, key=lambda r: row_res[r]["avg_launch_ms"]) if rows else None
     traffic = None
     prof_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
+        if dom is None:
+            raise KeyError("no rank rows")
         prof = json.load(open(prof_path))
         ent = prof.get("kernels", {}).get(dom)
         src = source_hash(*prof.get("sources", []))
@@ -256,7 +258,7 @@ def main():
             traffic = ent["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
-    roofline = {
+    roofline = None if dom is None else {
         "bound": "hbm",
         "kernel": KERNEL_NAMES[dom] + " (" + dom + ")",
         "achieved": round(row_res[dom]["algorithmic_GBps"], 1),
@@ -388,6 +390,11 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                        % args.serve_log_n,
            "slots": slots, "hbm_budget_bytes": budget, "device_free_bytes_at_start": int(free),
            "host_sa_bwt_s": t1 - t0, "loads": []}
+    # warm-up (untimed): first launches, pinned-memory pools, stream creation
+    w0 = make_workload(4999, text, 1e6, 0.05, max_requests=200)
+    ex0 = GpuExecutor(fm, w0, slots=slots, budget_bytes=budget)
+    Server(ex0, slots=slots, budget_bytes=budget).run(w0, deadline_s=60.0)
+    del ex0
     for k, load in enumerate(float(x) for x in args.serve_loads.split(",")):
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
         ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)

@@ -1,6 +1,7 @@
 """Microbenchmarks behind the query-kernel design choices (run on the GPU; print one line per point).
 
   python -m paper_2602_04103_amd.microbench gather   random 64/128-byte line gathers vs working set
+  python -m paper_2602_04103_amd.microbench rankws   rank / rank4 throughput against structure size
   python -m paper_2602_04103_amd.microbench lanes    BiRank rank on 2^36 bits: one lane per query
                                                      (several 16-byte loads per lane) vs lane pairs
 """
@@ -61,6 +62,45 @@ def lanes(args):
                                                                                     nq / t / 1e9), flush=True)
 
 
+def rankws(args):
+    """Rank throughput against structure size (cache-resident to HBM-resident)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    nq = 1 << 24
+    out = torch.empty(4 * nq, dtype=torch.int64, device="cuda")
+    for lg in args.qr_log_n:
+        n = 1 << lg
+        d = torch.from_numpy(datagen.bits(lg, 2 * n, 0.5).view(np.int64)).cuda()
+        h = qr.QuadRank(d, n)
+        del d
+        q = torch.from_numpy(datagen.queries(lg + 1, n, nq).view(np.int64)).cuda()
+        c = torch.from_numpy(datagen.symbols(lg + 2, nq)).cuda()
+        for pl in (1, 2):
+            h.set_tuning(lanes=2, per_lane=pl, block=256, grid_waves=0)
+            t1 = _time(lambda: h.rank(q, c, out[:nq]))
+            t4 = _time(lambda: h.rank4(q, out))
+            print("quadrank n=2^%d (%.2f GiB) per_pair=%d: rank %.2f G q/s, rank4 %.2f G q/s"
+                  % (lg, h.nbytes / 2**30, pl, nq / t1 / 1e9, nq / t4 / 1e9), flush=True)
+        h.free()
+        torch.cuda.empty_cache()
+    for lg in args.br_log_n:
+        n = 1 << lg
+        d = torch.from_numpy(datagen.bits(lg, n, 0.5).view(np.int64)).cuda()
+        h = qr.BiRank(d, n)
+        del d
+        q = torch.from_numpy(datagen.queries(lg + 1, n, nq).view(np.int64)).cuda()
+        for pl in (1, 2):
+            h.set_tuning(lanes=2, per_lane=pl, block=256, grid_waves=0)
+            t = _time(lambda: h.rank(q, out[:nq]))
+            print("birank n=2^%d (%.2f GiB) per_pair=%d: rank %.2f G q/s" % (lg, h.nbytes / 2**30, pl, nq / t / 1e9),
+                  flush=True)
+        h.free()
+        torch.cuda.empty_cache()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -68,8 +108,11 @@ def main(argv=None):
     g.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 2, 3, 4, 8])
     l = sub.add_parser("lanes")
     l.add_argument("--log-n", type=int, default=36)
+    r = sub.add_parser("rankws")
+    r.add_argument("--qr-log-n", type=int, nargs="+", default=[24, 28, 30, 31, 32, 33])
+    r.add_argument("--br-log-n", type=int, nargs="+", default=[28, 31, 33, 34, 35, 36])
     a = ap.parse_args(argv)
-    {"gather": gather, "lanes": lanes}[a.what](a)
+    {"gather": gather, "lanes": lanes, "rankws": rankws}[a.what](a)
 
 
 if __name__ == "__main__":

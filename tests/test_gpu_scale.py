@@ -1,0 +1,70 @@
+"""GPU parity at the full scale configuration, in the launch settings the benchmark uses: BiRank on
+2^36 bits (Bernoulli 0.5 and 0.05) and QuadRank on a 2^32-base text with planted repeats.  A full
+2^24-query batch runs on the GPU; 10^6 sampled outputs are recomputed by the oracle, and
+properties that hold at any size are checked on every output."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from tests.gpu_util import announce, require_gpu, to_dev, to_host_u64
+
+pytestmark = pytest.mark.gpu
+
+BATCH = 1 << 24
+BENCH_TUNINGS = [dict(lanes=2, per_lane=2, block=256, grid_waves=0), dict(lanes=2, per_lane=2, block=256, grid_waves=8),
+                 dict(lanes=2, per_lane=8, block=256, grid_waves=8), dict(lanes=2, per_lane=1, block=128, grid_waves=0)]
+
+
+@pytest.mark.parametrize("p,seed", [(0.5, 3636), (0.05, 3637)])
+def test_birank_2e36(p, seed):
+    qr = require_gpu()
+    n = 1 << 36
+    bits = datagen.bits(seed, n, p)
+    announce("birank 2^36", p)
+    h = qr.BiRank(to_dev(bits), n)
+    total = int(np.unpackbits(bits.view(np.uint8)).sum(dtype=np.int64))
+    q = datagen.queries(seed + 100, n, BATCH)
+    q[:4] = [0, n, n - 1, 1 << 35]
+    dq = to_dev(q)
+    rng = np.random.default_rng(seed)
+    sample = rng.choice(BATCH, 1_000_000, replace=False)
+    want = oracle.rank_bits(bits, n, q[sample])
+    for tune in BENCH_TUNINGS:
+        h.set_tuning(**tune)
+        got = to_host_u64(h.rank(dq))
+        assert np.array_equal(got[sample], want), tune
+        assert got[1] == total and got[0] == 0
+        assert np.all(got <= q)                                  # at most q ones before q
+    h.check()
+
+
+def test_quadrank_2e32_with_repeats():
+    qr = require_gpu()
+    n = 1 << 32
+    codes = datagen.dna_codes(3202, n)
+    datagen.plant_repeats(3203, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
+    hist = np.bincount(codes, minlength=4).astype(np.uint64)
+    packed = datagen.pack2(codes)
+    del codes
+    announce("quadrank 2^32")
+    h = qr.QuadRank(to_dev(packed), n)
+    q = datagen.queries(3204, n, BATCH)
+    q[:2] = [n, 0]
+    c = datagen.symbols(3205, BATCH)
+    dq, dc = to_dev(q), to_dev(c)
+    rng = np.random.default_rng(5)
+    sample = rng.choice(BATCH, 1_000_000, replace=False)
+    want1 = oracle.rank_dna(packed, n, q[sample], c[sample])
+    want4 = oracle.rank4_dna(packed, n, q[sample])
+    for tune in BENCH_TUNINGS:
+        h.set_tuning(**tune)
+        got1 = to_host_u64(h.rank(dq, dc))
+        got4 = to_host_u64(h.rank4(dq)).reshape(-1, 4)
+        assert np.array_equal(got1[sample], want1), tune
+        assert np.array_equal(got4[sample], want4), tune
+        assert np.array_equal(got4.sum(axis=1), q)               # sum over symbols = q
+        assert np.array_equal(got4[0], hist)                     # rank4(n) = histogram
+        assert np.array_equal(got1, got4[np.arange(BATCH), c.astype(np.int64)])
+    h.check()
