@@ -62,6 +62,10 @@ const char *qr_last_error(void);
 /* Library version string. */
 const char *qr_version(void);
 
+/* Inline-delta width of a layout (the paper's 16-bit default and its 32-bit variant, Sections 3/4). */
+#define QR_LAYOUT_16 0 /* 16-bit deltas + a shifted 32-bit offset per small superblock (default) */
+#define QR_LAYOUT_32 1 /* 32-bit deltas + an exact 64-bit offset per ~4e9-position superblock */
+
 /* ------------------------------------------------------------------------------------------------
  * BiRank (paper Section 3).  rank(q) = number of 1 bits among t_0 .. t_{q-1}.
  * Layout: 128-byte lines, each holding a 16-bit delta to the line's middle and 1008 data bits;
@@ -72,6 +76,12 @@ typedef struct qr_birank_s *qr_birank;
 
 /* Build from n_bits bits at d_bits (ceil(n_bits/64) u64 words; may be NULL iff n_bits == 0). */
 int birank_build(const uint64_t *d_bits, uint64_t n_bits, hipStream_t stream, qr_birank *out);
+/* Same with a layout choice.  QR_LAYOUT_32 (the BiRank32 variant): each line holds a 32-bit delta
+ * and 992 data bits, 2^22 lines share one exact u64 offset (3.23 % overhead instead of 1.64 %, and an
+ * offset array small enough to stay in cache); n < 2^48. */
+int birank_build_ex(const uint64_t *d_bits, uint64_t n_bits, int layout, hipStream_t stream, qr_birank *out);
+/* QR_LAYOUT_16 or QR_LAYOUT_32, or -1 for a NULL handle. */
+int birank_layout_kind(qr_birank h);
 /* d_out[i] = rank(d_q[i]) for i < nq (u64 in, u64 out; d_q and d_out may alias). */
 int birank_rank(qr_birank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t stream);
 /* Synchronise `stream`, return QR_ERANGE if any query since the last check had q > n, and clear. */
@@ -81,8 +91,8 @@ int birank_free(qr_birank h);
 uint64_t birank_len(qr_birank h);
 uint64_t birank_bytes(qr_birank h);
 int birank_layout(qr_birank h, const void **d_lines, uint64_t *n_lines, const void **d_super, uint64_t *n_super);
-/* Copy the structure to host memory: n_lines*128 bytes to h_lines, n_super*4 bytes to h_super
- * (synchronous; either pointer may be NULL to skip it). */
+/* Copy the structure to host memory: n_lines*128 bytes to h_lines, and n_super offsets (u32 for
+ * QR_LAYOUT_16, u64 for QR_LAYOUT_32) to h_super (synchronous; either pointer may be NULL). */
 int birank_export(qr_birank h, void *h_lines, void *h_super);
 
 /* ------------------------------------------------------------------------------------------------
@@ -95,6 +105,12 @@ typedef struct qr_quadrank_s *qr_quadrank;
 
 /* Build from n bases, 2-bit packed at d_packed2 (ceil(n/32) u64 words; NULL iff n == 0). */
 int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr_quadrank *out);
+/* Same with a layout choice.  QR_LAYOUT_32 (the QuadRank32 variant): each line holds four 32-bit
+ * deltas and 448 bases, 2^23 lines share four exact u64 offsets (14.3 % overhead instead of 6.7 %,
+ * and an offset array small enough to stay in cache); n < 2^48. */
+int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStream_t stream, qr_quadrank *out);
+/* QR_LAYOUT_16 or QR_LAYOUT_32, or -1 for a NULL handle. */
+int quadrank_layout_kind(qr_quadrank h);
 /* d_out[i] = rank(d_q[i], d_c[i]). */
 int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
                   hipStream_t stream);
@@ -106,7 +122,8 @@ uint64_t quadrank_len(qr_quadrank h);
 uint64_t quadrank_bytes(qr_quadrank h);
 int quadrank_layout(qr_quadrank h, const void **d_lines, uint64_t *n_lines, const void **d_super,
                     uint64_t *n_super);
-/* Copy the structure to host memory: n_lines*128 bytes and n_super*16 bytes (synchronous). */
+/* Copy the structure to host memory: n_lines*128 bytes, and n_super rows of four offsets (u32 for
+ * QR_LAYOUT_16, u64 for QR_LAYOUT_32) (synchronous; either pointer may be NULL). */
 int quadrank_export(qr_quadrank h, void *h_lines, void *h_super);
 
 /* ------------------------------------------------------------------------------------------------
@@ -141,10 +158,20 @@ int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint6
  * serving loop use. */
 int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
                     void *d_workspace, hipStream_t stream);
+/* Count flags for the *_ex calls. */
+#define QUADFM_BOTH_STRANDS 1u /* count P and its reverse complement (A<->T, C<->G, reversed): the
+                                  result is count(P) + count(rc(P)), saturating at 2^32-1; the empty
+                                  pattern still counts n+1 */
+/* The general persistent count: flags as above; d_workspace is an 8-byte queue head as for
+ * quadfm_count_ws, or NULL to use the handle's own (then calls must not overlap). */
+int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t flags,
+                    uint32_t *d_count, void *d_workspace, hipStream_t stream);
 /* Same result with one plain launch per batch of `batch` patterns, one lane per pattern
  * (batch = 0: a single launch over all patterns).  The baseline for the work-queue kernel. */
 int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
                          uint32_t *d_count, hipStream_t stream);
+int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
+                            uint32_t flags, uint32_t *d_count, hipStream_t stream);
 /* Synchronise `stream` (counts are then final). */
 int quadfm_check(qr_quadfm h, hipStream_t stream);
 int quadfm_free(qr_quadfm h);
@@ -204,7 +231,8 @@ int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx
                     uint32_t bytes_per_query, uint64_t *d_out, hipStream_t stream);
 
 /* Host-side reference of the library's exact division by the line payloads (for tests):
- * which = 0 -> floor(x / 1008) (BiRank), which = 1 -> floor(x / 480) (QuadRank). */
+ * which = 0 -> floor(x / 1008) (BiRank), 1 -> floor(x / 480) (QuadRank), 2 -> floor(x / 992)
+ * (BiRank, QR_LAYOUT_32), 3 -> floor(x / 448) (QuadRank, QR_LAYOUT_32); other values give ~0. */
 uint64_t qr_line_of(uint64_t x, int which);
 
 #ifdef __cplusplus

@@ -168,6 +168,29 @@ def count_backward(bwt_codes: np.ndarray, pat: np.ndarray, off: np.ndarray) -> n
     return out[:npat]
 
 
+def revcomp(codes: np.ndarray) -> np.ndarray:
+    """Reverse complement of DNA codes (A<->T, C<->G: code c -> 3 - c), read backwards."""
+    return (3 - np.asarray(codes, dtype=np.uint8)[::-1]).astype(np.uint8)
+
+
+def count_both_strands(text: np.ndarray, sa: np.ndarray, pat: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """count(P) + count(revcomp(P)) for every pattern (the empty pattern counts n+1 once); codes > 3
+    make a pattern count 0 on both strands.  Saturates at 2^32-1 like the u32 result it checks."""
+    npat = off.size - 1
+    fwd = count_sa(text, sa, pat, off)
+    rc = [revcomp(pat[int(off[i]):int(off[i + 1])]) for i in range(npat)]
+    for i in range(npat):
+        if np.any(pat[int(off[i]):int(off[i + 1])] > 3):
+            rc[i] = np.full(max(1, int(off[i + 1] - off[i])), 9, np.uint8)
+    roff = np.zeros(npat + 1, np.uint64)
+    roff[1:] = np.cumsum([x.size for x in rc])
+    rflat = np.concatenate(rc).astype(np.uint8) if rc else np.zeros(0, np.uint8)
+    rev = count_sa(text, sa, rflat, roff)
+    out = fwd + rev
+    out[(off[1:] - off[:-1]) == 0] = text.size + 1
+    return np.minimum(out, np.uint64(0xFFFFFFFF))
+
+
 def kmer_intervals(bwt_codes: np.ndarray, k: int = 8):
     """(lo, hi) arrays of length 4^k: the interval after k backward steps for every k-mer."""
     n = bwt_codes.size - 1

@@ -20,6 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libquadrank.so")
 
 QR_OK, QR_EINVAL, QR_ENOMEM, QR_EHIP, QR_ERANGE, QR_EDEVICE = 0, -1, -2, -3, -4, -5
+QUADFM_BOTH_STRANDS = 1
+QR_LAYOUT_16, QR_LAYOUT_32 = 0, 1
 
 
 class QRError(RuntimeError):
@@ -49,6 +51,8 @@ def lib():
             "qr_version": (C.c_char_p, []),
             "qr_line_of": (u64, [u64, ci]),
             "birank_build": (ci, [vp, u64, vp, C.POINTER(vp)]),
+            "birank_build_ex": (ci, [vp, u64, ci, vp, C.POINTER(vp)]),
+            "birank_layout_kind": (ci, [vp]),
             "birank_rank": (ci, [vp, vp, u64, vp, vp]),
             "birank_check": (ci, [vp, vp]),
             "birank_free": (ci, [vp]),
@@ -58,6 +62,8 @@ def lib():
             "birank_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
             "birank_export": (ci, [vp, vp, vp]),
             "quadrank_build": (ci, [vp, u64, vp, C.POINTER(vp)]),
+            "quadrank_build_ex": (ci, [vp, u64, ci, vp, C.POINTER(vp)]),
+            "quadrank_layout_kind": (ci, [vp]),
             "quadrank_rank": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadrank_rank4": (ci, [vp, vp, u64, vp, vp]),
             "quadrank_check": (ci, [vp, vp]),
@@ -79,6 +85,8 @@ def lib():
             "quadfm_count": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadfm_count_batched": (ci, [vp, vp, vp, u64, u64, vp, vp]),
             "quadfm_count_ws": (ci, [vp, vp, vp, u64, vp, vp, vp]),
+            "quadfm_count_ex": (ci, [vp, vp, vp, u64, C.c_uint32, vp, vp, vp]),
+            "quadfm_count_batched_ex": (ci, [vp, vp, vp, u64, u64, C.c_uint32, vp, vp]),
             "quadfm_check": (ci, [vp, vp]),
             "quadfm_free": (ci, [vp]),
             "quadfm_len": (u64, [vp]),
@@ -143,10 +151,10 @@ def qr_line_of(x: int, which: int) -> int:
 
 
 # ------------------------------------------------------------------------------------------ BiRank
-def birank_build(bits: torch.Tensor, n_bits: int, stream=None) -> int:
+def birank_build(bits: torch.Tensor, n_bits: int, stream=None, layout: int = QR_LAYOUT_16) -> int:
     h = vp()
-    _check(lib().birank_build(_dev(bits, "bits", W64, (n_bits + 63) // 64), n_bits, _stream(stream), C.byref(h)),
-           "birank_build")
+    _check(lib().birank_build_ex(_dev(bits, "bits", W64, (n_bits + 63) // 64), n_bits, layout, _stream(stream),
+                                 C.byref(h)), "birank_build")
     return h.value
 
 
@@ -165,10 +173,10 @@ def birank_free(h: int):
 
 
 # ---------------------------------------------------------------------------------------- QuadRank
-def quadrank_build(packed2: torch.Tensor, n: int, stream=None) -> int:
+def quadrank_build(packed2: torch.Tensor, n: int, stream=None, layout: int = QR_LAYOUT_16) -> int:
     h = vp()
-    _check(lib().quadrank_build(_dev(packed2, "packed2", W64, (n + 31) // 32), n, _stream(stream), C.byref(h)),
-           "quadrank_build")
+    _check(lib().quadrank_build_ex(_dev(packed2, "packed2", W64, (n + 31) // 32), n, layout, _stream(stream),
+                                   C.byref(h)), "quadrank_build")
     return h.value
 
 
@@ -236,6 +244,23 @@ def quadfm_count_ws(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.T
     _check(lib().quadfm_count_ws(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat,
                                  _dev(count, "count", W32, npat), _dev(workspace, "workspace", W64, 1),
                                  _stream(stream)), "quadfm_count_ws")
+    return count
+
+
+def quadfm_count_ex(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, flags: int = 0,
+                    workspace: torch.Tensor | None = None, stream=None):
+    npat = off.numel() - 1
+    ws = _dev(workspace, "workspace", W64, 1) if workspace is not None else None
+    _check(lib().quadfm_count_ex(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, flags,
+                                 _dev(count, "count", W32, npat), ws, _stream(stream)), "quadfm_count_ex")
+    return count
+
+
+def quadfm_count_batched_ex(h: int, pat: torch.Tensor, off: torch.Tensor, batch: int, flags: int, count: torch.Tensor,
+                            stream=None):
+    npat = off.numel() - 1
+    _check(lib().quadfm_count_batched_ex(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, batch, flags,
+                                         _dev(count, "count", W32, npat), _stream(stream)), "quadfm_count_batched_ex")
     return count
 
 
@@ -325,9 +350,10 @@ class BiRank(_Handle):
     """Binary rank structure built on the current device from n bits (u64 words, LSB first)."""
     _free = staticmethod(birank_free)
 
-    def __init__(self, bits: torch.Tensor, n_bits: int, stream=None):
-        super().__init__(birank_build(bits, n_bits, stream))
+    def __init__(self, bits: torch.Tensor, n_bits: int, stream=None, layout: int = QR_LAYOUT_16):
+        super().__init__(birank_build(bits, n_bits, stream, layout))
         self.n = n_bits
+        self.layout = layout
 
     def rank(self, q: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if out is None:
@@ -344,16 +370,16 @@ class BiRank(_Handle):
     def nbytes(self) -> int:
         return int(lib().birank_bytes(self.h))
 
-    def layout(self):
+    def raw_layout(self):
         """(lines_ptr, n_lines, super_ptr, n_super) device pointers of the raw layout."""
         return _layout(lib().birank_layout, self.h)
 
     def export(self):
         """Host copies (numpy) of the raw layout: (lines u64[n_lines, 16], super u32[n_super])."""
         import numpy as np
-        _, nl, _, ns = self.layout()
+        _, nl, _, ns = self.raw_layout()
         lines = np.empty((nl, 16), dtype=np.uint64)
-        sup = np.empty(ns, dtype=np.uint32)
+        sup = np.empty(ns, dtype=np.uint64 if self.layout == QR_LAYOUT_32 else np.uint32)
         _check(lib().birank_export(self.h, lines.ctypes.data, sup.ctypes.data), "birank_export")
         return lines, sup
 
@@ -362,9 +388,10 @@ class QuadRank(_Handle):
     """DNA rank structure built from n 2-bit packed bases."""
     _free = staticmethod(quadrank_free)
 
-    def __init__(self, packed2: torch.Tensor, n: int, stream=None):
-        super().__init__(quadrank_build(packed2, n, stream))
+    def __init__(self, packed2: torch.Tensor, n: int, stream=None, layout: int = QR_LAYOUT_16):
+        super().__init__(quadrank_build(packed2, n, stream, layout))
         self.n = n
+        self.layout = layout
 
     def rank(self, q: torch.Tensor, c: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if out is None:
@@ -386,15 +413,16 @@ class QuadRank(_Handle):
     def nbytes(self) -> int:
         return int(lib().quadrank_bytes(self.h))
 
-    def layout(self):
+    def raw_layout(self):
+        """(lines_ptr, n_lines, super_ptr, n_super) device pointers of the raw layout."""
         return _layout(lib().quadrank_layout, self.h)
 
     def export(self):
-        """Host copies (numpy): (lines u64[n_lines, 16], super u32[n_super, 4])."""
+        """Host copies (numpy): (lines u64[n_lines, 16], super u32 or u64 [n_super, 4])."""
         import numpy as np
-        _, nl, _, ns = self.layout()
+        _, nl, _, ns = self.raw_layout()
         lines = np.empty((nl, 16), dtype=np.uint64)
-        sup = np.empty((ns, 4), dtype=np.uint32)
+        sup = np.empty((ns, 4), dtype=np.uint64 if self.layout == QR_LAYOUT_32 else np.uint32)
         _check(lib().quadrank_export(self.h, lines.ctypes.data, sup.ctypes.data), "quadrank_export")
         return lines, sup
 
@@ -415,15 +443,20 @@ class QuadFm(_Handle):
         d = torch.from_numpy(bwt.view(np.int64)).cuda()
         return cls(d, int(np.asarray(text_codes).size) + 1, dollar, stream)
 
-    def count(self, pat: torch.Tensor, off: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    def count(self, pat: torch.Tensor, off: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+              both_strands: bool = False):
         if out is None:
             out = torch.empty(off.numel() - 1, dtype=torch.int32, device=off.device)
+        if both_strands:
+            return quadfm_count_ex(self.h, pat, off, out, QUADFM_BOTH_STRANDS, None, stream)
         return quadfm_count(self.h, pat, off, out, stream)
 
     def count_batched(self, pat: torch.Tensor, off: torch.Tensor, batch: int = 0, out: torch.Tensor | None = None,
-                      stream=None):
+                      stream=None, both_strands: bool = False):
         if out is None:
             out = torch.empty(off.numel() - 1, dtype=torch.int32, device=off.device)
+        if both_strands:
+            return quadfm_count_batched_ex(self.h, pat, off, batch, QUADFM_BOTH_STRANDS, out, stream)
         return quadfm_count_batched(self.h, pat, off, batch, out, stream)
 
     def check(self, stream=None):

@@ -1,20 +1,24 @@
-// BiRank on gfx950 (paper Section 3): binary rank with one 16-bit delta inlined per 128-byte line.
+// BiRank on gfx950 (paper Section 3): binary rank with a delta inlined in every 128-byte line.
 //
-// Line j (16 little-endian u64 words = 1024 bits):
-//   bits [0, 16)      b_j = rank(1008 j + 496) - 2^10 * s_{j/64}   (delta to the line's middle)
-//   bits [16, 1024)   input bits [1008 j, 1008 j + 1008)
-// The line's middle is line bit 512 (= data bit 496), so each half line is one 64-byte segment.
-// Superblock i = lines [64 i, 64 i + 64) = 64512 input bits = exactly 1008 input words;
-//   s_i = floor(rank(64512 i) / 2^10) as u32 (the paper's shifted 32-bit offset, Section 3,
-//   with shift 10 instead of 11 because 64 lines of 1008 bits fill the 16-bit delta).
-// Bound: b_j <= 63*1008 + 496 + (2^10 - 1) = 65023 < 2^16; s_i < 2^32 for n < 2^42.
-// There are floor(n/1008) + 1 lines and floor(n/64512) + 1 superblocks, so q = n always has a
-// line; bits past n are stored as zero and every delta is taken over that zero-padded text.
+// Two layouts, both with the delta measured to the line's middle (line bit 512), so each 64-byte
+// half of a line is one half of the block and a query popcounts at most 512 bits (Eq. (1)):
 //
-// Query (paper Eq. (1)): j = floor(q/1008), p = q - 1008 j + 16 (line bit of q);
-//   rank(q) = 2^10 s_{j/64} + b_j + popcount(line bits [512, p))   if p >= 512
-//   rank(q) = 2^10 s_{j/64} + b_j - popcount(line bits [p, 512))   if p <  512
-// so at most one 64-byte half line (512 bits) is popcounted.
+//   BR16 (default; the paper's BiRank16 re-derived for 128-byte lines)
+//     line j: bits [0,16) b_j, bits [16,1024) input bits [1008 j, 1008 j + 1008)
+//     b_j = rank(1008 j + 496) - 2^10 s_{j/64};  s_i = floor(rank(64512 i) / 2^10) (u32, the
+//     shifted 32-bit offset of Section 3 with shift 10: 64 lines of 1008 bits fill 16 bits)
+//     bounds: b_j <= 63*1008 + 496 + 1023 = 65023 < 2^16; s_i < 2^32 for n < 2^42
+//   BR32 (the paper's BiRank32 variant: a 32-bit inline value, much smaller offset array)
+//     line j: bits [0,32) b_j, bits [32,1024) input bits [992 j, 992 j + 992)
+//     b_j = rank(992 j + 480) - s_{j/2^22};  s_i = rank(992 * 2^22 * i) (u64, exact)
+//     bounds: b_j <= (2^22 - 1)*992 + 480 < 2^32; the offset array has one entry per 4.16e9 bits
+//
+// floor(n/B) + 1 lines, so q = n always has a line; bits past n are stored as zero and every
+// delta is taken over that zero-padded text.
+//
+// Query: j = floor(q/B), p = q - B j + HDR (line bit of q);
+//   rank(q) = offset_j + b_j + popcount(line bits [512, p))   if p >= 512
+//   rank(q) = offset_j + b_j - popcount(line bits [p, 512))   if p <  512
 #include <algorithm>
 #include <new>
 
@@ -22,11 +26,57 @@
 
 using namespace qr;
 
+namespace {
+
+struct BR16 {
+    static constexpr uint32_t HDR = 16, DATA = 1008, MID = 512;
+    static constexpr uint64_t SB_LINES = 64;     // lines per superblock
+    static constexpr uint32_t SB_LOG = 6;
+    static constexpr uint32_t SHIFT = 10;
+    static constexpr uint64_t MAGIC = 0x8208208208208209ull;  // ceil(2^73 / 1008)
+    static constexpr uint32_t MAGIC_T = 9;
+    static constexpr uint64_t MAX_N = (1ull << 42) - 1;
+    using Super = uint32_t;
+    __device__ __forceinline__ static uint64_t offset(const Super *__restrict__ s, uint64_t j) {
+        return (uint64_t)s[j >> SB_LOG] << SHIFT;
+    }
+    __device__ __forceinline__ static uint32_t delta(uint32_t w0) { return w0 & 0xffffu; }
+};
+
+// 32-bit inline deltas: floor(x/992) = mulhi(x, ceil(2^73/992)) >> 9, exact for x < 2^63
+// (e = m*992 - 2^73 = 736 < 992, Granlund-Montgomery).
+struct BR32 {
+    static constexpr uint32_t HDR = 32, DATA = 992, MID = 512;
+    static constexpr uint64_t SB_LINES = 1ull << 22;
+    static constexpr uint32_t SB_LOG = 22;
+    static constexpr uint32_t SHIFT = 0;
+    static constexpr uint64_t MAGIC = 0x8421084210842109ull;  // ceil(2^73 / 992)
+    static constexpr uint32_t MAGIC_T = 9;
+    static constexpr uint64_t MAX_N = (1ull << 48) - 1;
+    using Super = uint64_t;
+    __device__ __forceinline__ static uint64_t offset(const Super *__restrict__ s, uint64_t j) { return s[j >> SB_LOG]; }
+    __device__ __forceinline__ static uint32_t delta(uint32_t w0) { return w0; }
+};
+
+constexpr uint32_t GROUP_LINES = 64;  // lines per build workgroup (BR16: one superblock)
+
+template <class L>
+__host__ __device__ __forceinline__ uint64_t line_of(uint64_t q) {
+    return mulhi64(q, L::MAGIC) >> L::MAGIC_T;
+}
+
+}  // namespace
+
+namespace qr {
+uint64_t br32_line_of_host(uint64_t x) { return line_of<BR32>(x); }
+}  // namespace qr
+
 struct qr_birank_s {
     int device;
+    int layout;  // QR_LAYOUT_16 or QR_LAYOUT_32
     uint64_t n, n_lines, n_sb;
     uint64_t *lines;  // n_lines * 16 words
-    uint32_t *super;  // n_sb
+    void *super;      // n_sb entries of u32 (16-bit layout) or u64 (32-bit layout)
     uint32_t *err;    // sticky device error word
     qr_tuning tune;
 };
@@ -42,44 +92,55 @@ __device__ __forceinline__ uint64_t masked_word(const uint64_t *__restrict__ bit
     return x;
 }
 
-// Pass 1: number of 1 bits in each superblock (1008 consecutive input words).
+// Pass 1: number of 1 bits in each group of 64 lines (GROUP_LINES * DATA / 64 input words).
+template <class L>
 __global__ __launch_bounds__(256) void br_count_kernel(const uint64_t *__restrict__ bits, uint64_t n,
                                                        uint64_t n_words, uint32_t *__restrict__ cnt) {
-    const uint64_t sb = blockIdx.x;
-    const uint64_t w0 = sb * (BR_SB_BITS / 64);
+    constexpr uint32_t W = GROUP_LINES * L::DATA / 64;
+    const uint64_t g = blockIdx.x;
     uint32_t c = 0;
-    for (uint32_t k = threadIdx.x; k < BR_SB_BITS / 64; k += 256) c += __popcll(masked_word(bits, w0 + k, n, n_words));
+    for (uint32_t k = threadIdx.x; k < W; k += 256) c += __popcll(masked_word(bits, g * W + k, n, n_words));
     c = wave_sum(c);
     __shared__ uint32_t part[4];
     if (__lane_id() == 0) part[threadIdx.x / 64] = c;
     __syncthreads();
-    if (threadIdx.x == 0) cnt[sb] = part[0] + part[1] + part[2] + part[3];
+    if (threadIdx.x == 0) cnt[g] = part[0] + part[1] + part[2] + part[3];
 }
 
-// Pass 3: one 64-lane workgroup per superblock; lane t forms line 64 i + t.
+// Offsets of the 32-bit layout: s_i = exact rank at the first line of superblock i.
+__global__ void br32_super_kernel(const uint64_t *__restrict__ base, uint64_t n_groups, uint64_t n_sb,
+                                  uint64_t *__restrict__ super) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr uint64_t GPS = BR32::SB_LINES / GROUP_LINES;
+    if (i < n_sb) super[i] = base[std::min(i * GPS, n_groups - 1)];
+}
+
+// Pass 3: one 64-lane workgroup per group of 64 lines; lane t forms line 64 g + t.
 constexpr int OUT_STRIDE = 17;  // padded LDS row (u64) for the staged lines: avoids bank conflicts
 
+template <class L>
 __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict__ bits, uint64_t n, uint64_t n_words,
                                                       const uint64_t *__restrict__ base, uint64_t n_lines,
                                                       uint64_t *__restrict__ lines) {
-    constexpr int W = BR_SB_BITS / 64;  // 1008 input words
+    constexpr uint32_t W = GROUP_LINES * L::DATA / 64;
+    constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
     __shared__ uint64_t in[W + 2];
     __shared__ uint64_t stage[64 * OUT_STRIDE];
-    const uint64_t sb = blockIdx.x;
+    const uint64_t g = blockIdx.x;
     const int t = threadIdx.x;
-    for (int k = t; k < W + 2; k += 64) in[k] = k < W ? masked_word(bits, sb * W + k, n, n_words) : 0ull;
+    for (int k = t; k < (int)W + 2; k += 64) in[k] = k < (int)W ? masked_word(bits, g * W + k, n, n_words) : 0ull;
     __syncthreads();
 
-    auto get64 = [&](uint32_t b) -> uint64_t {  // input bits [b, b+64) of this superblock
+    auto get64 = [&](uint32_t b) -> uint64_t {  // input bits [b, b+64) of this group
         uint32_t w = b >> 6, sh = b & 63;
         uint64_t lo = in[w];
         return sh ? (lo >> sh) | (in[w + 1] << (64 - sh)) : lo;
     };
-    const uint32_t b0 = (uint32_t)BR_DATA_BITS * (uint32_t)t;
+    const uint32_t b0 = L::DATA * (uint32_t)t;
     uint64_t o[16];
-    o[0] = get64(b0) << BR_HDR;
+    o[0] = get64(b0) << L::HDR;
 #pragma unroll
-    for (int k = 1; k < 16; ++k) o[k] = get64(b0 + 64u * k - BR_HDR);
+    for (int k = 1; k < 16; ++k) o[k] = get64(b0 + 64u * k - L::HDR);
     uint32_t c_first = 0, c_second = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) c_first += __popcll(o[k]);
@@ -87,13 +148,16 @@ __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict
     for (int k = 8; k < 16; ++k) c_second += __popcll(o[k]);
     const uint32_t c_tot = c_first + c_second;
     const uint32_t before = wave_inclusive_scan<uint32_t>(c_tot) - c_tot;
-    const uint32_t rem = (uint32_t)(base[sb] & ((1u << BR_SHIFT) - 1u));
-    o[0] |= (uint64_t)(rem + before + c_first);
+    // offset of this line's superblock as the query reconstructs it
+    const uint64_t sb_base = base[(g / GPS) * GPS];
+    const uint64_t off = (sb_base >> L::SHIFT) << L::SHIFT;
+    const uint64_t delta = base[g] - off + before + c_first;
+    o[0] |= delta;
 #pragma unroll
     for (int k = 0; k < 16; ++k) stage[t * OUT_STRIDE + k] = o[k];
     __syncthreads();
-    const uint64_t l0 = sb * BR_LINES_PER_SB;
-    const uint32_t nl = (uint32_t)std::min<uint64_t>(BR_LINES_PER_SB, n_lines - l0);
+    const uint64_t l0 = g * GROUP_LINES;
+    const uint32_t nl = (uint32_t)std::min<uint64_t>(GROUP_LINES, n_lines - l0);
     uint4 *dst = reinterpret_cast<uint4 *>(lines + l0 * 16);
     for (uint32_t e = t; e < nl * 8; e += 64) {  // 8 uint4 per line, coalesced
         const uint64_t *src = stage + (e >> 3) * OUT_STRIDE + (e & 7) * 2;
@@ -112,51 +176,54 @@ __device__ __forceinline__ uint32_t half_count(const uint32_t (&h)[16], uint32_t
     return c;
 }
 
-// Query kernel: PER_LANE independent queries per lane, all loads issued before any popcount.
-template <int PER_LANE>
-__global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ lines, const uint32_t *__restrict__ super,
-                                                      uint64_t n, const uint64_t *__restrict__ Q, uint64_t nq,
+// One lane per query: the lane loads the half holding q, plus the line's first word for the delta
+// when q lies in the upper half.  PER_LANE independent queries per lane, loads before popcounts.
+template <class L, int PER_LANE>
+__global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ lines,
+                                                      const typename L::Super *__restrict__ super, uint64_t n,
+                                                      const uint64_t *__restrict__ Q, uint64_t nq,
                                                       uint64_t *__restrict__ out, uint32_t *__restrict__ err) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nq; i0 += stride * PER_LANE) {
-        uint64_t q[PER_LANE], j[PER_LANE];
-        uint32_t p[PER_LANE], hdr[PER_LANE], s[PER_LANE];
+        uint64_t q[PER_LANE], off[PER_LANE];
+        uint32_t p[PER_LANE], hdr[PER_LANE];
         uint32_t h[PER_LANE][16];
         bool bad[PER_LANE];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            const uint64_t i = i0 + u * stride;
-            q[u] = i < nq ? Q[i] : 0;
+            q[u] = Q[min(i0 + u * stride, nq - 1)];
             bad[u] = q[u] > n;
             if (bad[u]) q[u] = 0;  // line 0 always exists; the output is overwritten below
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            j[u] = br_line_of(q[u]);
-            p[u] = (uint32_t)(q[u] - j[u] * BR_DATA_BITS) + BR_HDR;
-            const bool up = p[u] >= BR_MID;
-            const uint4 *L = lines + j[u] * 8 + (up ? 4 : 0);
-            uint4 a = L[0], b = L[1], c = L[2], d = L[3];
+            const uint64_t j = line_of<L>(q[u]);
+            p[u] = (uint32_t)(q[u] - j * L::DATA) + L::HDR;
+            const bool up = p[u] >= L::MID;
+            const uint4 *H = lines + j * 8 + (up ? 4 : 0);
+            const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
             h[u][0] = a.x, h[u][1] = a.y, h[u][2] = a.z, h[u][3] = a.w;
             h[u][4] = b.x, h[u][5] = b.y, h[u][6] = b.z, h[u][7] = b.w;
             h[u][8] = c.x, h[u][9] = c.y, h[u][10] = c.z, h[u][11] = c.w;
             h[u][12] = d.x, h[u][13] = d.y, h[u][14] = d.z, h[u][15] = d.w;
-            hdr[u] = up ? reinterpret_cast<const uint32_t *>(lines)[j[u] * 32] : a.x;
-            s[u] = super[j[u] / BR_LINES_PER_SB];
+            hdr[u] = up ? reinterpret_cast<const uint32_t *>(lines)[j * 32] : a.x;
+            off[u] = L::offset(super, j);
+        }
+        uint64_t r[PER_LANE];
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) {
+            const bool up = p[u] >= L::MID;
+            const uint32_t cnt = half_count(h[u], up ? p[u] - L::MID : p[u], up);
+            const uint64_t mid = off[u] + L::delta(hdr[u]);
+            r[u] = bad[u] ? ~0ull : (up ? mid + cnt : mid - cnt);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const uint64_t i = i0 + u * stride;
-            if (i >= nq) continue;
-            const bool up = p[u] >= BR_MID;
-            const uint32_t cnt = half_count(h[u], up ? p[u] - BR_MID : p[u], up);
-            const uint64_t mid = ((uint64_t)s[u] << BR_SHIFT) + (hdr[u] & 0xffffu);
-            uint64_t r = up ? mid + cnt : mid - cnt;
-            if (bad[u]) {
-                r = ~0ull;
-                atomicOr(err, 1u);
+            if (i < nq) {
+                out[i] = r[u];
+                if (bad[u]) atomicOr(err, 1u);
             }
-            out[i] = r;
         }
     }
 }
@@ -166,16 +233,16 @@ __global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ 
 // each (measured on MI355X: far fewer address-translation misses on multi-GiB structures than one
 // lane issuing four loads).  The lane holding the half that contains q popcounts it; lane 0 adds
 // the superblock offset and delta; the two contributions are summed across the pair.
-template <int PER_PAIR>
+template <class L, int PER_PAIR>
 __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restrict__ lines,
-                                                           const uint32_t *__restrict__ super, uint64_t n,
+                                                           const typename L::Super *__restrict__ super, uint64_t n,
                                                            const uint64_t *__restrict__ Q, uint64_t nq,
                                                            uint64_t *__restrict__ out, uint32_t *__restrict__ err) {
     const uint32_t hf = threadIdx.x & 1u;
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
-        uint64_t q[PER_PAIR], r[PER_PAIR];
-        uint32_t p[PER_PAIR], s[PER_PAIR];
+        uint64_t q[PER_PAIR], r[PER_PAIR], off[PER_PAIR];
+        uint32_t p[PER_PAIR];
         uint32_t h[PER_PAIR][16];
         bool bad[PER_PAIR];
         // 1: query positions (index clamped so every load is unconditional and in bounds)
@@ -186,22 +253,22 @@ __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restri
         for (int u = 0; u < PER_PAIR; ++u) {
             bad[u] = q[u] > n;
             const uint64_t qq = bad[u] ? 0 : q[u];
-            const uint64_t j = br_line_of(qq);
-            p[u] = (uint32_t)(qq - j * BR_DATA_BITS) + BR_HDR;
-            const uint4 *L = lines + j * 8 + hf * 4;
-            const uint4 a = L[0], b = L[1], c = L[2], d = L[3];
+            const uint64_t j = line_of<L>(qq);
+            p[u] = (uint32_t)(qq - j * L::DATA) + L::HDR;
+            const uint4 *H = lines + j * 8 + hf * 4;
+            const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
             h[u][0] = a.x, h[u][1] = a.y, h[u][2] = a.z, h[u][3] = a.w;
             h[u][4] = b.x, h[u][5] = b.y, h[u][6] = b.z, h[u][7] = b.w;
             h[u][8] = c.x, h[u][9] = c.y, h[u][10] = c.z, h[u][11] = c.w;
             h[u][12] = d.x, h[u][13] = d.y, h[u][14] = d.z, h[u][15] = d.w;
-            s[u] = super[j / BR_LINES_PER_SB];
+            off[u] = L::offset(super, j);
         }
         // 3: count and combine across the pair
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
-            const bool up = p[u] >= BR_MID;
-            const uint32_t cnt = half_count(h[u], up ? p[u] - BR_MID : p[u], up) & (((uint32_t)up == hf) ? ~0u : 0u);
-            const uint64_t mine = hf == 0 ? ((uint64_t)s[u] << BR_SHIFT) + (h[u][0] & 0xffffu) - cnt : (uint64_t)cnt;
+            const bool up = p[u] >= L::MID;
+            const uint32_t cnt = half_count(h[u], up ? p[u] - L::MID : p[u], up) & (((uint32_t)up == hf) ? ~0u : 0u);
+            const uint64_t mine = hf == 0 ? off[u] + L::delta(h[u][0]) - cnt : (uint64_t)cnt;
             r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
         }
         // 4: results
@@ -216,32 +283,55 @@ __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restri
     }
 }
 
-template <int PL>
-hipError_t launch_rank_pair(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s,
-                            int block, int grid_waves) {
-    const uint64_t lanes_needed = 2 * ((nq + PL - 1) / PL);
-    uint64_t blocks = (lanes_needed + block - 1) / block;
-    if (grid_waves > 0) blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, (uint64_t)cu_count() * grid_waves * 64 / block));
+template <class L, int PL>
+hipError_t launch_rank_t(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s) {
+    const int block = h->tune.block ? h->tune.block : 256;
+    const int lanes = h->tune.lanes == 1 ? 1 : 2;
+    uint64_t blocks = (lanes * ((nq + PL - 1) / PL) + block - 1) / block;
+    if (h->tune.grid_waves > 0)
+        blocks = std::min<uint64_t>(blocks, std::max<uint64_t>(1, (uint64_t)cu_count() * h->tune.grid_waves * 64 / block));
     blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, 0x7fffffffull));
-    hipLaunchKernelGGL(br_rank_pair_kernel<PL>, dim3((uint32_t)blocks), dim3(block), 0, s,
-                       reinterpret_cast<const uint4 *>(h->lines), h->super, h->n, d_q, nq, d_out, h->err);
+    const uint4 *L4 = reinterpret_cast<const uint4 *>(h->lines);
+    const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
+    if (lanes == 2)
+        hipLaunchKernelGGL((br_rank_pair_kernel<L, PL>), dim3((uint32_t)blocks), dim3(block), 0, s, L4, S, h->n, d_q, nq,
+                           d_out, h->err);
+    else
+        hipLaunchKernelGGL((br_rank_kernel<L, PL>), dim3((uint32_t)blocks), dim3(block), 0, s, L4, S, h->n, d_q, nq,
+                           d_out, h->err);
     return hipGetLastError();
 }
 
-template <int PL>
-hipError_t launch_rank(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s,
-                       int block, int grid_waves) {
-    if (h->tune.lanes != 1) return launch_rank_pair<PL>(h, d_q, nq, d_out, s, block, grid_waves);
-    uint64_t lanes_needed = (nq + PL - 1) / PL;
-    uint64_t blocks = (lanes_needed + block - 1) / block;
-    if (grid_waves > 0) {
-        uint64_t cap = (uint64_t)cu_count() * grid_waves * 64 / block;
-        if (cap < 1) cap = 1;
-        blocks = std::min<uint64_t>(blocks, cap);
+template <class L>
+hipError_t launch_rank(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s) {
+    switch (h->tune.per_lane ? h->tune.per_lane : 1) {
+        case 1: return launch_rank_t<L, 1>(h, d_q, nq, d_out, s);
+        case 2: return launch_rank_t<L, 2>(h, d_q, nq, d_out, s);
+        case 4: return launch_rank_t<L, 4>(h, d_q, nq, d_out, s);
+        default: return launch_rank_t<L, 8>(h, d_q, nq, d_out, s);
     }
-    blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, 0x7fffffffull));
-    hipLaunchKernelGGL(br_rank_kernel<PL>, dim3((uint32_t)blocks), dim3(block), 0, s,
-                       reinterpret_cast<const uint4 *>(h->lines), h->super, h->n, d_q, nq, d_out, h->err);
+}
+
+template <class L>
+hipError_t build_t(qr_birank_s *h, const uint64_t *d_bits, uint32_t *cnt, uint64_t *base, uint64_t n_groups,
+                   hipStream_t stream) {
+    const uint64_t n_words = (h->n + 63) / 64;
+    hipLaunchKernelGGL(br_count_kernel<L>, dim3((uint32_t)n_groups), dim3(256), 0, stream, d_bits, h->n, n_words, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (L::SHIFT) {  // 16-bit layout: a group is a superblock, the scan writes the shifted offsets
+        e = launch_scan_counts(cnt, n_groups, 1, L::SHIFT, base, reinterpret_cast<uint32_t *>(h->super), stream);
+    } else {  // 32-bit layout: scan into base, then pick one exact offset per superblock
+        e = launch_scan_counts(cnt, n_groups, 1, 0, base, nullptr, stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(br32_super_kernel, dim3((uint32_t)((h->n_sb + 255) / 256)), dim3(256), 0, stream, base,
+                               n_groups, h->n_sb, reinterpret_cast<uint64_t *>(h->super));
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(br_write_kernel<L>, dim3((uint32_t)n_groups), dim3(64), 0, stream, d_bits, h->n, n_words, base,
+                       h->n_lines, h->lines);
     return hipGetLastError();
 }
 
@@ -257,18 +347,25 @@ void release(qr_birank_s *h) {
 
 extern "C" {
 
-int birank_build(const uint64_t *d_bits, uint64_t n, hipStream_t stream, qr_birank *out) {
+int birank_build_ex(const uint64_t *d_bits, uint64_t n, int layout, hipStream_t stream, qr_birank *out) {
     if (!out) {
         set_error("birank_build: out is NULL");
         return QR_EINVAL;
     }
     *out = nullptr;
     if (((uintptr_t)d_bits & 7) || (!d_bits && n)) {
-        set_error("birank_build: d_bits is NULL with n = %llu", (unsigned long long)n);
+        set_error("birank_build: d_bits is NULL (with n = %llu) or not 8-byte aligned", (unsigned long long)n);
         return QR_EINVAL;
     }
-    if (n > BR_MAX_N) {
-        set_error("birank_build: n = %llu exceeds the layout limit 2^42 - 1", (unsigned long long)n);
+    if (layout != QR_LAYOUT_16 && layout != QR_LAYOUT_32) {
+        set_error("birank_build: unknown layout %d", layout);
+        return QR_EINVAL;
+    }
+    const bool l32 = layout == QR_LAYOUT_32;
+    const uint64_t max_n = l32 ? BR32::MAX_N : BR16::MAX_N;
+    if (n > max_n) {
+        set_error("birank_build: n = %llu exceeds the layout limit %llu", (unsigned long long)n,
+                  (unsigned long long)max_n);
         return QR_ERANGE;
     }
     qr_birank_s *h = new (std::nothrow) qr_birank_s{};
@@ -278,11 +375,14 @@ int birank_build(const uint64_t *d_bits, uint64_t n, hipStream_t stream, qr_bira
         set_error("hipGetDevice failed");
         return QR_EHIP;
     }
+    const uint64_t data = l32 ? BR32::DATA : BR16::DATA;
+    const uint64_t sb_lines = l32 ? BR32::SB_LINES : BR16::SB_LINES;
+    h->layout = layout;
     h->n = n;
-    h->n_lines = n / BR_DATA_BITS + 1;
-    h->n_sb = n / BR_SB_BITS + 1;
+    h->n_lines = n / data + 1;
+    h->n_sb = (h->n_lines - 1) / sb_lines + 1;
     h->tune = qr_tuning{256, 1, 0, 2};
-    const uint64_t n_words = (n + 63) / 64;
+    const uint64_t n_groups = (h->n_lines - 1) / GROUP_LINES + 1;
     uint32_t *cnt = nullptr;
     uint64_t *base = nullptr;
     auto fail = [&](int code) {
@@ -291,23 +391,18 @@ int birank_build(const uint64_t *d_bits, uint64_t n, hipStream_t stream, qr_bira
         release(h);
         return code;
     };
-    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 4) != hipSuccess ||
-        hipMalloc(&h->err, 4) != hipSuccess || hipMalloc(&cnt, h->n_sb * 4) != hipSuccess ||
-        hipMalloc(&base, h->n_sb * 8) != hipSuccess) {
+    const size_t super_bytes = h->n_sb * (l32 ? 8 : 4);
+    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, super_bytes) != hipSuccess ||
+        hipMalloc(&h->err, 4) != hipSuccess || hipMalloc(&cnt, n_groups * 4) != hipSuccess ||
+        hipMalloc(&base, n_groups * 8) != hipSuccess) {
         (void)hipGetLastError();
         set_error("birank_build: device allocation of %llu bytes failed",
-                  (unsigned long long)(h->n_lines * 128 + h->n_sb * 16));
+                  (unsigned long long)(h->n_lines * 128 + super_bytes));
         return fail(QR_ENOMEM);
     }
     if (hipMemsetAsync(h->err, 0, 4, stream) != hipSuccess) return fail(QR_EHIP);
-    hipLaunchKernelGGL(br_count_kernel, dim3((uint32_t)h->n_sb), dim3(256), 0, stream, d_bits, n, n_words, cnt);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = launch_scan_counts(cnt, h->n_sb, 1, BR_SHIFT, base, h->super, stream);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(br_write_kernel, dim3((uint32_t)h->n_sb), dim3(64), 0, stream, d_bits, n, n_words, base,
-                           h->n_lines, h->lines);
-        e = hipGetLastError();
-    }
+    hipError_t e = l32 ? build_t<BR32>(h, d_bits, cnt, base, n_groups, stream)
+                       : build_t<BR16>(h, d_bits, cnt, base, n_groups, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         set_error("birank_build: %s", hipGetErrorString(e));
@@ -317,6 +412,10 @@ int birank_build(const uint64_t *d_bits, uint64_t n, hipStream_t stream, qr_bira
     (void)hipFree(base);
     *out = h;
     return QR_OK;
+}
+
+int birank_build(const uint64_t *d_bits, uint64_t n, hipStream_t stream, qr_birank *out) {
+    return birank_build_ex(d_bits, n, QR_LAYOUT_16, stream, out);
 }
 
 int birank_rank(qr_birank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t stream) {
@@ -331,15 +430,8 @@ int birank_rank(qr_birank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, 
     int rc = check_device(h->device);
     if (rc) return rc;
     if (!nq) return QR_OK;
-    const int block = h->tune.block ? h->tune.block : 256;
-    const int pl = h->tune.per_lane ? h->tune.per_lane : 1;
-    hipError_t e;
-    switch (pl) {
-        case 1: e = launch_rank<1>(h, d_q, nq, d_out, stream, block, h->tune.grid_waves); break;
-        case 2: e = launch_rank<2>(h, d_q, nq, d_out, stream, block, h->tune.grid_waves); break;
-        case 4: e = launch_rank<4>(h, d_q, nq, d_out, stream, block, h->tune.grid_waves); break;
-        default: e = launch_rank<8>(h, d_q, nq, d_out, stream, block, h->tune.grid_waves); break;
-    }
+    const hipError_t e = h->layout == QR_LAYOUT_32 ? launch_rank<BR32>(h, d_q, nq, d_out, stream)
+                                                   : launch_rank<BR16>(h, d_q, nq, d_out, stream);
     if (e != hipSuccess) {
         set_error("birank_rank launch: %s", hipGetErrorString(e));
         return QR_EHIP;
@@ -369,7 +461,10 @@ int birank_free(qr_birank h) {
 }
 
 uint64_t birank_len(qr_birank h) { return h ? h->n : 0; }
-uint64_t birank_bytes(qr_birank h) { return h ? h->n_lines * 128 + h->n_sb * 4 : 0; }
+uint64_t birank_bytes(qr_birank h) {
+    return h ? h->n_lines * 128 + h->n_sb * (h->layout == QR_LAYOUT_32 ? 8 : 4) : 0;
+}
+int birank_layout_kind(qr_birank h) { return h ? h->layout : -1; }
 
 int birank_layout(qr_birank h, const void **d_lines, uint64_t *n_lines, const void **d_super, uint64_t *n_super) {
     if (!h) return QR_EINVAL;
@@ -385,7 +480,8 @@ int birank_export(qr_birank h, void *h_lines, void *h_super) {
     int rc = check_device(h->device);
     if (rc) return rc;
     if (h_lines) QR_HIP(hipMemcpy(h_lines, h->lines, h->n_lines * 128, hipMemcpyDeviceToHost));
-    if (h_super) QR_HIP(hipMemcpy(h_super, h->super, h->n_sb * 4, hipMemcpyDeviceToHost));
+    if (h_super)
+        QR_HIP(hipMemcpy(h_super, h->super, h->n_sb * (h->layout == QR_LAYOUT_32 ? 8 : 4), hipMemcpyDeviceToHost));
     return QR_OK;
 }
 

@@ -62,17 +62,34 @@ __device__ __forceinline__ uint64_t fm_C(const FmDev &f, uint32_t c) {
     return (lo & ~m2) | (hi & m2);
 }
 
-// One backward step of the interval [sp, ep) with symbol c.
+// rank(q, c) over the BWT from the half line holding q, with the '$' correction for A.
+__device__ __forceinline__ uint64_t rank_bwt(const FmDev &f, const HalfLine &h, uint64_t q, uint32_t c) {
+    uint64_t r = rank1_from_half(h, c);
+    if (c == 0) r -= q > f.dollar;
+    return r;
+}
+
+// One backward step of the interval [sp, ep) with symbol c.  When sp and ep lie in the same half
+// line (most steps once the interval is small) both ranks come from one load: the second load is
+// issued only by the lanes whose ep lies elsewhere.
 __device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint64_t &sp, uint64_t &ep) {
-    HalfLine a, b;
+    HalfLine a;
     load_half(f.lines, f.super, sp, a);
-    load_half(f.lines, f.super, ep, b);
-    uint64_t rs = rank1_from_half(a, c), re = rank1_from_half(b, c);
-    if (c == 0) {
-        rs -= sp > f.dollar;
-        re -= ep > f.dollar;
-    }
+    const uint64_t js = qr_line_of(sp), je = qr_line_of(ep);
+    const bool ups = (uint32_t)(sp - js * QR_DATA_BASES) + QR_HDR >= QR_MID;
+    const bool upe = (uint32_t)(ep - je * QR_DATA_BASES) + QR_HDR >= QR_MID;
     const uint64_t base = fm_C(f, c);
+    const uint64_t rs = rank_bwt(f, a, sp, c);
+    uint64_t re;
+    if (js == je && ups == upe) {
+        HalfLine b = a;
+        b.t = upe ? (uint32_t)(ep - je * QR_DATA_BASES) + QR_HDR - QR_MID : (uint32_t)(ep - je * QR_DATA_BASES) + QR_HDR;
+        re = rank_bwt(f, b, ep, c);
+    } else {
+        HalfLine b;
+        load_half(f.lines, f.super, ep, b);
+        re = rank_bwt(f, b, ep, c);
+    }
     sp = base + rs;
     ep = base + re;
 }
@@ -103,33 +120,40 @@ __global__ void fm_totals_kernel(FmDev f, unsigned long long *__restrict__ out4)
     out4[4] = rank1_from_half(d1, 0) - rank1_from_half(d0, 0);
 }
 
-// Per-lane search state.
+// Per-lane search state.  The backward search over a pattern P reads P from its end; over the
+// reverse complement of P it reads P from its start and complements every code (c -> 3 - c).
 struct Search {
     uint64_t sp, ep;
     const uint8_t *P;  // pattern start
-    uint32_t i;        // characters still to process: P[0..i)
-    uint64_t buf;      // bytes [buf_at, buf_at + 8) of the pattern, holding P[i-1]
-    uintptr_t buf_at;
+    uint32_t m;        // pattern length
+    uint32_t left;     // characters still to process
+    uint32_t pos;      // index in P of the next character to read
+    uint32_t rc;       // 0: P itself, 1: its reverse complement
+    uint32_t acc;      // count of the first strand, when counting both
+    uint64_t buf;      // bytes [buf_at, buf_end) of the pattern (8 of them, or 1 near the pattern ends)
+    uintptr_t buf_at, buf_end;
     uintptr_t lo, hi;  // the pattern's byte range [lo, hi): no read leaves it
 };
 
-// Initialise the search for a pattern; returns true if its count is already known (written to cnt).
-__device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restrict__ pat, const uint64_t *__restrict__ off,
-                                        uint64_t p, Search &s, uint32_t &cnt) {
-    const uint64_t o = off[p], m = off[p + 1] - o;
-    s.P = pat + o;
-    s.lo = (uintptr_t)s.P;
-    s.hi = s.lo + m;
+__device__ __forceinline__ uint32_t strand_code(uint32_t c, uint32_t rc) { return (rc && c <= 3u) ? 3u - c : c; }
+
+// Sum of the two strands' counts, saturating at 2^32 - 1 (reachable only for texts over 2^31 bases).
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+    const uint64_t t = (uint64_t)a + b;
+    return t > 0xffffffffull ? 0xffffffffu : (uint32_t)t;
+}
+
+// Start the search of one strand; returns true if its count is already known (written to cnt).
+__device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc, uint32_t &cnt) {
+    s.rc = rc;
     s.buf_at = ~(uintptr_t)0;
-    if (m == 0) {
-        cnt = (uint32_t)f.n1;
-        return true;
-    }
+    const uint32_t m = s.m;
     if (m >= KMER) {
+        // the first 8 characters searched: P[m-8..m) for P, the complement of P[0..8) reversed for rc(P)
         uint32_t w = 0;
         bool bad = false;
         for (int t = 0; t < KMER; ++t) {
-            const uint32_t c = s.P[m - KMER + t];
+            const uint32_t c = strand_code(s.P[rc ? KMER - 1 - t : m - KMER + t], rc);
             bad |= c > 3;
             w = (w << 2) | (c & 3u);
         }
@@ -140,52 +164,90 @@ __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restric
         const uint2 iv = f.table[w];
         s.sp = iv.x;
         s.ep = iv.y;
-        s.i = (uint32_t)(m - KMER);
+        s.left = m - KMER;
+        s.pos = rc ? KMER : m - KMER - 1;
     } else {
         s.sp = 0;
         s.ep = f.n1;
-        s.i = (uint32_t)m;
+        s.left = m;
+        s.pos = rc ? 0 : m - 1;
     }
-    if (s.sp >= s.ep || s.i == 0) {
+    if (s.sp >= s.ep || s.left == 0) {
         cnt = s.sp < s.ep ? (uint32_t)(s.ep - s.sp) : 0u;
         return true;
     }
     return false;
 }
 
-// Next character P[i-1].  Characters are fetched 8 at a time with one aligned load when the whole
-// aligned 8-byte window lies inside the pattern, else one byte at a time.
+// Initialise the search for a pattern; returns true if its count is already known (written to cnt).
+template <bool BOTH>
+__device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restrict__ pat, const uint64_t *__restrict__ off,
+                                        uint64_t p, Search &s, uint32_t &cnt) {
+    const uint64_t o = off[p], m = off[p + 1] - o;
+    s.P = pat + o;
+    s.m = (uint32_t)m;
+    s.lo = (uintptr_t)s.P;
+    s.hi = s.lo + m;
+    s.acc = 0;
+    if (m == 0) {  // the empty pattern matches at every position 0..n (counted once)
+        cnt = (uint32_t)f.n1;
+        return true;
+    }
+    if (!fm_start(f, s, 0, cnt)) return false;
+    if (!BOTH) return true;
+    s.acc = cnt;  // forward strand finished at once: go on with the reverse complement
+    if (!fm_start(f, s, 1, cnt)) return false;
+    cnt = sat_add(cnt, s.acc);
+    return true;
+}
+
+// Next character of the current strand.  Characters are fetched 8 at a time with one aligned load
+// when the whole aligned 8-byte window lies inside the pattern, else one byte at a time.
 __device__ __forceinline__ uint32_t next_char(Search &s) {
-    const uintptr_t a = (uintptr_t)(s.P + s.i - 1);
-    if (s.buf_at == ~(uintptr_t)0 || a < s.buf_at) {
+    const uintptr_t a = (uintptr_t)(s.P + s.pos);
+    if (s.buf_at == ~(uintptr_t)0 || a < s.buf_at || a >= s.buf_end) {
         const uintptr_t w = a & ~(uintptr_t)7;
         if (w >= s.lo && w + 8 <= s.hi) {
             s.buf_at = w;
+            s.buf_end = w + 8;
             s.buf = *reinterpret_cast<const uint64_t *>(w);
         } else {
             s.buf_at = a;
+            s.buf_end = a + 1;
             s.buf = *reinterpret_cast<const uint8_t *>(a);
         }
     }
-    return (uint32_t)(s.buf >> (8 * (a - s.buf_at))) & 0xffu;
+    const uint32_t c = (uint32_t)(s.buf >> (8 * (a - s.buf_at))) & 0xffu;
+    s.pos = s.rc ? s.pos + 1 : s.pos - 1;
+    return strand_code(c, s.rc);
 }
 
-// Advance one character; returns true when the search has finished (count in cnt).
+// Advance one character; returns true when the pattern's count is final (in cnt).
+template <bool BOTH>
 __device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &cnt) {
     const uint32_t c = next_char(s);
+    bool fin;
     if (c > 3) {
         cnt = 0;
+        fin = true;
+    } else {
+        fm_step(f, c, s.sp, s.ep);
+        --s.left;
+        fin = s.sp >= s.ep || s.left == 0;
+        if (fin) cnt = s.sp < s.ep ? (uint32_t)(s.ep - s.sp) : 0u;
+    }
+    if (!fin) return false;
+    if (!BOTH || s.rc) {
+        cnt = sat_add(cnt, s.acc);
         return true;
     }
-    fm_step(f, c, s.sp, s.ep);
-    --s.i;
-    if (s.sp >= s.ep || s.i == 0) {
-        cnt = s.sp < s.ep ? (uint32_t)(s.ep - s.sp) : 0u;
-        return true;
-    }
-    return false;
+    s.acc = cnt;  // forward strand done: start the reverse complement
+    if (!fm_start(f, s, 1, cnt)) return false;
+    cnt = sat_add(cnt, s.acc);
+    return true;
 }
 
+template <bool BOTH>
 __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                        const uint64_t *__restrict__ off, uint64_t p0, uint64_t np,
                                                        uint32_t *__restrict__ count) {
@@ -194,14 +256,15 @@ __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *_
     const uint64_t p = p0 + k;
     Search s;
     uint32_t cnt = 0;
-    if (!fm_init(f, pat, off, p, s, cnt))
-        while (!fm_advance(f, s, cnt)) {
+    if (!fm_init<BOTH>(f, pat, off, p, s, cnt))
+        while (!fm_advance<BOTH>(f, s, cnt)) {
         }
     count[p] = cnt;
 }
 
 __global__ void fill_zero_u64(unsigned long long *p) { *p = 0ull; }
 
+template <bool BOTH>
 __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                             const uint64_t *__restrict__ off, uint64_t npat,
                                                             uint32_t *__restrict__ count,
@@ -212,9 +275,10 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
     Search s;
     s.sp = s.ep = 0;
     s.P = pat;
-    s.i = 0;
+    s.m = s.left = s.pos = s.rc = s.acc = 0;
     s.buf = 0;
     s.buf_at = ~(uintptr_t)0;
+    s.buf_end = 0;
     s.lo = s.hi = 0;
     while (true) {
         if (!drained) {
@@ -232,7 +296,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
                     if (mine < npat) {
                         p = mine;
                         uint32_t cnt = 0;
-                        if (fm_init(f, pat, off, p, s, cnt)) count[p] = cnt;
+                        if (fm_init<BOTH>(f, pat, off, p, s, cnt)) count[p] = cnt;
                         else active = true;
                     }
                 }
@@ -244,7 +308,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
         }
         if (active) {
             uint32_t cnt = 0;
-            if (fm_advance(f, s, cnt)) {
+            if (fm_advance<BOTH>(f, s, cnt)) {
                 count[p] = cnt;
                 active = false;
             }
@@ -367,7 +431,7 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
 }
 
 static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
-                            unsigned long long *head, hipStream_t stream) {
+                            unsigned long long *head, uint32_t flags, hipStream_t stream) {
     const int block = h->tune.block ? h->tune.block : 256;
     const uint32_t refill = h->tune.per_lane > 0 ? (uint32_t)h->tune.per_lane : 16u;
     const int wpc = h->tune.grid_waves > 0 ? h->tune.grid_waves : 16;
@@ -376,37 +440,55 @@ static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d
     blocks = std::max<uint64_t>(1, std::min(blocks, need));
     hipLaunchKernelGGL(fill_zero_u64, dim3(1), dim3(1), 0, stream, head);
     QR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(fm_persistent_kernel, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat, d_off,
-                       npat, d_count, head, refill);
+    if (flags & QUADFM_BOTH_STRANDS)
+        hipLaunchKernelGGL(fm_persistent_kernel<true>, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat,
+                           d_off, npat, d_count, head, refill);
+    else
+        hipLaunchKernelGGL(fm_persistent_kernel<false>, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat,
+                           d_off, npat, d_count, head, refill);
     QR_HIP(hipGetLastError());
     return QR_OK;
 }
 
+int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t flags,
+                    uint32_t *d_count, void *d_workspace, hipStream_t stream) {
+    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_ex");
+    if (rc) return rc;
+    if (flags & ~QUADFM_BOTH_STRANDS) {
+        set_error("quadfm_count_ex: unknown flag bits 0x%x", flags);
+        return QR_EINVAL;
+    }
+    if (d_workspace && ((uintptr_t)d_workspace & 7)) {
+        set_error("quadfm_count_ex: d_workspace must be 8-byte aligned");
+        return QR_EINVAL;
+    }
+    if (!npat) return QR_OK;
+    unsigned long long *head = d_workspace ? reinterpret_cast<unsigned long long *>(d_workspace) : h->head;
+    return count_persistent(h, d_pat, d_off, npat, d_count, head, flags, stream);
+}
+
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
                  hipStream_t stream) {
-    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count");
-    if (rc) return rc;
-    if (!npat) return QR_OK;
-    return count_persistent(h, d_pat, d_off, npat, d_count, h->head, stream);
+    return quadfm_count_ex(h, d_pat, d_off, npat, 0u, d_count, nullptr, stream);
 }
 
 int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
                     void *d_workspace, hipStream_t stream) {
-    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_ws");
-    if (rc) return rc;
-    if (!d_workspace || ((uintptr_t)d_workspace & 7)) {
-        set_error("quadfm_count_ws: d_workspace must be a non-null, 8-byte aligned device pointer");
+    if (!d_workspace) {
+        set_error("quadfm_count_ws: d_workspace is NULL");
         return QR_EINVAL;
     }
-    if (!npat) return QR_OK;
-    return count_persistent(h, d_pat, d_off, npat, d_count, reinterpret_cast<unsigned long long *>(d_workspace),
-                            stream);
+    return quadfm_count_ex(h, d_pat, d_off, npat, 0u, d_count, d_workspace, stream);
 }
 
-int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
-                         uint32_t *d_count, hipStream_t stream) {
+int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
+                            uint32_t flags, uint32_t *d_count, hipStream_t stream) {
     int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_batched");
     if (rc) return rc;
+    if (flags & ~QUADFM_BOTH_STRANDS) {
+        set_error("quadfm_count_batched_ex: unknown flag bits 0x%x", flags);
+        return QR_EINVAL;
+    }
     if (!batch) batch = npat;
     const FmDev f = dev_view(h);
     for (uint64_t p0 = 0; p0 < npat; p0 += batch) {
@@ -416,11 +498,20 @@ int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_of
             set_error("quadfm_count_batched: batch too large");
             return QR_EINVAL;
         }
-        hipLaunchKernelGGL(fm_batch_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off, p0, np,
-                           d_count);
+        if (flags & QUADFM_BOTH_STRANDS)
+            hipLaunchKernelGGL(fm_batch_kernel<true>, dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off, p0, np,
+                               d_count);
+        else
+            hipLaunchKernelGGL(fm_batch_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off, p0,
+                               np, d_count);
         QR_HIP(hipGetLastError());
     }
     return QR_OK;
+}
+
+int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
+                         uint32_t *d_count, hipStream_t stream) {
+    return quadfm_count_batched_ex(h, d_pat, d_off, npat, batch, 0u, d_count, stream);
 }
 
 int quadfm_check(qr_quadfm h, hipStream_t stream) {

@@ -1,22 +1,27 @@
-// QuadRank on gfx950 (paper Section 4): DNA rank with four 16-bit deltas inlined per 128-byte line
-// and the text stored transposed (a plane of low bits and a plane of high bits).
+// QuadRank on gfx950 (paper Section 4): DNA rank with four deltas inlined per 128-byte line and
+// the text stored transposed (a plane of low bits and a plane of high bits).
 //
 // Line j = 16 little-endian u64 words = 8 pairs (lo_k, hi_k) = (word 2k, word 2k+1), k = 0..7.
 // Pair k holds line base slots [64k, 64k+64): bit b of lo_k / hi_k is the low / high bit of slot
-// 64k + b.  Slots [0, 32) hold the deltas instead of bases:
-//   lo_0 bits [0,16) = b_{j,A}, [16,32) = b_{j,C};   hi_0 bits [0,16) = b_{j,G}, [16,32) = b_{j,T}
-// Slots [32, 512) hold bases 480 j .. 480 j + 479 (slot = base - 480 j + 32).
-// The line's middle is slot 256 (base 480 j + 224); each half line (pairs 0-3 or 4-7) is one
-// 64-byte segment.  b_{j,c} = rank(480 j + 224, c) - 2^12 * s_{j/128, c}.
-// Superblock i = lines [128 i, 128 i + 128) = 61440 bases = exactly 1920 packed input words;
-//   s_{i,c} = floor(rank(61440 i, c) / 2^12), stored as four u32 per superblock.
-// Bound: b <= 127*480 + 224 + (2^12 - 1) = 65279 < 2^16; s < 2^32 for n < 2^44.
-// floor(n/480) + 1 lines and floor(n/61440) + 1 superblocks; bases past n are stored as A (code 0)
-// and every delta is taken over that padded text, so the padding cancels for every q <= n.
+// 64k + b.  The first HDR slots hold the deltas instead of bases; the rest hold DATA bases
+// (slot = base - DATA j + HDR).  The line's middle is slot 256, so each half line (pairs 0-3 or
+// 4-7) is one 64-byte segment, and a query counts at most 256 slots.
 //
-// Query: j = floor(q/480), p = q - 480 j + 32 (slot of q);
-//   rank(q,c) = 2^12 s_{j/128,c} + b_{j,c} + #c in slots [256, p)   if p >= 256
-//   rank(q,c) = 2^12 s_{j/128,c} + b_{j,c} - #c in slots [p, 256)   if p <  256
+//   QR16 (default; the paper's QuadRank16 re-derived for 128-byte lines): HDR = 32 slots,
+//     lo_0 bits [0,16) = b_A, [16,32) = b_C; hi_0 bits [0,16) = b_G, [16,32) = b_T (the listing's
+//     delta placement c + (c&2) in u16 units); DATA = 480; middle = base 224;
+//     b_{j,c} = rank(480 j + 224, c) - 2^12 s_{j/128, c};  s_{i,c} = floor(rank(61440 i, c) / 2^12)
+//     bounds: b <= 127*480 + 224 + 4095 = 65279 < 2^16; s < 2^32 for n < 2^44
+//   QR32 (a 32-bit inline variant): HDR = 64 slots, lo_0 = b_A | b_C << 32, hi_0 = b_G | b_T << 32;
+//     DATA = 448; middle = base 192; b_{j,c} = rank(448 j + 192, c) - s_{j/2^23, c} (s exact, u64)
+//     bounds: b <= (2^23 - 1)*448 + 192 < 2^32
+//
+// floor(n/DATA) + 1 lines; bases past n are stored as A (code 0) and every delta is taken over that
+// padded text, so the padding cancels for every q <= n.
+//
+// Query: j = floor(q/DATA), p = q - DATA j + HDR (slot of q);
+//   rank(q,c) = offset_{j,c} + b_{j,c} + #c in slots [256, p)   if p >= 256
+//   rank(q,c) = offset_{j,c} + b_{j,c} - #c in slots [p, 256)   if p <  256
 // Symbol c matches where (lo XNOR c_0) AND (hi XNOR c_1).  rank4 counts the range once per
 // plane: T = |lo&hi|, C = |lo| - T, G = |hi| - T, A = len - T - C - G.
 #include <algorithm>
@@ -29,14 +34,17 @@ using namespace qr;
 
 struct qr_quadrank_s {
     int device;
+    int layout;  // QR_LAYOUT_16 or QR_LAYOUT_32
     uint64_t n, n_lines, n_sb;
     uint64_t *lines;  // n_lines * 16 words
-    uint32_t *super;  // n_sb * 4
+    void *super;      // n_sb * 4 offsets: u32 (16-bit layout) or u64 (32-bit layout)
     uint32_t *err;
     qr_tuning tune;
 };
 
 namespace {
+
+constexpr uint32_t GROUP_LINES = 128;  // lines per build workgroup (QR16: one superblock)
 
 __device__ __forceinline__ uint64_t masked_packed(const uint64_t *__restrict__ packed, uint64_t w, uint64_t n,
                                                   uint64_t n_words) {
@@ -56,13 +64,14 @@ __device__ __forceinline__ void word_counts(uint64_t x, uint32_t &cC, uint32_t &
     cG += __popcll(hi) - t;
 }
 
-// Pass 1: symbol counts of each superblock (1920 packed words, padded with A).
+// Pass 1: symbol counts of each group of 128 lines (padded with A).
+template <class L>
 __global__ __launch_bounds__(256) void qr_count_kernel(const uint64_t *__restrict__ packed, uint64_t n,
                                                        uint64_t n_words, uint32_t *__restrict__ cnt) {
-    constexpr uint32_t W = QR_SB_BASES / 32;
-    const uint64_t sb = blockIdx.x;
+    constexpr uint32_t W = GROUP_LINES * L::WORDS;
+    const uint64_t g = blockIdx.x;
     uint32_t cC = 0, cG = 0, cT = 0;
-    for (uint32_t k = threadIdx.x; k < W; k += 256) word_counts(masked_packed(packed, sb * W + k, n, n_words), cC, cG, cT);
+    for (uint32_t k = threadIdx.x; k < W; k += 256) word_counts(masked_packed(packed, g * W + k, n, n_words), cC, cG, cT);
     cC = wave_sum(cC), cG = wave_sum(cG), cT = wave_sum(cT);
     __shared__ uint32_t part[4][3];
     if (__lane_id() == 0) part[threadIdx.x / 64][0] = cC, part[threadIdx.x / 64][1] = cG, part[threadIdx.x / 64][2] = cT;
@@ -70,68 +79,91 @@ __global__ __launch_bounds__(256) void qr_count_kernel(const uint64_t *__restric
     if (threadIdx.x == 0) {
         uint32_t C = 0, G = 0, T = 0;
         for (int w = 0; w < 4; ++w) C += part[w][0], G += part[w][1], T += part[w][2];
-        cnt[4 * sb + 0] = (uint32_t)QR_SB_BASES - C - G - T;
-        cnt[4 * sb + 1] = C;
-        cnt[4 * sb + 2] = G;
-        cnt[4 * sb + 3] = T;
+        cnt[4 * g + 0] = GROUP_LINES * L::DATA - C - G - T;
+        cnt[4 * g + 1] = C;
+        cnt[4 * g + 2] = G;
+        cnt[4 * g + 3] = T;
     }
 }
 
-// Pass 3: one 128-lane workgroup per superblock; lane t forms line 128 i + t from packed words
-// [15 t, 15 t + 15) of the superblock.
+// Offsets of the 32-bit layout: s_{i,c} = exact rank at the first line of superblock i.
+__global__ void qr32_super_kernel(const uint64_t *__restrict__ base, uint64_t n_groups, uint64_t n_sb,
+                                  uint64_t *__restrict__ super) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr uint64_t GPS = QR32::SB_LINES / GROUP_LINES;
+    if (e < 4 * n_sb) super[e] = base[4 * std::min((e / 4) * GPS, n_groups - 1) + (e & 3)];
+}
+
+// Pass 3: one 128-lane workgroup per group; lane t forms line 128 g + t from packed words
+// [WORDS t, WORDS t + WORDS) of the group.
 constexpr int OUT_STRIDE = 17;
 
+template <class L>
 __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restrict__ packed, uint64_t n,
                                                        uint64_t n_words, const uint64_t *__restrict__ base,
                                                        uint64_t n_lines, uint64_t *__restrict__ lines) {
-    constexpr uint32_t W = QR_SB_BASES / 32;  // 1920
+    constexpr uint32_t W = GROUP_LINES * L::WORDS;
+    constexpr uint32_t FIRST = (L::MID - L::HDR) / 32;   // packed words in the lower half
+    constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
     __shared__ uint64_t in[W];
     __shared__ uint64_t stage[128 * OUT_STRIDE];
     __shared__ uint64_t wave_tot[2];
-    const uint64_t sb = blockIdx.x;
+    const uint64_t g = blockIdx.x;
     const int t = threadIdx.x;
-    for (uint32_t k = t; k < W; k += 128) in[k] = masked_packed(packed, sb * W + k, n, n_words);
+    for (uint32_t k = t; k < W; k += 128) in[k] = masked_packed(packed, g * W + k, n, n_words);
     __syncthreads();
 
-    uint32_t lo[15], hi[15];
-    uint32_t fC = 0, fG = 0, fT = 0, aC = 0, aG = 0, aT = 0;  // first-half and whole-line counts
+    uint32_t lo[L::WORDS], hi[L::WORDS];
+    uint32_t fC = 0, fG = 0, fT = 0, aC = 0, aG = 0, aT = 0;  // lower-half and whole-line counts
 #pragma unroll
-    for (int k = 0; k < 15; ++k) {
-        const uint64_t x = in[15 * t + k];
+    for (int k = 0; k < (int)L::WORDS; ++k) {
+        const uint64_t x = in[L::WORDS * t + k];
         lo[k] = even_bits(x);
         hi[k] = even_bits(x >> 1);
-        if (k < 7) word_counts(x, fC, fG, fT);
+        if (k < (int)FIRST) word_counts(x, fC, fG, fT);
         word_counts(x, aC, aG, aT);
     }
-    const uint32_t fA = 224 - fC - fG - fT, aA = 480 - aC - aG - aT;
-    // Exclusive scan of the four line totals over the 128 lines; each fits 16 bits (<= 61440), so
-    // the four are packed into one u64 and scanned together.
+    const uint32_t fA = 32 * FIRST - fC - fG - fT, aA = L::DATA - aC - aG - aT;
+    // Exclusive scan of the four line totals over the 128 lines; each stays below 2^16 over a
+    // group (<= 128 * 480), so the four are packed into one u64 and scanned together.
     const uint64_t tot = (uint64_t)aA | ((uint64_t)aC << 16) | ((uint64_t)aG << 32) | ((uint64_t)aT << 48);
     uint64_t incl = wave_inclusive_scan<uint64_t>(tot);
     if (__lane_id() == 63) wave_tot[t / 64] = incl;
     __syncthreads();
     if (t >= 64) incl += wave_tot[0];
     const uint64_t before = incl - tot;
-    const uint64_t *bs = base + 4 * sb;
-    const uint32_t m = (1u << QR_SHIFT) - 1u;
-    const uint32_t dA = (uint32_t)(bs[0] & m) + (uint32_t)(before & 0xffff) + fA;
-    const uint32_t dC = (uint32_t)(bs[1] & m) + (uint32_t)((before >> 16) & 0xffff) + fC;
-    const uint32_t dG = (uint32_t)(bs[2] & m) + (uint32_t)((before >> 32) & 0xffff) + fG;
-    const uint32_t dT = (uint32_t)(bs[3] & m) + (uint32_t)((before >> 48) & 0xffff) + fT;
+    const uint32_t first[4] = {fA, fC, fG, fT};
+    uint64_t d[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t sb_base = base[4 * ((g / GPS) * GPS) + c];
+        const uint64_t off = (sb_base >> L::SHIFT) << L::SHIFT;  // the offset the query reconstructs
+        d[c] = base[4 * g + c] - off + ((before >> (16 * c)) & 0xffffu) + first[c];
+    }
 
     uint64_t o[16];
-    o[0] = (uint64_t)(dA | (dC << 16)) | ((uint64_t)lo[0] << 32);
-    o[1] = (uint64_t)(dG | (dT << 16)) | ((uint64_t)hi[0] << 32);
+    if (L::HDR == 32) {  // deltas in the low 32 slots of pair 0, bases 0..31 in its high 32 slots
+        o[0] = (d[0] | (d[1] << 16)) | ((uint64_t)lo[0] << 32);
+        o[1] = (d[2] | (d[3] << 16)) | ((uint64_t)hi[0] << 32);
 #pragma unroll
-    for (int k = 1; k < 8; ++k) {
-        o[2 * k] = (uint64_t)lo[2 * k - 1] | ((uint64_t)lo[2 * k] << 32);
-        o[2 * k + 1] = (uint64_t)hi[2 * k - 1] | ((uint64_t)hi[2 * k] << 32);
+        for (int k = 1; k < 8; ++k) {
+            o[2 * k] = (uint64_t)lo[2 * k - 1] | ((uint64_t)lo[2 * k] << 32);
+            o[2 * k + 1] = (uint64_t)hi[2 * k - 1] | ((uint64_t)hi[2 * k] << 32);
+        }
+    } else {  // deltas fill pair 0; pair k >= 1 holds packed words 2k-2 and 2k-1
+        o[0] = d[0] | (d[1] << 32);
+        o[1] = d[2] | (d[3] << 32);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            o[2 * k] = (uint64_t)lo[2 * k - 2] | ((uint64_t)lo[2 * k - 1] << 32);
+            o[2 * k + 1] = (uint64_t)hi[2 * k - 2] | ((uint64_t)hi[2 * k - 1] << 32);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 16; ++k) stage[t * OUT_STRIDE + k] = o[k];
     __syncthreads();
-    const uint64_t l0 = sb * QR_LINES_PER_SB;
-    const uint32_t nl = (uint32_t)std::min<uint64_t>(QR_LINES_PER_SB, n_lines - l0);
+    const uint64_t l0 = g * GROUP_LINES;
+    const uint32_t nl = (uint32_t)std::min<uint64_t>(GROUP_LINES, n_lines - l0);
     uint4 *dst = reinterpret_cast<uint4 *>(lines + l0 * 16);
     for (uint32_t e = t; e < nl * 8; e += 128) {
         const uint64_t *src = stage + (e >> 3) * OUT_STRIDE + (e & 7) * 2;
@@ -140,91 +172,121 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
     }
 }
 
-template <int PER_LANE>
-__global__ __launch_bounds__(256) void qr_rank1_kernel(const uint4 *__restrict__ lines, const uint32_t *__restrict__ super,
-                                                       uint64_t n, const uint64_t *__restrict__ Q,
-                                                       const uint8_t *__restrict__ Cs, uint64_t nq,
-                                                       uint64_t *__restrict__ out, uint32_t *__restrict__ err) {
+// ---- one lane per query (lanes = 1) --------------------------------------------------------------
+template <class L>
+__device__ __forceinline__ void load_lane_half(const uint4 *__restrict__ lines, uint64_t q, PairHalf &ph, uint4 &hdr) {
+    ph.j = qline_of<L>(q);
+    const uint32_t p = (uint32_t)(q - ph.j * L::DATA) + L::HDR;
+    ph.up = p >= L::MID;
+    ph.t = ph.up ? p - L::MID : p;
+    const uint4 *H = lines + ph.j * 8 + (ph.up ? 4 : 0);
+    const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
+    ph.w[0] = a.x, ph.w[1] = a.y, ph.w[2] = a.z, ph.w[3] = a.w;
+    ph.w[4] = b.x, ph.w[5] = b.y, ph.w[6] = b.z, ph.w[7] = b.w;
+    ph.w[8] = c.x, ph.w[9] = c.y, ph.w[10] = c.z, ph.w[11] = c.w;
+    ph.w[12] = d.x, ph.w[13] = d.y, ph.w[14] = d.z, ph.w[15] = d.w;
+    hdr = ph.up ? lines[ph.j * 8] : a;
+}
+
+template <class L, int PER_LANE>
+__global__ __launch_bounds__(256) void qr_rank1_kernel(const uint4 *__restrict__ lines,
+                                                       const typename L::Super *__restrict__ super, uint64_t n,
+                                                       const uint64_t *__restrict__ Q, const uint8_t *__restrict__ Cs,
+                                                       uint64_t nq, uint64_t *__restrict__ out,
+                                                       uint32_t *__restrict__ err) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nq; i0 += stride * PER_LANE) {
-        uint64_t q[PER_LANE];
+        uint64_t q[PER_LANE], off[PER_LANE], r[PER_LANE];
         uint32_t c[PER_LANE];
         bool bad[PER_LANE];
-        HalfLine hl[PER_LANE];
+        PairHalf ph[PER_LANE];
+        uint4 hdr[PER_LANE];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            const uint64_t i = i0 + u * stride;
-            q[u] = i < nq ? Q[i] : 0;
-            c[u] = i < nq ? Cs[i] : 0;
-            bad[u] = q[u] > n || c[u] > 3;
-            if (bad[u]) q[u] = 0, c[u] = 0;
+            const uint64_t i = min(i0 + u * stride, nq - 1);
+            q[u] = Q[i];
+            c[u] = Cs[i];
         }
 #pragma unroll
-        for (int u = 0; u < PER_LANE; ++u) load_half(lines, super, q[u], hl[u]);
+        for (int u = 0; u < PER_LANE; ++u) {
+            bad[u] = q[u] > n || c[u] > 3;
+            load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u]);
+            off[u] = L::offset1(super, ph[u].j, c[u] & 3u);
+        }
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) {
+            const uint32_t cc = c[u] & 3u;
+            const uint32_t cnt = pair_count1(ph[u], (uint32_t)ph[u].up, cc);
+            const uint64_t mid = off[u] + L::delta(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc);
+            r[u] = bad[u] ? ~0ull : (ph[u].up ? mid + cnt : mid - cnt);
+        }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const uint64_t i = i0 + u * stride;
-            if (i >= nq) continue;
-            uint64_t r = rank1_from_half(hl[u], c[u]);
-            if (bad[u]) {
-                r = ~0ull;
-                atomicOr(err, 1u);
+            if (i < nq) {
+                out[i] = r[u];
+                if (bad[u]) atomicOr(err, 1u);
             }
-            out[i] = r;
         }
     }
 }
 
-template <int PER_LANE>
-__global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__ lines, const uint32_t *__restrict__ super,
-                                                       uint64_t n, const uint64_t *__restrict__ Q, uint64_t nq,
+template <class L, int PER_LANE>
+__global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__ lines,
+                                                       const typename L::Super *__restrict__ super, uint64_t n,
+                                                       const uint64_t *__restrict__ Q, uint64_t nq,
                                                        uint64_t *__restrict__ out4, uint32_t *__restrict__ err) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nq; i0 += stride * PER_LANE) {
         uint64_t q[PER_LANE];
         bool bad[PER_LANE];
-        HalfLine hl[PER_LANE];
+        PairHalf ph[PER_LANE];
+        uint4 hdr[PER_LANE];
+        uint64_t off[PER_LANE][4];
+#pragma unroll
+        for (int u = 0; u < PER_LANE; ++u) q[u] = Q[min(i0 + u * stride, nq - 1)];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            const uint64_t i = i0 + u * stride;
-            q[u] = i < nq ? Q[i] : 0;
             bad[u] = q[u] > n;
-            if (bad[u]) q[u] = 0;
+            load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u]);
+            L::offset4(super, ph[u].j, off[u]);
         }
 #pragma unroll
-        for (int u = 0; u < PER_LANE; ++u) load_half(lines, super, q[u], hl[u]);
-#pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            const uint64_t i = i0 + u * stride;
-            if (i >= nq) continue;
+            uint32_t cnt[4];
+            pair_count4(ph[u], (uint32_t)ph[u].up, cnt);
             uint64_t r[4];
-            rank4_from_half(hl[u], r);
-            if (bad[u]) {
-                r[0] = r[1] = r[2] = r[3] = ~0ull;
-                atomicOr(err, 1u);
+#pragma unroll
+            for (uint32_t cc = 0; cc < 4; ++cc) {
+                const uint64_t mid = off[u][cc] + L::delta(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc);
+                r[cc] = bad[u] ? ~0ull : (ph[u].up ? mid + cnt[cc] : mid - cnt[cc]);
             }
-            ulonglong2 *o = reinterpret_cast<ulonglong2 *>(out4 + 4 * i);
-            o[0] = make_ulonglong2(r[0], r[1]);
-            o[1] = make_ulonglong2(r[2], r[3]);
+            const uint64_t i = i0 + u * stride;
+            if (i < nq) {
+                ulonglong2 *o = reinterpret_cast<ulonglong2 *>(out4 + 4 * i);
+                o[0] = make_ulonglong2(r[0], r[1]);
+                o[1] = make_ulonglong2(r[2], r[3]);
+                if (bad[u]) atomicOr(err, 1u);
+            }
         }
     }
 }
 
-// Lane-pair kernels (default): lanes 2k, 2k+1 serve one query, lane hf loading half hf of the line
-// (64 contiguous bytes), so each wave load instruction touches 32 lines.  The lane holding q's half
-// counts; lane 0 adds offset and delta; the two contributions are summed across the pair.
-template <int PER_PAIR>
+// ---- lane pairs (default) --------------------------------------------------------------------------
+// Lanes 2k, 2k+1 serve one query, lane hf loading half hf of the line (64 contiguous bytes), so each
+// wave load instruction touches 32 lines.  The lane holding q's half counts; lane 0 adds offset and
+// delta; the two contributions are summed across the pair.
+template <class L, int PER_PAIR>
 __global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restrict__ lines,
-                                                            const uint32_t *__restrict__ super, uint64_t n,
+                                                            const typename L::Super *__restrict__ super, uint64_t n,
                                                             const uint64_t *__restrict__ Q,
                                                             const uint8_t *__restrict__ Cs, uint64_t nq,
                                                             uint64_t *__restrict__ out, uint32_t *__restrict__ err) {
     const uint32_t hf = threadIdx.x & 1u;
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
-        uint64_t q[PER_PAIR], r[PER_PAIR];
+        uint64_t q[PER_PAIR], r[PER_PAIR], off[PER_PAIR];
         uint32_t c[PER_PAIR];
-        uint4 s[PER_PAIR];
         bool bad[PER_PAIR];
         PairHalf ph[PER_PAIR];
 #pragma unroll
@@ -236,14 +298,15 @@ __global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restr
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             bad[u] = q[u] > n || c[u] > 3;
-            load_pair_half(lines, bad[u] ? 0 : q[u], hf, ph[u]);
-            s[u] = reinterpret_cast<const uint4 *>(super)[ph[u].j / QR_LINES_PER_SB];
+            load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
+            off[u] = L::offset1(super, ph[u].j, c[u] & 3u);
         }
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint32_t cc = c[u] & 3u;
             const uint32_t cnt = pair_count1(ph[u], hf, cc);
-            const uint64_t mine = hf == 0 ? ((uint64_t)sel4(s[u], cc) << QR_SHIFT) + pair_delta(ph[u], cc) - cnt : (uint64_t)cnt;
+            const uint64_t mine =
+                hf == 0 ? off[u] + L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc) - cnt : (uint64_t)cnt;
             r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
         }
 #pragma unroll
@@ -257,16 +320,16 @@ __global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restr
     }
 }
 
-template <int PER_PAIR>
+template <class L, int PER_PAIR>
 __global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restrict__ lines,
-                                                            const uint32_t *__restrict__ super, uint64_t n,
+                                                            const typename L::Super *__restrict__ super, uint64_t n,
                                                             const uint64_t *__restrict__ Q, uint64_t nq,
                                                             uint64_t *__restrict__ out4, uint32_t *__restrict__ err) {
     const uint32_t hf = threadIdx.x & 1u;
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
         uint64_t q[PER_PAIR], ra[PER_PAIR], rb[PER_PAIR];
-        uint4 s[PER_PAIR];
+        uint64_t off[PER_PAIR][4];
         bool bad[PER_PAIR];
         PairHalf ph[PER_PAIR];
 #pragma unroll
@@ -274,8 +337,8 @@ __global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restr
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             bad[u] = q[u] > n;
-            load_pair_half(lines, bad[u] ? 0 : q[u], hf, ph[u]);
-            s[u] = reinterpret_cast<const uint4 *>(super)[ph[u].j / QR_LINES_PER_SB];
+            load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
+            L::offset4(super, ph[u].j, off[u]);
         }
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
@@ -284,8 +347,9 @@ __global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restr
             uint64_t r[4];
 #pragma unroll
             for (uint32_t cc = 0; cc < 4; ++cc) {
-                const uint64_t mine = hf == 0 ? ((uint64_t)sel4(s[u], cc) << QR_SHIFT) + pair_delta(ph[u], cc) - cnt[cc]
-                                              : (uint64_t)cnt[cc];
+                const uint64_t mine =
+                    hf == 0 ? off[u][cc] + L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc) - cnt[cc]
+                            : (uint64_t)cnt[cc];
                 r[cc] = mine + pair_swap64(mine);
             }
             // lane 0 writes symbols A, C and lane 1 writes G, T of the row
@@ -317,32 +381,109 @@ uint64_t grid_for(uint64_t nq, int pl, int block, int grid_waves, int lanes) {
     return std::max<uint64_t>(1, std::min<uint64_t>(blocks, 0x7fffffffull));
 }
 
-}  // namespace
-
-namespace qr {
-
-// Build the QuadRank layout into caller-provided arrays (also used by the FM-index build).
-int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, uint32_t *super, hipStream_t stream) {
-    const uint64_t n_lines = n / QR_DATA_BASES + 1, n_sb = n / QR_SB_BASES + 1, n_words = (n + 31) / 32;
+template <class L>
+hipError_t build_t(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, void *super, hipStream_t stream) {
+    const uint64_t n_lines = n / L::DATA + 1, n_sb = (n_lines - 1) / L::SB_LINES + 1;
+    const uint64_t n_groups = (n_lines - 1) / GROUP_LINES + 1, n_words = (n + 31) / 32;
     uint32_t *cnt = nullptr;
     uint64_t *base = nullptr;
-    if (hipMalloc(&cnt, n_sb * 16) != hipSuccess || hipMalloc(&base, n_sb * 32) != hipSuccess) {
+    if (hipMalloc(&cnt, n_groups * 16) != hipSuccess || hipMalloc(&base, n_groups * 32) != hipSuccess) {
         (void)hipGetLastError();
         if (cnt) (void)hipFree(cnt);
-        set_error("quadrank build: temporary allocation failed");
-        return QR_ENOMEM;
+        return hipErrorOutOfMemory;
     }
-    hipLaunchKernelGGL(qr_count_kernel, dim3((uint32_t)n_sb), dim3(256), 0, stream, d_packed2, n, n_words, cnt);
+    hipLaunchKernelGGL(qr_count_kernel<L>, dim3((uint32_t)n_groups), dim3(256), 0, stream, d_packed2, n, n_words, cnt);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = launch_scan_counts(cnt, n_sb, 4, QR_SHIFT, base, super, stream);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(qr_write_kernel, dim3((uint32_t)n_sb), dim3(128), 0, stream, d_packed2, n, n_words, base,
+        if (L::SHIFT) {
+            e = launch_scan_counts(cnt, n_groups, 4, L::SHIFT, base, reinterpret_cast<uint32_t *>(super), stream);
+        } else {
+            e = launch_scan_counts(cnt, n_groups, 4, 0, base, nullptr, stream);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(qr32_super_kernel, dim3((uint32_t)((4 * n_sb + 255) / 256)), dim3(256), 0, stream, base,
+                                   n_groups, n_sb, reinterpret_cast<uint64_t *>(super));
+                e = hipGetLastError();
+            }
+        }
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(qr_write_kernel<L>, dim3((uint32_t)n_groups), dim3(128), 0, stream, d_packed2, n, n_words, base,
                            n_lines, lines);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     (void)hipFree(cnt);
     (void)hipFree(base);
+    return e;
+}
+
+template <class L>
+int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out, hipStream_t s) {
+    const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
+    const int lanes = h->tune.lanes == 1 ? 1 : 2;
+    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
+    const uint4 *Ln = reinterpret_cast<const uint4 *>(h->lines);
+    const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
+#define QR_RANK1(K, P) hipLaunchKernelGGL((K<L, P>), g, b, 0, s, Ln, S, h->n, d_q, d_c, nq, d_out, h->err)
+    if (lanes == 2) {
+        switch (pl) {
+            case 1: QR_RANK1(qr_rank1_pair_kernel, 1); break;
+            case 2: QR_RANK1(qr_rank1_pair_kernel, 2); break;
+            case 4: QR_RANK1(qr_rank1_pair_kernel, 4); break;
+            default: QR_RANK1(qr_rank1_pair_kernel, 8); break;
+        }
+    } else {
+        switch (pl) {
+            case 1: QR_RANK1(qr_rank1_kernel, 1); break;
+            case 2: QR_RANK1(qr_rank1_kernel, 2); break;
+            case 4: QR_RANK1(qr_rank1_kernel, 4); break;
+            default: QR_RANK1(qr_rank1_kernel, 8); break;
+        }
+    }
+#undef QR_RANK1
+    QR_HIP(hipGetLastError());
+    return QR_OK;
+}
+
+template <class L>
+int launch_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t s) {
+    const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
+    const int lanes = h->tune.lanes == 1 ? 1 : 2;
+    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
+    const uint4 *Ln = reinterpret_cast<const uint4 *>(h->lines);
+    const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
+#define QR_RANK4(K, P) hipLaunchKernelGGL((K<L, P>), g, b, 0, s, Ln, S, h->n, d_q, nq, d_out4, h->err)
+    if (lanes == 2) {
+        switch (pl) {
+            case 1: QR_RANK4(qr_rank4_pair_kernel, 1); break;
+            case 2: QR_RANK4(qr_rank4_pair_kernel, 2); break;
+            case 4: QR_RANK4(qr_rank4_pair_kernel, 4); break;
+            default: QR_RANK4(qr_rank4_pair_kernel, 8); break;
+        }
+    } else {
+        switch (pl) {
+            case 1: QR_RANK4(qr_rank4_kernel, 1); break;
+            case 2: QR_RANK4(qr_rank4_kernel, 2); break;
+            case 4: QR_RANK4(qr_rank4_kernel, 4); break;
+            default: QR_RANK4(qr_rank4_kernel, 8); break;
+        }
+    }
+#undef QR_RANK4
+    QR_HIP(hipGetLastError());
+    return QR_OK;
+}
+
+}  // namespace
+
+namespace qr {
+
+// Build the 16-bit QuadRank layout into caller-provided arrays (used by the FM-index build).
+int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, uint32_t *super, hipStream_t stream) {
+    hipError_t e = build_t<QR16>(d_packed2, n, lines, super, stream);
+    if (e == hipErrorOutOfMemory) {
+        set_error("quadrank build: temporary allocation failed");
+        return QR_ENOMEM;
+    }
     if (e != hipSuccess) {
         set_error("quadrank build: %s", hipGetErrorString(e));
         return QR_EHIP;
@@ -354,18 +495,25 @@ int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, 
 
 extern "C" {
 
-int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr_quadrank *out) {
+int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStream_t stream, qr_quadrank *out) {
     if (!out) {
         set_error("quadrank_build: out is NULL");
         return QR_EINVAL;
     }
     *out = nullptr;
     if (((uintptr_t)d_packed2 & 7) || (!d_packed2 && n)) {
-        set_error("quadrank_build: d_packed2 is NULL with n = %llu", (unsigned long long)n);
+        set_error("quadrank_build: d_packed2 is NULL (with n = %llu) or not 8-byte aligned", (unsigned long long)n);
         return QR_EINVAL;
     }
-    if (n > QR_MAX_N) {
-        set_error("quadrank_build: n = %llu exceeds the layout limit 2^44 - 1", (unsigned long long)n);
+    if (layout != QR_LAYOUT_16 && layout != QR_LAYOUT_32) {
+        set_error("quadrank_build: unknown layout %d", layout);
+        return QR_EINVAL;
+    }
+    const bool l32 = layout == QR_LAYOUT_32;
+    const uint64_t max_n = l32 ? QR32::MAX_N : QR16::MAX_N;
+    if (n > max_n) {
+        set_error("quadrank_build: n = %llu exceeds the layout limit %llu", (unsigned long long)n,
+                  (unsigned long long)max_n);
         return QR_ERANGE;
     }
     qr_quadrank_s *h = new (std::nothrow) qr_quadrank_s{};
@@ -374,15 +522,17 @@ int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr
         delete h;
         return QR_EHIP;
     }
+    h->layout = layout;
     h->n = n;
-    h->n_lines = n / QR_DATA_BASES + 1;
-    h->n_sb = n / QR_SB_BASES + 1;
+    h->n_lines = n / (l32 ? QR32::DATA : QR16::DATA) + 1;
+    h->n_sb = (h->n_lines - 1) / (l32 ? QR32::SB_LINES : QR16::SB_LINES) + 1;
     h->tune = qr_tuning{256, 1, 0, 2};
-    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 16) != hipSuccess ||
+    const size_t super_bytes = h->n_sb * 4 * (l32 ? 8 : 4);
+    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, super_bytes) != hipSuccess ||
         hipMalloc(&h->err, 4) != hipSuccess) {
         (void)hipGetLastError();
         set_error("quadrank_build: device allocation of %llu bytes failed",
-                  (unsigned long long)(h->n_lines * 128 + h->n_sb * 16));
+                  (unsigned long long)(h->n_lines * 128 + super_bytes));
         release(h);
         return QR_ENOMEM;
     }
@@ -390,13 +540,19 @@ int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr
         release(h);
         return QR_EHIP;
     }
-    int rc = quadrank_build_into(d_packed2, n, h->lines, h->super, stream);
-    if (rc) {
+    const hipError_t e = l32 ? build_t<QR32>(d_packed2, n, h->lines, h->super, stream)
+                             : build_t<QR16>(d_packed2, n, h->lines, h->super, stream);
+    if (e != hipSuccess) {
+        set_error("quadrank_build: %s", hipGetErrorString(e));
         release(h);
-        return rc;
+        return e == hipErrorOutOfMemory ? QR_ENOMEM : QR_EHIP;
     }
     *out = h;
     return QR_OK;
+}
+
+int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr_quadrank *out) {
+    return quadrank_build_ex(d_packed2, n, QR_LAYOUT_16, stream, out);
 }
 
 static int qr_launch_common(qr_quadrank h, uint64_t nq, const void *a, const void *b, const char *what) {
@@ -420,56 +576,16 @@ int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64
         return QR_EINVAL;
     }
     if (!nq) return QR_OK;
-    const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
-    const int lanes = h->tune.lanes == 1 ? 1 : 2;
-    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
-    const uint4 *L = reinterpret_cast<const uint4 *>(h->lines);
-    if (lanes == 2) {
-        switch (pl) {
-            case 1: hipLaunchKernelGGL(qr_rank1_pair_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-            case 2: hipLaunchKernelGGL(qr_rank1_pair_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-            case 4: hipLaunchKernelGGL(qr_rank1_pair_kernel<4>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-            default: hipLaunchKernelGGL(qr_rank1_pair_kernel<8>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-        }
-        QR_HIP(hipGetLastError());
-        return QR_OK;
-    }
-    switch (pl) {
-        case 1: hipLaunchKernelGGL(qr_rank1_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-        case 2: hipLaunchKernelGGL(qr_rank1_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-        case 4: hipLaunchKernelGGL(qr_rank1_kernel<4>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-        default: hipLaunchKernelGGL(qr_rank1_kernel<8>, g, b, 0, stream, L, h->super, h->n, d_q, d_c, nq, d_out, h->err); break;
-    }
-    QR_HIP(hipGetLastError());
-    return QR_OK;
+    return h->layout == QR_LAYOUT_32 ? launch_rank1<QR32>(h, d_q, d_c, nq, d_out, stream)
+                                     : launch_rank1<QR16>(h, d_q, d_c, nq, d_out, stream);
 }
 
 int quadrank_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t stream) {
     int rc = qr_launch_common(h, nq, d_q, d_out4, "quadrank_rank4");
     if (rc) return rc;
     if (!nq) return QR_OK;
-    const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
-    const int lanes = h->tune.lanes == 1 ? 1 : 2;
-    const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
-    const uint4 *L = reinterpret_cast<const uint4 *>(h->lines);
-    if (lanes == 2) {
-        switch (pl) {
-            case 1: hipLaunchKernelGGL(qr_rank4_pair_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-            case 2: hipLaunchKernelGGL(qr_rank4_pair_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-            case 4: hipLaunchKernelGGL(qr_rank4_pair_kernel<4>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-            default: hipLaunchKernelGGL(qr_rank4_pair_kernel<8>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-        }
-        QR_HIP(hipGetLastError());
-        return QR_OK;
-    }
-    switch (pl) {
-        case 1: hipLaunchKernelGGL(qr_rank4_kernel<1>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-        case 2: hipLaunchKernelGGL(qr_rank4_kernel<2>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-        case 4: hipLaunchKernelGGL(qr_rank4_kernel<4>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-        default: hipLaunchKernelGGL(qr_rank4_kernel<8>, g, b, 0, stream, L, h->super, h->n, d_q, nq, d_out4, h->err); break;
-    }
-    QR_HIP(hipGetLastError());
-    return QR_OK;
+    return h->layout == QR_LAYOUT_32 ? launch_rank4<QR32>(h, d_q, nq, d_out4, stream)
+                                     : launch_rank4<QR16>(h, d_q, nq, d_out4, stream);
 }
 
 int quadrank_check(qr_quadrank h, hipStream_t stream) {
@@ -493,7 +609,10 @@ int quadrank_free(qr_quadrank h) {
 }
 
 uint64_t quadrank_len(qr_quadrank h) { return h ? h->n : 0; }
-uint64_t quadrank_bytes(qr_quadrank h) { return h ? h->n_lines * 128 + h->n_sb * 16 : 0; }
+uint64_t quadrank_bytes(qr_quadrank h) {
+    return h ? h->n_lines * 128 + h->n_sb * 4 * (h->layout == QR_LAYOUT_32 ? 8 : 4) : 0;
+}
+int quadrank_layout_kind(qr_quadrank h) { return h ? h->layout : -1; }
 
 int quadrank_layout(qr_quadrank h, const void **d_lines, uint64_t *n_lines, const void **d_super,
                     uint64_t *n_super) {
@@ -510,7 +629,8 @@ int quadrank_export(qr_quadrank h, void *h_lines, void *h_super) {
     int rc = check_device(h->device);
     if (rc) return rc;
     if (h_lines) QR_HIP(hipMemcpy(h_lines, h->lines, h->n_lines * 128, hipMemcpyDeviceToHost));
-    if (h_super) QR_HIP(hipMemcpy(h_super, h->super, h->n_sb * 16, hipMemcpyDeviceToHost));
+    if (h_super)
+        QR_HIP(hipMemcpy(h_super, h->super, h->n_sb * 4 * (h->layout == QR_LAYOUT_32 ? 8 : 4), hipMemcpyDeviceToHost));
     return QR_OK;
 }
 

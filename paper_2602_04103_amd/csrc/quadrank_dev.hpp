@@ -98,6 +98,65 @@ __device__ __forceinline__ void rank4_from_half(const HalfLine &hl, uint64_t (&r
     }
 }
 
+// ---- layouts -------------------------------------------------------------------------------------
+// QR16: four 16-bit deltas in slots [0,32) (lo_0 low half = A | C << 16, hi_0 low half = G | T << 16),
+//       480 bases, 128 lines per superblock, offsets s = floor(rank / 2^12) as u32.
+// QR32: four 32-bit deltas in slots [0,64) (lo_0 = A | C << 32, hi_0 = G | T << 32), 448 bases,
+//       2^23 lines per superblock, exact u64 offsets.  floor(x/448) = mulhi(x, ceil(2^72/448)) >> 8,
+//       exact for x < 2^63 (e = 384 < 448).
+struct QR16 {
+    static constexpr uint32_t HDR = 32, DATA = 480, MID = 256, WORDS = 15;
+    static constexpr uint64_t SB_LINES = 128;
+    static constexpr uint32_t SB_LOG = 7, SHIFT = 12;
+    static constexpr uint64_t MAGIC = QR_MAGIC;
+    static constexpr uint32_t MAGIC_T = QR_MAGIC_T;
+    static constexpr uint64_t MAX_N = (1ull << 44) - 1;
+    using Super = uint32_t;
+    // delta of symbol c from the line's first four u32 words
+    __device__ __forceinline__ static uint32_t delta(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t c) {
+        (void)w1, (void)w3;
+        const uint32_t m2 = 0u - ((c >> 1) & 1u);
+        const uint32_t d = (w0 & ~m2) | (w2 & m2);
+        return (d >> (16u * (c & 1u))) & 0xffffu;
+    }
+    __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__ s, uint64_t j, uint32_t c) {
+        return (uint64_t)sel4(reinterpret_cast<const uint4 *>(s)[j >> SB_LOG], c) << SHIFT;
+    }
+    __device__ __forceinline__ static void offset4(const Super *__restrict__ s, uint64_t j, uint64_t (&o)[4]) {
+        const uint4 v = reinterpret_cast<const uint4 *>(s)[j >> SB_LOG];
+        o[0] = (uint64_t)v.x << SHIFT, o[1] = (uint64_t)v.y << SHIFT, o[2] = (uint64_t)v.z << SHIFT,
+        o[3] = (uint64_t)v.w << SHIFT;
+    }
+};
+
+struct QR32 {
+    static constexpr uint32_t HDR = 64, DATA = 448, MID = 256, WORDS = 14;
+    static constexpr uint64_t SB_LINES = 1ull << 23;
+    static constexpr uint32_t SB_LOG = 23, SHIFT = 0;
+    static constexpr uint64_t MAGIC = 0x924924924924924aull;  // ceil(2^72 / 448)
+    static constexpr uint32_t MAGIC_T = 8;
+    static constexpr uint64_t MAX_N = (1ull << 48) - 1;
+    using Super = uint64_t;
+    __device__ __forceinline__ static uint32_t delta(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t c) {
+        const uint32_t m1 = 0u - (c & 1u), m2 = 0u - ((c >> 1) & 1u);
+        const uint32_t lo = (w0 & ~m1) | (w1 & m1), hi = (w2 & ~m1) | (w3 & m1);
+        return (lo & ~m2) | (hi & m2);
+    }
+    __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__ s, uint64_t j, uint32_t c) {
+        return s[4 * (j >> SB_LOG) + (c & 3u)];
+    }
+    __device__ __forceinline__ static void offset4(const Super *__restrict__ s, uint64_t j, uint64_t (&o)[4]) {
+        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(s + 4 * (j >> SB_LOG));
+        const ulonglong2 a = p[0], b = p[1];
+        o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+    }
+};
+
+template <class L>
+__host__ __device__ __forceinline__ uint64_t qline_of(uint64_t q) {
+    return mulhi64(q, L::MAGIC) >> L::MAGIC_T;
+}
+
 // ---- lane-pair form: lane hf (0/1) of a pair holds half hf of the line -------------------------
 struct PairHalf {
     uint32_t w[16];  // half hf of the line, same word order as HalfLine::w
@@ -106,11 +165,12 @@ struct PairHalf {
     uint64_t j;      // line index
 };
 
+template <class L>
 __device__ __forceinline__ void load_pair_half(const uint4 *__restrict__ lines, uint64_t q, uint32_t hf, PairHalf &ph) {
-    ph.j = qr_line_of(q);
-    const uint32_t p = (uint32_t)(q - ph.j * QR_DATA_BASES) + QR_HDR;
-    ph.up = p >= QR_MID;
-    ph.t = ph.up ? p - QR_MID : p;
+    ph.j = qline_of<L>(q);
+    const uint32_t p = (uint32_t)(q - ph.j * L::DATA) + L::HDR;
+    ph.up = p >= L::MID;
+    ph.t = ph.up ? p - L::MID : p;
     const uint4 *H = lines + ph.j * 8 + hf * 4;
     const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
     ph.w[0] = a.x, ph.w[1] = a.y, ph.w[2] = a.z, ph.w[3] = a.w;
@@ -159,13 +219,6 @@ __device__ __forceinline__ void pair_count4(const PairHalf &ph, uint32_t hf, uin
     cnt[1] = cL - cT;
     cnt[2] = cH - cT;
     cnt[3] = cT;
-}
-
-// Delta b_{j,c} from lane 0's half (pair 0 low words).
-__device__ __forceinline__ uint32_t pair_delta(const PairHalf &ph, uint32_t c) {
-    const uint32_t m2 = 0u - ((c >> 1) & 1u);
-    const uint32_t d = (ph.w[0] & ~m2) | (ph.w[2] & m2);
-    return (d >> (16u * (c & 1u))) & 0xffffu;
 }
 
 }  // namespace qr

@@ -3,7 +3,8 @@
 //
 // Counts are `ncol` interleaved u32 columns (1 for BiRank, 4 for QuadRank).  The pass writes
 //   base[i*ncol + c] = sum_{k < i} cnt[k*ncol + c]            (u64, kept for pass 3)
-//   super[i*ncol + c] = base[i*ncol + c] >> shift             (u32, the shifted superblock offset)
+//   super[i*ncol + c] = base[i*ncol + c] >> shift             (u32, the shifted superblock offset;
+//                                                              skipped when super is null)
 // A single workgroup handles any length: the rows are split into 1024 contiguous chunks, each
 // thread reduces its chunk, the chunk totals are scanned in LDS and each thread then rewrites
 // its chunk.  Superblock arrays are small (about 1e6 rows at 2^36 bits) so one CU suffices.
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_counts_kernel(const uint32_
         uint64_t run = before + incl - local;
         for (uint64_t r = r0; r < r1; ++r) {
             base[r * ncol + c] = run;
-            super[r * ncol + c] = (uint32_t)(run >> shift);
+            if (super) super[r * ncol + c] = (uint32_t)(run >> shift);
             run += cnt[r * ncol + c];
         }
         __syncthreads();

@@ -156,3 +156,24 @@ def test_fm_config3_full_sampled():
     want = oracle.count_naive(codes, spat, soff).astype(np.uint32)
     assert np.array_equal(got[sample], want)
     assert got.max() <= n
+
+
+@pytest.mark.parametrize("n", [3, 5000, 200_000])
+def test_fm_both_strands(n):
+    """count(P) + count(reverse complement of P), persistent and per-batch kernels."""
+    qr = require_gpu()
+    codes = make_text(600 + n, n)
+    pats = edge_patterns(codes, 11 * n)
+    sp, so, _ = datagen.patterns(n + 7, codes, 5000, minlen=1, maxlen=60, frac_sampled=0.8, sub=0.02)
+    pats += [sp[int(so[i]):int(so[i + 1])] for i in range(so.size - 1)]
+    pats += [oracle.revcomp(p) for p in pats[:50]]                 # palindromic and mirrored cases
+    pat, off = csr(pats)
+    announce("fm-both-strands", n, len(pats))
+    fm = qr.QuadFm.from_text(codes)
+    sa = oracle.suffix_array(codes)
+    want = oracle.count_both_strands(codes, sa, pat, off).astype(np.uint32)
+    dp, do = to_dev(pat), to_dev(off)
+    got = fm.count(dp, do, both_strands=True).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+    got_b = fm.count_batched(dp, do, 777, both_strands=True).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got_b, want)

@@ -17,30 +17,47 @@ BENCH_TUNINGS = [dict(lanes=2, per_lane=2, block=256, grid_waves=0), dict(lanes=
                  dict(lanes=2, per_lane=8, block=256, grid_waves=8), dict(lanes=2, per_lane=1, block=128, grid_waves=0)]
 
 
+def boundary_queries(n, sb, line, mid):
+    """Positions around every superblock start of a layout (and line middles next to it)."""
+    pts = set()
+    for k in range(1, n // sb + 1):
+        for d in (-1, 0, 1, mid - 1, mid, mid + 1, line - 1, line, -line):
+            pts.add(k * sb + d)
+    return np.array(sorted(x for x in pts if 0 <= x <= n), dtype=np.uint64)
+
+
 @pytest.mark.parametrize("p,seed", [(0.5, 3636), (0.05, 3637)])
 def test_birank_2e36(p, seed):
+    """Both layouts: the 16-bit one (superblocks of 64 lines) and the 32-bit one, whose 2^22-line
+    superblocks are crossed 16 times at this size."""
     qr = require_gpu()
     n = 1 << 36
     bits = datagen.bits(seed, n, p)
-    announce("birank 2^36", p)
-    h = qr.BiRank(to_dev(bits), n)
     total = int(np.unpackbits(bits.view(np.uint8)).sum(dtype=np.int64))
     q = datagen.queries(seed + 100, n, BATCH)
-    q[:4] = [0, n, n - 1, 1 << 35]
+    fixed = np.concatenate([np.array([0, n, n - 1, 1 << 35], np.uint64), boundary_queries(n, (1 << 22) * 992, 992, 480),
+                            boundary_queries(min(n, 64 * 64512 * 3), 64 * 1008, 1008, 496)])
+    q[:fixed.size] = fixed
     dq = to_dev(q)
     rng = np.random.default_rng(seed)
-    sample = rng.choice(BATCH, 1_000_000, replace=False)
+    sample = np.union1d(rng.choice(BATCH, 1_000_000, replace=False), np.arange(fixed.size))
     want = oracle.rank_bits(bits, n, q[sample])
-    for tune in BENCH_TUNINGS:
-        h.set_tuning(**tune)
-        got = to_host_u64(h.rank(dq))
-        assert np.array_equal(got[sample], want), tune
-        assert got[1] == total and got[0] == 0
-        assert np.all(got <= q)                                  # at most q ones before q
-    h.check()
+    for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32):
+        announce("birank 2^36", p, "layout", layout)
+        h = qr.BiRank(to_dev(bits), n, layout=layout)
+        for tune in BENCH_TUNINGS:
+            h.set_tuning(**tune)
+            got = to_host_u64(h.rank(dq))
+            assert np.array_equal(got[sample], want), (layout, tune)
+            assert got[1] == total and got[0] == 0
+            assert np.all(got <= q)                              # at most q ones before q
+        h.check()
+        del h
+        torch.cuda.empty_cache()
 
 
 def test_quadrank_2e32_with_repeats():
+    """Both layouts; the 32-bit one has its superblock boundary at 2^23 lines = 3758096384 bases."""
     qr = require_gpu()
     n = 1 << 32
     codes = datagen.dna_codes(3202, n)
@@ -48,23 +65,27 @@ def test_quadrank_2e32_with_repeats():
     hist = np.bincount(codes, minlength=4).astype(np.uint64)
     packed = datagen.pack2(codes)
     del codes
-    announce("quadrank 2^32")
-    h = qr.QuadRank(to_dev(packed), n)
     q = datagen.queries(3204, n, BATCH)
-    q[:2] = [n, 0]
+    fixed = np.concatenate([np.array([n, 0], np.uint64), boundary_queries(n, (1 << 23) * 448, 448, 192)])
+    q[:fixed.size] = fixed
     c = datagen.symbols(3205, BATCH)
     dq, dc = to_dev(q), to_dev(c)
     rng = np.random.default_rng(5)
-    sample = rng.choice(BATCH, 1_000_000, replace=False)
+    sample = np.union1d(rng.choice(BATCH, 1_000_000, replace=False), np.arange(fixed.size))
     want1 = oracle.rank_dna(packed, n, q[sample], c[sample])
     want4 = oracle.rank4_dna(packed, n, q[sample])
-    for tune in BENCH_TUNINGS:
-        h.set_tuning(**tune)
-        got1 = to_host_u64(h.rank(dq, dc))
-        got4 = to_host_u64(h.rank4(dq)).reshape(-1, 4)
-        assert np.array_equal(got1[sample], want1), tune
-        assert np.array_equal(got4[sample], want4), tune
-        assert np.array_equal(got4.sum(axis=1), q)               # sum over symbols = q
-        assert np.array_equal(got4[0], hist)                     # rank4(n) = histogram
-        assert np.array_equal(got1, got4[np.arange(BATCH), c.astype(np.int64)])
-    h.check()
+    for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32):
+        announce("quadrank 2^32 layout", layout)
+        h = qr.QuadRank(to_dev(packed), n, layout=layout)
+        for tune in BENCH_TUNINGS:
+            h.set_tuning(**tune)
+            got1 = to_host_u64(h.rank(dq, dc))
+            got4 = to_host_u64(h.rank4(dq)).reshape(-1, 4)
+            assert np.array_equal(got1[sample], want1), (layout, tune)
+            assert np.array_equal(got4[sample], want4), (layout, tune)
+            assert np.array_equal(got4.sum(axis=1), q)           # sum over symbols = q
+            assert np.array_equal(got4[0], hist)                 # rank4(n) = histogram
+            assert np.array_equal(got1, got4[np.arange(BATCH), c.astype(np.int64)])
+        h.check()
+        del h
+        torch.cuda.empty_cache()

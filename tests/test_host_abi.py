@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_line_division_is_exact():
     import paper_2602_04103_amd as qr
     rng = np.random.default_rng(1)
-    for which, d, limit in ((0, 1008, 1 << 42), (1, 480, 1 << 44)):
+    for which, d, limit in ((0, 1008, 1 << 42), (1, 480, 1 << 44), (2, 992, 1 << 48), (3, 448, 1 << 48)):
         xs = list(range(0, 5000)) + [int(x) for x in rng.integers(0, limit, 20000, dtype=np.int64)]
         for k in (1, 2, 63, 64, 127, 128, (limit // d) - 1, (1 << 40) // d, (1 << 62) // d):
             xs += [k * d - 1, k * d, k * d + 1]
@@ -53,6 +53,11 @@ def test_host_argument_validation():
     assert L.birank_build(fake, 10, None, None) == qr.QR_EINVAL
     assert L.quadrank_build(None, 5, None, C.byref(h)) == qr.QR_EINVAL
     assert L.quadrank_build(fake, (1 << 44), None, C.byref(h)) == qr.QR_ERANGE
+    assert L.birank_build_ex(fake, (1 << 48), qr.QR_LAYOUT_32, None, C.byref(h)) == qr.QR_ERANGE
+    assert L.quadrank_build_ex(fake, (1 << 48), qr.QR_LAYOUT_32, None, C.byref(h)) == qr.QR_ERANGE
+    assert L.birank_build_ex(fake, 10, 7, None, C.byref(h)) == qr.QR_EINVAL
+    assert L.quadrank_build_ex(fake, 10, -1, None, C.byref(h)) == qr.QR_EINVAL
+    assert L.birank_layout_kind(None) == -1 and L.quadrank_layout_kind(None) == -1
     assert L.birank_rank(None, fake, 1, fake, None) == qr.QR_EINVAL
     assert L.quadrank_rank(None, fake, fake, 1, fake, None) == qr.QR_EINVAL
     assert L.quadrank_rank4(None, fake, 1, fake, None) == qr.QR_EINVAL

@@ -270,3 +270,17 @@ def test_generators_deterministic():
     assert all(np.array_equal(x, y) for x, y in zip(p1, p2))
     L = np.diff(p1[1].astype(np.int64))
     assert L.min() >= 20 and L.max() <= 250
+
+
+def test_revcomp_and_both_strands_by_hand():
+    # ACGTTG reversed is GTTGCA, complemented CAACGT (worked by hand: A<->T, C<->G)
+    assert "".join("ACGT"[c] for c in oracle.revcomp(codes_of("ACGTTG"))) == "CAACGT"
+    text = codes_of("ACGTTGCAAT")
+    sa = oracle.suffix_array(text)
+    # "AT": forward once (positions 8-9); its reverse complement is AT again: 1 + 1 = 2
+    # "TTG": forward once; reverse complement CAA occurs once (positions 6-8): 2
+    # "GCA": forward once; reverse complement TGC occurs once (positions 4-6): 2
+    # "ACG": forward once; reverse complement CGT occurs once (positions 1-3): 2
+    # "TTT": 0 + reverse complement AAA: 0
+    pat, off = csr(["AT", "TTG", "GCA", "ACG", "TTT", ""])
+    assert oracle.count_both_strands(text, sa, pat, off).tolist() == [2, 2, 2, 2, 0, 11]
