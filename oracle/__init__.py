@@ -9,6 +9,8 @@ Functions cite the passage they follow:
   rank_bits  — Section 1 rank definition with sigma = 2, rank(q) = rank(q, 1) (Section 3)
   rank_dna   — Section 1 rank definition rank(q, c) over the DNA alphabet
   rank4_dna  — Section 4: the ranks of all four symbols at one position
+  prefix_rank_dna — the count of characters at most c before q (the operation proposed in the
+               paper's closing section for a bidirectional FM-index)
   count_*    — Appendix D: count-only exact search; naive, suffix-array and
                textbook backward-search statements of the same count
 """
@@ -51,6 +53,8 @@ def _load():
         lib.or_rank_dna.argtypes = [vp, u64, vp, vp, u64, vp]
         lib.or_rank4_dna.restype = i64
         lib.or_rank4_dna.argtypes = [vp, u64, vp, u64, vp]
+        lib.or_prefix_rank_dna.restype = i64
+        lib.or_prefix_rank_dna.argtypes = [vp, u64, vp, vp, u64, vp]
         lib.or_unpack2.argtypes = [vp, u64, vp]
         lib.or_count_naive.argtypes = [vp, u64, vp, vp, u64, vp]
         lib.or_suffix_array.argtypes = [vp, u64, vp]
@@ -108,6 +112,19 @@ def rank4_dna(packed: np.ndarray, n: int, q: np.ndarray) -> np.ndarray:
     rc = _load().or_rank4_dna(_p(_nonempty(packed, np.uint64)), n, _p(_nonempty(q, np.uint64)), q.size, _p(out))
     if rc < 0:
         raise MemoryError("oracle rank4_dna")
+    return out[: q.size]
+
+
+def prefix_rank_dna(packed: np.ndarray, n: int, q: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """prefix_rank(q, c) = number of characters t_i <= c with i < q (out of range -> 2^64-1)."""
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.uint8)
+    assert q.size == c.size
+    out = np.empty(max(q.size, 1), dtype=np.uint64)
+    rc = _load().or_prefix_rank_dna(_p(_nonempty(packed, np.uint64)), n, _p(_nonempty(q, np.uint64)),
+                                    _p(_nonempty(c, np.uint8)), q.size, _p(out))
+    if rc < 0:
+        raise MemoryError("oracle prefix_rank_dna")
     return out[: q.size]
 
 

@@ -134,6 +134,32 @@ int64_t or_rank4_dna(const uint64_t *packed, uint64_t n, const uint64_t *q, uint
     return bad;
 }
 
+/* prefix_rank(q, c) = #{ i < q : t_i <= c }, the count of characters at most c (the operation the
+   paper's closing section names for a bidirectional FM-index), over the same per-word prefix counts. */
+int64_t or_prefix_rank_dna(const uint64_t *packed, uint64_t n, const uint64_t *q, const uint8_t *c, uint64_t nq,
+                           uint64_t *out) {
+    uint64_t nw;
+    uint64_t *W = dna_prefix(packed, n, &nw);
+    if (!W) return -1;
+    int64_t bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int64_t i = 0; i < (int64_t)nq; ++i) {
+        uint64_t p = q[i];
+        unsigned s = c[i];
+        if (p > n || s > 3) {
+            out[i] = OR_BAD;
+            bad++;
+            continue;
+        }
+        uint64_t k = p / 32, v = 0;
+        for (unsigned x = 0; x <= s; ++x) v += W[4 * k + x];
+        for (uint64_t j = 32 * k; j < p; ++j) v += (base_at(packed, j) <= s);
+        out[i] = v;
+    }
+    free(W);
+    return bad;
+}
+
 /* ---- FM-index count ------------------------------------------------------------------------------ */
 
 void or_unpack2(const uint64_t *packed, uint64_t n, uint8_t *codes) {

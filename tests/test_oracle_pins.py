@@ -142,6 +142,45 @@ def test_rank_dna_invariants():
     assert np.all(bad == oracle.BAD)
 
 
+def test_golden_prefix_rank():
+    g = json.load(open(GOLDEN))
+    for e in g["prefix_rank"]:
+        codes = codes_of(e["text"])
+        packed = datagen.pack2(codes, tail_garbage=True, seed=3)
+        for c in range(4):
+            q = np.array(e["q"], dtype=np.uint64)
+            got = oracle.prefix_rank_dna(packed, codes.size, q, np.full(q.size, c, np.uint8))
+            assert got.tolist() == [r[c] for r in e["prefix_rank"]]
+
+
+@pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 97])
+def test_prefix_rank_bruteforce(n):
+    codes = datagen.dna_codes(21 + n, n)
+    packed = datagen.pack2(codes, tail_garbage=True, seed=n + 5)
+    q = np.arange(n + 1, dtype=np.uint64)
+    for c in range(4):
+        want = [sum(1 for i in range(k) if codes[i] <= c) for k in range(n + 1)]
+        assert oracle.prefix_rank_dna(packed, n, q, np.full(q.size, c, np.uint8)).tolist() == want
+
+
+def test_prefix_rank_invariants():
+    """prefix_rank(q, T) = q; at q = n the four values are the cumulative histogram; one step in q
+    adds [t_q <= c]; out-of-range q or c give the error value."""
+    n = 50_003
+    codes = datagen.dna_codes(8, n)
+    packed = datagen.pack2(codes, tail_garbage=True, seed=2)
+    q = np.arange(n + 1, dtype=np.uint64)
+    hist = np.cumsum(np.bincount(codes, minlength=4)).astype(np.uint64)
+    for c in range(4):
+        pr = oracle.prefix_rank_dna(packed, n, q, np.full(q.size, c, np.uint8))
+        assert pr[n] == hist[c]
+        assert np.array_equal(pr[1:] - pr[:-1], (codes <= c).astype(np.uint64))
+        if c == 3:
+            assert np.array_equal(pr, q)
+    bad = oracle.prefix_rank_dna(packed, n, np.array([n + 1, 5], np.uint64), np.array([0, 4], np.uint8))
+    assert np.all(bad == oracle.BAD)
+
+
 def test_rank_dna_all_same_symbol():
     n = 4097
     for c in range(4):
