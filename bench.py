@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
     ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05")
+    ap.add_argument("--layouts", default="16,32",
+                    help="inline-delta widths to build for each rank row; the tuner picks one per row")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tuning-from", default=None,
                     help="apply the launch settings recorded in an earlier bench JSON line instead of tuning")
@@ -106,6 +108,8 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     rows = [r for r in args.rows.split(",") if r]
+    layouts = [int(x) for x in args.layouts.split(",") if x]
+    layout_id = {16: qr.QR_LAYOUT_16, 32: qr.QR_LAYOUT_32}
     t_setup = time.time()
 
     def to_dev(a):
@@ -126,11 +130,13 @@ def main():
         del codes
         d = to_dev(packed_q)
         log("quadrank text generated %.1fs" % (time.time() - t0))
-        torch.cuda.synchronize()
-        t0 = time.time()
-        structs["quadrank"] = qr.QuadRank(d, n_qr)
-        builds["quadrank_build_s"] = time.time() - t0
-        builds["quadrank_bytes"] = structs["quadrank"].nbytes
+        structs["quadrank"] = {}
+        for L in layouts:
+            torch.cuda.synchronize()
+            t0 = time.time()
+            structs["quadrank"][L] = qr.QuadRank(d, n_qr, layout=layout_id[L])
+            builds["quadrank%d_build_s" % L] = time.time() - t0
+            builds["quadrank%d_bytes" % L] = structs["quadrank"][L].nbytes
         del d
         if "quadrank_rank" in rows:
             qsets["quadrank_rank"] = (to_dev(datagen.queries(3204, n_qr, TOTAL_Q)), to_dev(datagen.symbols(3205, TOTAL_Q)))
@@ -143,10 +149,14 @@ def main():
             continue
         t0 = time.time()
         d = to_dev(datagen.bits(seed, n_br, dens))
-        torch.cuda.synchronize()
         t1 = time.time()
-        structs[row] = qr.BiRank(d, n_br)
-        builds[row.replace("rank", "build") + "_s"] = time.time() - t1
+        structs[row] = {}
+        for L in layouts:
+            torch.cuda.synchronize()
+            t2 = time.time()
+            structs[row][L] = qr.BiRank(d, n_br, layout=layout_id[L])
+            builds["birank%d_build_p%g_s" % (L, dens)] = time.time() - t2
+            builds["birank%d_bytes" % L] = structs[row][L].nbytes
         del d
         qsets[row] = (to_dev(datagen.queries(seed + 100, n_br, TOTAL_Q)), None)
         log("%s ready (gen %.1fs)" % (row, t1 - t0))
@@ -155,18 +165,24 @@ def main():
     outs = torch.empty(BATCH * 4, dtype=torch.int64, device=dev)
     bl = batches(TOTAL_Q, BATCH)
 
-    def launch(row, k):
+    choice = {row: layouts[0] for row in rows}  # layout each row runs on (set by the tuner)
+
+    def handle(row, L=None):
+        return structs["quadrank" if row.startswith("quadrank") else row][choice[row] if L is None else L]
+
+    def launch(row, k, L=None):
         o, cnt = bl[k % len(bl)]
         q, c = qsets[row]
+        h = handle(row, L)
         if row == "quadrank_rank":
-            structs["quadrank"].rank(q[o:o + cnt], c[o:o + cnt], outs[:cnt])
+            h.rank(q[o:o + cnt], c[o:o + cnt], outs[:cnt])
         elif row == "quadrank_rank4":
-            structs["quadrank"].rank4(q[o:o + cnt], outs[:4 * cnt])
+            h.rank4(q[o:o + cnt], outs[:4 * cnt])
         else:
-            structs[row].rank(q[o:o + cnt], outs[:cnt])
+            h.rank(q[o:o + cnt], outs[:cnt])
 
     # ------------------------------------------------------------------ autotune (untimed)
-    tuning = {}
+    tuning, by_layout = {}, {row: {} for row in rows}
     fixed = None
     if args.tuning_from:
         with open(args.tuning_from) as f:
@@ -175,26 +191,33 @@ def main():
         fixed["_fm"] = (prev.get("fm") or {}).get("tuning")
         args.fm_tuning = fixed["_fm"]
     for row in rows:
-        h = structs["quadrank"] if row.startswith("quadrank") else structs[row]
         if fixed and isinstance(fixed.get(row), dict):
-            h.set_tuning(**fixed[row])
-            tuning[row] = fixed[row]
+            t = dict(fixed[row])
+            L = int(t.pop("layout", 16))
+            choice[row] = L if L in layouts else layouts[0]
+            handle(row).set_tuning(**t)
+            tuning[row] = t
             continue
         if args.no_tune:
-            h.set_tuning(lanes=2, per_lane=1, block=256, grid_waves=0)
+            handle(row).set_tuning(lanes=2, per_lane=1, block=256, grid_waves=0)
             tuning[row] = "default"
             continue
-        best, table = autotune.tune(row, h.n, h.set_tuning, lambda r=row: launch(r, 0), autotune.RANK_CANDIDATES,
-                                    use_cache=False)
-        tuning[row] = best
-        log("tuned %s -> %s (%s)" % (row, best, ", ".join("%.3f" % (t * 1e3) for _, t in table[:6])))
-        if row == "quadrank_rank4":  # rank and rank4 share the handle: keep the per-row setting
-            tuning["_rank4_setting"] = best
+        best_t = None
+        for L in layouts:
+            h = handle(row, L)
+            best, table = autotune.tune("%s|L%d" % (row, L), h.n, h.set_tuning, lambda r=row, L=L: launch(r, 0, L),
+                                        autotune.RANK_CANDIDATES, use_cache=False)
+            t_best = min(t for _, t in table)
+            by_layout[row][str(L)] = {"tuned_launch_ms": round(t_best * 1e3, 4), "tuning": best,
+                                      "queries_per_s": BATCH / t_best}
+            log("tuned %s layout %d -> %s %.3f ms (%s)" % (row, L, best, t_best * 1e3,
+                                                          ", ".join("%.3f" % (t * 1e3) for _, t in table[:6])))
+            if best_t is None or t_best < best_t:
+                best_t, choice[row], tuning[row] = t_best, L, best
 
     def apply(row):
-        h = structs["quadrank"] if row.startswith("quadrank") else structs[row]
         if tuning.get(row) not in (None, "default"):
-            h.set_tuning(**tuning[row])
+            handle(row).set_tuning(**tuning[row])
 
     if args.calibrate_copy:
         src = torch.zeros(1 << 27, dtype=torch.int64, device=dev)
@@ -237,10 +260,13 @@ def main():
             "lines_per_query": 1,
             "roofline_frac_hbm": achieved / HBM_PEAK_GBS,
             "algorithmic_GBps": achieved,
-            "tuning": tuning.get(row),
+            "tuning": (dict(tuning[row], layout=choice[row]) if isinstance(tuning.get(row), dict)
+                       else tuning.get(row)),
+            "layout": choice[row],
+            "by_layout": by_layout[row],
         }
-        log("%-20s %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline" % (row, qps / 1e9, per_launch * 1e3,
-                                                                        100 * achieved / HBM_PEAK_GBS))
+        log("%-20s L%d %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline" % (
+            row, choice[row], qps / 1e9, per_launch * 1e3, 100 * achieved / HBM_PEAK_GBS))
     ms_per_step = wall / args.steps * 1e3
     value = step_queries / wall if rows else None
 
@@ -252,15 +278,16 @@ def main():
         if dom is None:
             raise KeyError("no rank rows")
         prof = json.load(open(prof_path))
-        ent = prof.get("kernels", {}).get(dom)
-        src = source_hash(*prof.get("sources", []))
-        if ent and src == prof.get("source_hash"):
+        ent = prof.get("kernels", {}).get("%s|L%d" % (dom, choice[dom]))
+        if ent and source_hash(*ent.get("sources", [])) == ent.get("source_hash"):
             traffic = ent["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
     roofline = None if dom is None else {
         "bound": "hbm",
-        "kernel": KERNEL_NAMES[dom] + " (" + dom + ")",
+        "kernel": "%s<%s%d> (%s)" % (KERNEL_NAMES[dom], "QR" if dom.startswith("quadrank") else "BR", choice[dom], dom),
+        "row": dom,
+        "layout": choice[dom],
         "achieved": round(row_res[dom]["algorithmic_GBps"], 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",

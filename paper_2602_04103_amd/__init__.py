@@ -74,6 +74,7 @@ def lib():
             "quadrank_set_tuning": (ci, [vp, C.POINTER(qr_tuning)]),
             "quadrank_export": (ci, [vp, vp, vp]),
             "qr_gather_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
+            "qr_gather_lanes_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
             "qr_graph_begin": (ci, [vp]),
             "qr_graph_end": (ci, [vp, C.POINTER(vp)]),
             "qr_graph_launch": (ci, [vp, vp]),
@@ -208,6 +209,14 @@ def qr_gather_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, bytes_
     _check(lib().qr_gather_bench(_dev(lines, "lines", W64 + W8 + W32, n_lines * 16 if lines.element_size() == 8 else 1),
                                  n_lines, _dev(idx, "idx", W64), nq, bytes_per_query, _dev(out, "out", W64, nq),
                                  _stream(stream)), "qr_gather_bench")
+    return out
+
+
+def qr_gather_lanes_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, lanes: int, out: torch.Tensor,
+                          stream=None):
+    nq = idx.numel()
+    _check(lib().qr_gather_lanes_bench(_dev(lines, "lines", W64, n_lines * 16), n_lines, _dev(idx, "idx", W64), nq,
+                                       lanes, _dev(out, "out", W64, nq), _stream(stream)), "qr_gather_lanes_bench")
     return out
 
 

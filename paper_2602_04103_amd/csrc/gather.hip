@@ -26,7 +26,55 @@ __global__ __launch_bounds__(256) void gather_kernel(const uint4 *__restrict__ l
     out[i] = s;
 }
 
+// LANES lanes share one query: lane t of the group reads 16-byte segments [t S, t S + S) of the line,
+// S = 8 / LANES, and the group's sum is reduced across its lanes; the group's first lane writes it.
+template <int LANES>
+__global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restrict__ lines, uint64_t n_lines,
+                                                           const uint64_t *__restrict__ idx, uint64_t nq,
+                                                           uint64_t *__restrict__ out) {
+    constexpr int S = 8 / LANES;
+    const uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / LANES;
+    const int t = threadIdx.x % LANES;
+    const uint64_t i = g < nq ? g : nq - 1;  // whole groups stay active for the reduction
+    const uint64_t l = mulhi64(idx[i], n_lines);
+    const uint4 *L = lines + l * 8 + t * S;
+    uint4 v[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) v[k] = L[k];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) s += v[k].x + v[k].y + v[k].z + v[k].w;
+#pragma unroll
+    for (int m = 1; m < LANES; m <<= 1) s += __shfl_xor(s, m, 64);
+    if (t == 0 && g < nq) out[g] = s;
+}
+
 }  // namespace
+
+extern "C" int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
+                                     uint32_t lanes, uint64_t *d_out, hipStream_t stream) {
+    if (!d_lines || !n_lines || (nq && (!d_idx || !d_out)) || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) ||
+        ((uintptr_t)d_lines & 15) || ((uintptr_t)d_idx & 7) || ((uintptr_t)d_out & 7)) {
+        set_error("qr_gather_lanes_bench: bad arguments");
+        return QR_EINVAL;
+    }
+    if (!nq) return QR_OK;
+    const uint64_t blocks = (nq * lanes + 255) / 256;
+    if (blocks > 0x7fffffffull) {
+        set_error("qr_gather_lanes_bench: nq too large");
+        return QR_EINVAL;
+    }
+    const uint4 *L = reinterpret_cast<const uint4 *>(d_lines);
+    const dim3 g((uint32_t)blocks), b(256);
+    switch (lanes) {
+        case 1: hipLaunchKernelGGL(gather_lanes_kernel<1>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
+        case 2: hipLaunchKernelGGL(gather_lanes_kernel<2>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
+        case 4: hipLaunchKernelGGL(gather_lanes_kernel<4>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
+        default: hipLaunchKernelGGL(gather_lanes_kernel<8>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
+    }
+    QR_HIP(hipGetLastError());
+    return QR_OK;
+}
 
 extern "C" int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
                                uint32_t bytes_per_query, uint64_t *d_out, hipStream_t stream) {

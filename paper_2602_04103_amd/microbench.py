@@ -4,6 +4,8 @@
   python -m paper_2602_04103_amd.microbench rankws   rank / rank4 throughput against structure size
   python -m paper_2602_04103_amd.microbench lanes    BiRank rank on 2^36 bits: one lane per query
                                                      (several 16-byte loads per lane) vs lane pairs
+  python -m paper_2602_04103_amd.microbench glanes   whole-line random gathers read by 1/2/4/8 lanes
+                                                     per line, against working set
 """
 from __future__ import annotations
 
@@ -37,6 +39,26 @@ def gather(args):
             t = _time(lambda: qr.qr_gather_bench(buf, nl, idx, b, out))
             print("gather ws=%.3f GiB bytes=%d: %.2f G lines/s (%.0f GB/s of 128-byte lines)"
                   % (gib, b, nq / t / 1e9, nq * 128 / t / 1e9), flush=True)
+        del buf
+        torch.cuda.empty_cache()
+
+
+def glanes(args):
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    nq = 1 << 24
+    idx = torch.from_numpy(datagen.bits(7, nq * 64).view(np.int64)).cuda()  # raw 64-bit draws
+    out = torch.empty(nq, dtype=torch.int64, device="cuda")
+    for gib in args.gib:
+        nl = int(gib * (1 << 30)) // 128
+        buf = torch.ones(nl * 16, dtype=torch.int64, device="cuda")
+        for ln in (1, 2, 4, 8):
+            t = _time(lambda: qr.qr_gather_lanes_bench(buf, nl, idx, ln, out))
+            print("glanes ws=%.3f GiB lanes=%d: %.2f G lines/s (%.0f GB/s of 128-byte lines)"
+                  % (gib, ln, nq / t / 1e9, nq * 128 / t / 1e9), flush=True)
         del buf
         torch.cuda.empty_cache()
 
@@ -106,13 +128,15 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="what", required=True)
     g = sub.add_parser("gather")
     g.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 2, 3, 4, 8])
+    gl = sub.add_parser("glanes")
+    gl.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 4, 8, 16])
     l = sub.add_parser("lanes")
     l.add_argument("--log-n", type=int, default=36)
     r = sub.add_parser("rankws")
     r.add_argument("--qr-log-n", type=int, nargs="+", default=[24, 28, 30, 31, 32, 33])
     r.add_argument("--br-log-n", type=int, nargs="+", default=[28, 31, 33, 34, 35, 36])
     a = ap.parse_args(argv)
-    {"gather": gather, "lanes": lanes, "rankws": rankws}[a.what](a)
+    {"gather": gather, "glanes": glanes, "lanes": lanes, "rankws": rankws}[a.what](a)
 
 
 if __name__ == "__main__":

@@ -2,11 +2,14 @@
 
   python -m paper_2602_04103_amd.profiling stats DIR [--cmd "..."]        kernel-trace statistics table
   python -m paper_2602_04103_amd.profiling counters DIR COUNTER [...]     per-kernel mean of PMC counters
-  python -m paper_2602_04103_amd.profiling traffic FETCH_DIR WRITE_DIR --copy-bytes B --out JSON
+  python -m paper_2602_04103_amd.profiling traffic FETCH_DIR WRITE_DIR --row ROW --layout 16|32 \
+      --copy-bytes B --out JSON
 
-`traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM bytes per launch of each rank
-kernel, scaled by what the same counters read for a plain device copy of known size in the same
-runs (the calibration factor), and records a hash of the kernel sources they were taken with."""
+`traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM bytes per launch of the rank
+kernel of one benchmark row and layout (the profiled run runs only that row), scaled by what the
+same counters read for a plain device copy of known size in the same runs (the calibration
+factor).  Entries are merged into JSON under the key "ROW|L<layout>", each with a hash of the
+kernel sources it was taken with; entries whose sources have changed since are dropped."""
 from __future__ import annotations
 
 import argparse
@@ -19,7 +22,8 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = ["quadrank.hip", "quadrank_dev.hpp", "birank.hip", "common.hpp"]
+# the kernel sources each row's counters depend on (a record goes stale when any of them changes)
+ROW_SOURCES = {"birank": ["birank.hip", "common.hpp"], "quadrank": ["quadrank.hip", "quadrank_dev.hpp", "common.hpp"]}
 ROW_KERNELS = {
     "quadrank_rank": "qr_rank1_pair_kernel",
     "quadrank_rank4": "qr_rank4_pair_kernel",
@@ -57,9 +61,9 @@ def counter_values(d: str, counter: str):
     return res
 
 
-def source_hash() -> str:
+def source_hash(names) -> str:
     h = hashlib.sha256()
-    for nme in SOURCES:
+    for nme in names:
         with open(os.path.join(ROOT, "paper_2602_04103_amd", "csrc", nme), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -105,18 +109,34 @@ def cmd_traffic(a):
     # the copy reads and writes copy_bytes once each: factors convert counter KiB to bytes
     f_fac = a.copy_bytes / (max(copy_f) * 1024.0)
     w_fac = a.copy_bytes / (max(copy_w) * 1024.0)
-    out = {"sources": SOURCES, "source_hash": source_hash(), "fetch_factor": f_fac, "write_factor": w_fac,
-           "copy_bytes": a.copy_bytes, "kernels": {}}
-    for row, kname in ROW_KERNELS.items():
-        fv, wv = _match(fetch, kname), _match(write, kname)
-        if not fv or not wv:
-            continue
-        out["kernels"][row] = {
-            "kernel": kname,
-            "fetch_kib_per_dispatch": statistics.mean(fv),
-            "write_kib_per_dispatch": statistics.mean(wv),
-            "hbm_bytes_per_launch": statistics.mean(fv) * 1024.0 * f_fac + statistics.mean(wv) * 1024.0 * w_fac,
-        }
+    out = {"kernels": {}}
+    try:
+        with open(a.out) as f:
+            prev = json.load(f)
+        for k, v in prev.get("kernels", {}).items():  # keep records whose sources are unchanged
+            if v.get("source_hash") == source_hash(v.get("sources", [])):
+                out["kernels"][k] = v
+    except (OSError, ValueError):
+        pass
+    srcs = ROW_SOURCES["quadrank" if a.row.startswith("quadrank") else "birank"]
+    kname = ROW_KERNELS[a.row]
+    token = ("QR" if a.row.startswith("quadrank") else "BR") + str(a.layout)
+    sel = lambda d: [x for k, v in d.items() if kname in k and token in k for x in v]  # noqa: E731
+    fv, wv = sel(fetch), sel(write)
+    if not fv or not wv:
+        sys.exit("no dispatches of %s for layout %s in the counter output" % (kname, a.layout))
+    out["kernels"]["%s|L%d" % (a.row, a.layout)] = {
+        "kernel": "%s<%s>" % (kname, token),
+        "sources": srcs,
+        "source_hash": source_hash(srcs),
+        "dispatches": len(fv),
+        "fetch_kib_per_dispatch": statistics.mean(fv),
+        "write_kib_per_dispatch": statistics.mean(wv),
+        "fetch_factor": f_fac,
+        "write_factor": w_fac,
+        "copy_bytes": a.copy_bytes,
+        "hbm_bytes_per_launch": statistics.mean(fv) * 1024.0 * f_fac + statistics.mean(wv) * 1024.0 * w_fac,
+    }
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
@@ -135,6 +155,8 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
+    t.add_argument("--row", required=True, choices=sorted(ROW_KERNELS))
+    t.add_argument("--layout", type=int, required=True, choices=(16, 32))
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--copy-kernel", default="elementwise")
     t.add_argument("--out", required=True)
