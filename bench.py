@@ -35,12 +35,14 @@ TOTAL_Q = 10 ** 9
 BYTES_PER_QUERY = {
     "quadrank_rank": 128 + 8 + 1 + 8,
     "quadrank_rank4": 128 + 8 + 32,
+    "quadrank_prefix_rank": 128 + 8 + 1 + 8,
     "birank_rank_p0.5": 128 + 8 + 8,
     "birank_rank_p0.05": 128 + 8 + 8,
 }
 KERNEL_NAMES = {
     "quadrank_rank": "qr_rank1_pair_kernel",
     "quadrank_rank4": "qr_rank4_pair_kernel",
+    "quadrank_prefix_rank": "qr_prefix_pair_kernel",
     "birank_rank_p0.5": "br_rank_pair_kernel",
     "birank_rank_p0.05": "br_rank_pair_kernel",
 }
@@ -80,7 +82,8 @@ def main():
     ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8", help="offered loads, patterns/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
-    ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05")
+    ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05",
+                    help="comma-separated rank rows of the step; quadrank_prefix_rank is an optional extra row")
     ap.add_argument("--layouts", default="16,32",
                     help="inline-delta widths to build for each rank row; the tuner picks one per row")
     ap.add_argument("--json-out", default=None)
@@ -142,6 +145,9 @@ def main():
             qsets["quadrank_rank"] = (to_dev(datagen.queries(3204, n_qr, TOTAL_Q)), to_dev(datagen.symbols(3205, TOTAL_Q)))
         if "quadrank_rank4" in rows:
             qsets["quadrank_rank4"] = (to_dev(datagen.queries(3206, n_qr, TOTAL_Q)), None)
+        if "quadrank_prefix_rank" in rows:  # optional row (not in the default step)
+            qsets["quadrank_prefix_rank"] = (to_dev(datagen.queries(3207, n_qr, TOTAL_Q)),
+                                             to_dev(datagen.symbols(3208, TOTAL_Q)))
     n_br = 1 << 36
     for dens, seed in ((0.5, 3636), (0.05, 3637)):
         row = "birank_rank_p%g" % dens
@@ -178,6 +184,8 @@ def main():
             h.rank(q[o:o + cnt], c[o:o + cnt], outs[:cnt])
         elif row == "quadrank_rank4":
             h.rank4(q[o:o + cnt], outs[:4 * cnt])
+        elif row == "quadrank_prefix_rank":
+            h.prefix_rank(q[o:o + cnt], c[o:o + cnt], outs[:cnt])
         else:
             h.rank(q[o:o + cnt], outs[:cnt])
 

@@ -114,6 +114,11 @@ int quadrank_layout_kind(qr_quadrank h);
 /* d_out[i] = rank(d_q[i], d_c[i]). */
 int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
                   hipStream_t stream);
+/* d_out[i] = prefix_rank(d_q[i], d_c[i]) = number of characters t_j <= d_c[i] with j < d_q[i]: the
+ * operation the paper's closing section (Future work) proposes for a bidirectional FM-index.  Same
+ * arguments, errors and launch settings as quadrank_rank; c = 3 gives q. */
+int quadrank_prefix_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
+                         hipStream_t stream);
 /* d_out4[4*i + c] = rank(d_q[i], c) for c = 0..3 (q-major rows of four u64). */
 int quadrank_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t stream);
 int quadrank_check(qr_quadrank h, hipStream_t stream);

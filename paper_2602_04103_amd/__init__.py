@@ -66,6 +66,7 @@ def lib():
             "quadrank_layout_kind": (ci, [vp]),
             "quadrank_rank": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadrank_rank4": (ci, [vp, vp, u64, vp, vp]),
+            "quadrank_prefix_rank": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadrank_check": (ci, [vp, vp]),
             "quadrank_free": (ci, [vp]),
             "quadrank_len": (u64, [vp]),
@@ -185,6 +186,13 @@ def quadrank_rank(h: int, q: torch.Tensor, c: torch.Tensor, out: torch.Tensor, s
     nq = q.numel()
     _check(lib().quadrank_rank(h, _dev(q, "q", W64), _dev(c, "c", W8, nq), nq, _dev(out, "out", W64, nq),
                                _stream(stream)), "quadrank_rank")
+    return out
+
+
+def quadrank_prefix_rank(h: int, q: torch.Tensor, c: torch.Tensor, out: torch.Tensor, stream=None):
+    nq = q.numel()
+    _check(lib().quadrank_prefix_rank(h, _dev(q, "q", W64), _dev(c, "c", W8, nq), nq, _dev(out, "out", W64, nq),
+                                      _stream(stream)), "quadrank_prefix_rank")
     return out
 
 
@@ -411,6 +419,13 @@ class QuadRank(_Handle):
         if out4 is None:
             out4 = torch.empty((q.numel(), 4), dtype=torch.int64, device=q.device)
         return quadrank_rank4(self.h, q, out4, stream)
+
+    def prefix_rank(self, q: torch.Tensor, c: torch.Tensor, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+        """Count of characters at most c before each q."""
+        if out is None:
+            out = torch.empty(q.numel(), dtype=torch.int64, device=q.device)
+        return quadrank_prefix_rank(self.h, q, c, out, stream)
 
     def check(self, stream=None):
         quadrank_check(self.h, stream)

@@ -188,12 +188,13 @@ __device__ __forceinline__ void load_lane_half(const uint4 *__restrict__ lines, 
     hdr = ph.up ? lines[ph.j * 8] : a;
 }
 
-template <class L, int PER_LANE>
-__global__ __launch_bounds__(256) void qr_rank1_kernel(const uint4 *__restrict__ lines,
-                                                       const typename L::Super *__restrict__ super, uint64_t n,
-                                                       const uint64_t *__restrict__ Q, const uint8_t *__restrict__ Cs,
-                                                       uint64_t nq, uint64_t *__restrict__ out,
-                                                       uint32_t *__restrict__ err) {
+// rank(q, c) (PREFIX = false) or prefix_rank(q, c) = #{i < q : t_i <= c} (PREFIX = true): the same
+// walk with the symbol test, the delta and the offset replaced by their sums over the symbols <= c.
+template <class L, int PER_LANE, bool PREFIX>
+__device__ __forceinline__ void sym_lane_body(const uint4 *__restrict__ lines, const typename L::Super *__restrict__ super,
+                                              uint64_t n, const uint64_t *__restrict__ Q,
+                                              const uint8_t *__restrict__ Cs, uint64_t nq, uint64_t *__restrict__ out,
+                                              uint32_t *__restrict__ err) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nq; i0 += stride * PER_LANE) {
         uint64_t q[PER_LANE], off[PER_LANE], r[PER_LANE];
@@ -211,13 +212,15 @@ __global__ __launch_bounds__(256) void qr_rank1_kernel(const uint4 *__restrict__
         for (int u = 0; u < PER_LANE; ++u) {
             bad[u] = q[u] > n || c[u] > 3;
             load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u]);
-            off[u] = L::offset1(super, ph[u].j, c[u] & 3u);
+            off[u] = PREFIX ? offset_le<L>(super, ph[u].j, c[u] & 3u) : L::offset1(super, ph[u].j, c[u] & 3u);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            const uint32_t cc = c[u] & 3u;
-            const uint32_t cnt = pair_count1(ph[u], (uint32_t)ph[u].up, cc);
-            const uint64_t mid = off[u] + L::delta(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc);
+            const uint32_t cc = c[u] & 3u, hu = (uint32_t)ph[u].up;
+            const uint32_t cnt = PREFIX ? pair_count_le(ph[u], hu, cc) : pair_count1(ph[u], hu, cc);
+            const uint64_t d = PREFIX ? delta_le<L>(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc)
+                                      : (uint64_t)L::delta(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc);
+            const uint64_t mid = off[u] + d;
             r[u] = bad[u] ? ~0ull : (ph[u].up ? mid + cnt : mid - cnt);
         }
 #pragma unroll
@@ -229,6 +232,21 @@ __global__ __launch_bounds__(256) void qr_rank1_kernel(const uint4 *__restrict__
             }
         }
     }
+}
+
+#define QR_SYM_ARGS                                                                                              \
+    const uint4 *__restrict__ lines, const typename L::Super *__restrict__ super, uint64_t n,                    \
+        const uint64_t *__restrict__ Q, const uint8_t *__restrict__ Cs, uint64_t nq, uint64_t *__restrict__ out, \
+        uint32_t *__restrict__ err
+
+template <class L, int PER_LANE>
+__global__ __launch_bounds__(256) void qr_rank1_kernel(QR_SYM_ARGS) {
+    sym_lane_body<L, PER_LANE, false>(lines, super, n, Q, Cs, nq, out, err);
+}
+
+template <class L, int PER_LANE>
+__global__ __launch_bounds__(256) void qr_prefix_kernel(QR_SYM_ARGS) {
+    sym_lane_body<L, PER_LANE, true>(lines, super, n, Q, Cs, nq, out, err);
 }
 
 template <class L, int PER_LANE>
@@ -276,12 +294,11 @@ __global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__
 // Lanes 2k, 2k+1 serve one query, lane hf loading half hf of the line (64 contiguous bytes), so each
 // wave load instruction touches 32 lines.  The lane holding q's half counts; lane 0 adds offset and
 // delta; the two contributions are summed across the pair.
-template <class L, int PER_PAIR>
-__global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restrict__ lines,
-                                                            const typename L::Super *__restrict__ super, uint64_t n,
-                                                            const uint64_t *__restrict__ Q,
-                                                            const uint8_t *__restrict__ Cs, uint64_t nq,
-                                                            uint64_t *__restrict__ out, uint32_t *__restrict__ err) {
+template <class L, int PER_PAIR, bool PREFIX>
+__device__ __forceinline__ void sym_pair_body(const uint4 *__restrict__ lines, const typename L::Super *__restrict__ super,
+                                              uint64_t n, const uint64_t *__restrict__ Q,
+                                              const uint8_t *__restrict__ Cs, uint64_t nq, uint64_t *__restrict__ out,
+                                              uint32_t *__restrict__ err) {
     const uint32_t hf = threadIdx.x & 1u;
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
@@ -299,14 +316,18 @@ __global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restr
         for (int u = 0; u < PER_PAIR; ++u) {
             bad[u] = q[u] > n || c[u] > 3;
             load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
-            off[u] = L::offset1(super, ph[u].j, c[u] & 3u);
+            off[u] = PREFIX ? offset_le<L>(super, ph[u].j, c[u] & 3u) : L::offset1(super, ph[u].j, c[u] & 3u);
         }
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint32_t cc = c[u] & 3u;
-            const uint32_t cnt = pair_count1(ph[u], hf, cc);
-            const uint64_t mine =
-                hf == 0 ? off[u] + L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc) - cnt : (uint64_t)cnt;
+            const uint32_t cnt = PREFIX ? pair_count_le(ph[u], hf, cc) : pair_count1(ph[u], hf, cc);
+            uint64_t mine = cnt;
+            if (hf == 0) {
+                const uint64_t d = PREFIX ? delta_le<L>(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc)
+                                          : (uint64_t)L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc);
+                mine = off[u] + d - cnt;
+            }
             r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
         }
 #pragma unroll
@@ -318,6 +339,16 @@ __global__ __launch_bounds__(256) void qr_rank1_pair_kernel(const uint4 *__restr
             }
         }
     }
+}
+
+template <class L, int PER_PAIR>
+__global__ __launch_bounds__(256) void qr_rank1_pair_kernel(QR_SYM_ARGS) {
+    sym_pair_body<L, PER_PAIR, false>(lines, super, n, Q, Cs, nq, out, err);
+}
+
+template <class L, int PER_PAIR>
+__global__ __launch_bounds__(256) void qr_prefix_pair_kernel(QR_SYM_ARGS) {
+    sym_pair_body<L, PER_PAIR, true>(lines, super, n, Q, Cs, nq, out, err);
 }
 
 template <class L, int PER_PAIR>
@@ -417,7 +448,7 @@ hipError_t build_t(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, void 
     return e;
 }
 
-template <class L>
+template <class L, bool PREFIX>
 int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out, hipStream_t s) {
     const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
     const int lanes = h->tune.lanes == 1 ? 1 : 2;
@@ -425,21 +456,27 @@ int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_
     const uint4 *Ln = reinterpret_cast<const uint4 *>(h->lines);
     const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
 #define QR_RANK1(K, P) hipLaunchKernelGGL((K<L, P>), g, b, 0, s, Ln, S, h->n, d_q, d_c, nq, d_out, h->err)
-    if (lanes == 2) {
-        switch (pl) {
-            case 1: QR_RANK1(qr_rank1_pair_kernel, 1); break;
-            case 2: QR_RANK1(qr_rank1_pair_kernel, 2); break;
-            case 4: QR_RANK1(qr_rank1_pair_kernel, 4); break;
-            default: QR_RANK1(qr_rank1_pair_kernel, 8); break;
+#define QR_RANK1_PL(K)                          \
+    switch (pl) {                               \
+        case 1: QR_RANK1(K, 1); break;          \
+        case 2: QR_RANK1(K, 2); break;          \
+        case 4: QR_RANK1(K, 4); break;          \
+        default: QR_RANK1(K, 8); break;         \
+    }
+    if (PREFIX) {
+        if (lanes == 2) {
+            QR_RANK1_PL(qr_prefix_pair_kernel)
+        } else {
+            QR_RANK1_PL(qr_prefix_kernel)
         }
     } else {
-        switch (pl) {
-            case 1: QR_RANK1(qr_rank1_kernel, 1); break;
-            case 2: QR_RANK1(qr_rank1_kernel, 2); break;
-            case 4: QR_RANK1(qr_rank1_kernel, 4); break;
-            default: QR_RANK1(qr_rank1_kernel, 8); break;
+        if (lanes == 2) {
+            QR_RANK1_PL(qr_rank1_pair_kernel)
+        } else {
+            QR_RANK1_PL(qr_rank1_kernel)
         }
     }
+#undef QR_RANK1_PL
 #undef QR_RANK1
     QR_HIP(hipGetLastError());
     return QR_OK;
@@ -555,13 +592,15 @@ int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr
     return quadrank_build_ex(d_packed2, n, QR_LAYOUT_16, stream, out);
 }
 
-static int qr_launch_common(qr_quadrank h, uint64_t nq, const void *a, const void *b, const char *what) {
+// out_align: 8 for u64 outputs, 16 for the rank4 rows (written as 16-byte pairs)
+static int qr_launch_common(qr_quadrank h, uint64_t nq, const void *a, const void *b, uintptr_t out_align,
+                            const char *what) {
     if (!h || (nq && (!a || !b))) {
         set_error("%s: null handle or pointer", what);
         return QR_EINVAL;
     }
-    if (((uintptr_t)a & 7) || ((uintptr_t)b & 15)) {
-        set_error("%s: d_q must be 8-byte and the output 16-byte aligned", what);
+    if (((uintptr_t)a & 7) || ((uintptr_t)b & (out_align - 1))) {
+        set_error("%s: d_q must be 8-byte and the output %u-byte aligned", what, (unsigned)out_align);
         return QR_EINVAL;
     }
     return check_device(h->device);
@@ -569,19 +608,32 @@ static int qr_launch_common(qr_quadrank h, uint64_t nq, const void *a, const voi
 
 int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
                   hipStream_t stream) {
-    int rc = qr_launch_common(h, nq, d_q, d_out, "quadrank_rank");
+    int rc = qr_launch_common(h, nq, d_q, d_out, 8, "quadrank_rank");
     if (rc) return rc;
     if (nq && !d_c) {
         set_error("quadrank_rank: d_c is NULL");
         return QR_EINVAL;
     }
     if (!nq) return QR_OK;
-    return h->layout == QR_LAYOUT_32 ? launch_rank1<QR32>(h, d_q, d_c, nq, d_out, stream)
-                                     : launch_rank1<QR16>(h, d_q, d_c, nq, d_out, stream);
+    return h->layout == QR_LAYOUT_32 ? launch_rank1<QR32, false>(h, d_q, d_c, nq, d_out, stream)
+                                     : launch_rank1<QR16, false>(h, d_q, d_c, nq, d_out, stream);
+}
+
+int quadrank_prefix_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
+                         hipStream_t stream) {
+    int rc = qr_launch_common(h, nq, d_q, d_out, 8, "quadrank_prefix_rank");
+    if (rc) return rc;
+    if (nq && !d_c) {
+        set_error("quadrank_prefix_rank: d_c is NULL");
+        return QR_EINVAL;
+    }
+    if (!nq) return QR_OK;
+    return h->layout == QR_LAYOUT_32 ? launch_rank1<QR32, true>(h, d_q, d_c, nq, d_out, stream)
+                                     : launch_rank1<QR16, true>(h, d_q, d_c, nq, d_out, stream);
 }
 
 int quadrank_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t stream) {
-    int rc = qr_launch_common(h, nq, d_q, d_out4, "quadrank_rank4");
+    int rc = qr_launch_common(h, nq, d_q, d_out4, 16, "quadrank_rank4");
     if (rc) return rc;
     if (!nq) return QR_OK;
     return h->layout == QR_LAYOUT_32 ? launch_rank4<QR32>(h, d_q, nq, d_out4, stream)

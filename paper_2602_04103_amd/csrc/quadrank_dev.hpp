@@ -196,6 +196,43 @@ __device__ __forceinline__ uint32_t pair_count1(const PairHalf &ph, uint32_t hf,
     return cnt;
 }
 
+// Slots of this lane's share of the range whose symbol is at most c (zero unless the lane holds q's
+// half).  Symbol s = lo + 2 hi exceeds c exactly where: c = A: lo | hi; c = C: hi; c = G: lo & hi;
+// c = T: nowhere.  Counted as the range length minus the slots above c.
+__device__ __forceinline__ uint32_t pair_count_le(const PairHalf &ph, uint32_t hf, uint32_t c) {
+    if ((uint32_t)ph.up != hf) return 0u;
+    const uint32_t inv = ph.up ? 0u : 0xffffffffu;
+    const uint32_t ma = 0u - (c & 1u), mb = 0u - ((c >> 1) & 1u);
+    uint32_t gt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const uint32_t m = prefix_mask32(ph.t, 2 * k + sub) ^ inv;
+            const uint32_t lo = ph.w[4 * k + sub], hi = ph.w[4 * k + 2 + sub];
+            const uint32_t above = (mb & lo & hi & ~ma) | (~mb & (hi | (lo & ~ma)));
+            gt += __popc(above & m);
+        }
+    }
+    return (ph.up ? ph.t : QR_MID - ph.t) - gt;
+}
+
+// Sums over the symbols x <= c of the line deltas and of the superblock offsets.
+template <class L>
+__device__ __forceinline__ uint64_t delta_le(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t c) {
+    uint64_t d = 0;
+#pragma unroll
+    for (uint32_t x = 0; x < 4; ++x) d += x <= c ? (uint64_t)L::delta(w0, w1, w2, w3, x) : 0ull;
+    return d;
+}
+
+template <class L>
+__device__ __forceinline__ uint64_t offset_le(const typename L::Super *__restrict__ s, uint64_t j, uint32_t c) {
+    uint64_t o[4];
+    L::offset4(s, j, o);
+    return o[0] + (c >= 1 ? o[1] : 0ull) + (c >= 2 ? o[2] : 0ull) + (c >= 3 ? o[3] : 0ull);
+}
+
 __device__ __forceinline__ void pair_count4(const PairHalf &ph, uint32_t hf, uint32_t (&cnt)[4]) {
     if ((uint32_t)ph.up != hf) {
         cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0u;

@@ -27,6 +27,7 @@ ROW_SOURCES = {"birank": ["birank.hip", "common.hpp"], "quadrank": ["quadrank.hi
 ROW_KERNELS = {
     "quadrank_rank": "qr_rank1_pair_kernel",
     "quadrank_rank4": "qr_rank4_pair_kernel",
+    "quadrank_prefix_rank": "qr_prefix_pair_kernel",
     "birank_rank_p0.5": "br_rank_pair_kernel",
     "birank_rank_p0.05": "br_rank_pair_kernel",
 }

@@ -57,7 +57,8 @@ def test_birank_2e36(p, seed):
 
 
 def test_quadrank_2e32_with_repeats():
-    """Both layouts; the 32-bit one has its superblock boundary at 2^23 lines = 3758096384 bases."""
+    """Both layouts (rank, rank4 and prefix_rank); the 32-bit layout has its superblock boundary at
+    2^23 lines = 3758096384 bases."""
     qr = require_gpu()
     n = 1 << 32
     codes = datagen.dna_codes(3202, n)
@@ -74,6 +75,7 @@ def test_quadrank_2e32_with_repeats():
     sample = np.union1d(rng.choice(BATCH, 1_000_000, replace=False), np.arange(fixed.size))
     want1 = oracle.rank_dna(packed, n, q[sample], c[sample])
     want4 = oracle.rank4_dna(packed, n, q[sample])
+    wantp = oracle.prefix_rank_dna(packed, n, q[sample], c[sample])
     for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32):
         announce("quadrank 2^32 layout", layout)
         h = qr.QuadRank(to_dev(packed), n, layout=layout)
@@ -86,6 +88,10 @@ def test_quadrank_2e32_with_repeats():
             assert np.array_equal(got4.sum(axis=1), q)           # sum over symbols = q
             assert np.array_equal(got4[0], hist)                 # rank4(n) = histogram
             assert np.array_equal(got1, got4[np.arange(BATCH), c.astype(np.int64)])
+        # prefix_rank in the last tuning: oracle on the sample, partial sums of rank4 everywhere
+        gotp = to_host_u64(h.prefix_rank(dq, dc))
+        assert np.array_equal(gotp[sample], wantp), layout
+        assert np.array_equal(gotp, np.cumsum(got4, axis=1)[np.arange(BATCH), c.astype(np.int64)])
         h.check()
         del h
         torch.cuda.empty_cache()
