@@ -13,6 +13,8 @@ Functions cite the passage they follow:
                paper's closing section for a bidirectional FM-index)
   count_*    — Appendix D: count-only exact search; naive, suffix-array and
                textbook backward-search statements of the same count
+  locate_sa  — the positions of every occurrence in suffix-array order (the locate query the
+               paper's closing section proposes for its FM-index)
 """
 from __future__ import annotations
 
@@ -61,6 +63,7 @@ def _load():
         lib.or_bwt.restype = u64
         lib.or_bwt.argtypes = [vp, u64, vp, vp]
         lib.or_count_sa.argtypes = [vp, u64, vp, vp, vp, u64, vp]
+        lib.or_interval_sa.argtypes = [vp, u64, vp, vp, vp, u64, vp, vp]
         lib.or_count_backward.restype = C.c_int
         lib.or_count_backward.argtypes = [vp, u64, vp, vp, u64, vp]
         lib.or_kmer_intervals.restype = C.c_int
@@ -169,6 +172,31 @@ def count_sa(text: np.ndarray, sa: np.ndarray, pat: np.ndarray, off: np.ndarray)
                             _p(_nonempty(pat, np.uint8)), _p(np.ascontiguousarray(off, dtype=np.uint64)), npat,
                             _p(out))
     return out[:npat]
+
+
+def interval_sa(text: np.ndarray, sa: np.ndarray, pat: np.ndarray, off: np.ndarray):
+    """(lo, hi): the suffix-array range of the suffixes of T$ that start with each pattern."""
+    npat = off.size - 1
+    lo = np.empty(max(npat, 1), dtype=np.uint64)
+    hi = np.empty(max(npat, 1), dtype=np.uint64)
+    if npat:
+        _load().or_interval_sa(_p(_nonempty(text, np.uint8)), text.size, _p(np.ascontiguousarray(sa, dtype=np.int64)),
+                               _p(_nonempty(pat, np.uint8)), _p(np.ascontiguousarray(off, dtype=np.uint64)), npat,
+                               _p(lo), _p(hi))
+    return lo[:npat], hi[:npat]
+
+
+def locate_sa(text: np.ndarray, sa: np.ndarray, pat: np.ndarray, off: np.ndarray):
+    """locate: the text positions of every occurrence of each pattern, in suffix-array order
+    (SA[lo..hi) of the pattern's range).  Returns (start, pos): pattern i owns
+    pos[start[i]:start[i+1]].  The empty pattern owns all n+1 suffixes."""
+    lo, hi = interval_sa(text, sa, pat, off)
+    lens = (hi - lo).astype(np.int64)
+    start = np.zeros(lo.size + 1, dtype=np.uint64)
+    start[1:] = np.cumsum(lens)
+    total = int(start[-1])
+    rows = np.repeat(lo.astype(np.int64) - start[:-1].astype(np.int64), lens) + np.arange(total, dtype=np.int64)
+    return start, np.asarray(sa, dtype=np.int64)[rows].astype(np.uint64)
 
 
 def count_backward(bwt_codes: np.ndarray, pat: np.ndarray, off: np.ndarray) -> np.ndarray:

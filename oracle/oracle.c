@@ -231,9 +231,10 @@ static int cmp_prefix(const uint8_t *T, uint64_t n, uint64_t i, const uint8_t *P
     return 0;
 }
 
-/* count via binary search for the SA range of suffixes that start with P */
-void or_count_sa(const uint8_t *text, uint64_t n, const int64_t *sa, const uint8_t *pat, const uint64_t *off,
-                 uint64_t npat, uint64_t *out) {
+/* The SA range [lo, hi) of the suffixes that start with P, by binary search; [0, 0) when P holds
+   a code > 3 (it cannot occur in an ACGT text). */
+void or_interval_sa(const uint8_t *text, uint64_t n, const int64_t *sa, const uint8_t *pat, const uint64_t *off,
+                    uint64_t npat, uint64_t *lo_out, uint64_t *hi_out) {
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < (int64_t)npat; ++p) {
         const uint8_t *P = pat + off[p];
@@ -241,7 +242,7 @@ void or_count_sa(const uint8_t *text, uint64_t n, const int64_t *sa, const uint8
         int bad = 0;
         for (uint64_t t = 0; t < m; ++t) bad |= P[t] > 3;
         if (bad) {
-            out[p] = 0;
+            lo_out[p] = hi_out[p] = 0;
             continue;
         }
         /* lo = first k with suffix(SA[k]) >= P (prefix-wise); hi = first k with suffix > P */
@@ -256,8 +257,19 @@ void or_count_sa(const uint8_t *text, uint64_t n, const int64_t *sa, const uint8
             uint64_t mid = a + (b - a) / 2;
             if (cmp_prefix(text, n, (uint64_t)sa[mid], P, m) <= 0) a = mid + 1; else b = mid;
         }
-        out[p] = a - lo;
+        lo_out[p] = lo;
+        hi_out[p] = a;
     }
+}
+
+/* count = size of that SA range */
+void or_count_sa(const uint8_t *text, uint64_t n, const int64_t *sa, const uint8_t *pat, const uint64_t *off,
+                 uint64_t npat, uint64_t *out) {
+    uint64_t *lo = (uint64_t *)malloc((npat ? npat : 1) * sizeof(uint64_t));
+    if (!lo) abort();
+    or_interval_sa(text, n, sa, pat, off, npat, lo, out);
+    for (uint64_t p = 0; p < npat; ++p) out[p] -= lo[p];
+    free(lo);
 }
 
 /* Textbook backward search over a BWT in which '$' is its own symbol (code 4).

@@ -242,6 +242,45 @@ def test_count_three_ways_vs_bruteforce(seed):
     assert oracle.count_backward(b, pat2, off2).tolist() == want
 
 
+def test_golden_locate():
+    g = json.load(open(GOLDEN))
+    for e in g["locate"]:
+        text = codes_of(e["text"])
+        pat, off = csr(e["patterns"])
+        start, pos = oracle.locate_sa(text, oracle.suffix_array(text), pat, off)
+        got = [pos[int(start[i]):int(start[i + 1])].tolist() for i in range(len(e["patterns"]))]
+        assert got == e["positions"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_locate_bruteforce(seed):
+    """Each pattern's positions are exactly the starts where it occurs (brute force), listed in
+    increasing order of their suffixes (compared with the end of text smallest)."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 300))
+    text = datagen.dna_codes(700 + seed, n)
+    if seed % 2:
+        text[n // 2:] = text[: n - n // 2]  # a long repeat
+    pats = [text[i:i + k] for i, k in zip(rng.integers(0, n, 40), rng.integers(1, 12, 40))]
+    pats += [rng.integers(0, 4, k).astype(np.uint8) for k in rng.integers(1, 5, 20)]
+    pats += [np.array([1, 5, 2], np.uint8), np.zeros(0, np.uint8)]
+    off = np.zeros(len(pats) + 1, np.uint64)
+    off[1:] = np.cumsum([p.size for p in pats])
+    flat = np.concatenate(pats).astype(np.uint8)
+    start, pos = oracle.locate_sa(text, oracle.suffix_array(text), flat, off)
+    s = "".join("ACGT"[c] for c in text)
+    for i, p in enumerate(pats):
+        got = pos[int(start[i]):int(start[i + 1])].tolist()
+        if p.size and p.max() > 3:
+            assert got == []
+            continue
+        ps = "".join("ACGT"[c] for c in p)
+        occ = [k for k in range(n + 1) if s.startswith(ps, k)]
+        assert sorted(got) == occ
+        sufs = [s[k:] for k in got]
+        assert sufs == sorted(sufs)                  # Python orders a proper prefix first, as '$' does
+
+
 def test_count_extension_invariant():
     # sum over c of count(cP) = count(P) - [T starts with P]   (every occurrence but the one at 0 extends left)
     n = 5000
