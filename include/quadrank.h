@@ -144,6 +144,11 @@ typedef struct qr_quadfm_s *qr_quadfm;
  * with '$' stored as A (code 0) and its row returned in *dollar_pos.  h_text holds n codes 0..3.
  * QR_EINVAL on a code > 3, QR_ERANGE if n+1 > 2^32-1, QR_ENOMEM if host memory runs out. */
 int quadfm_bwt_host(const uint8_t *h_text, uint64_t n, uint64_t *h_bwt_packed2, uint64_t *dollar_pos);
+/* Same, plus (when rate > 0) the suffix-array sample that locate needs: bit k of h_mark_bits
+ * (ceil((n+1)/64) words) is set iff SA[k] of T$ is a multiple of rate, and h_samples (floor(n/rate)+1
+ * u32) lists SA[k] of the marked rows in row order.  rate = 0 leaves both untouched (may be NULL). */
+int quadfm_index_host(const uint8_t *h_text, uint64_t n, uint32_t rate, uint64_t *h_bwt_packed2, uint64_t *dollar_pos,
+                      uint64_t *h_mark_bits, uint32_t *h_samples);
 
 /* Build the index from the packed BWT (n_plus_1 symbols at d_bwt_packed2, '$' stored as A at row
  * dollar_pos).  Builds QuadRank over the BWT, the C array and the 8-mer interval table. */
@@ -177,7 +182,31 @@ int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_of
                          uint32_t *d_count, hipStream_t stream);
 int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
                             uint32_t flags, uint32_t *d_count, hipStream_t stream);
-/* Synchronise `stream` (counts are then final). */
+/* The backward search of quadfm_count (persistent kernel), writing each pattern's final BWT interval
+ * instead of its size: d_iv[2i] = sp, d_iv[2i+1] = ep (u32 pairs, 8-byte aligned), [0, 0) when the
+ * pattern does not occur (or holds a code > 3); the empty pattern gives [0, n+1).  The paper's
+ * batched query returns these intervals (Appendix D). */
+int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_iv,
+                     hipStream_t stream);
+
+/* Locate (the extension the paper's closing section proposes): the text position of every
+ * occurrence, from a text-position sample of the suffix array (quadfm_index_host's mark bits and
+ * samples, device copies).  attach builds a BiRank over the n+1 mark bits and copies the samples
+ * (the handle owns both; a second attach replaces them); QR_EINVAL unless exactly floor(n/rate)+1
+ * rows are marked, including the row of '$'.  Synchronous. */
+int quadfm_locate_attach(qr_quadfm h, const uint64_t *d_mark_bits, const uint32_t *d_samples, uint64_t n_samples,
+                         uint32_t rate, hipStream_t stream);
+/* d_start[i] = sum over k < i of (ep_k - sp_k) for i = 0..npat (npat+1 u64; d_start[npat] is the
+ * number of positions quadfm_locate will write). */
+int quadfm_locate_offsets(qr_quadfm h, const uint32_t *d_iv, uint64_t npat, uint64_t *d_start, hipStream_t stream);
+/* For each pattern i and row r of its interval, d_pos[d_start[i] + r - sp_i] = SA[r], the text
+ * position of that occurrence (u32), so each pattern's positions come in suffix-array order.  total =
+ * d_start[npat].  Each position takes at most rate - 1 LF steps.  A walk that meets no sampled row
+ * (only possible with inconsistent sample data) writes UINT32_MAX and sets the sticky error. */
+int quadfm_locate(qr_quadfm h, const uint32_t *d_iv, const uint64_t *d_start, uint64_t npat, uint64_t total,
+                  uint32_t *d_pos, hipStream_t stream);
+/* Synchronise `stream` (counts, intervals and positions are then final); QR_ERANGE (and clear) if a
+ * locate walk failed since the last check. */
 int quadfm_check(qr_quadfm h, hipStream_t stream);
 int quadfm_free(qr_quadfm h);
 uint64_t quadfm_len(qr_quadfm h);   /* n (text length, without '$') */

@@ -83,6 +83,11 @@ def lib():
         }
         optional = {
             "quadfm_bwt_host": (ci, [vp, u64, vp, C.POINTER(u64)]),
+            "quadfm_index_host": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp]),
+            "quadfm_intervals": (ci, [vp, vp, vp, u64, vp, vp]),
+            "quadfm_locate_attach": (ci, [vp, vp, vp, u64, C.c_uint32, vp]),
+            "quadfm_locate_offsets": (ci, [vp, vp, u64, vp, vp]),
+            "quadfm_locate": (ci, [vp, vp, vp, u64, u64, vp, vp]),
             "quadfm_build": (ci, [vp, u64, u64, vp, C.POINTER(vp)]),
             "quadfm_count": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadfm_count_batched": (ci, [vp, vp, vp, u64, u64, vp, vp]),
@@ -241,6 +246,22 @@ def quadfm_bwt_host(text_codes):
     return out, int(d.value)
 
 
+def quadfm_index_host(text_codes, rate: int):
+    """Host input preparation with the suffix-array sample for locate: (packed BWT, dollar row,
+    mark bits u64[ceil((n+1)/64)], samples u32[n // rate + 1])."""
+    import numpy as np
+    t = np.ascontiguousarray(text_codes, dtype=np.uint8)
+    n = t.size
+    out = np.zeros(max(1, (n + 1 + 31) // 32), dtype=np.uint64)
+    marks = np.zeros(max(1, (n + 1 + 63) // 64), dtype=np.uint64)
+    samples = np.zeros(n // rate + 1, dtype=np.uint32)
+    d = u64()
+    src = t if n else np.zeros(1, np.uint8)
+    _check(lib().quadfm_index_host(src.ctypes.data, n, rate, out.ctypes.data, C.byref(d), marks.ctypes.data,
+                                   samples.ctypes.data), "quadfm_index_host")
+    return out, int(d.value), marks, samples
+
+
 def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None) -> int:
     h = vp()
     _check(lib().quadfm_build(_dev(bwt_packed2, "bwt_packed2", W64, (n_plus_1 + 31) // 32), n_plus_1, dollar_pos,
@@ -286,6 +307,32 @@ def quadfm_count_batched(h: int, pat: torch.Tensor, off: torch.Tensor, batch: in
     _check(lib().quadfm_count_batched(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, batch,
                                       _dev(count, "count", W32, npat), _stream(stream)), "quadfm_count_batched")
     return count
+
+
+def quadfm_intervals(h: int, pat: torch.Tensor, off: torch.Tensor, iv: torch.Tensor, stream=None):
+    npat = off.numel() - 1
+    _check(lib().quadfm_intervals(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat,
+                                  _dev(iv, "iv", W32, 2 * npat), _stream(stream)), "quadfm_intervals")
+    return iv
+
+
+def quadfm_locate_attach(h: int, marks: torch.Tensor, samples: torch.Tensor, rate: int, stream=None):
+    _check(lib().quadfm_locate_attach(h, _dev(marks, "marks", W64), _dev(samples, "samples", W32), samples.numel(),
+                                      rate, _stream(stream)), "quadfm_locate_attach")
+
+
+def quadfm_locate_offsets(h: int, iv: torch.Tensor, start: torch.Tensor, stream=None):
+    npat = iv.numel() // 2
+    _check(lib().quadfm_locate_offsets(h, _dev(iv, "iv", W32, 2 * npat), npat, _dev(start, "start", W64, npat + 1),
+                                       _stream(stream)), "quadfm_locate_offsets")
+    return start
+
+
+def quadfm_locate(h: int, iv: torch.Tensor, start: torch.Tensor, total: int, pos: torch.Tensor, stream=None):
+    npat = iv.numel() // 2
+    _check(lib().quadfm_locate(h, _dev(iv, "iv", W32, 2 * npat), _dev(start, "start", W64, npat + 1), npat, total,
+                               _dev(pos, "pos", W32, total), _stream(stream)), "quadfm_locate")
+    return pos
 
 
 def quadfm_check(h: int, stream=None):
@@ -460,12 +507,42 @@ class QuadFm(_Handle):
         self.n = n_plus_1 - 1
 
     @classmethod
-    def from_text(cls, text_codes, stream=None):
-        """Host SA/BWT construction, then the device build."""
+    def from_text(cls, text_codes, stream=None, locate_rate: int = 0):
+        """Host SA/BWT construction, then the device build; with locate_rate > 0 also the
+        suffix-array sample at that rate, attached for locate."""
         import numpy as np
-        bwt, dollar = quadfm_bwt_host(text_codes)
-        d = torch.from_numpy(bwt.view(np.int64)).cuda()
-        return cls(d, int(np.asarray(text_codes).size) + 1, dollar, stream)
+        n1 = int(np.asarray(text_codes).size) + 1
+        if not locate_rate:
+            bwt, dollar = quadfm_bwt_host(text_codes)
+            return cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream)
+        bwt, dollar, marks, samples = quadfm_index_host(text_codes, locate_rate)
+        fm = cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream)
+        fm.attach_locate(torch.from_numpy(marks.view(np.int64)).cuda(), torch.from_numpy(samples.view(np.int32)).cuda(),
+                         locate_rate, stream)
+        return fm
+
+    def attach_locate(self, marks: torch.Tensor, samples: torch.Tensor, rate: int, stream=None):
+        quadfm_locate_attach(self.h, marks, samples, rate, stream)
+
+    def intervals(self, pat: torch.Tensor, off: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """(npat, 2) u32 (as int32) BWT intervals [sp, ep) of every pattern."""
+        if out is None:
+            out = torch.empty((off.numel() - 1, 2), dtype=torch.int32, device=off.device)
+        return quadfm_intervals(self.h, pat, off, out, stream)
+
+    def locate(self, pat: torch.Tensor, off: torch.Tensor, stream=None):
+        """(start, pos): pattern i occurs at text positions pos[start[i]:start[i+1]] (u32 as int32,
+        suffix-array order).  Synchronises once to size the output."""
+        npat = off.numel() - 1
+        iv = self.intervals(pat, off, stream=stream)
+        start = torch.empty(npat + 1, dtype=torch.int64, device=off.device)
+        quadfm_locate_offsets(self.h, iv, start, stream)
+        quadfm_check(self.h, stream)  # the offsets are final once the stream has drained
+        total = int(start[npat].item())
+        pos = torch.empty(max(total, 1), dtype=torch.int32, device=off.device)[:total]
+        if total:
+            quadfm_locate(self.h, iv, start, total, pos, stream)
+        return start, pos
 
     def count(self, pat: torch.Tensor, off: torch.Tensor, out: torch.Tensor | None = None, stream=None,
               both_strands: bool = False):

@@ -23,47 +23,13 @@
 #include <new>
 
 #include "common.hpp"
+#include "birank_dev.hpp"
 
 using namespace qr;
 
 namespace {
 
-struct BR16 {
-    static constexpr uint32_t HDR = 16, DATA = 1008, MID = 512;
-    static constexpr uint64_t SB_LINES = 64;     // lines per superblock
-    static constexpr uint32_t SB_LOG = 6;
-    static constexpr uint32_t SHIFT = 10;
-    static constexpr uint64_t MAGIC = 0x8208208208208209ull;  // ceil(2^73 / 1008)
-    static constexpr uint32_t MAGIC_T = 9;
-    static constexpr uint64_t MAX_N = (1ull << 42) - 1;
-    using Super = uint32_t;
-    __device__ __forceinline__ static uint64_t offset(const Super *__restrict__ s, uint64_t j) {
-        return (uint64_t)s[j >> SB_LOG] << SHIFT;
-    }
-    __device__ __forceinline__ static uint32_t delta(uint32_t w0) { return w0 & 0xffffu; }
-};
-
-// 32-bit inline deltas: floor(x/992) = mulhi(x, ceil(2^73/992)) >> 9, exact for x < 2^63
-// (e = m*992 - 2^73 = 736 < 992, Granlund-Montgomery).
-struct BR32 {
-    static constexpr uint32_t HDR = 32, DATA = 992, MID = 512;
-    static constexpr uint64_t SB_LINES = 1ull << 22;
-    static constexpr uint32_t SB_LOG = 22;
-    static constexpr uint32_t SHIFT = 0;
-    static constexpr uint64_t MAGIC = 0x8421084210842109ull;  // ceil(2^73 / 992)
-    static constexpr uint32_t MAGIC_T = 9;
-    static constexpr uint64_t MAX_N = (1ull << 48) - 1;
-    using Super = uint64_t;
-    __device__ __forceinline__ static uint64_t offset(const Super *__restrict__ s, uint64_t j) { return s[j >> SB_LOG]; }
-    __device__ __forceinline__ static uint32_t delta(uint32_t w0) { return w0; }
-};
-
 constexpr uint32_t GROUP_LINES = 64;  // lines per build workgroup (BR16: one superblock)
-
-template <class L>
-__host__ __device__ __forceinline__ uint64_t line_of(uint64_t q) {
-    return mulhi64(q, L::MAGIC) >> L::MAGIC_T;
-}
 
 }  // namespace
 
@@ -166,15 +132,6 @@ __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict
     }
 }
 
-// Masked popcount of one 512-bit half line given as 16 u32 words.  Counts positions [0, t) of the
-// half when `upper`, and positions [t, 512) otherwise.
-__device__ __forceinline__ uint32_t half_count(const uint32_t (&h)[16], uint32_t t, bool upper) {
-    const uint32_t inv = upper ? 0u : 0xffffffffu;
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) c += __popc(h[k] & (prefix_mask32(t, k) ^ inv));
-    return c;
-}
 
 // One lane per query: the lane loads the half holding q, plus the line's first word for the delta
 // when q lies in the upper half.  PER_LANE independent queries per lane, loads before popcounts.

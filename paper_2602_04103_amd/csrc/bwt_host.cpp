@@ -121,8 +121,12 @@ struct Sais {
     }
 };
 
+// BWT of T$ and, when rate > 0, the suffix-array sample for locate: row k is marked (bit k of
+// mark_bits) iff SA[k] is a multiple of rate, and samples[] lists SA[k] of the marked rows in row
+// order (positions 0, rate, 2 rate, ... <= n: floor(n/rate) + 1 of them).
 template <typename Idx>
-int bwt_from_text(const uint8_t *text, uint64_t n, uint64_t *bwt_packed, uint64_t *dollar_pos) {
+int bwt_from_text(const uint8_t *text, uint64_t n, uint64_t *bwt_packed, uint64_t *dollar_pos, uint32_t rate,
+                  uint64_t *mark_bits, uint32_t *samples) {
     // s = text codes + 1 followed by the sentinel 0.
     std::vector<uint8_t> s;
     std::vector<Idx> SA;
@@ -146,16 +150,33 @@ int bwt_from_text(const uint8_t *text, uint64_t n, uint64_t *bwt_packed, uint64_
         bwt_packed[k / 32] |= code << (2 * (k % 32));
     }
     *dollar_pos = dpos;
+    if (rate) {
+        std::memset(mark_bits, 0, ((n + 1 + 63) / 64) * 8);
+        uint64_t m = 0;
+        for (uint64_t k = 0; k <= n; ++k) {
+            const uint64_t j = (uint64_t)SA[k];
+            if (j % rate == 0) {
+                mark_bits[k / 64] |= 1ull << (k % 64);
+                samples[m++] = (uint32_t)j;
+            }
+        }
+    }
     return QR_OK;
 }
 
 }  // namespace
 
-extern "C" int quadfm_bwt_host(const uint8_t *h_text, uint64_t n, uint64_t *h_bwt_packed2, uint64_t *dollar_pos) {
-    if ((!h_text && n) || !h_bwt_packed2 || !dollar_pos) return QR_EINVAL;
+extern "C" int quadfm_index_host(const uint8_t *h_text, uint64_t n, uint32_t rate, uint64_t *h_bwt_packed2,
+                                 uint64_t *dollar_pos, uint64_t *h_mark_bits, uint32_t *h_samples) {
+    if ((!h_text && n) || !h_bwt_packed2 || !dollar_pos || (rate && (!h_mark_bits || !h_samples))) return QR_EINVAL;
     if (n + 1 > 0xffffffffull) return QR_ERANGE;  // the FM-index counts are u32 intervals
     for (uint64_t i = 0; i < n; ++i)
         if (h_text[i] > 3) return QR_EINVAL;
-    if (n + 1 < 0x7fffffffull) return bwt_from_text<int32_t>(h_text, n, h_bwt_packed2, dollar_pos);
-    return bwt_from_text<int64_t>(h_text, n, h_bwt_packed2, dollar_pos);
+    if (n + 1 < 0x7fffffffull)
+        return bwt_from_text<int32_t>(h_text, n, h_bwt_packed2, dollar_pos, rate, h_mark_bits, h_samples);
+    return bwt_from_text<int64_t>(h_text, n, h_bwt_packed2, dollar_pos, rate, h_mark_bits, h_samples);
+}
+
+extern "C" int quadfm_bwt_host(const uint8_t *h_text, uint64_t n, uint64_t *h_bwt_packed2, uint64_t *dollar_pos) {
+    return quadfm_index_host(h_text, n, 0, h_bwt_packed2, dollar_pos, nullptr, nullptr);
 }

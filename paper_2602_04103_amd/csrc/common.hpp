@@ -31,10 +31,10 @@ int check_device(int dev);
 // Number of compute units of the current device (cached per device).
 int cu_count();
 
-// Build pass 2 (scan.hip): exclusive prefix sums of `ncol` interleaved u32 count columns.
 // Host-side line index of the 32-bit BiRank layout (defined with its kernels).
 uint64_t br32_line_of_host(uint64_t x);
 
+// Build pass 2 (scan.hip): exclusive prefix sums of `ncol` interleaved u32 count columns.
 hipError_t launch_scan_counts(const uint32_t *cnt, uint64_t nrow, int ncol, uint32_t shift, uint64_t *base,
                               uint32_t *super, hipStream_t s);
 

@@ -17,9 +17,19 @@
 //                         lanes finish, the wave claims as many new patterns as it has idle lanes
 //                         with one atomic add on the queue head, so no lane idles while work remains
 //                         (the GPU counterpart of the paper's active list with swap-pop).
+// Both can write the final BWT interval [sp, ep) instead of its size (the paper's query_batch
+// returns intervals).
+//
+// Locate (the extension the paper's closing section proposes), with a text-position sample of the
+// suffix array: row k is marked iff SA[k] is a multiple of the sampling rate s, a BiRank over the
+// n+1 mark bits gives each marked row its index into the stored SA values, and SA[k] of an
+// unmarked row is found by LF steps, k <- C[B[k]] + rank_B(k, B[k]) (each steps one text position
+// back), until a marked row: SA[k] = sample + steps, at most s - 1 steps.  The row of '$' has
+// SA = 0 and is always marked, so the walk never steps through '$'.
 #include <algorithm>
 #include <new>
 
+#include "birank_dev.hpp"
 #include "common.hpp"
 #include "quadrank_dev.hpp"
 
@@ -39,8 +49,13 @@ struct qr_quadfm_s {
     uint32_t *super;
     uint2 *table;                // 4^8 intervals (sp, ep)
     unsigned long long *head;    // device work-queue head
-    uint32_t *err;
+    uint32_t *err;               // sticky device error word (locate)
     qr_tuning tune;              // persistent kernel: block, refill threshold (per_lane), waves per CU
+    // locate support (absent until quadfm_locate_attach)
+    qr_birank marks;             // BiRank (16-bit layout) over the n+1 mark bits
+    uint32_t *samples;           // SA values of the marked rows, in row order
+    uint64_t n_samples;
+    uint32_t rate;
 };
 
 namespace {
@@ -247,10 +262,23 @@ __device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &
     return true;
 }
 
-template <bool BOTH>
+// Write a finished pattern's result: its count, or (IV) its final interval, [0, 0) when empty.
+template <bool IV>
+__device__ __forceinline__ void emit(const FmDev &f, uint32_t *__restrict__ out, uint64_t p, const Search &s,
+                                     uint32_t cnt) {
+    if (!IV) {
+        out[p] = cnt;
+        return;
+    }
+    uint2 v = make_uint2(0u, 0u);
+    if (cnt) v = s.m == 0 ? make_uint2(0u, (uint32_t)f.n1) : make_uint2((uint32_t)s.sp, (uint32_t)s.ep);
+    reinterpret_cast<uint2 *>(out)[p] = v;
+}
+
+template <bool BOTH, bool IV>
 __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                        const uint64_t *__restrict__ off, uint64_t p0, uint64_t np,
-                                                       uint32_t *__restrict__ count) {
+                                                       uint32_t *__restrict__ out) {
     const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
     const uint64_t p = p0 + k;
@@ -259,15 +287,15 @@ __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *_
     if (!fm_init<BOTH>(f, pat, off, p, s, cnt))
         while (!fm_advance<BOTH>(f, s, cnt)) {
         }
-    count[p] = cnt;
+    emit<IV>(f, out, p, s, cnt);
 }
 
 __global__ void fill_zero_u64(unsigned long long *p) { *p = 0ull; }
 
-template <bool BOTH>
+template <bool BOTH, bool IV>
 __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                             const uint64_t *__restrict__ off, uint64_t npat,
-                                                            uint32_t *__restrict__ count,
+                                                            uint32_t *__restrict__ out,
                                                             unsigned long long *__restrict__ head, uint32_t refill_min) {
     const uint32_t lane = __lane_id();
     bool active = false, drained = false;
@@ -296,7 +324,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
                     if (mine < npat) {
                         p = mine;
                         uint32_t cnt = 0;
-                        if (fm_init<BOTH>(f, pat, off, p, s, cnt)) count[p] = cnt;
+                        if (fm_init<BOTH>(f, pat, off, p, s, cnt)) emit<IV>(f, out, p, s, cnt);
                         else active = true;
                     }
                 }
@@ -309,15 +337,107 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
         if (active) {
             uint32_t cnt = 0;
             if (fm_advance<BOTH>(f, s, cnt)) {
-                count[p] = cnt;
+                emit<IV>(f, out, p, s, cnt);
                 active = false;
             }
         }
     }
 }
 
+// ---- locate ---------------------------------------------------------------------------------------
+// start[i] = sum over k < i of (ep_k - sp_k), i = 0..npat, by one workgroup walking the intervals in
+// tiles of 1024 x 8 (each lane 8 consecutive entries) and carrying the running total.
+constexpr int ISCAN_THREADS = 1024, ISCAN_ITEMS = 8;
+
+__global__ __launch_bounds__(ISCAN_THREADS) void iv_scan_kernel(const uint2 *__restrict__ iv, uint64_t npat,
+                                                                unsigned long long *__restrict__ start) {
+    __shared__ uint64_t wave_tot[ISCAN_THREADS / 64];
+    __shared__ uint64_t tile_total;
+    const uint32_t t = threadIdx.x;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < npat; base += (uint64_t)ISCAN_THREADS * ISCAN_ITEMS) {
+        const uint64_t i0 = base + (uint64_t)t * ISCAN_ITEMS;
+        uint64_t v[ISCAN_ITEMS], mine = 0;
+#pragma unroll
+        for (int k = 0; k < ISCAN_ITEMS; ++k) {
+            const uint64_t i = i0 + k;
+            uint64_t len = 0;
+            if (i < npat) {
+                const uint2 e = iv[i];
+                len = e.y > e.x ? e.y - e.x : 0u;
+            }
+            v[k] = mine;
+            mine += len;
+        }
+        const uint64_t incl = wave_inclusive_scan<uint64_t>(mine);
+        if (__lane_id() == 63) wave_tot[t / 64] = incl;
+        __syncthreads();
+        uint64_t before = carry + incl - mine;
+        for (uint32_t w = 0; w < t / 64; ++w) before += wave_tot[w];
+        if (t == ISCAN_THREADS - 1) tile_total = before + mine - carry;
+#pragma unroll
+        for (int k = 0; k < ISCAN_ITEMS; ++k)
+            if (i0 + k < npat) start[i0 + k] = before + v[k];
+        __syncthreads();
+        carry += tile_total;
+        __syncthreads();
+    }
+    if (t == 0) start[npat] = carry;
+}
+
+struct LocDev {
+    const uint4 *mlines;      // BiRank (16-bit layout) over the mark bits
+    const uint32_t *msuper;
+    const uint32_t *samples;  // SA values of the marked rows
+    uint32_t rate;
+};
+
+// SA[row] by LF steps to the nearest marked row (at most rate - 1 of them); false if none is
+// reached within rate steps, which only inconsistent sample data can cause.
+__device__ __forceinline__ bool sa_of_row(const FmDev &f, const LocDev &d, uint64_t row, uint32_t &pos) {
+    for (uint32_t steps = 0; steps < d.rate && row < f.n1; ++steps) {
+        uint32_t marked = 0;
+        const uint64_t k = br_rank_bit<BR16>(d.mlines, d.msuper, row, marked);
+        if (marked) {
+            pos = d.samples[k] + steps;
+            return true;
+        }
+        HalfLine h;
+        load_half(f.lines, f.super, row, h);
+        const uint32_t c = symbol_from_half(h);
+        row = fm_C(f, c) + rank_bwt(f, h, row, c);
+    }
+    return false;
+}
+
+// One lane per output: output g belongs to the last pattern p with start[p] <= g, and is
+// SA[sp_p + g - start[p]].
+__global__ __launch_bounds__(256) void fm_locate_kernel(FmDev f, LocDev d, const uint2 *__restrict__ iv,
+                                                        const unsigned long long *__restrict__ start, uint64_t npat,
+                                                        uint64_t total, uint32_t *__restrict__ pos,
+                                                        uint32_t *__restrict__ err) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        uint64_t lo = 0, hi = npat;  // start[lo] <= g < start[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (start[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t row = iv[lo].x + (g - start[lo]);
+        uint32_t v = 0;
+        if (!sa_of_row(f, d, row, v)) {
+            v = 0xffffffffu;
+            atomicOr(err, 1u);
+        }
+        pos[g] = v;
+    }
+}
+
 void release(qr_quadfm_s *h) {
     if (!h) return;
+    if (h->marks) (void)birank_free(h->marks);
+    if (h->samples) (void)hipFree(h->samples);
     if (h->lines) (void)hipFree(h->lines);
     if (h->super) (void)hipFree(h->super);
     if (h->table) (void)hipFree(h->table);
@@ -430,8 +550,9 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
     return QR_OK;
 }
 
+// flags: QUADFM_BOTH_STRANDS; iv: write intervals (uint2 per pattern) instead of counts
 static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
-                            unsigned long long *head, uint32_t flags, hipStream_t stream) {
+                            unsigned long long *head, uint32_t flags, bool iv, hipStream_t stream) {
     const int block = h->tune.block ? h->tune.block : 256;
     const uint32_t refill = h->tune.per_lane > 0 ? (uint32_t)h->tune.per_lane : 16u;
     const int wpc = h->tune.grid_waves > 0 ? h->tune.grid_waves : 16;
@@ -440,12 +561,16 @@ static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d
     blocks = std::max<uint64_t>(1, std::min(blocks, need));
     hipLaunchKernelGGL(fill_zero_u64, dim3(1), dim3(1), 0, stream, head);
     QR_HIP(hipGetLastError());
-    if (flags & QUADFM_BOTH_STRANDS)
-        hipLaunchKernelGGL(fm_persistent_kernel<true>, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat,
-                           d_off, npat, d_count, head, refill);
+    const dim3 g((uint32_t)blocks), b(block);
+    if (iv)
+        hipLaunchKernelGGL((fm_persistent_kernel<false, true>), g, b, 0, stream, dev_view(h), d_pat, d_off, npat, d_count,
+                           head, refill);
+    else if (flags & QUADFM_BOTH_STRANDS)
+        hipLaunchKernelGGL((fm_persistent_kernel<true, false>), g, b, 0, stream, dev_view(h), d_pat, d_off, npat, d_count,
+                           head, refill);
     else
-        hipLaunchKernelGGL(fm_persistent_kernel<false>, dim3((uint32_t)blocks), dim3(block), 0, stream, dev_view(h), d_pat,
-                           d_off, npat, d_count, head, refill);
+        hipLaunchKernelGGL((fm_persistent_kernel<false, false>), g, b, 0, stream, dev_view(h), d_pat, d_off, npat, d_count,
+                           head, refill);
     QR_HIP(hipGetLastError());
     return QR_OK;
 }
@@ -464,7 +589,19 @@ int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, ui
     }
     if (!npat) return QR_OK;
     unsigned long long *head = d_workspace ? reinterpret_cast<unsigned long long *>(d_workspace) : h->head;
-    return count_persistent(h, d_pat, d_off, npat, d_count, head, flags, stream);
+    return count_persistent(h, d_pat, d_off, npat, d_count, head, flags, false, stream);
+}
+
+int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_iv,
+                     hipStream_t stream) {
+    int rc = count_args(h, d_pat, d_off, npat, d_iv, "quadfm_intervals");
+    if (rc) return rc;
+    if ((uintptr_t)d_iv & 7) {
+        set_error("quadfm_intervals: d_iv must be 8-byte aligned");
+        return QR_EINVAL;
+    }
+    if (!npat) return QR_OK;
+    return count_persistent(h, d_pat, d_off, npat, d_iv, h->head, 0u, true, stream);
 }
 
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
@@ -499,11 +636,11 @@ int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d
             return QR_EINVAL;
         }
         if (flags & QUADFM_BOTH_STRANDS)
-            hipLaunchKernelGGL(fm_batch_kernel<true>, dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off, p0, np,
-                               d_count);
+            hipLaunchKernelGGL((fm_batch_kernel<true, false>), dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off,
+                               p0, np, d_count);
         else
-            hipLaunchKernelGGL(fm_batch_kernel<false>, dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off, p0,
-                               np, d_count);
+            hipLaunchKernelGGL((fm_batch_kernel<false, false>), dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat,
+                               d_off, p0, np, d_count);
         QR_HIP(hipGetLastError());
     }
     return QR_OK;
@@ -518,7 +655,116 @@ int quadfm_check(qr_quadfm h, hipStream_t stream) {
     if (!h) return QR_EINVAL;
     int rc = check_device(h->device);
     if (rc) return rc;
+    uint32_t v = 0;
     QR_HIP(hipStreamSynchronize(stream));
+    QR_HIP(hipMemcpy(&v, h->err, 4, hipMemcpyDeviceToHost));
+    QR_HIP(hipMemset(h->err, 0, 4));
+    if (v) {
+        set_error("quadfm: a locate walk reached no sampled row (inconsistent mark bits or samples)");
+        return QR_ERANGE;
+    }
+    return QR_OK;
+}
+
+int quadfm_locate_attach(qr_quadfm h, const uint64_t *d_mark_bits, const uint32_t *d_samples, uint64_t n_samples,
+                         uint32_t rate, hipStream_t stream) {
+    if (!h || !d_mark_bits || !d_samples || rate == 0 || ((uintptr_t)d_mark_bits & 7) || ((uintptr_t)d_samples & 3)) {
+        set_error("quadfm_locate_attach: null or misaligned pointer, or rate 0");
+        return QR_EINVAL;
+    }
+    int rc = check_device(h->device);
+    if (rc) return rc;
+    const uint64_t n = h->n1 - 1;
+    if (n_samples != n / rate + 1) {
+        set_error("quadfm_locate_attach: %llu samples given; rate %u over n = %llu needs %llu",
+                  (unsigned long long)n_samples, rate, (unsigned long long)n, (unsigned long long)(n / rate + 1));
+        return QR_EINVAL;
+    }
+    qr_birank marks = nullptr;
+    rc = birank_build_ex(d_mark_bits, h->n1, QR_LAYOUT_16, stream, &marks);
+    if (rc) return rc;
+    // the marks must number n_samples and include the row of '$' (SA = 0)
+    uint64_t *dq = nullptr, *dr = nullptr, *samples = nullptr;
+    if (hipMalloc(&dq, 24) != hipSuccess || hipMalloc(&dr, 24) != hipSuccess ||
+        hipMalloc(&samples, n_samples * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        if (dq) (void)hipFree(dq);
+        if (dr) (void)hipFree(dr);
+        (void)birank_free(marks);
+        set_error("quadfm_locate_attach: device allocation failed");
+        return QR_ENOMEM;
+    }
+    const uint64_t q[3] = {h->n1, h->dollar, h->dollar + 1};
+    uint64_t r[3] = {0, 0, 0};
+    hipError_t e = hipMemcpyAsync(dq, q, 24, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) rc = birank_rank(marks, dq, 3, dr, stream);
+    if (e == hipSuccess && rc == QR_OK) e = hipMemcpyAsync(r, dr, 24, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && rc == QR_OK)
+        e = hipMemcpyAsync(samples, d_samples, n_samples * 4, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && rc == QR_OK) e = hipStreamSynchronize(stream);
+    (void)hipFree(dq);
+    (void)hipFree(dr);
+    if (e != hipSuccess || rc != QR_OK || r[0] != n_samples || r[2] - r[1] != 1) {
+        (void)hipFree(samples);
+        (void)birank_free(marks);
+        if (e != hipSuccess) {
+            set_error("quadfm_locate_attach: %s", hipGetErrorString(e));
+            return QR_EHIP;
+        }
+        if (rc != QR_OK) return rc;
+        set_error("quadfm_locate_attach: %llu rows marked (need %llu) or the row of '$' unmarked",
+                  (unsigned long long)r[0], (unsigned long long)n_samples);
+        return QR_EINVAL;
+    }
+    if (h->marks) (void)birank_free(h->marks);
+    if (h->samples) (void)hipFree(h->samples);
+    h->marks = marks;
+    h->samples = reinterpret_cast<uint32_t *>(samples);
+    h->n_samples = n_samples;
+    h->rate = rate;
+    return QR_OK;
+}
+
+int quadfm_locate_offsets(qr_quadfm h, const uint32_t *d_iv, uint64_t npat, uint64_t *d_start, hipStream_t stream) {
+    if (!h || !d_start || (npat && !d_iv) || ((uintptr_t)d_iv & 7) || ((uintptr_t)d_start & 7)) {
+        set_error("quadfm_locate_offsets: null or misaligned pointer");
+        return QR_EINVAL;
+    }
+    int rc = check_device(h->device);
+    if (rc) return rc;
+    hipLaunchKernelGGL(iv_scan_kernel, dim3(1), dim3(ISCAN_THREADS), 0, stream, reinterpret_cast<const uint2 *>(d_iv), npat,
+                       reinterpret_cast<unsigned long long *>(d_start));
+    QR_HIP(hipGetLastError());
+    return QR_OK;
+}
+
+int quadfm_locate(qr_quadfm h, const uint32_t *d_iv, const uint64_t *d_start, uint64_t npat, uint64_t total,
+                  uint32_t *d_pos, hipStream_t stream) {
+    if (!h || (total && (!d_iv || !d_start || !d_pos || !npat)) || ((uintptr_t)d_iv & 7) || ((uintptr_t)d_start & 7) ||
+        ((uintptr_t)d_pos & 3)) {
+        set_error("quadfm_locate: null or misaligned pointer, or outputs without patterns");
+        return QR_EINVAL;
+    }
+    if (!h->marks) {
+        set_error("quadfm_locate: no suffix-array sample attached (quadfm_locate_attach)");
+        return QR_EINVAL;
+    }
+    int rc = check_device(h->device);
+    if (rc) return rc;
+    if (!total) return QR_OK;
+    const void *ml = nullptr, *ms = nullptr;
+    rc = birank_layout(h->marks, &ml, nullptr, &ms, nullptr);
+    if (rc) return rc;
+    LocDev d;
+    d.mlines = reinterpret_cast<const uint4 *>(ml);
+    d.msuper = reinterpret_cast<const uint32_t *>(ms);
+    d.samples = h->samples;
+    d.rate = h->rate;
+    const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, (uint64_t)cu_count() * 32));
+    hipLaunchKernelGGL(fm_locate_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, dev_view(h), d,
+                       reinterpret_cast<const uint2 *>(d_iv), reinterpret_cast<const unsigned long long *>(d_start), npat,
+                       total, d_pos, h->err);
+    QR_HIP(hipGetLastError());
     return QR_OK;
 }
 
@@ -529,7 +775,9 @@ int quadfm_free(qr_quadfm h) {
 
 uint64_t quadfm_len(qr_quadfm h) { return h ? h->n1 - 1 : 0; }
 uint64_t quadfm_bytes(qr_quadfm h) {
-    return h ? h->n_lines * 128 + h->n_sb * 16 + KMER_ENTRIES * sizeof(uint2) : 0;
+    if (!h) return 0;
+    return h->n_lines * 128 + h->n_sb * 16 + KMER_ENTRIES * sizeof(uint2) +
+           (h->marks ? birank_bytes(h->marks) + h->n_samples * 4 : 0);
 }
 
 int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t) {

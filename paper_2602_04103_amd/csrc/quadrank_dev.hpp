@@ -75,6 +75,23 @@ __device__ __forceinline__ uint64_t rank1_from_half(const HalfLine &hl, uint32_t
     return hl.up ? mid + cnt : mid - cnt;
 }
 
+// The symbol stored at the slot of q (the half line's slot t), picked with masks.
+__device__ __forceinline__ uint32_t symbol_from_half(const HalfLine &hl) {
+    const uint32_t word = hl.t >> 5;  // 32-slot word of the half: pair word >> 1, its low/high u32 word & 1
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+#pragma unroll
+        for (uint32_t sub = 0; sub < 2; ++sub) {
+            const uint32_t m = (word == 2 * k + sub) ? 0xffffffffu : 0u;
+            lo |= hl.w[4 * k + sub] & m;
+            hi |= hl.w[4 * k + 2 + sub] & m;
+        }
+    }
+    const uint32_t b = hl.t & 31u;
+    return ((lo >> b) & 1u) | (((hi >> b) & 1u) << 1);
+}
+
 __device__ __forceinline__ void rank4_from_half(const HalfLine &hl, uint64_t (&r)[4]) {
     const uint32_t inv = hl.up ? 0u : 0xffffffffu;
     uint32_t cT = 0, cL = 0, cH = 0;

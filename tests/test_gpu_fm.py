@@ -136,14 +136,15 @@ def test_fm_config3_full_sampled():
     """Text of 2^28 bases with 1000 planted 10-kb repeats x 20 copies; 10^7 patterns (lengths
     20..250, 90% sampled with 1% substitutions, 10% iid).  All counts come from the persistent
     kernel; 200 sampled patterns are recounted by the oracle's direct scan, and the per-batch
-    kernel must agree with the persistent one on every pattern."""
+    kernel must agree with the persistent one on every pattern.  Intervals and locate (SA sampled
+    at rate 32) are checked on the same index."""
     qr = require_gpu()
     n = 1 << 28
     codes = datagen.dna_codes(2028, n)
     datagen.plant_repeats(2029, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
     pat, off, kind = datagen.patterns(2030, codes, 10 ** 7)
     announce("fm-config3 build")
-    fm = qr.QuadFm.from_text(codes)
+    fm = qr.QuadFm.from_text(codes, locate_rate=32)
     announce("fm-config3 count")
     dp, do = to_dev(pat), to_dev(off)
     got = fm.count(dp, do).cpu().numpy().view(np.uint32)
@@ -156,6 +157,20 @@ def test_fm_config3_full_sampled():
     want = oracle.count_naive(codes, spat, soff).astype(np.uint32)
     assert np.array_equal(got[sample], want)
     assert got.max() <= n
+    # intervals have the counted sizes; locate on the sample returns that many distinct positions,
+    # each a true occurrence (so exactly the occurrence set), in suffix order
+    iv = fm.intervals(dp, do).cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal((iv[:, 1] - iv[:, 0]).astype(np.uint32), got)
+    announce("fm-config3 locate")
+    start, pos = fm.locate(to_dev(spat), to_dev(soff))
+    start, pos = start.cpu().numpy(), pos.cpu().numpy().view(np.uint32).astype(np.int64)
+    for k in range(len(sp)):
+        ps = pos[start[k]:start[k + 1]]
+        assert ps.size == want[k] and np.unique(ps).size == ps.size
+        for x in ps:
+            assert np.array_equal(codes[x:x + sp[k].size], sp[k])
+        sufs = [codes[x:x + 300].tobytes() for x in ps]          # 300 > pattern length: order by suffix
+        assert all(a <= b for a, b in zip(sufs, sufs[1:]))
 
 
 @pytest.mark.parametrize("n", [3, 5000, 200_000])

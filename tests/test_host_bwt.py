@@ -44,3 +44,24 @@ def test_bwt_rejects_bad_codes():
     import paper_2602_04103_amd as qr
     with pytest.raises(qr.QRError):
         qr.quadfm_bwt_host(np.array([0, 1, 4, 2], np.uint8))
+
+
+@pytest.mark.parametrize("n,rate", [(0, 1), (1, 1), (5, 2), (100, 7), (1000, 32), (20000, 32), (4097, 4096)])
+def test_index_host_sa_sample(n, rate):
+    """Mark bit k is set iff SA[k] is a multiple of rate, and the samples are SA of the marked rows in
+    row order (oracle suffix array); the BWT is the same as without the sample."""
+    import paper_2602_04103_amd as qr
+    codes = datagen.dna_codes(2000 + n, n)
+    if n >= 1000:
+        datagen.plant_repeats(7, codes, nseg=3, seglen=200, copies=4, sub=0.01)
+    packed, dollar, marks, samples = qr.quadfm_index_host(codes, rate)
+    p2, d2 = qr.quadfm_bwt_host(codes)
+    assert dollar == d2 and np.array_equal(packed, p2)
+    sa = oracle.suffix_array(codes).astype(np.int64)
+    bits = np.unpackbits(marks.view(np.uint8), bitorder="little")
+    want = (sa % rate == 0)
+    assert np.array_equal(bits[:n + 1].astype(bool), want)
+    assert not bits[n + 1:].any()
+    assert samples.size == n // rate + 1
+    assert np.array_equal(samples.astype(np.int64), sa[want])
+    assert bits[dollar] == 1                       # SA = 0 at the row of '$'
