@@ -11,8 +11,9 @@ around each launch on the stream the kernels run on.
 
 The FM-index rows run the batched-count configuration (2^28-base text with the same repeat
 planting, 10^7 patterns of length 20..250, 90% sampled with 1% substitutions, 10% iid) with the
-persistent work-queue kernel and with one plain launch per batch, in their own timed loop.
-The CPU baseline times the oracle on the host cores on a bounded sample of the same workload.
+persistent work-queue kernel and with one plain launch per batch, in their own timed loop, then
+locate every occurrence of every pattern (intervals, output offsets, LF walks over a suffix-array
+sample at rate 32).  The CPU baseline times the oracle on the host cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -76,6 +77,8 @@ def main():
     ap.add_argument("--no-fm", action="store_true", help="skip the FM-index rows")
     ap.add_argument("--fm-patterns", type=int, default=10 ** 7)
     ap.add_argument("--fm-reps", type=int, default=3)
+    ap.add_argument("--fm-locate-rate", type=int, default=32,
+                    help="suffix-array sampling rate of the locate measurement (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
@@ -361,9 +364,17 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     codes = datagen.dna_codes(2828, n)
     datagen.plant_repeats(2829, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
     t1 = time.time()
-    bwt, dollar = qr.quadfm_bwt_host(codes)
+    rate = args.fm_locate_rate
+    if rate:
+        bwt, dollar, marks, samples = qr.quadfm_index_host(codes, rate)
+    else:
+        bwt, dollar = qr.quadfm_bwt_host(codes)
     t2 = time.time()
     fm = qr.QuadFm(to_dev(bwt), n + 1, dollar)
+    count_bytes = fm.nbytes
+    if rate:
+        fm.attach_locate(to_dev(marks), torch.from_numpy(samples.view(np.int32)).to(dev), rate)
+        del marks, samples
     torch.cuda.synchronize()
     t3 = time.time()
     pat, off, kind = datagen.patterns(2830, codes, args.fm_patterns)
@@ -388,7 +399,7 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
                        "+ sentinel; %d patterns, lengths 20..250, 90%% sampled with 1%% substitutions, 10%% iid"
                        % npat,
            "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3, "tuning": best,
-           "index_bytes": fm.nbytes, "bits_per_base": fm.nbytes * 8 / n, "pattern_chars": total_chars,
+           "index_bytes": count_bytes, "bits_per_base": count_bytes * 8 / n, "pattern_chars": total_chars,
            "host_sa_bwt_s": t2 - t1, "device_build_s": t3 - t2}
     for batch in (1 << 16, 1 << 20, 0):
         t_b = autotune.time_launch(lambda: fm.count_batched(dp, do, batch, cnt_b), reps=args.fm_reps)
@@ -400,6 +411,23 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     res["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
     log("fm persistent %.1f M patterns/s; batched best %.1f M; gain %.2fx; equal=%s" % (
         npat / t_p / 1e6, best_b / 1e6, res["gain_vs_best_batched"], res["persistent_equals_batched"]))
+    if rate:
+        # locate every occurrence of every pattern: intervals, output offsets, then the LF walks
+        iv = torch.empty((npat, 2), dtype=torch.int32, device=dev)
+        start = torch.empty(npat + 1, dtype=torch.int64, device=dev)
+        t_iv = autotune.time_launch(lambda: fm.intervals(dp, do, iv), reps=args.fm_reps)
+        t_off = autotune.time_launch(lambda: qr.quadfm_locate_offsets(fm.h, iv, start), reps=args.fm_reps)
+        total = int(start[npat].item())
+        pos = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+        t_loc = autotune.time_launch(lambda: qr.quadfm_locate(fm.h, iv, start, total, pos), reps=args.fm_reps)
+        fm.check()
+        res.update({"locate_rate": rate, "locate_sample_bytes": fm.nbytes - count_bytes, "locate_positions": total,
+                    "intervals_ms": t_iv * 1e3, "locate_offsets_ms": t_off * 1e3, "locate_ms": t_loc * 1e3,
+                    "locate_positions_per_s": total / t_loc,
+                    "locate_patterns_per_s_end_to_end": npat / (t_iv + t_off + t_loc),
+                    "intervals_sizes_equal_counts": bool(torch.equal(iv[:, 1] - iv[:, 0], cnt))})
+        log("fm locate (rate %d): %d positions, %.1f M positions/s; intervals %.2f ms, offsets %.2f ms, walks %.2f ms"
+            % (rate, total, total / t_loc / 1e6, t_iv * 1e3, t_off * 1e3, t_loc * 1e3))
     fm.free()
     return res
 

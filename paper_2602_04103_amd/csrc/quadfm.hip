@@ -345,44 +345,85 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
 }
 
 // ---- locate ---------------------------------------------------------------------------------------
-// start[i] = sum over k < i of (ep_k - sp_k), i = 0..npat, by one workgroup walking the intervals in
-// tiles of 1024 x 8 (each lane 8 consecutive entries) and carrying the running total.
-constexpr int ISCAN_THREADS = 1024, ISCAN_ITEMS = 8;
+// start[i] = sum over k < i of (ep_k - sp_k), i = 0..npat, in three passes over tiles of
+// ISCAN_TILE intervals without any workspace: (1) each tile's total goes to start[first index of
+// the tile]; (2) one workgroup turns those totals into exclusive tile offsets in place and writes
+// start[npat]; (3) each tile reads its offset, then scans its intervals over it.
+constexpr int ISCAN_BLOCK = 256, ISCAN_ITEMS = 16;
+constexpr uint64_t ISCAN_TILE = (uint64_t)ISCAN_BLOCK * ISCAN_ITEMS;
 
-__global__ __launch_bounds__(ISCAN_THREADS) void iv_scan_kernel(const uint2 *__restrict__ iv, uint64_t npat,
-                                                                unsigned long long *__restrict__ start) {
-    __shared__ uint64_t wave_tot[ISCAN_THREADS / 64];
-    __shared__ uint64_t tile_total;
+__device__ __forceinline__ uint64_t iv_len(const uint2 *__restrict__ iv, uint64_t i, uint64_t npat) {
+    if (i >= npat) return 0;
+    const uint2 e = iv[i];
+    return e.y > e.x ? e.y - e.x : 0u;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the exclusive prefix, total in *tot.
+__device__ __forceinline__ uint64_t block_exclusive(uint64_t v, uint64_t *wave_tot, uint64_t *tot) {
     const uint32_t t = threadIdx.x;
+    const uint64_t incl = wave_inclusive_scan<uint64_t>(v);
+    if (__lane_id() == 63) wave_tot[t / 64] = incl;
+    __syncthreads();
+    uint64_t before = incl - v, all = 0;
+    for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+        if (w < t / 64) before += wave_tot[w];
+        all += wave_tot[w];
+    }
+    *tot = all;
+    return before;
+}
+
+__global__ __launch_bounds__(ISCAN_BLOCK) void iv_tile_totals(const uint2 *__restrict__ iv, uint64_t npat,
+                                                              unsigned long long *__restrict__ start) {
+    __shared__ uint64_t wave_tot[ISCAN_BLOCK / 64];
+    const uint64_t i0 = blockIdx.x * ISCAN_TILE + (uint64_t)threadIdx.x * ISCAN_ITEMS;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < ISCAN_ITEMS; ++k) mine += iv_len(iv, i0 + k, npat);
+    uint64_t tot;
+    (void)block_exclusive(mine, wave_tot, &tot);
+    if (threadIdx.x == 0) start[blockIdx.x * ISCAN_TILE] = tot;
+}
+
+constexpr int ISCAN_TOP = 1024;
+
+__global__ __launch_bounds__(ISCAN_TOP) void iv_tile_offsets(uint64_t ntiles, uint64_t npat,
+                                                             unsigned long long *__restrict__ start) {
+    __shared__ uint64_t wave_tot[ISCAN_TOP / 64];
+    __shared__ uint64_t chunk_total;
     uint64_t carry = 0;
-    for (uint64_t base = 0; base < npat; base += (uint64_t)ISCAN_THREADS * ISCAN_ITEMS) {
-        const uint64_t i0 = base + (uint64_t)t * ISCAN_ITEMS;
-        uint64_t v[ISCAN_ITEMS], mine = 0;
-#pragma unroll
-        for (int k = 0; k < ISCAN_ITEMS; ++k) {
-            const uint64_t i = i0 + k;
-            uint64_t len = 0;
-            if (i < npat) {
-                const uint2 e = iv[i];
-                len = e.y > e.x ? e.y - e.x : 0u;
-            }
-            v[k] = mine;
-            mine += len;
-        }
-        const uint64_t incl = wave_inclusive_scan<uint64_t>(mine);
-        if (__lane_id() == 63) wave_tot[t / 64] = incl;
+    for (uint64_t b0 = 0; b0 < ntiles; b0 += ISCAN_TOP) {
+        const uint64_t b = b0 + threadIdx.x;
+        const uint64_t v = b < ntiles ? start[b * ISCAN_TILE] : 0;
+        uint64_t tot;
+        const uint64_t before = block_exclusive(v, wave_tot, &tot);
+        if (b < ntiles) start[b * ISCAN_TILE] = carry + before;
+        if (threadIdx.x == 0) chunk_total = tot;
         __syncthreads();
-        uint64_t before = carry + incl - mine;
-        for (uint32_t w = 0; w < t / 64; ++w) before += wave_tot[w];
-        if (t == ISCAN_THREADS - 1) tile_total = before + mine - carry;
-#pragma unroll
-        for (int k = 0; k < ISCAN_ITEMS; ++k)
-            if (i0 + k < npat) start[i0 + k] = before + v[k];
-        __syncthreads();
-        carry += tile_total;
+        carry += chunk_total;
         __syncthreads();
     }
-    if (t == 0) start[npat] = carry;
+    if (threadIdx.x == 0) start[npat] = carry;
+}
+
+__global__ __launch_bounds__(ISCAN_BLOCK) void iv_tile_scan(const uint2 *__restrict__ iv, uint64_t npat,
+                                                            unsigned long long *__restrict__ start) {
+    __shared__ uint64_t wave_tot[ISCAN_BLOCK / 64];
+    __shared__ uint64_t tile_off;
+    if (threadIdx.x == 0) tile_off = start[blockIdx.x * ISCAN_TILE];
+    __syncthreads();  // the offset is read before this tile overwrites its first entry
+    const uint64_t i0 = blockIdx.x * ISCAN_TILE + (uint64_t)threadIdx.x * ISCAN_ITEMS;
+    uint64_t v[ISCAN_ITEMS], mine = 0;
+#pragma unroll
+    for (int k = 0; k < ISCAN_ITEMS; ++k) {
+        v[k] = mine;
+        mine += iv_len(iv, i0 + k, npat);
+    }
+    uint64_t tot;
+    const uint64_t before = tile_off + block_exclusive(mine, wave_tot, &tot);
+#pragma unroll
+    for (int k = 0; k < ISCAN_ITEMS; ++k)
+        if (i0 + k < npat) start[i0 + k] = before + v[k];
 }
 
 struct LocDev {
@@ -732,9 +773,23 @@ int quadfm_locate_offsets(qr_quadfm h, const uint32_t *d_iv, uint64_t npat, uint
     }
     int rc = check_device(h->device);
     if (rc) return rc;
-    hipLaunchKernelGGL(iv_scan_kernel, dim3(1), dim3(ISCAN_THREADS), 0, stream, reinterpret_cast<const uint2 *>(d_iv), npat,
-                       reinterpret_cast<unsigned long long *>(d_start));
+    const uint2 *iv = reinterpret_cast<const uint2 *>(d_iv);
+    unsigned long long *st = reinterpret_cast<unsigned long long *>(d_start);
+    const uint64_t ntiles = (npat + ISCAN_TILE - 1) / ISCAN_TILE;
+    if (ntiles > 0x7fffffffull) {
+        set_error("quadfm_locate_offsets: npat too large");
+        return QR_EINVAL;
+    }
+    if (ntiles) {
+        hipLaunchKernelGGL(iv_tile_totals, dim3((uint32_t)ntiles), dim3(ISCAN_BLOCK), 0, stream, iv, npat, st);
+        QR_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(iv_tile_offsets, dim3(1), dim3(ISCAN_TOP), 0, stream, ntiles, npat, st);
     QR_HIP(hipGetLastError());
+    if (ntiles) {
+        hipLaunchKernelGGL(iv_tile_scan, dim3((uint32_t)ntiles), dim3(ISCAN_BLOCK), 0, stream, iv, npat, st);
+        QR_HIP(hipGetLastError());
+    }
     return QR_OK;
 }
 

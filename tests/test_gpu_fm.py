@@ -159,8 +159,14 @@ def test_fm_config3_full_sampled():
     assert got.max() <= n
     # intervals have the counted sizes; locate on the sample returns that many distinct positions,
     # each a true occurrence (so exactly the occurrence set), in suffix order
-    iv = fm.intervals(dp, do).cpu().numpy().view(np.uint32).astype(np.int64)
+    iv_d = fm.intervals(dp, do)
+    iv = iv_d.cpu().numpy().view(np.uint32).astype(np.int64)
     assert np.array_equal((iv[:, 1] - iv[:, 0]).astype(np.uint32), got)
+    # output offsets over all 10^7 intervals (thousands of scan tiles) = running sum of the counts
+    st = torch.empty(10 ** 7 + 1, dtype=torch.int64, device="cuda")
+    qr.quadfm_locate_offsets(fm.h, iv_d, st)
+    want_st = np.concatenate([[0], np.cumsum(got.astype(np.uint64))]).astype(np.uint64)
+    assert np.array_equal(st.cpu().numpy().view(np.uint64), want_st)
     announce("fm-config3 locate")
     start, pos = fm.locate(to_dev(spat), to_dev(soff))
     start, pos = start.cpu().numpy(), pos.cpu().numpy().view(np.uint32).astype(np.int64)
