@@ -90,8 +90,10 @@ __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict
                                                       uint64_t *__restrict__ lines) {
     constexpr uint32_t W = GROUP_LINES * L::DATA / 64;
     constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
-    __shared__ uint64_t in[W + 2];
-    __shared__ uint64_t stage[64 * OUT_STRIDE];
+    // one LDS buffer holds the group's input words, then (after a barrier) the staged output lines
+    constexpr uint32_t BUF = (W + 2 > 64 * OUT_STRIDE) ? W + 2 : 64 * OUT_STRIDE;
+    __shared__ uint64_t buf[BUF];
+    uint64_t *in = buf, *stage = buf;
     const uint64_t g = blockIdx.x;
     const int t = threadIdx.x;
     for (int k = t; k < (int)W + 2; k += 64) in[k] = k < (int)W ? masked_word(bits, g * W + k, n, n_words) : 0ull;
@@ -119,6 +121,7 @@ __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict
     const uint64_t off = (sb_base >> L::SHIFT) << L::SHIFT;
     const uint64_t delta = base[g] - off + before + c_first;
     o[0] |= delta;
+    __syncthreads();  // every lane has read its input words: the buffer now takes the output
 #pragma unroll
     for (int k = 0; k < 16; ++k) stage[t * OUT_STRIDE + k] = o[k];
     __syncthreads();

@@ -105,9 +105,11 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
     constexpr uint32_t W = GROUP_LINES * L::WORDS;
     constexpr uint32_t FIRST = (L::MID - L::HDR) / 32;   // packed words in the lower half
     constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
-    __shared__ uint64_t in[W];
-    __shared__ uint64_t stage[128 * OUT_STRIDE];
+    // one LDS buffer holds the group's input words, then (after a barrier) the staged output lines
+    constexpr uint32_t BUF = (W > 128 * OUT_STRIDE) ? W : 128 * OUT_STRIDE;
+    __shared__ uint64_t buf[BUF];
     __shared__ uint64_t wave_tot[2];
+    uint64_t *in = buf, *stage = buf;
     const uint64_t g = blockIdx.x;
     const int t = threadIdx.x;
     for (uint32_t k = t; k < W; k += 128) in[k] = masked_packed(packed, g * W + k, n, n_words);
@@ -159,6 +161,7 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
             o[2 * k + 1] = (uint64_t)hi[2 * k - 2] | ((uint64_t)hi[2 * k - 1] << 32);
         }
     }
+    __syncthreads();  // every lane has read its input words: the buffer now takes the output
 #pragma unroll
     for (int k = 0; k < 16; ++k) stage[t * OUT_STRIDE + k] = o[k];
     __syncthreads();
