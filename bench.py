@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
     ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8", help="offered loads, patterns/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
+    ap.add_argument("--serve-python", action="store_true",
+                    help="run the sweep with the Python scheduling loop instead of the native one")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
     ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05",
                     help="comma-separated rank rows of the step; quadrank_prefix_rank is an optional extra row")
@@ -435,7 +437,7 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
 def bench_serve(args, qr, datagen, np, torch, to_dev):
     """Poisson request arrivals against a device-resident index; each request holds 1..4096 patterns
     (log-uniform), lengths 20..250; offered loads swept; latency from arrival to counts on the host."""
-    from paper_2602_04103_amd.serve import GpuExecutor, Server, make_workload
+    from paper_2602_04103_amd.serve import GpuExecutor, NativeServer, Server, make_workload
     n = 1 << args.serve_log_n
     t0 = time.time()
     text = datagen.dna_codes(3030, n)
@@ -458,11 +460,19 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     ex0 = GpuExecutor(fm, w0, slots=slots, budget_bytes=budget)
     Server(ex0, slots=slots, budget_bytes=budget).run(w0, deadline_s=60.0)
     del ex0
+    ns0 = NativeServer(fm, slots=slots, budget_bytes=budget)
+    ns0.run(w0, deadline_s=60.0)
+    ns0.free()
+    res["loop"] = "python" if args.serve_python else "native"
     for k, load in enumerate(float(x) for x in args.serve_loads.split(",")):
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
-        ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)
-        srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
-                     free_bytes_fn=lambda: torch.cuda.mem_get_info()[0])
+        if args.serve_python:
+            ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)
+            srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
+                         free_bytes_fn=lambda: torch.cuda.mem_get_info()[0])
+        else:
+            ex = srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
+                                    check_free_memory=True)
         st = srv.run(w, deadline_s=120.0)
         summ = st.summary()
         summ["offered_patterns_per_s"] = load
@@ -470,6 +480,8 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
         summ["equal_to_direct_count"] = bool(np.array_equal(ex.counts(0, int(w.req_off[-1])), d_all))
         res["loads"].append(summ)
+        if not args.serve_python:
+            srv.free()
         log("serve load %.0e: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, %d batches, max in flight %d, equal=%s"
             % (load, summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6, summ["batches"],
                summ["max_inflight_batches"], summ["equal_to_direct_count"]))

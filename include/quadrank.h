@@ -240,6 +240,37 @@ int quadrank_set_tuning(qr_quadrank h, const qr_tuning *t);
 int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
 
 /* ------------------------------------------------------------------------------------------------
+ * Serving loop (continuous batching of FM-index count requests against a device-resident index).
+ * Requests r = 0..nreq-1 own patterns [h_req_off[r], h_req_off[r+1]) of the CSR (h_pat, h_off) and
+ * arrive at h_arrival_s[r] seconds after the run starts (non-decreasing).  Whenever one of `slots`
+ * streams is free, every request that has arrived is admitted first-in first-out as one batch of at
+ * most max_batch_patterns patterns (a larger single request is still admitted alone) whose device
+ * bytes fit the budget's first-fit arena; with QR_SERVE_CHECK_FREE_MEMORY, a batch larger than the
+ * device's free memory also waits.  Each batch copies its patterns in, counts them with the
+ * persistent kernel on its slot's stream and copies the counts to h_counts[h_req_off[r]..].
+ * h_finish_s[r] receives the time at which the host saw request r's batch complete.  For
+ * asynchronous copies, h_pat, h_off and h_counts should be pinned host memory (hipHostMalloc);
+ * pageable memory works but serialises the copies.  The server owns its arena, streams and queue
+ * heads; the index must outlive it.  run returns once every request is done (QR_ERANGE if
+ * deadline_s passes first or a request alone exceeds the budget), with no copy in flight.
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct qr_server_s *qr_server;
+#define QR_SERVE_CHECK_FREE_MEMORY 1u
+typedef struct {
+    uint64_t batches;            /* batches launched */
+    uint64_t max_inflight;       /* most batches in flight at once */
+    uint64_t max_reserved_bytes; /* most arena bytes reserved at once */
+    double wall_s;               /* run time */
+} qr_serve_stats;
+
+int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t max_batch_patterns, uint32_t flags,
+                     qr_server *out);
+int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, const uint64_t *h_req_off, uint64_t nreq,
+                  const double *h_arrival_s, uint32_t *h_counts, double *h_finish_s, double deadline_s,
+                  qr_serve_stats *stats);
+int qr_server_free(qr_server s);
+
+/* ------------------------------------------------------------------------------------------------
  * HIP graph capture of launch sequences.  Between qr_graph_begin(stream) and qr_graph_end(stream,
  * &g), calls to the enqueue-only entry points on `stream` (birank_rank, quadrank_rank,
  * quadrank_rank4, quadfm_count, quadfm_count_ws, quadfm_count_batched) are recorded instead of

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libquadrank.so")
 
 QR_OK, QR_EINVAL, QR_ENOMEM, QR_EHIP, QR_ERANGE, QR_EDEVICE = 0, -1, -2, -3, -4, -5
 QUADFM_BOTH_STRANDS = 1
+QR_SERVE_CHECK_FREE_MEMORY = 1
 QR_LAYOUT_16, QR_LAYOUT_32 = 0, 1
 
 
@@ -32,6 +33,11 @@ class QRError(RuntimeError):
 
 class qr_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("per_lane", C.c_int32), ("grid_waves", C.c_int32), ("lanes", C.c_int32)]
+
+
+class qr_serve_stats(C.Structure):
+    _fields_ = [("batches", C.c_uint64), ("max_inflight", C.c_uint64), ("max_reserved_bytes", C.c_uint64),
+                ("wall_s", C.c_double)]
 
 
 _lib = None
@@ -76,6 +82,9 @@ def lib():
             "quadrank_export": (ci, [vp, vp, vp]),
             "qr_gather_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
             "qr_gather_lanes_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
+            "qr_server_create": (ci, [vp, ci, u64, u64, C.c_uint32, C.POINTER(vp)]),
+            "qr_server_run": (ci, [vp, vp, vp, vp, u64, vp, vp, vp, C.c_double, C.POINTER(qr_serve_stats)]),
+            "qr_server_free": (ci, [vp]),
             "qr_graph_begin": (ci, [vp]),
             "qr_graph_end": (ci, [vp, C.POINTER(vp)]),
             "qr_graph_launch": (ci, [vp, vp]),

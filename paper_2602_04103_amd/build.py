@@ -13,7 +13,8 @@ OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libquadrank.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "scan.hip", "birank.hip", "quadrank.hip", "quadfm.hip", "gather.hip", "graph.hip", "bwt_host.cpp"]
+SOURCES = ["api.hip", "scan.hip", "birank.hip", "quadrank.hip", "quadfm.hip", "gather.hip", "graph.hip", "serve.hip",
+           "bwt_host.cpp"]
 
 FLAGS = [
     "--offload-arch=" + ARCH,

@@ -1,0 +1,304 @@
+// Native serving loop for FM-index count requests: continuous batching against a device-resident
+// QuadFm index, the host-side core behind the serving row.
+//
+// Requests arrive over time (their arrival times are given), each holding a contiguous block of
+// patterns.  Whenever a slot (a stream with its own work-queue head) is free, every request that has
+// arrived is admitted FIFO as one batch, as large as the pattern cap and the device arena allow; an
+// optional live free-memory check can also hold admission back.  A batch copies its pattern bytes
+// and offsets into the arena, rebases the offsets on the device, runs the persistent count kernel
+// on the slot's stream, copies the counts back and records an event.  Up to `slots` batches are in
+// flight at once, so batches that arrive while others run overlap on the device.  A request
+// finishes when the host sees its batch's event complete.
+//
+// The policy (FIFO batches, first-fit arena of 256-byte aligned blocks, batch byte budget) is the
+// same as the scheduler the Python tests exercise with a CPU stand-in.
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace qr;
+
+namespace {
+
+constexpr uint64_t ALIGN = 256;
+
+uint64_t pad(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// First-fit allocator over [0, size): sorted, disjoint, coalesced free ranges.
+struct Arena {
+    uint64_t size = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> free_;
+
+    void reset(uint64_t s) {
+        size = s;
+        free_.assign(1, {0, s});
+    }
+    bool alloc(uint64_t nbytes, uint64_t &at) {
+        for (size_t k = 0; k < free_.size(); ++k) {
+            const uint64_t a = free_[k].first, b = free_[k].second;
+            const uint64_t s = (a + ALIGN - 1) / ALIGN * ALIGN;
+            if (s + nbytes <= b) {
+                std::vector<std::pair<uint64_t, uint64_t>> pieces;
+                if (s > a) pieces.push_back({a, s});
+                if (s + nbytes < b) pieces.push_back({s + nbytes, b});
+                free_.erase(free_.begin() + k);
+                free_.insert(free_.begin() + k, pieces.begin(), pieces.end());
+                at = s;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t start, uint64_t nbytes) {
+        const std::pair<uint64_t, uint64_t> blk{start, start + nbytes};
+        free_.insert(std::lower_bound(free_.begin(), free_.end(), blk), blk);
+        std::vector<std::pair<uint64_t, uint64_t>> merged;
+        for (const auto &r : free_) {
+            if (!merged.empty() && merged.back().second >= r.first)
+                merged.back().second = std::max(merged.back().second, r.second);
+            else
+                merged.push_back(r);
+        }
+        free_.swap(merged);
+    }
+};
+
+// off[i] -= base for i < n: the batch's offsets, copied as they are, made relative to its first byte
+__global__ void rebase_offsets(uint64_t *__restrict__ off, uint64_t n, uint64_t base) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) off[i] -= base;
+}
+
+struct Inflight {
+    bool busy = false;
+    uint64_t r0 = 0, r1 = 0, base = 0, nbytes = 0;
+};
+
+}  // namespace
+
+struct qr_server_s {
+    int device;
+    qr_quadfm fm;
+    int slots;
+    uint64_t budget, max_batch_patterns;
+    uint32_t flags;
+    uint8_t *arena_dev;
+    unsigned long long *heads;  // one work-queue head per slot
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+void release_server(qr_server_s *s) {
+    if (!s) return;
+    for (hipEvent_t e : s->events)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t st : s->streams)
+        if (st) (void)hipStreamDestroy(st);
+    if (s->arena_dev) (void)hipFree(s->arena_dev);
+    if (s->heads) (void)hipFree(s->heads);
+    delete s;
+}
+
+void drain(qr_server_s *s) {
+    for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t max_batch_patterns, uint32_t flags,
+                     qr_server *out) {
+    if (!out) return QR_EINVAL;
+    *out = nullptr;
+    if (!fm || slots < 1 || slots > 64 || budget_bytes < 4 * ALIGN || max_batch_patterns == 0 ||
+        (flags & ~QR_SERVE_CHECK_FREE_MEMORY)) {
+        set_error("qr_server_create: need an index, 1..64 slots, a budget of at least 1 KiB and a batch cap");
+        return QR_EINVAL;
+    }
+    qr_server_s *s = new (std::nothrow) qr_server_s{};
+    if (!s) return QR_ENOMEM;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return QR_EHIP;
+    }
+    s->fm = fm;
+    s->slots = slots;
+    s->budget = budget_bytes;
+    s->max_batch_patterns = max_batch_patterns;
+    s->flags = flags;
+    s->streams.assign(slots, nullptr);
+    s->events.assign(slots, nullptr);
+    if (hipMalloc(&s->arena_dev, budget_bytes) != hipSuccess || hipMalloc(&s->heads, 8 * (size_t)slots) != hipSuccess) {
+        (void)hipGetLastError();
+        release_server(s);
+        set_error("qr_server_create: device allocation of %llu bytes failed", (unsigned long long)budget_bytes);
+        return QR_ENOMEM;
+    }
+    for (int k = 0; k < slots; ++k) {
+        if (hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->events[k], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            release_server(s);
+            set_error("qr_server_create: stream or event creation failed");
+            return QR_EHIP;
+        }
+    }
+    *out = s;
+    return QR_OK;
+}
+
+int qr_server_free(qr_server s) {
+    if (s) drain(s);
+    release_server(s);
+    return QR_OK;
+}
+
+int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, const uint64_t *h_req_off, uint64_t nreq,
+                  const double *h_arrival_s, uint32_t *h_counts, double *h_finish_s, double deadline_s,
+                  qr_serve_stats *stats) {
+    if (!s || (nreq && (!h_off || !h_req_off || !h_arrival_s || !h_counts || !h_finish_s))) {
+        set_error("qr_server_run: null server or array");
+        return QR_EINVAL;
+    }
+    int rc = check_device(s->device);
+    if (rc) return rc;
+    for (uint64_t r = 0; r < nreq; ++r) {
+        if (h_req_off[r + 1] < h_req_off[r] || (r && h_arrival_s[r] < h_arrival_s[r - 1])) {
+            set_error("qr_server_run: request offsets and arrival times must be non-decreasing");
+            return QR_EINVAL;
+        }
+    }
+    if (nreq && h_req_off[nreq] && !h_pat && h_off[h_req_off[nreq]] > h_off[h_req_off[0]]) {
+        set_error("qr_server_run: h_pat is NULL");
+        return QR_EINVAL;
+    }
+    auto batch_bytes = [&](uint64_t r0, uint64_t r1) {
+        const uint64_t p0 = h_req_off[r0], p1 = h_req_off[r1];
+        return pad(h_off[p1] - h_off[p0]) + pad(8 * (p1 - p0 + 1)) + pad(4 * (p1 - p0)) + ALIGN;
+    };
+    Arena arena;
+    arena.reset(s->budget);
+    std::vector<Inflight> fl(s->slots);
+    std::vector<int> free_slots;
+    for (int k = s->slots - 1; k >= 0; --k) free_slots.push_back(k);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    uint64_t nxt = 0, done = 0, batches = 0, reserved = 0, max_reserved = 0, inflight = 0, max_inflight = 0;
+    int err = QR_OK;
+    while (done < nreq) {
+        const double now = elapsed();
+        if (now > deadline_s) {
+            set_error("qr_server_run: deadline of %.1f s passed with %llu of %llu requests done", deadline_s,
+                      (unsigned long long)done, (unsigned long long)nreq);
+            err = QR_ERANGE;
+            break;
+        }
+        bool progressed = false;
+        // completions, in any order
+        for (int k = 0; k < s->slots; ++k) {
+            if (!fl[k].busy) continue;
+            const hipError_t q = hipEventQuery(s->events[k]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                set_error("qr_server_run: %s", hipGetErrorString(q));
+                err = QR_EHIP;
+                break;
+            }
+            const double t = elapsed();
+            for (uint64_t r = fl[k].r0; r < fl[k].r1; ++r) h_finish_s[r] = t;
+            done += fl[k].r1 - fl[k].r0;
+            arena.release(fl[k].base, fl[k].nbytes);
+            reserved -= fl[k].nbytes;
+            fl[k].busy = false;
+            --inflight;
+            free_slots.push_back(k);
+            progressed = true;
+        }
+        if (err) break;
+        // admissions: every arrived request, FIFO, in one batch per free slot
+        while (!free_slots.empty() && nxt < nreq && h_arrival_s[nxt] <= now) {
+            const uint64_t arrived = (uint64_t)(std::upper_bound(h_arrival_s + nxt, h_arrival_s + nreq, now) - h_arrival_s);
+            uint64_t r1 = nxt + 1;
+            while (r1 < arrived && h_req_off[r1 + 1] - h_req_off[nxt] <= s->max_batch_patterns) ++r1;
+            uint64_t nb = batch_bytes(nxt, r1);
+            while (r1 > nxt + 1 && nb > s->budget) nb = batch_bytes(nxt, --r1);
+            if (nb > s->budget) {
+                set_error("qr_server_run: request %llu needs %llu bytes, more than the budget %llu", (unsigned long long)nxt,
+                          (unsigned long long)nb, (unsigned long long)s->budget);
+                err = QR_ERANGE;
+                break;
+            }
+            if (s->flags & QR_SERVE_CHECK_FREE_MEMORY) {
+                size_t fr = 0, tot = 0;
+                if (hipMemGetInfo(&fr, &tot) != hipSuccess || nb > fr) break;
+            }
+            uint64_t base = 0;
+            if (!arena.alloc(nb, base)) break;  // wait for a batch to finish
+            const int k = free_slots.back();
+            free_slots.pop_back();
+            const uint64_t p0 = h_req_off[nxt], p1 = h_req_off[r1], npat = p1 - p0;
+            const uint64_t c0 = h_off[p0], chars = h_off[p1] - c0;
+            uint8_t *d_pat = s->arena_dev + base;
+            uint64_t *d_off = reinterpret_cast<uint64_t *>(s->arena_dev + base + pad(chars));
+            uint32_t *d_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(d_off) + pad(8 * (npat + 1)));
+            hipStream_t st = s->streams[k];
+            hipError_t e = hipSuccess;
+            if (chars) e = hipMemcpyAsync(d_pat, h_pat + c0, chars, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(d_off, h_off + p0, 8 * (npat + 1), hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(rebase_offsets, dim3((uint32_t)((npat + 1 + 255) / 256)), dim3(256), 0, st, d_off, npat + 1,
+                                   c0);
+                e = hipGetLastError();
+            }
+            if (e != hipSuccess) {
+                set_error("qr_server_run: %s", hipGetErrorString(e));
+                err = QR_EHIP;
+                break;
+            }
+            rc = quadfm_count_ws(s->fm, d_pat, d_off, npat, d_cnt, s->heads + k, st);
+            if (rc) {
+                err = rc;
+                break;
+            }
+            e = hipMemcpyAsync(h_counts + p0, d_cnt, 4 * npat, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(s->events[k], st);
+            if (e != hipSuccess) {
+                set_error("qr_server_run: %s", hipGetErrorString(e));
+                err = QR_EHIP;
+                break;
+            }
+            fl[k] = Inflight{true, nxt, r1, base, nb};
+            reserved += nb;
+            max_reserved = std::max(max_reserved, reserved);
+            ++inflight;
+            max_inflight = std::max(max_inflight, inflight);
+            ++batches;
+            nxt = r1;
+            progressed = true;
+        }
+        if (err) break;
+        if (!progressed) {
+            // nothing to do until an arrival or a completion: poll again shortly
+            const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(2);
+            while (std::chrono::steady_clock::now() < until) {
+            }
+        }
+    }
+    drain(s);  // no copy may still target the caller's buffers on return
+    if (stats) {
+        stats->batches = batches;
+        stats->max_inflight = max_inflight;
+        stats->max_reserved_bytes = max_reserved;
+        stats->wall_s = elapsed();
+    }
+    return err;
+}
+
+}  // extern "C"

@@ -12,7 +12,8 @@ device.  A request completes when the host observes its batch's completion event
 completion time minus arrival time.
 
 The scheduler is written against a small executor interface (`submit`, `poll`, `counts`), with the
-GPU executor below and a CPU stand-in for tests of the scheduling logic.
+GPU executor below and a CPU stand-in for tests of the scheduling logic.  `NativeServer` runs the
+same policy in the library's native loop (qr_server_*), which is what the benchmark measures.
 """
 from __future__ import annotations
 
@@ -182,6 +183,59 @@ class FakeExecutor:
 
     def sync(self):
         pass
+
+
+# ------------------------------------------------------------------------------------------ native loop
+class NativeServer:
+    """The same policy run by the library's native loop (qr_server_*): slots, arena budget, batch cap
+    and the optional free-memory check; host buffers are pinned once per workload."""
+
+    def __init__(self, fm, slots: int, budget_bytes: int, max_batch_patterns: int = 1 << 18,
+                 check_free_memory: bool = False):
+        import ctypes as C
+
+        import paper_2602_04103_amd as qr
+        self.qr, self.fm = qr, fm
+        h = C.c_void_p()
+        flags = qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0
+        qr._check(qr.lib().qr_server_create(fm.h, slots, int(budget_bytes), int(max_batch_patterns), flags,
+                                            C.byref(h)), "qr_server_create")
+        self.h = h.value
+        self.counts_host = None
+
+    def run(self, w: Workload, deadline_s: float = 600.0) -> "ServeStats":
+        import ctypes as C
+
+        import torch
+        qr = self.qr
+        h_pat = torch.from_numpy(w.pat if w.pat.size else np.zeros(1, np.uint8)).pin_memory()
+        h_off = torch.from_numpy(np.ascontiguousarray(w.off, dtype=np.uint64).view(np.int64)).pin_memory()
+        h_cnt = torch.zeros(max(1, int(w.off.size - 1)), dtype=torch.int32).pin_memory()
+        req_off = np.ascontiguousarray(w.req_off, dtype=np.uint64)
+        arrival = np.ascontiguousarray(w.arrival, dtype=np.float64)
+        finish = np.full(w.nreq, np.nan)
+        st = qr.qr_serve_stats()
+        qr._check(qr.lib().qr_server_run(self.h, h_pat.data_ptr(), h_off.data_ptr(), req_off.ctypes.data, w.nreq,
+                                         arrival.ctypes.data, h_cnt.data_ptr(), finish.ctypes.data, float(deadline_s),
+                                         C.byref(st)), "qr_server_run")
+        self.counts_host = h_cnt.numpy()[: int(w.off.size - 1)]
+        return ServeStats(latency_s=finish - arrival, finish_s=finish, batches=int(st.batches),
+                          max_inflight=int(st.max_inflight), max_reserved_bytes=int(st.max_reserved_bytes),
+                          patterns=int(w.req_off[-1]), wall_s=float(st.wall_s))
+
+    def counts(self, p0: int, p1: int) -> np.ndarray:
+        return self.counts_host[p0:p1]
+
+    def free(self):
+        if self.h:
+            self.qr.lib().qr_server_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------------------------------ scheduler

@@ -80,3 +80,62 @@ def test_serve_tight_budget_still_exact(index):
     assert st.max_reserved_bytes <= budget
     served = np.concatenate([srv.counts_of(w, r) for r in range(w.nreq)])
     assert np.array_equal(served, oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
+
+
+# ------------------------------------------------------------------------------ native serving loop
+def native(qr, fm, w, slots, budget, max_batch, check_free=False):
+    from paper_2602_04103_amd.serve import NativeServer
+    srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=max_batch,
+                       check_free_memory=check_free)
+    st = srv.run(w, deadline_s=120.0)
+    return srv, st
+
+
+def test_native_poisson_mix_equals_alone_and_oracle(index):
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import make_workload
+    w = make_workload(87, text, rate_patterns_per_s=4e6, duration_s=0.25, max_size=4096)
+    announce("native serve poisson", w.nreq)
+    srv, st = native(qr, fm, w, slots=4, budget=32 << 20, max_batch=1 << 15, check_free=True)
+    assert not np.isnan(st.finish_s).any()
+    assert np.all(st.finish_s >= w.arrival)                 # nothing finishes before it arrives
+    served = srv.counts(0, int(w.req_off[-1]))
+    assert np.array_equal(served, oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
+    rng = np.random.default_rng(4)
+    for r in rng.choice(w.nreq, min(200, w.nreq), replace=False):
+        p0, p1 = int(w.req_off[r]), int(w.req_off[r + 1])
+        assert np.array_equal(served[p0:p1], alone_counts(qr, fm, w, int(r)))
+    srv.free()
+
+
+def test_native_burst_overlaps_and_tight_budget(index):
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import make_workload
+    w = make_workload(88, text, rate_patterns_per_s=1e8, duration_s=0.01, max_size=512)
+    w.arrival[:] = 0.0
+    announce("native serve burst", w.nreq)
+    srv, st = native(qr, fm, w, slots=4, budget=16 << 20, max_batch=2048)
+    assert st.max_inflight >= 2 and st.max_inflight <= 4
+    assert st.max_reserved_bytes <= 16 << 20
+    want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
+    assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
+    srv.free()
+    one = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
+    announce("native serve tight budget", 2 * one)
+    srv, st = native(qr, fm, w, slots=4, budget=2 * one, max_batch=256)
+    assert st.max_reserved_bytes <= 2 * one
+    assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
+    srv.free()
+
+
+def test_native_rejects_request_over_budget(index):
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import make_workload
+    w = make_workload(89, text, rate_patterns_per_s=1e6, duration_s=0.01, max_size=4096)
+    from paper_2602_04103_amd.serve import NativeServer
+    assert max(w.batch_bytes(r, r + 1) for r in range(w.nreq)) > 4096
+    announce("native serve over budget")
+    srv = NativeServer(fm, slots=2, budget_bytes=4096, max_batch_patterns=1 << 15)
+    with pytest.raises(qr.QRError):
+        srv.run(w, deadline_s=30.0)
+    srv.free()
