@@ -411,6 +411,17 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     res["gain_vs_best_batched"] = res["persistent_patterns_per_s"] / best_b
     res["gain_vs_batch_2^16"] = res["persistent_patterns_per_s"] / res["batched_65536_patterns_per_s"]
     res["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
+    # roofline of the persistent kernel: algorithmic lines (128 B each) per pattern from a sample
+    work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev)
+    achieved = npat / t_p * work["lines_per_pattern"] * 128 / 1e9
+    res["work"] = work
+    res["roofline"] = {"bound": "hbm", "kernel": "fm_persistent_kernel", "achieved": round(achieved, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "note": "algorithmic 128-byte lines; the 72 MB index fits the 256 MB MALL, so the "
+                               "line reads are served mostly from cache and the fraction can exceed HBM's"}
+    log("fm work: %.1f steps, %.1f lines, %.1f half lines per pattern -> %.0f GB/s of lines (%.0f%% of HBM)" % (
+        work["steps_per_pattern"], work["lines_per_pattern"], work["half_lines_per_pattern"], achieved,
+        100 * achieved / HBM_PEAK_GBS))
     log("fm persistent %.1f M patterns/s; batched best %.1f M; gain %.2fx; equal=%s" % (
         npat / t_p / 1e6, best_b / 1e6, res["gain_vs_best_batched"], res["persistent_equals_batched"]))
     if rate:
@@ -432,6 +443,45 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
             % (rate, total, total / t_loc / 1e6, t_iv * 1e3, t_off * 1e3, t_loc * 1e3))
     fm.free()
     return res
+
+
+def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, sample=2000, seed=11):
+    """Backward steps, lines and half-line loads per pattern, on a sample of the workload: the
+    search of P starts from the interval of its last 8 characters and step k (k = 1..m-8) turns the
+    interval of the suffix P[m-8-k+1..m) into that of P[m-8-k..m), stopping once it is empty.  A
+    step reads one 128-byte line when sp and ep share a line (else two), and one 64-byte half when
+    they share a half line (else two halves).  The suffix intervals come from quadfm_intervals."""
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(npat, min(sample, npat), replace=False))
+    sufs, owner = [], []
+    for p in idx:
+        P = pat[int(off[p]):int(off[p + 1])]
+        m = P.size
+        for k in range(0, m - 7):  # suffix lengths 8..m
+            sufs.append(P[m - 8 - k:])
+            owner.append(p)
+    soff = np.zeros(len(sufs) + 1, np.uint64)
+    soff[1:] = np.cumsum([x.size for x in sufs])
+    iv = fm.intervals(to_dev(np.concatenate(sufs)), to_dev(soff)).cpu().numpy().view(np.uint32).astype(np.int64)
+    DATA, HDR, MID = 480, 32, 256  # the FM index's 16-bit QuadRank layout
+    steps = lines = halves = 0
+    i = 0
+    for p in idx:
+        m = int(off[p + 1] - off[p])
+        k_max = m - 8
+        for k in range(1, k_max + 1):
+            sp, ep = iv[i + k - 1]
+            if ep <= sp:
+                break
+            js, je = sp // DATA, ep // DATA
+            hs, he = (sp - js * DATA + HDR) >= MID, (ep - je * DATA + HDR) >= MID
+            steps += 1
+            lines += 1 if js == je else 2
+            halves += 1 if (js == je and hs == he) else 2
+        i += k_max + 1
+    n = idx.size
+    return {"sample_patterns": int(n), "steps_per_pattern": steps / n, "lines_per_pattern": lines / n,
+            "half_lines_per_pattern": halves / n}
 
 
 def bench_serve(args, qr, datagen, np, torch, to_dev):
