@@ -150,6 +150,16 @@ int quadfm_bwt_host(const uint8_t *h_text, uint64_t n, uint64_t *h_bwt_packed2, 
 int quadfm_index_host(const uint8_t *h_text, uint64_t n, uint32_t rate, uint64_t *h_bwt_packed2, uint64_t *dollar_pos,
                       uint64_t *h_mark_bits, uint32_t *h_samples);
 
+/* The same outputs built on the device (the input preparation that quadfm_index_host does on the
+ * host): the suffix array of T$ by prefix doubling over a radix sort, then the packed BWT
+ * (d_bwt_packed2, ceil((n+1)/32) words) with the row of '$' returned in *dollar_pos (host), and
+ * with rate > 0 the mark bits (ceil((n+1)/64) words) and samples (floor(n/rate)+1 u32).  d_text
+ * holds n codes 0..3 on the device.  Synchronous; allocates about 40 (n+1) bytes of temporaries.
+ * QR_EINVAL on a code > 3, QR_ERANGE if n+1 exceeds 2^32 - 4097, QR_ENOMEM if the temporaries do
+ * not fit.  Results are identical to quadfm_index_host's. */
+int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t rate, uint64_t *d_bwt_packed2, uint64_t *dollar_pos,
+                        uint64_t *d_mark_bits, uint32_t *d_samples, hipStream_t stream);
+
 /* Build the index from the packed BWT (n_plus_1 symbols at d_bwt_packed2, '$' stored as A at row
  * dollar_pos).  Builds QuadRank over the BWT, the C array and the 8-mer interval table. */
 int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,

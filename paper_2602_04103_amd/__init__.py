@@ -93,6 +93,7 @@ def lib():
         optional = {
             "quadfm_bwt_host": (ci, [vp, u64, vp, C.POINTER(u64)]),
             "quadfm_index_host": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp]),
+            "quadfm_index_device": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp, vp]),
             "quadfm_intervals": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadfm_locate_attach": (ci, [vp, vp, vp, u64, C.c_uint32, vp]),
             "quadfm_locate_offsets": (ci, [vp, vp, u64, vp, vp]),
@@ -269,6 +270,24 @@ def quadfm_index_host(text_codes, rate: int):
     _check(lib().quadfm_index_host(src.ctypes.data, n, rate, out.ctypes.data, C.byref(d), marks.ctypes.data,
                                    samples.ctypes.data), "quadfm_index_host")
     return out, int(d.value), marks, samples
+
+
+def quadfm_index_device(text: torch.Tensor, rate: int = 0, stream=None):
+    """Device input preparation from n text codes on the device: (packed BWT, dollar row, mark bits,
+    samples) as device tensors (the last two None when rate == 0)."""
+    n = text.numel()
+    dev = text.device
+    bwt = torch.empty(max(1, (n + 1 + 31) // 32), dtype=torch.int64, device=dev)
+    marks = samples = None
+    mp = sp = None
+    if rate:
+        marks = torch.empty(max(1, (n + 1 + 63) // 64), dtype=torch.int64, device=dev)
+        samples = torch.empty(n // rate + 1, dtype=torch.int32, device=dev)
+        mp, sp = _dev(marks, "marks", W64), _dev(samples, "samples", W32)
+    d = u64()
+    _check(lib().quadfm_index_device(_dev(text, "text", W8) if n else None, n, rate, _dev(bwt, "bwt", W64), C.byref(d),
+                                     mp, sp, _stream(stream)), "quadfm_index_device")
+    return bwt, int(d.value), marks, samples
 
 
 def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None) -> int:
@@ -516,11 +535,19 @@ class QuadFm(_Handle):
         self.n = n_plus_1 - 1
 
     @classmethod
-    def from_text(cls, text_codes, stream=None, locate_rate: int = 0):
-        """Host SA/BWT construction, then the device build; with locate_rate > 0 also the
-        suffix-array sample at that rate, attached for locate."""
+    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = False):
+        """Host SA/BWT construction (or, with device_sa, the device one), then the device build;
+        with locate_rate > 0 also the suffix-array sample at that rate, attached for locate."""
         import numpy as np
         n1 = int(np.asarray(text_codes).size) + 1
+        if device_sa:
+            t = torch.from_numpy(np.ascontiguousarray(text_codes, dtype=np.uint8)).cuda()
+            bwt, dollar, marks, samples = quadfm_index_device(t, locate_rate, stream)
+            del t
+            fm = cls(bwt, n1, dollar, stream)
+            if locate_rate:
+                fm.attach_locate(marks, samples, locate_rate, stream)
+            return fm
         if not locate_rate:
             bwt, dollar = quadfm_bwt_host(text_codes)
             return cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream)

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libquadrank.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "scan.hip", "birank.hip", "quadrank.hip", "quadfm.hip", "gather.hip", "graph.hip", "serve.hip",
-           "bwt_host.cpp"]
+           "sa_device.hip", "bwt_host.cpp"]
 
 FLAGS = [
     "--offload-arch=" + ARCH,
