@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-fm", action="store_true", help="skip the FM-index rows")
     ap.add_argument("--fm-patterns", type=int, default=10 ** 7)
     ap.add_argument("--fm-reps", type=int, default=3)
+    ap.add_argument("--host-sa", action="store_true",
+                    help="prepare the FM-index input (suffix array, BWT) with host SA-IS instead of on the device")
     ap.add_argument("--fm-locate-rate", type=int, default=32,
                     help="suffix-array sampling rate of the locate measurement (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -367,16 +369,26 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     datagen.plant_repeats(2829, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
     t1 = time.time()
     rate = args.fm_locate_rate
-    if rate:
-        bwt, dollar, marks, samples = qr.quadfm_index_host(codes, rate)
+    if args.host_sa:
+        if rate:
+            bwt, dollar, marks, samples = qr.quadfm_index_host(codes, rate)
+            marks, samples = to_dev(marks), torch.from_numpy(samples.view(np.int32)).to(dev)
+        else:
+            bwt, dollar = qr.quadfm_bwt_host(codes)
+        bwt = to_dev(bwt)
     else:
-        bwt, dollar = qr.quadfm_bwt_host(codes)
+        d_text = torch.from_numpy(codes).to(dev)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        bwt, dollar, marks, samples = qr.quadfm_index_device(d_text, rate)
+        del d_text
     t2 = time.time()
-    fm = qr.QuadFm(to_dev(bwt), n + 1, dollar)
+    fm = qr.QuadFm(bwt, n + 1, dollar)
     count_bytes = fm.nbytes
     if rate:
-        fm.attach_locate(to_dev(marks), torch.from_numpy(samples.view(np.int32)).to(dev), rate)
+        fm.attach_locate(marks, samples, rate)
         del marks, samples
+    del bwt
     torch.cuda.synchronize()
     t3 = time.time()
     pat, off, kind = datagen.patterns(2830, codes, args.fm_patterns)
@@ -384,7 +396,8 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     dp, do = to_dev(pat), to_dev(off)
     npat = args.fm_patterns
     total_chars = int(off[-1])
-    log("fm index: text %.1fs, host SA+BWT %.1fs, device build %.2fs" % (t1 - t0, t2 - t1, t3 - t2))
+    log("fm index: text %.1fs, %s SA+BWT %.2fs, device build %.2fs" % (t1 - t0, "host" if args.host_sa else "device",
+                                                                       t2 - t1, t3 - t2))
     cnt = torch.empty(npat, dtype=torch.int32, device=dev)
     cnt_b = torch.empty(npat, dtype=torch.int32, device=dev)
     if isinstance(getattr(args, "fm_tuning", None), dict):
@@ -402,7 +415,7 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
                        % npat,
            "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3, "tuning": best,
            "index_bytes": count_bytes, "bits_per_base": count_bytes * 8 / n, "pattern_chars": total_chars,
-           "host_sa_bwt_s": t2 - t1, "device_build_s": t3 - t2}
+           "sa_bwt_s": t2 - t1, "sa_bwt_on": "host" if args.host_sa else "device", "device_build_s": t3 - t2}
     for batch in (1 << 16, 1 << 20, 0):
         t_b = autotune.time_launch(lambda: fm.count_batched(dp, do, batch, cnt_b), reps=args.fm_reps)
         res["batched_%s_patterns_per_s" % (batch or "all")] = npat / t_b
@@ -492,19 +505,23 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     t0 = time.time()
     text = datagen.dna_codes(3030, n)
     datagen.plant_repeats(3031, text, nseg=1000, seglen=10_000, copies=20, sub=0.01)
-    bwt, dollar = qr.quadfm_bwt_host(text)
+    if args.host_sa:
+        bwt, dollar = qr.quadfm_bwt_host(text)
+        bwt = to_dev(bwt)
+    else:
+        bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0)
     t1 = time.time()
-    fm = qr.QuadFm(to_dev(bwt), n + 1, dollar)
+    fm = qr.QuadFm(bwt, n + 1, dollar)
     del bwt
     fm.set_tuning(block=64, refill=32, waves_per_cu=8)
-    log("serve index 2^%d: host SA+BWT %.1fs" % (args.serve_log_n, t1 - t0))
+    log("serve index 2^%d: text + %s SA+BWT %.1fs" % (args.serve_log_n, "host" if args.host_sa else "device", t1 - t0))
     slots, budget = 4, 256 << 20
     free, total = torch.cuda.mem_get_info()
     res = {"workload": "QuadFm serving: 2^%d-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs); "
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
            "slots": slots, "hbm_budget_bytes": budget, "device_free_bytes_at_start": int(free),
-           "host_sa_bwt_s": t1 - t0, "loads": []}
+           "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": []}
     # warm-up (untimed): first launches, pinned-memory pools, stream creation
     w0 = make_workload(4999, text, 1e6, 0.05, max_requests=200)
     ex0 = GpuExecutor(fm, w0, slots=slots, budget_bytes=budget)

@@ -137,14 +137,15 @@ def test_fm_config3_full_sampled():
     20..250, 90% sampled with 1% substitutions, 10% iid).  All counts come from the persistent
     kernel; 200 sampled patterns are recounted by the oracle's direct scan, and the per-batch
     kernel must agree with the persistent one on every pattern.  Intervals and locate (SA sampled
-    at rate 32) are checked on the same index."""
+    at rate 32) are checked on the same index, whose input (suffix array, BWT, sample) is prepared
+    on the device."""
     qr = require_gpu()
     n = 1 << 28
     codes = datagen.dna_codes(2028, n)
     datagen.plant_repeats(2029, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
     pat, off, kind = datagen.patterns(2030, codes, 10 ** 7)
     announce("fm-config3 build")
-    fm = qr.QuadFm.from_text(codes, locate_rate=32)
+    fm = qr.QuadFm.from_text(codes, locate_rate=32, device_sa=True)
     announce("fm-config3 count")
     dp, do = to_dev(pat), to_dev(off)
     got = fm.count(dp, do).cpu().numpy().view(np.uint32)
