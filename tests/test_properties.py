@@ -1,0 +1,122 @@
+"""Property tests (hypothesis, CPU): the oracle's rank, rank4, prefix_rank, count and locate
+against brute force and their invariants on arbitrary small inputs, and the serving arena
+allocator's invariants under arbitrary allocation/release sequences."""
+import numpy as np
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+import datagen
+import oracle
+from paper_2602_04103_amd.serve import Arena
+
+SETTINGS = settings(max_examples=60, deadline=None)
+bits_st = st.lists(st.integers(0, 1), min_size=0, max_size=300)
+dna_st = st.lists(st.integers(0, 3), min_size=0, max_size=200)
+
+
+def pack_bits(bits):
+    n = len(bits)
+    words = np.zeros(max(1, (n + 63) // 64), np.uint64)
+    for i, b in enumerate(bits):
+        if b:
+            words[i // 64] |= np.uint64(1) << np.uint64(i % 64)
+    return words
+
+
+@SETTINGS
+@given(bits_st, st.integers(0, 2 ** 63))
+def test_rank_bits_is_prefix_popcount(bits, garbage):
+    n = len(bits)
+    words = pack_bits(bits)
+    if n % 64:  # bits past n must not matter
+        words[-1] |= np.uint64(garbage) << np.uint64(n % 64)
+    q = np.arange(n + 1, dtype=np.uint64)
+    r = oracle.rank_bits(words, n, q)
+    assert r.tolist() == [sum(bits[:k]) for k in range(n + 1)]
+
+
+@SETTINGS
+@given(dna_st)
+def test_rank_rank4_prefix_rank_agree_with_brute_force(codes):
+    c = np.array(codes, np.uint8)
+    n = c.size
+    packed = datagen.pack2(c, tail_garbage=True, seed=n)
+    q = np.arange(n + 1, dtype=np.uint64)
+    r4 = oracle.rank4_dna(packed, n, q)
+    for s in range(4):
+        want = [sum(1 for x in codes[:k] if x == s) for k in range(n + 1)]
+        assert r4[:, s].tolist() == want
+        assert oracle.rank_dna(packed, n, q, np.full(q.size, s, np.uint8)).tolist() == want
+        pr = oracle.prefix_rank_dna(packed, n, q, np.full(q.size, s, np.uint8))
+        assert pr.tolist() == [sum(1 for x in codes[:k] if x <= s) for k in range(n + 1)]
+    assert np.array_equal(r4.sum(axis=1), q)
+
+
+def brute_positions(text, p):
+    t, m = list(text), len(p)
+    return [i for i in range(len(t) + 1) if t[i:i + m] == list(p)] if m else list(range(len(t) + 1))
+
+
+@SETTINGS
+@given(st.lists(st.integers(0, 1), min_size=0, max_size=80),
+       st.lists(st.lists(st.integers(0, 3), min_size=0, max_size=6), min_size=1, max_size=12))
+def test_counts_and_locate_agree_with_brute_force(text01, pats):
+    """Texts over {A, C} force many repeats; patterns over ACGT include absent symbols."""
+    text = np.array(text01, np.uint8)
+    n = text.size
+    off = np.zeros(len(pats) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in pats])
+    flat = np.array([x for p in pats for x in p], np.uint8)
+    sa = oracle.suffix_array(text)
+    b, _ = oracle.bwt(text, sa)
+    want = [len(brute_positions(text01, p)) for p in pats]
+    assert oracle.count_naive(text, flat, off).tolist() == want
+    assert oracle.count_sa(text, sa, flat, off).tolist() == want
+    assert oracle.count_backward(b, flat, off).tolist() == want
+    start, pos = oracle.locate_sa(text, sa, flat, off)
+    for i, p in enumerate(pats):
+        got = pos[int(start[i]):int(start[i + 1])].tolist()
+        assert sorted(got) == brute_positions(text01, p)
+    assert sorted(sa.tolist()) == list(range(n + 1))
+
+
+@SETTINGS
+@given(st.lists(st.integers(0, 3), min_size=1, max_size=60),
+       st.lists(st.lists(st.integers(0, 3), min_size=1, max_size=5), min_size=1, max_size=8))
+def test_both_strands_is_the_sum_of_the_strands(text, pats):
+    t = np.array(text, np.uint8)
+    sa = oracle.suffix_array(t)
+    off = np.zeros(len(pats) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in pats])
+    flat = np.array([x for p in pats for x in p], np.uint8)
+    rc = [oracle.revcomp(np.array(p, np.uint8)) for p in pats]
+    assert all(np.array_equal(oracle.revcomp(r), np.array(p, np.uint8)) for r, p in zip(rc, pats))
+    both = oracle.count_both_strands(t, sa, flat, off)
+    want = [len(brute_positions(text, p)) + len(brute_positions(text, r.tolist())) for p, r in zip(pats, rc)]
+    assert both.tolist() == want
+
+
+@settings(max_examples=100, deadline=None)
+@given(st.integers(1024, 1 << 20), st.lists(st.tuples(st.booleans(), st.integers(1, 50_000)), max_size=60))
+def test_arena_blocks_never_overlap_and_bytes_balance(size, ops):
+    a = Arena(size)
+    live = []
+    for is_alloc, nbytes in ops:
+        if is_alloc or not live:
+            at = a.alloc(nbytes)
+            if at is not None:
+                assert at % 256 == 0 and at + nbytes <= size
+                for s0, n0 in live:
+                    assert at + nbytes <= s0 or s0 + n0 <= at
+                live.append((at, nbytes))
+        else:
+            s0, n0 = live.pop(len(live) // 2)
+            a.release(s0, n0)
+        # free ranges are sorted, disjoint and inside the arena
+        for (x0, x1), (y0, y1) in zip(a.free, a.free[1:]):
+            assert x1 < y0
+        assert all(0 <= x0 < x1 <= size for x0, x1 in a.free)
+        assert a.free_bytes + sum(n for _, n in live) == size
+    for s0, n0 in live:
+        a.release(s0, n0)
+    assert a.free == [(0, size)]
