@@ -13,7 +13,8 @@
 // histogram in LDS, stored digit-major; (2) an exclusive scan of all histograms gives every
 // (digit, tile) its output base; (3) each tile walks its keys in order, ranks equal digits within a
 // wavefront with 9 ballots (lanes whose digits match), adds the counts of earlier wavefronts and
-// earlier rows of the tile, and scatters.
+// earlier rows of the tile, places the keys in LDS in sorted order and writes them out as one
+// contiguous run per digit.
 //
 // Outputs: the packed BWT ('$' stored as A at its row), the row of '$', and optionally the
 // suffix-array sample of locate (mark bits of rows whose SA value is a multiple of the rate and
@@ -147,13 +148,25 @@ __global__ __launch_bounds__(BLK) void rs_hist(const uint64_t *__restrict__ keys
     hist[(uint64_t)t * ntiles + blockIdx.x] = h[t];
 }
 
+// Scatter of one tile: its keys are first placed in LDS in sorted (digit, then input) order, then
+// written out as contiguous runs per digit, so consecutive lanes store to consecutive addresses.
 __global__ __launch_bounds__(BLK) void rs_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                   uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t n,
-                                                  uint32_t shift, const uint32_t *__restrict__ offs, uint32_t ntiles) {
-    __shared__ uint32_t base[256];
+                                                  uint32_t shift, const uint32_t *__restrict__ hist,
+                                                  const uint32_t *__restrict__ offs, uint32_t ntiles) {
+    __shared__ uint64_t skey[TILE];
+    __shared__ uint32_t sval[TILE];
+    __shared__ uint32_t gbase[256];   // global start of this tile's run of each digit
+    __shared__ uint32_t lstart[256];  // start of each digit's run inside the tile
+    __shared__ uint32_t run[256];     // keys of each digit placed so far
     __shared__ uint32_t wcnt[BLK / 64][256];
+    __shared__ uint32_t wsh[BLK / 64];
     const uint32_t t = threadIdx.x, w = t / 64, lane = __lane_id();
-    base[t] = offs[(uint64_t)t * ntiles + blockIdx.x];
+    const uint64_t hidx = (uint64_t)t * ntiles + blockIdx.x;
+    gbase[t] = offs[hidx];
+    uint32_t tot;
+    lstart[t] = block_excl<OpAdd>(hist[hidx], wsh, &tot);
+    run[t] = 0;
 #pragma unroll
     for (int k = 0; k < BLK / 64; ++k) wcnt[k][t] = 0;
     __syncthreads();
@@ -176,10 +189,10 @@ __global__ __launch_bounds__(BLK) void rs_scatter(const uint64_t *__restrict__ k
         if (valid && rank == 0) wcnt[w][d] = __popcll(same);
         __syncthreads();
         if (valid) {
-            uint32_t pos = base[d] + rank;
-            for (uint32_t k = 0; k < w; ++k) pos += wcnt[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
+            uint32_t lp = lstart[d] + run[d] + rank;
+            for (uint32_t k = 0; k < w; ++k) lp += wcnt[k][d];
+            skey[lp] = key;
+            sval[lp] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -188,8 +201,16 @@ __global__ __launch_bounds__(BLK) void rs_scatter(const uint64_t *__restrict__ k
             add += wcnt[k][t];
             wcnt[k][t] = 0;
         }
-        base[t] += add;
+        run[t] += add;
         __syncthreads();
+    }
+    const uint32_t cnt = (uint32_t)min<uint64_t>(TILE, (uint64_t)n - tile0);
+    for (uint32_t p = t; p < cnt; p += BLK) {
+        const uint64_t key = skey[p];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t pos = gbase[d] + (p - lstart[d]);
+        kout[pos] = key;
+        vout[pos] = sval[p];
     }
 }
 
@@ -214,14 +235,42 @@ __global__ void init_keys(const uint8_t *__restrict__ text, uint32_t n, uint64_t
     val[i] = (uint32_t)i;
 }
 
-// g[i] = i where sorted key i starts a group (differs from key i-1), else 0; counts group starts
-__global__ void group_heads(const uint64_t *__restrict__ key, uint32_t N, uint32_t *__restrict__ g,
-                            unsigned long long *__restrict__ heads) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool h = i < N && (i == 0 || key[i] != key[i - 1]);
-    if (i < N) g[i] = h ? (uint32_t)i : 0u;
-    const uint64_t b = __ballot(h);
-    if (__lane_id() == 0 && b) atomicAdd(heads, (unsigned long long)__popcll(b));
+// g[i] = i where sorted key i starts a group (differs from key i-1), else 0; the number of group
+// starts of each tile of 4096 goes to tcount[tile] (summed by sum_u32, not by a shared atomic)
+__global__ __launch_bounds__(BLK) void group_heads(const uint64_t *__restrict__ key, uint32_t N,
+                                                   uint32_t *__restrict__ g, uint32_t *__restrict__ tcount) {
+    __shared__ uint32_t wsum[BLK / 64];
+    const uint64_t i0 = (uint64_t)blockIdx.x * TILE + threadIdx.x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint64_t i = i0 + (uint64_t)j * BLK;
+        if (i < N) {
+            const bool h = i == 0 || key[i] != key[i - 1];
+            g[i] = h ? (uint32_t)i : 0u;
+            c += h;
+        }
+    }
+    c = wave_sum(c);
+    if (__lane_id() == 0) wsum[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) tcount[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// *out = sum of x[0..n) (one workgroup)
+__global__ __launch_bounds__(TOP) void sum_u32(const uint32_t *__restrict__ x, uint64_t n,
+                                               unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long wsum[TOP / 64];
+    unsigned long long c = 0;
+    for (uint64_t i = threadIdx.x; i < n; i += TOP) c += x[i];
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (__lane_id() == 0) wsum[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < TOP / 64; ++w) t += wsum[w];
+        *out = t;
+    }
 }
 
 __global__ void set_rank(const uint32_t *__restrict__ sa, const uint32_t *__restrict__ gstart, uint32_t N,
@@ -305,7 +354,7 @@ hipError_t radix_sort(Buffers &B, uint32_t N, uint32_t bits, hipStream_t s) {
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = scan_u32<OpAdd, false>(B.hist, nh, B.offs, B.aux, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(rs_scatter, dim3(nt), dim3(BLK), 0, s, B.k0, B.v0, B.k1, B.v1, N, shift, B.offs, nt);
+        hipLaunchKernelGGL(rs_scatter, dim3(nt), dim3(BLK), 0, s, B.k0, B.v0, B.k1, B.v1, N, shift, B.hist, B.offs, nt);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         std::swap(B.k0, B.k1);
@@ -316,10 +365,10 @@ hipError_t radix_sort(Buffers &B, uint32_t N, uint32_t bits, hipStream_t s) {
 
 // sorted keys in k0 -> group starts (max-scan of heads) -> rank[]; returns the number of groups
 hipError_t regroup(Buffers &B, uint32_t N, hipStream_t s, uint64_t &groups) {
-    hipError_t e = hipMemsetAsync(B.cnt, 0, 8, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(group_heads, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.k0, N, B.g, B.cnt);
-    e = hipGetLastError();
+    const uint32_t nt = blocks_for(N, TILE);
+    hipLaunchKernelGGL(group_heads, dim3(nt), dim3(BLK), 0, s, B.k0, N, B.g, B.hist);
+    hipLaunchKernelGGL(sum_u32, dim3(1), dim3(TOP), 0, s, B.hist, (uint64_t)nt, B.cnt);
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = scan_u32<OpMax, true>(B.g, N, B.g, B.aux, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(set_rank, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.v0, B.g, N, B.rank);
