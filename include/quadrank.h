@@ -167,7 +167,9 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
 /* Count occurrences of npat patterns given in CSR form: pattern p is the codes
  * d_pat[d_off[p] .. d_off[p+1]) (u8 codes 0..3; u64 offsets, npat+1 of them); d_count[p] receives
  * the size of its BWT interval (u32).  An empty pattern counts n+1; a pattern with a code > 3
- * counts 0 (it cannot occur in an ACGT text).  Runs the persistent work-queue kernel: resident
+ * counts 0 (it cannot occur in an ACGT text).  The offsets must not decrease: a pattern with
+ * d_off[p+1] < d_off[p] is not read, counts 0 and sets the sticky error (QR_EINVAL from
+ * quadfm_check).  Runs the persistent work-queue kernel: resident
  * wavefronts pull patterns from a device queue until it drains.  Calls on one handle must not
  * overlap in time (they share the queue head); use one handle per concurrent stream. */
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
@@ -215,8 +217,8 @@ int quadfm_locate_offsets(qr_quadfm h, const uint32_t *d_iv, uint64_t npat, uint
  * (only possible with inconsistent sample data) writes UINT32_MAX and sets the sticky error. */
 int quadfm_locate(qr_quadfm h, const uint32_t *d_iv, const uint64_t *d_start, uint64_t npat, uint64_t total,
                   uint32_t *d_pos, hipStream_t stream);
-/* Synchronise `stream` (counts, intervals and positions are then final); QR_ERANGE (and clear) if a
- * locate walk failed since the last check. */
+/* Synchronise `stream` (counts, intervals and positions are then final); report and clear the sticky
+ * error: QR_EINVAL if a pattern's offsets decreased, QR_ERANGE if a locate walk failed. */
 int quadfm_check(qr_quadfm h, hipStream_t stream);
 int quadfm_free(qr_quadfm h);
 uint64_t quadfm_len(qr_quadfm h);   /* n (text length, without '$') */

@@ -69,7 +69,10 @@ struct FmDev {
     const uint2 *table;
     uint64_t n1, dollar;
     uint64_t C0, C1, C2, C3;
+    uint32_t *err;  // sticky error word: ERR_WALK (locate), ERR_OFFSETS (a decreasing offset pair)
 };
+
+constexpr uint32_t ERR_WALK = 1u, ERR_OFFSETS = 2u;
 
 __device__ __forceinline__ uint64_t fm_C(const FmDev &f, uint32_t c) {
     const uint64_t m1 = 0ull - (c & 1u), m2 = 0ull - ((c >> 1) & 1u);
@@ -198,7 +201,14 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
 template <bool BOTH>
 __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restrict__ pat, const uint64_t *__restrict__ off,
                                         uint64_t p, Search &s, uint32_t &cnt) {
-    const uint64_t o = off[p], m = off[p + 1] - o;
+    const uint64_t o = off[p], e = off[p + 1];
+    if (e < o || e - o > 0xffffffffull) {  // not a pattern: nothing of it is read
+        atomicOr(f.err, ERR_OFFSETS);
+        s.m = 0;
+        cnt = 0;
+        return true;
+    }
+    const uint64_t m = e - o;
     s.P = pat + o;
     s.m = (uint32_t)m;
     s.lo = (uintptr_t)s.P;
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(256) void fm_locate_kernel(FmDev f, LocDev d, const
         uint32_t v = 0;
         if (!sa_of_row(f, d, row, v)) {
             v = 0xffffffffu;
-            atomicOr(err, 1u);
+            atomicOr(err, ERR_WALK);
         }
         pos[g] = v;
     }
@@ -495,6 +505,7 @@ FmDev dev_view(const qr_quadfm_s *h) {
     f.n1 = h->n1;
     f.dollar = h->dollar;
     f.C0 = h->C[0], f.C1 = h->C[1], f.C2 = h->C[2], f.C3 = h->C[3];
+    f.err = h->err;
     return f;
 }
 
@@ -700,7 +711,11 @@ int quadfm_check(qr_quadfm h, hipStream_t stream) {
     QR_HIP(hipStreamSynchronize(stream));
     QR_HIP(hipMemcpy(&v, h->err, 4, hipMemcpyDeviceToHost));
     QR_HIP(hipMemset(h->err, 0, 4));
-    if (v) {
+    if (v & ERR_OFFSETS) {
+        set_error("quadfm: a pattern's offsets decrease (d_off[p+1] < d_off[p]); it was counted as 0");
+        return QR_EINVAL;
+    }
+    if (v & ERR_WALK) {
         set_error("quadfm: a locate walk reached no sampled row (inconsistent mark bits or samples)");
         return QR_ERANGE;
     }

@@ -175,6 +175,15 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             return QR_EINVAL;
         }
     }
+    if (nreq) {
+        for (uint64_t p = h_req_off[0]; p < h_req_off[nreq]; ++p) {
+            if (h_off[p + 1] < h_off[p]) {
+                set_error("qr_server_run: pattern offsets must be non-decreasing (h_off[%llu] > h_off[%llu])",
+                          (unsigned long long)p, (unsigned long long)(p + 1));
+                return QR_EINVAL;
+            }
+        }
+    }
     if (nreq && h_req_off[nreq] && !h_pat && h_off[h_req_off[nreq]] > h_off[h_req_off[0]]) {
         set_error("qr_server_run: h_pat is NULL");
         return QR_EINVAL;

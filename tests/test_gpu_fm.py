@@ -199,3 +199,31 @@ def test_fm_both_strands(n):
     assert np.array_equal(got, want)
     got_b = fm.count_batched(dp, do, 777, both_strands=True).cpu().numpy().view(np.uint32)
     assert np.array_equal(got_b, want)
+
+
+def test_fm_decreasing_offsets_count_zero_and_report():
+    """A pattern whose offsets decrease is not read: it counts 0 (interval [0, 0)) and the sticky
+    error reports it; the patterns around it are counted normally."""
+    qr = require_gpu()
+    codes = make_text(8, 5000)
+    announce("fm-bad-offsets")
+    fm = qr.QuadFm.from_text(codes)
+    pat = codes[100:110].copy()
+    off = np.array([0, 5, 3, 10], np.uint64)  # pattern 1 runs backwards
+    want = oracle.count_naive(codes, pat, np.array([0, 5, 5, 10], np.uint64)).astype(np.uint32)
+    want[1] = 0
+    for kernel in ("persistent", "batched", "intervals"):
+        dp, do = to_dev(pat), to_dev(off)
+        if kernel == "persistent":
+            got = fm.count(dp, do).cpu().numpy().view(np.uint32)
+        elif kernel == "batched":
+            got = fm.count_batched(dp, do, 2).cpu().numpy().view(np.uint32)
+        else:
+            iv = fm.intervals(dp, do).cpu().numpy().view(np.uint32)
+            got = (iv[:, 1] - iv[:, 0]).astype(np.uint32)
+        want[2] = oracle.count_naive(codes, pat[3:10].copy(), np.array([0, 7], np.uint64))[0]
+        assert np.array_equal(got, want), kernel
+        with pytest.raises(qr.QRError) as ei:
+            fm.check()
+        assert ei.value.status == qr.QR_EINVAL
+        fm.check()

@@ -139,3 +139,18 @@ def test_native_rejects_request_over_budget(index):
     with pytest.raises(qr.QRError):
         srv.run(w, deadline_s=30.0)
     srv.free()
+
+
+def test_native_rejects_decreasing_pattern_offsets(index):
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import NativeServer, make_workload
+    w = make_workload(90, text, rate_patterns_per_s=1e6, duration_s=0.01, max_size=64)
+    w.off = w.off.copy()
+    k = int(w.req_off[1])  # break the order inside the second request
+    w.off[k + 1] = w.off[k] - 1 if w.off[k] > 0 else w.off[k]
+    assert np.any(np.diff(w.off.astype(np.int64)) < 0)
+    announce("native serve bad offsets")
+    srv = NativeServer(fm, slots=2, budget_bytes=1 << 20)
+    with pytest.raises(qr.QRError):
+        srv.run(w, deadline_s=30.0)
+    srv.free()
