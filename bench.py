@@ -93,6 +93,7 @@ def main():
                     help="comma-separated rank rows of the step; quadrank_prefix_rank is an optional extra row")
     ap.add_argument("--layouts", default="16,32",
                     help="inline-delta widths to build for each rank row; the tuner picks one per row")
+    ap.add_argument("--no-extra", action="store_true", help="skip the prefix_rank row timed outside the step")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tuning-from", default=None,
                     help="apply the launch settings recorded in an earlier bench JSON line instead of tuning")
@@ -311,6 +312,33 @@ def main():
         "bytes_per_query": BYTES_PER_QUERY[dom],
     }
 
+    # ------------------------------------------------------------------ extra rows (not in the step)
+    # prefix_rank(q, c) on the QuadRank row's queries, structure and launch settings
+    extra = {}
+    if not args.no_extra and "quadrank_rank" in qsets:
+        h = handle("quadrank_rank")
+        apply("quadrank_rank")
+        q, c = qsets["quadrank_rank"]
+        evs = []
+        for k in range(args.warmup + args.steps):
+            o, cnt = bl[k % len(bl)]
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            h.prefix_rank(q[o:o + cnt], c[o:o + cnt], outs[:cnt])
+            b.record(stream)
+            if k >= args.warmup:
+                evs.append((a, b, cnt))
+        torch.cuda.synchronize()
+        secs = sum(a.elapsed_time(b) / 1e3 for a, b, _ in evs)
+        nq = sum(c_ for _, _, c_ in evs)
+        achieved = BYTES_PER_QUERY["quadrank_prefix_rank"] * nq / secs / 1e9
+        extra["quadrank_prefix_rank"] = {"queries_per_s": nq / secs, "avg_launch_ms": secs / len(evs) * 1e3,
+                                         "roofline_frac_hbm": achieved / HBM_PEAK_GBS, "algorithmic_GBps": achieved,
+                                         "layout": choice["quadrank_rank"], "in_step": False}
+        log("%-20s L%d %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline (outside the step)" % (
+            "quadrank_prefix_rank", choice["quadrank_rank"], nq / secs / 1e9, secs / len(evs) * 1e3,
+            100 * achieved / HBM_PEAK_GBS))
+
     # ------------------------------------------------------------------ FM-index rows
     fm_res = None
     if not args.no_fm:
@@ -348,6 +376,7 @@ def main():
             "queries_per_step": step_queries // args.steps,
         },
         "rows": row_res,
+        "extra_rows": extra,
         "builds": builds,
         "roofline": roofline,
         "fm": fm_res,
@@ -424,6 +453,12 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     res["gain_vs_best_batched"] = res["persistent_patterns_per_s"] / best_b
     res["gain_vs_batch_2^16"] = res["persistent_patterns_per_s"] / res["batched_65536_patterns_per_s"]
     res["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
+    # both strands: every pattern and its reverse complement, one persistent launch
+    cnt2 = torch.empty(npat, dtype=torch.int32, device=dev)
+    t_2 = autotune.time_launch(lambda: fm.count(dp, do, cnt2, both_strands=True), reps=args.fm_reps)
+    res["both_strands_patterns_per_s"] = npat / t_2
+    res["both_strands_ms"] = t_2 * 1e3
+    log("fm both strands %.1f M patterns/s (%.2f ms)" % (npat / t_2 / 1e6, t_2 * 1e3))
     # roofline of the persistent kernel: algorithmic lines (128 B each) per pattern from a sample
     work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev)
     achieved = npat / t_p * work["lines_per_pattern"] * 128 / 1e9
