@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--no-fm", action="store_true", help="skip the FM-index rows")
     ap.add_argument("--fm-patterns", type=int, default=10 ** 7)
     ap.add_argument("--fm-reps", type=int, default=3)
+    ap.add_argument("--fm-kmers", default="8,10,12", help="start-table sizes to try; the fastest is measured")
     ap.add_argument("--host-sa", action="store_true",
                     help="prepare the FM-index input (suffix array, BWT) with host SA-IS instead of on the device")
     ap.add_argument("--fm-locate-rate", type=int, default=32,
@@ -412,22 +413,30 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
         bwt, dollar, marks, samples = qr.quadfm_index_device(d_text, rate)
         del d_text
     t2 = time.time()
-    fm = qr.QuadFm(bwt, n + 1, dollar)
-    count_bytes = fm.nbytes
-    if rate:
-        fm.attach_locate(marks, samples, rate)
-        del marks, samples
-    del bwt
+    kmers = [int(x) for x in args.fm_kmers.split(",") if x]
+    fms = {k: qr.QuadFm(bwt, n + 1, dollar, kmer=k) for k in kmers}
     torch.cuda.synchronize()
     t3 = time.time()
     pat, off, kind = datagen.patterns(2830, codes, args.fm_patterns)
     del codes
     dp, do = to_dev(pat), to_dev(off)
     npat = args.fm_patterns
+    # start-table size: the count rate of each k (default launch settings); the fastest is used below
+    cnt = torch.empty(npat, dtype=torch.int32, device=dev)
+    by_kmer = {k: npat / autotune.time_launch(lambda f=f: f.count(dp, do, cnt), reps=2) for k, f in fms.items()}
+    kbest = max(by_kmer, key=by_kmer.get)
+    log("fm start table: " + ", ".join("k=%d %.1f M patterns/s" % (k, v / 1e6) for k, v in by_kmer.items()))
+    fm = fms.pop(kbest)
+    for f in fms.values():
+        f.free()
+    count_bytes = fm.nbytes
+    if rate:
+        fm.attach_locate(marks, samples, rate)
+        del marks, samples
+    del bwt
     total_chars = int(off[-1])
     log("fm index: text %.1fs, %s SA+BWT %.2fs, device build %.2fs" % (t1 - t0, "host" if args.host_sa else "device",
                                                                        t2 - t1, t3 - t2))
-    cnt = torch.empty(npat, dtype=torch.int32, device=dev)
     cnt_b = torch.empty(npat, dtype=torch.int32, device=dev)
     if isinstance(getattr(args, "fm_tuning", None), dict):
         best = args.fm_tuning
@@ -444,7 +453,8 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
                        % npat,
            "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3, "tuning": best,
            "index_bytes": count_bytes, "bits_per_base": count_bytes * 8 / n, "pattern_chars": total_chars,
-           "sa_bwt_s": t2 - t1, "sa_bwt_on": "host" if args.host_sa else "device", "device_build_s": t3 - t2}
+           "sa_bwt_s": t2 - t1, "sa_bwt_on": "host" if args.host_sa else "device",
+           "device_build_s_all_kmers": t3 - t2, "kmer": kbest, "by_kmer_patterns_per_s": by_kmer}
     for batch in (1 << 16, 1 << 20, 0):
         t_b = autotune.time_launch(lambda: fm.count_batched(dp, do, batch, cnt_b), reps=args.fm_reps)
         res["batched_%s_patterns_per_s" % (batch or "all")] = npat / t_b
@@ -460,7 +470,7 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     res["both_strands_ms"] = t_2 * 1e3
     log("fm both strands %.1f M patterns/s (%.2f ms)" % (npat / t_2 / 1e6, t_2 * 1e3))
     # roofline of the persistent kernel: algorithmic lines (128 B each) per pattern from a sample
-    work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev)
+    work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=kbest)
     achieved = npat / t_p * work["lines_per_pattern"] * 128 / 1e9
     res["work"] = work
     res["roofline"] = {"bound": "hbm", "kernel": "fm_persistent_kernel", "achieved": round(achieved, 1),
@@ -493,20 +503,21 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     return res
 
 
-def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, sample=2000, seed=11):
+def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=8, sample=2000, seed=11):
     """Backward steps, lines and half-line loads per pattern, on a sample of the workload: the
-    search of P starts from the interval of its last 8 characters and step k (k = 1..m-8) turns the
-    interval of the suffix P[m-8-k+1..m) into that of P[m-8-k..m), stopping once it is empty.  A
-    step reads one 128-byte line when sp and ep share a line (else two), and one 64-byte half when
-    they share a half line (else two halves).  The suffix intervals come from quadfm_intervals."""
+    search of P starts from the interval of its last K = kmer characters and step k (k = 1..m-K)
+    turns the interval of the suffix P[m-K-k+1..m) into that of P[m-K-k..m), stopping once it is
+    empty.  A step reads one 128-byte line when sp and ep share a line (else two), and one 64-byte
+    half when they share a half line (else two halves).  The suffix intervals come from
+    quadfm_intervals."""
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(npat, min(sample, npat), replace=False))
     sufs, owner = [], []
     for p in idx:
         P = pat[int(off[p]):int(off[p + 1])]
         m = P.size
-        for k in range(0, m - 7):  # suffix lengths 8..m
-            sufs.append(P[m - 8 - k:])
+        for k in range(0, m - kmer + 1):  # suffix lengths K..m
+            sufs.append(P[m - kmer - k:])
             owner.append(p)
     soff = np.zeros(len(sufs) + 1, np.uint64)
     soff[1:] = np.cumsum([x.size for x in sufs])
@@ -516,7 +527,7 @@ def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, sample=2000, seed=11):
     i = 0
     for p in idx:
         m = int(off[p + 1] - off[p])
-        k_max = m - 8
+        k_max = m - kmer
         for k in range(1, k_max + 1):
             sp, ep = iv[i + k - 1]
             if ep <= sp:

@@ -164,6 +164,11 @@ int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t rate, uint64
  * dollar_pos).  Builds QuadRank over the BWT, the C array and the 8-mer interval table. */
 int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,
                  qr_quadfm *out);
+/* Same with a start table of k-mer intervals, 1 <= kmer <= 12 (4^kmer u32 pairs: 512 KiB at 8, 8 MiB
+ * at 10, 128 MiB at 12); patterns of at least kmer characters take their first kmer backward steps
+ * from it. */
+int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
+                    hipStream_t stream, qr_quadfm *out);
 /* Count occurrences of npat patterns given in CSR form: pattern p is the codes
  * d_pat[d_off[p] .. d_off[p+1]) (u8 codes 0..3; u64 offsets, npat+1 of them); d_count[p] receives
  * the size of its BWT interval (u32).  An empty pattern counts n+1; a pattern with a code > 3
@@ -223,8 +228,8 @@ int quadfm_check(qr_quadfm h, hipStream_t stream);
 int quadfm_free(qr_quadfm h);
 uint64_t quadfm_len(qr_quadfm h);   /* n (text length, without '$') */
 uint64_t quadfm_bytes(qr_quadfm h); /* device bytes of the index */
-/* Device pointer and entry count (4^8) of the 8-mer table of u32 pairs (sp, ep); an empty interval
- * is stored as (0, 0).  quadfm_export_table copies the 2*4^8 u32 to host memory. */
+/* Device pointer and entry count (4^k) of the k-mer table of u32 pairs (sp, ep); an empty interval
+ * is stored as (0, 0).  quadfm_export_table copies the 2*4^k u32 to host memory. */
 int quadfm_table(qr_quadfm h, const void **d_table, uint64_t *entries);
 int quadfm_export_table(qr_quadfm h, uint32_t *h_pairs);
 /* C[c] = 1 + number of text characters smaller than c, for c = 0..3. */

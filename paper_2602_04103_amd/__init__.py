@@ -95,6 +95,7 @@ def lib():
             "quadfm_index_host": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp]),
             "quadfm_index_device": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp, vp]),
             "quadfm_intervals": (ci, [vp, vp, vp, u64, vp, vp]),
+            "quadfm_build_ex": (ci, [vp, u64, u64, C.c_uint32, vp, C.POINTER(vp)]),
             "quadfm_locate_attach": (ci, [vp, vp, vp, u64, C.c_uint32, vp]),
             "quadfm_locate_offsets": (ci, [vp, vp, u64, vp, vp]),
             "quadfm_locate": (ci, [vp, vp, vp, u64, u64, vp, vp]),
@@ -290,10 +291,10 @@ def quadfm_index_device(text: torch.Tensor, rate: int = 0, stream=None):
     return bwt, int(d.value), marks, samples
 
 
-def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None) -> int:
+def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None, kmer: int = 8) -> int:
     h = vp()
-    _check(lib().quadfm_build(_dev(bwt_packed2, "bwt_packed2", W64, (n_plus_1 + 31) // 32), n_plus_1, dollar_pos,
-                              _stream(stream), C.byref(h)), "quadfm_build")
+    _check(lib().quadfm_build_ex(_dev(bwt_packed2, "bwt_packed2", W64, (n_plus_1 + 31) // 32), n_plus_1, dollar_pos,
+                                 kmer, _stream(stream), C.byref(h)), "quadfm_build")
     return h.value
 
 
@@ -530,12 +531,13 @@ class QuadFm(_Handle):
     """Count-only FM-index built from a packed BWT of T$ ('$' stored as A at row dollar_pos)."""
     _free = staticmethod(quadfm_free)
 
-    def __init__(self, bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None):
-        super().__init__(quadfm_build(bwt_packed2, n_plus_1, dollar_pos, stream))
+    def __init__(self, bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None, kmer: int = 8):
+        super().__init__(quadfm_build(bwt_packed2, n_plus_1, dollar_pos, stream, kmer))
+        self.kmer = kmer
         self.n = n_plus_1 - 1
 
     @classmethod
-    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = False):
+    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = False, kmer: int = 8):
         """Host SA/BWT construction (or, with device_sa, the device one), then the device build;
         with locate_rate > 0 also the suffix-array sample at that rate, attached for locate."""
         import numpy as np
@@ -544,15 +546,15 @@ class QuadFm(_Handle):
             t = torch.from_numpy(np.ascontiguousarray(text_codes, dtype=np.uint8)).cuda()
             bwt, dollar, marks, samples = quadfm_index_device(t, locate_rate, stream)
             del t
-            fm = cls(bwt, n1, dollar, stream)
+            fm = cls(bwt, n1, dollar, stream, kmer)
             if locate_rate:
                 fm.attach_locate(marks, samples, locate_rate, stream)
             return fm
         if not locate_rate:
             bwt, dollar = quadfm_bwt_host(text_codes)
-            return cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream)
+            return cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream, kmer)
         bwt, dollar, marks, samples = quadfm_index_host(text_codes, locate_rate)
-        fm = cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream)
+        fm = cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream, kmer)
         fm.attach_locate(torch.from_numpy(marks.view(np.int64)).cuda(), torch.from_numpy(samples.view(np.int32)).cuda(),
                          locate_rate, stream)
         return fm
@@ -609,9 +611,9 @@ class QuadFm(_Handle):
         return c
 
     def table(self):
-        """(sp, ep) u32 arrays of the 4^8 entries of the 8-mer table."""
+        """(sp, ep) u32 arrays of the 4^k entries of the k-mer start table."""
         import numpy as np
-        t = np.zeros(2 * 65536, dtype=np.uint32)
+        t = np.zeros(2 * 4 ** self.kmer, dtype=np.uint32)
         _check(lib().quadfm_export_table(self.h, t.ctypes.data), "quadfm_export_table")
         return t[0::2].copy(), t[1::2].copy()
 

@@ -5,10 +5,11 @@
 //   - BWT of T$ with the single '$' stored as A at row dollar; rank_B(q, A) = rank(q, A) - [q > dollar]
 //     corrects it (the sentinel handled by storing its position, Appendix D);
 //   - C[c] = 1 + #{text characters < c} ('$' sorts first and occupies row 0's bucket);
-//   - a lookup table of the interval of every 8-mer (the prefix table for the first 8 characters
-//     the backward search processes, i.e. the pattern's last 8), built by 8 backward steps.
-// Count of pattern P (length m): start from table[P[m-8..m)] (or [0, n+1) when m < 8), then for
-// i = m-9 down to 0 (m-1 down to 0): c = P[i], sp = C[c] + rank_B(sp, c), ep = C[c] + rank_B(ep, c),
+//   - a lookup table of the interval of every k-mer (the prefix table for the first k characters
+//     the backward search processes, i.e. the pattern's last k), built by k backward steps; k = 8
+//     as in the paper by default, up to 12 as a build option.
+// Count of pattern P (length m): start from table[P[m-k..m)] (or [0, n+1) when m < k), then for
+// i = m-k-1 down to 0 (m-1 down to 0): c = P[i], sp = C[c] + rank_B(sp, c), ep = C[c] + rank_B(ep, c),
 // stopping once sp >= ep; the count is ep - sp (0 when empty).  m = 0 counts n+1; a code > 3 counts 0.
 //
 // Two count kernels:
@@ -51,6 +52,7 @@ struct qr_quadfm_s {
     unsigned long long *head;    // device work-queue head
     uint32_t *err;               // sticky device error word (locate)
     qr_tuning tune;              // persistent kernel: block, refill threshold (per_lane), waves per CU
+    uint32_t kmer;               // characters resolved by the start table (4^kmer entries)
     // locate support (absent until quadfm_locate_attach)
     qr_birank marks;             // BiRank (16-bit layout) over the n+1 mark bits
     uint32_t *samples;           // SA values of the marked rows, in row order
@@ -60,8 +62,7 @@ struct qr_quadfm_s {
 
 namespace {
 
-constexpr int KMER = 8;
-constexpr uint32_t KMER_ENTRIES = 1u << (2 * KMER);
+constexpr uint32_t KMER_DEFAULT = 8, KMER_MAX = 12;  // the start table holds 4^k intervals
 
 struct FmDev {
     const uint4 *lines;
@@ -70,6 +71,7 @@ struct FmDev {
     uint64_t n1, dollar;
     uint64_t C0, C1, C2, C3;
     uint32_t *err;  // sticky error word: ERR_WALK (locate), ERR_OFFSETS (a decreasing offset pair)
+    uint32_t kmer;  // characters resolved by the start table
 };
 
 constexpr uint32_t ERR_WALK = 1u, ERR_OFFSETS = 2u;
@@ -114,9 +116,9 @@ __device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint64_t &sp
 
 __global__ __launch_bounds__(256) void fm_table_kernel(FmDev f, uint2 *__restrict__ table) {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= KMER_ENTRIES) return;
+    if (w >= (1u << (2 * f.kmer))) return;
     uint64_t sp = 0, ep = f.n1;
-    for (int k = 0; k < KMER && sp < ep; ++k) fm_step(f, (w >> (2 * k)) & 3u, sp, ep);
+    for (uint32_t k = 0; k < f.kmer && sp < ep; ++k) fm_step(f, (w >> (2 * k)) & 3u, sp, ep);
     if (sp >= ep) sp = ep = 0;
     table[w] = make_uint2((uint32_t)sp, (uint32_t)ep);
 }
@@ -166,12 +168,13 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
     s.rc = rc;
     s.buf_at = ~(uintptr_t)0;
     const uint32_t m = s.m;
-    if (m >= KMER) {
-        // the first 8 characters searched: P[m-8..m) for P, the complement of P[0..8) reversed for rc(P)
+    const uint32_t K = f.kmer;
+    if (m >= K) {
+        // the first K characters searched: P[m-K..m) for P, the complement of P[0..K) reversed for rc(P)
         uint32_t w = 0;
         bool bad = false;
-        for (int t = 0; t < KMER; ++t) {
-            const uint32_t c = strand_code(s.P[rc ? KMER - 1 - t : m - KMER + t], rc);
+        for (uint32_t t = 0; t < K; ++t) {
+            const uint32_t c = strand_code(s.P[rc ? K - 1 - t : m - K + t], rc);
             bad |= c > 3;
             w = (w << 2) | (c & 3u);
         }
@@ -182,8 +185,8 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
         const uint2 iv = f.table[w];
         s.sp = iv.x;
         s.ep = iv.y;
-        s.left = m - KMER;
-        s.pos = rc ? KMER : m - KMER - 1;
+        s.left = m - K;
+        s.pos = rc ? K : m - K - 1;
     } else {
         s.sp = 0;
         s.ep = f.n1;
@@ -506,6 +509,7 @@ FmDev dev_view(const qr_quadfm_s *h) {
     f.dollar = h->dollar;
     f.C0 = h->C[0], f.C1 = h->C[1], f.C2 = h->C[2], f.C3 = h->C[3];
     f.err = h->err;
+    f.kmer = h->kmer;
     return f;
 }
 
@@ -527,10 +531,14 @@ int count_args(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_
 
 extern "C" {
 
-int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,
-                 qr_quadfm *out) {
+int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
+                    hipStream_t stream, qr_quadfm *out) {
     if (!out) return QR_EINVAL;
     *out = nullptr;
+    if (kmer < 1 || kmer > KMER_MAX) {
+        set_error("quadfm_build: the start table resolves 1..%u characters, not %u", KMER_MAX, kmer);
+        return QR_EINVAL;
+    }
     if (!d_bwt_packed2 || n_plus_1 == 0 || dollar_pos >= n_plus_1 || ((uintptr_t)d_bwt_packed2 & 7)) {
         set_error("quadfm_build: need a BWT of n+1 >= 1 symbols and dollar_pos < n+1");
         return QR_EINVAL;
@@ -547,12 +555,14 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
     }
     h->n1 = n_plus_1;
     h->dollar = dollar_pos;
+    h->kmer = kmer;
+    const uint64_t entries = 1ull << (2 * kmer);
     h->n_lines = n_plus_1 / QR_DATA_BASES + 1;
     h->n_sb = n_plus_1 / QR_SB_BASES + 1;
     h->tune = qr_tuning{256, 16, 16, 0};
     unsigned long long *tot = nullptr;
     if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 16) != hipSuccess ||
-        hipMalloc(&h->table, KMER_ENTRIES * sizeof(uint2)) != hipSuccess || hipMalloc(&h->head, 8) != hipSuccess ||
+        hipMalloc(&h->table, entries * sizeof(uint2)) != hipSuccess || hipMalloc(&h->head, 8) != hipSuccess ||
         hipMalloc(&h->err, 4) != hipSuccess || hipMalloc(&tot, 40) != hipSuccess) {
         (void)hipGetLastError();
         if (tot) (void)hipFree(tot);
@@ -589,7 +599,7 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
         return QR_EINVAL;
     }
     f = dev_view(h);
-    hipLaunchKernelGGL(fm_table_kernel, dim3(KMER_ENTRIES / 256), dim3(256), 0, stream, f, h->table);
+    hipLaunchKernelGGL(fm_table_kernel, dim3((uint32_t)((entries + 255) / 256)), dim3(256), 0, stream, f, h->table);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemsetAsync(h->err, 0, 4, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -600,6 +610,11 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
     }
     *out = h;
     return QR_OK;
+}
+
+int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,
+                 qr_quadfm *out) {
+    return quadfm_build_ex(d_bwt_packed2, n_plus_1, dollar_pos, KMER_DEFAULT, stream, out);
 }
 
 // flags: QUADFM_BOTH_STRANDS; iv: write intervals (uint2 per pattern) instead of counts
@@ -846,7 +861,7 @@ int quadfm_free(qr_quadfm h) {
 uint64_t quadfm_len(qr_quadfm h) { return h ? h->n1 - 1 : 0; }
 uint64_t quadfm_bytes(qr_quadfm h) {
     if (!h) return 0;
-    return h->n_lines * 128 + h->n_sb * 16 + KMER_ENTRIES * sizeof(uint2) +
+    return h->n_lines * 128 + h->n_sb * 16 + (1ull << (2 * h->kmer)) * sizeof(uint2) +
            (h->marks ? birank_bytes(h->marks) + h->n_samples * 4 : 0);
 }
 
@@ -864,7 +879,7 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t) {
 int quadfm_table(qr_quadfm h, const void **d_table, uint64_t *entries) {
     if (!h) return QR_EINVAL;
     if (d_table) *d_table = h->table;
-    if (entries) *entries = KMER_ENTRIES;
+    if (entries) *entries = 1ull << (2 * h->kmer);
     return QR_OK;
 }
 
@@ -872,7 +887,7 @@ int quadfm_export_table(qr_quadfm h, uint32_t *h_pairs) {
     if (!h || !h_pairs) return QR_EINVAL;
     int rc = check_device(h->device);
     if (rc) return rc;
-    QR_HIP(hipMemcpy(h_pairs, h->table, KMER_ENTRIES * sizeof(uint2), hipMemcpyDeviceToHost));
+    QR_HIP(hipMemcpy(h_pairs, h->table, (1ull << (2 * h->kmer)) * sizeof(uint2), hipMemcpyDeviceToHost));
     return QR_OK;
 }
 

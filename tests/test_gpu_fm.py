@@ -227,3 +227,44 @@ def test_fm_decreasing_offsets_count_zero_and_report():
             fm.check()
         assert ei.value.status == qr.QR_EINVAL
         fm.check()
+
+
+@pytest.mark.parametrize("kmer", [1, 5, 10, 12])
+def test_fm_start_table_sizes(kmer):
+    """Start tables of other k: the table equals the oracle's k-mer intervals, and counts, both-strand
+    counts and intervals equal the oracle's for patterns shorter and longer than k."""
+    qr = require_gpu()
+    n = 20_000 if kmer == 12 else 100_003
+    codes = make_text(70 + kmer, n)
+    pats = edge_patterns(codes, 3 * kmer)
+    sp, so, _ = datagen.patterns(71 + kmer, codes, 3000, minlen=1, maxlen=40, frac_sampled=0.8, sub=0.02)
+    pats += [sp[int(so[i]):int(so[i + 1])] for i in range(so.size - 1)]
+    pat, off = csr(pats)
+    announce("fm-kmer", kmer, n)
+    fm = qr.QuadFm.from_text(codes, kmer=kmer)
+    sa = oracle.suffix_array(codes)
+    b, _ = oracle.bwt(codes, sa)
+    lo, hi = oracle.kmer_intervals(b, kmer)
+    tsp, tep = fm.table()
+    nonempty = hi > lo
+    assert np.array_equal(tsp[nonempty], lo[nonempty].astype(np.uint32))
+    assert np.array_equal(tep[nonempty], hi[nonempty].astype(np.uint32))
+    assert not np.any(tsp[~nonempty]) and not np.any(tep[~nonempty])
+    want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
+    assert np.array_equal(gpu_counts(fm, pat, off), want)
+    assert np.array_equal(gpu_counts(fm, pat, off, batch=1000), want)
+    dp, do = to_dev(pat), to_dev(off)
+    both = fm.count(dp, do, both_strands=True).cpu().numpy().view(np.uint32)
+    assert np.array_equal(both, oracle.count_both_strands(codes, sa, pat, off).astype(np.uint32))
+    iv = fm.intervals(dp, do).cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal((iv[:, 1] - iv[:, 0]).astype(np.uint32), want)
+    fm.check()
+
+
+def test_fm_rejects_bad_kmer():
+    qr = require_gpu()
+    codes = datagen.dna_codes(3, 1000)
+    announce("fm-bad-kmer")
+    for k in (0, 13):
+        with pytest.raises(qr.QRError):
+            qr.QuadFm.from_text(codes, kmer=k)
