@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
     ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8", help="offered loads, patterns/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
+    ap.add_argument("--serve-kmer", type=int, default=12, help="start-table size of the served index")
     ap.add_argument("--serve-python", action="store_true",
                     help="run the sweep with the Python scheduling loop instead of the native one")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
@@ -557,7 +558,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     else:
         bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0)
     t1 = time.time()
-    fm = qr.QuadFm(bwt, n + 1, dollar)
+    fm = qr.QuadFm(bwt, n + 1, dollar, kmer=args.serve_kmer)
     del bwt
     fm.set_tuning(block=64, refill=32, waves_per_cu=8)
     log("serve index 2^%d: text + %s SA+BWT %.1fs" % (args.serve_log_n, "host" if args.host_sa else "device", t1 - t0))
@@ -566,7 +567,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     res = {"workload": "QuadFm serving: 2^%d-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs); "
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
-           "slots": slots, "hbm_budget_bytes": budget, "device_free_bytes_at_start": int(free),
+           "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "device_free_bytes_at_start": int(free),
            "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": []}
     # warm-up (untimed): first launches, pinned-memory pools, stream creation
     w0 = make_workload(4999, text, 1e6, 0.05, max_requests=200)
