@@ -3,6 +3,7 @@
 #include <mutex>
 
 #include "common.hpp"
+#include "birank_dev.hpp"
 #include "quadrank_dev.hpp"
 
 namespace qr {
@@ -65,9 +66,9 @@ const char *qr_version(void) { return "quadrank-mi355x 0.1 (gfx950)"; }
 
 uint64_t qr_line_of(uint64_t x, int which) {
     switch (which) {
-        case 0: return qr::br_line_of(x);
-        case 1: return qr::qr_line_of(x);
-        case 2: return qr::br32_line_of_host(x);
+        case 0: return qr::line_of<qr::BR16>(x);
+        case 1: return qr::qline_of<qr::QR16>(x);
+        case 2: return qr::line_of<qr::BR32>(x);
         case 3: return qr::qline_of<qr::QR32>(x);
         default: return ~0ull;
     }

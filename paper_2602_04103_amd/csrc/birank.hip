@@ -33,10 +33,6 @@ constexpr uint32_t GROUP_LINES = 64;  // lines per build workgroup (BR16: one su
 
 }  // namespace
 
-namespace qr {
-uint64_t br32_line_of_host(uint64_t x) { return line_of<BR32>(x); }
-}  // namespace qr
-
 struct qr_birank_s {
     int device;
     int layout;  // QR_LAYOUT_16 or QR_LAYOUT_32

@@ -31,9 +31,6 @@ int check_device(int dev);
 // Number of compute units of the current device (cached per device).
 int cu_count();
 
-// Host-side line index of the 32-bit BiRank layout (defined with its kernels).
-uint64_t br32_line_of_host(uint64_t x);
-
 // Build pass 2 (scan.hip): exclusive prefix sums of `ncol` interleaved u32 count columns.
 hipError_t launch_scan_counts(const uint32_t *cnt, uint64_t nrow, int ncol, uint32_t shift, uint64_t *base,
                               uint32_t *super, hipStream_t s);
@@ -45,16 +42,8 @@ hipError_t launch_scan_counts(const uint32_t *cnt, uint64_t nrow, int ncol, uint
 // quotient is the high word of the 128-bit product shifted right by t.
 //   1008 (BiRank payload):  s = 73, e = 880 -> exact for x < 2^63
 //    480 (QuadRank payload): s = 72, e = 224 -> exact for x < 2^63
-constexpr uint64_t BR_DATA_BITS = 1008;  // data bits per BiRank line
-constexpr uint64_t BR_LINES_PER_SB = 64;  // lines per BiRank superblock
-constexpr uint64_t BR_SB_BITS = BR_DATA_BITS * BR_LINES_PER_SB;  // 64512 = 1008 input words
-constexpr uint32_t BR_SHIFT = 10;        // superblock offset is rank >> 10
-constexpr uint32_t BR_MID = 512;         // line bit position of the middle (delta refers here)
-constexpr uint32_t BR_HDR = 16;          // line bits taken by the delta
-constexpr uint64_t BR_MAGIC = 0x8208208208208209ull;  // ceil(2^73 / 1008)
-constexpr uint32_t BR_MAGIC_T = 9;
-constexpr uint64_t BR_MAX_N = (1ull << 42) - 1;
-
+// The BiRank constants live with its layout traits (birank_dev.hpp); the 16-bit QuadRank constants
+// below serve the FM-index, whose BWT uses that layout.
 constexpr uint64_t QR_DATA_BASES = 480;  // bases per QuadRank line
 constexpr uint64_t QR_LINES_PER_SB = 128;
 constexpr uint64_t QR_SB_BASES = QR_DATA_BASES * QR_LINES_PER_SB;  // 61440 = 1920 input words
@@ -63,12 +52,10 @@ constexpr uint32_t QR_MID = 256;         // line base position of the middle
 constexpr uint32_t QR_HDR = 32;          // base slots taken by the four deltas
 constexpr uint64_t QR_MAGIC = 0x8888888888888889ull;  // ceil(2^72 / 480)
 constexpr uint32_t QR_MAGIC_T = 8;
-constexpr uint64_t QR_MAX_N = (1ull << 44) - 1;
 
 __host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
     return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) >> 64);
 }
-__host__ __device__ __forceinline__ uint64_t br_line_of(uint64_t q) { return mulhi64(q, BR_MAGIC) >> BR_MAGIC_T; }
 __host__ __device__ __forceinline__ uint64_t qr_line_of(uint64_t q) { return mulhi64(q, QR_MAGIC) >> QR_MAGIC_T; }
 
 // Mask selecting bit positions [0, t) of the 32-bit word that covers positions [32k, 32k+32).
