@@ -290,7 +290,8 @@ int qr_server_free(qr_server s);
 /* ------------------------------------------------------------------------------------------------
  * HIP graph capture of launch sequences.  Between qr_graph_begin(stream) and qr_graph_end(stream,
  * &g), calls to the enqueue-only entry points on `stream` (birank_rank, quadrank_rank,
- * quadrank_rank4, quadfm_count, quadfm_count_ws, quadfm_count_batched) are recorded instead of
+ * quadrank_rank4, quadrank_prefix_rank, quadfm_count[_ex|_ws], quadfm_count_batched[_ex],
+ * quadfm_intervals, quadfm_locate_offsets, quadfm_locate) are recorded instead of
  * run; qr_graph_launch replays the whole sequence with one launch, with the same pointers and sizes.
  * Build, *_check, *_export and *_free synchronise or allocate and must not be called while
  * capturing.  stream must not be the null stream.  The graph owns no caller buffer: those must

@@ -57,3 +57,53 @@ def test_graph_replays_rank_rank4_and_counts():
         assert torch.equal(o1, e1) and torch.equal(o4, e4)
         assert torch.equal(of, ef) and torch.equal(ob, eb) and torch.equal(orr, er)
     g.free()
+
+
+def test_graph_replays_prefix_rank_intervals_and_locate():
+    """prefix_rank on the 32-bit layout and the whole locate pipeline (intervals, output offsets, LF
+    walks; the number of positions taken from an eager run) captured in one graph."""
+    qr = require_gpu()
+    n = 3 * 57344 + 99
+    codes = datagen.dna_codes(71, n)
+    h = qr.QuadRank(to_dev(datagen.pack2(codes)), n, layout=qr.QR_LAYOUT_32)
+    q = to_dev(datagen.queries(72, n, 200_000))
+    c = to_dev(datagen.symbols(73, 200_000))
+    text = codes[:60_000].copy()
+    datagen.plant_repeats(74, text, nseg=5, seglen=1000, copies=6, sub=0.01)
+    fm = qr.QuadFm.from_text(text, locate_rate=8, device_sa=True)
+    pat, off, _ = datagen.patterns(75, text, 5000, minlen=8, maxlen=40)
+    dp, do = to_dev(pat), to_dev(off)
+    npat = off.size - 1
+
+    ep = h.prefix_rank(q, c).clone()
+    eiv = fm.intervals(dp, do).clone()
+    est = torch.empty(npat + 1, dtype=torch.int64, device="cuda")
+    qr.quadfm_locate_offsets(fm.h, eiv, est)
+    total = int(est[npat].item())
+    epos = torch.empty(total, dtype=torch.int32, device="cuda")
+    qr.quadfm_locate(fm.h, eiv, est, total, epos)
+    fm.check()
+    assert total > npat // 2
+
+    s = torch.cuda.Stream()
+    op, oiv = torch.empty_like(ep), torch.empty_like(eiv)
+    ost, opos = torch.empty_like(est), torch.empty_like(epos)
+    announce("graph capture locate", total)
+    with torch.cuda.stream(s):
+        g = qr.Graph(s)
+        with g:
+            h.prefix_rank(q, c, op, stream=s)
+            fm.intervals(dp, do, oiv, stream=s)
+            qr.quadfm_locate_offsets(fm.h, oiv, ost, stream=s)
+            qr.quadfm_locate(fm.h, oiv, ost, total, opos, stream=s)
+    for rep in range(3):
+        for t in (op, oiv, ost, opos):
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        announce("graph replay locate", rep)
+        g.launch(s)
+        s.synchronize()
+        assert torch.equal(op, ep) and torch.equal(oiv, eiv)
+        assert torch.equal(ost, est) and torch.equal(opos, epos)
+    fm.check()
+    g.free()
