@@ -3,9 +3,14 @@
  *
  * Implements the data structures of "QuadRank: Engineering a High Throughput
  * Rank" (Groot Koerkamp, arXiv 2602.04103) as GPU kernels:
- *   BiRank    — binary rank(q)                       (paper Section 3)
- *   QuadRank  — DNA rank(q, c) and rank4(q)           (paper Section 4)
- *   QuadFm    — count-only FM-index backward search   (paper Appendix D)
+ *   BiRank    — binary rank(q)                                     (paper Section 3)
+ *   QuadRank  — DNA rank(q, c), rank4(q) and prefix_rank(q, c)      (paper Section 4;
+ *               prefix_rank from the closing section)
+ *   QuadFm    — FM-index backward search: counts, intervals, and   (paper Appendix D;
+ *               locate by a sampled suffix array, with the input    locate from the
+ *               (suffix array, BWT) prepared on the host or device   closing section)
+ * plus a native continuous-batching serving loop, graph capture and
+ * microbenchmarks.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -28,8 +33,10 @@
  * - Handles own their device memory, released by the matching *_free.  A
  *   handle is bound to the device that was current at build time; calls must
  *   be made with that device current.  Concurrent queries on one handle
- *   (from several streams or threads) are allowed; build/free are not
- *   concurrent with anything else on that handle.
+ *   (from several streams or threads) are allowed, except QuadFm's persistent
+ *   count and interval calls, which share the handle's work-queue head
+ *   (quadfm_count_ws / quadfm_count_ex take a caller-owned head instead);
+ *   build/free are not concurrent with anything else on that handle.
  * - Errors: argument errors detectable on the host return a negative status
  *   and change nothing.  Errors that only the device sees (a query with
  *   q > n, a symbol c > 3) write UINT64_MAX to that output element and set a
