@@ -537,9 +537,10 @@ class QuadFm(_Handle):
         self.n = n_plus_1 - 1
 
     @classmethod
-    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = False, kmer: int = 8):
-        """Host SA/BWT construction (or, with device_sa, the device one), then the device build;
-        with locate_rate > 0 also the suffix-array sample at that rate, attached for locate."""
+    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = True, kmer: int = 8):
+        """Suffix array and BWT built on the device (device_sa=False: on the host with SA-IS), then
+        the index build; with locate_rate > 0 also the suffix-array sample at that rate, attached
+        for locate."""
         import numpy as np
         n1 = int(np.asarray(text_codes).size) + 1
         if device_sa:

@@ -57,12 +57,13 @@ def test_fm_small_texts_all_kernels(n):
     pats += [sp[int(so[i]):int(so[i + 1])] for i in range(so.size - 1)]
     pat, off = csr(pats)
     announce("fm-small", n, len(pats))
-    fm = qr.QuadFm.from_text(codes)
     sa = oracle.suffix_array(codes)
     want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
-    assert np.array_equal(gpu_counts(fm, pat, off), want)
-    assert np.array_equal(gpu_counts(fm, pat, off, batch=0), want)
-    assert np.array_equal(gpu_counts(fm, pat, off, batch=333), want)
+    for device_sa in (True, False):  # index input prepared on the device and on the host
+        fm = qr.QuadFm.from_text(codes, device_sa=device_sa)
+        assert np.array_equal(gpu_counts(fm, pat, off), want)
+        assert np.array_equal(gpu_counts(fm, pat, off, batch=0), want)
+        assert np.array_equal(gpu_counts(fm, pat, off, batch=333), want)
 
 
 def test_fm_c_array_and_kmer_table():
