@@ -104,8 +104,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the rank structures and the FM-index are replicated per GPU; see the sharding notes)",
+        print("bench.py runs on exactly one GPU: the rank structures and the FM-index have no multi-GPU "
+              "path here (they would be replicated per GPU, with the queries split between GPUs)",
               file=sys.stderr)
         sys.exit(2)
 

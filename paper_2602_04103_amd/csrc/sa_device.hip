@@ -5,7 +5,7 @@
 // Suffixes of T$ (N = n+1 of them, suffix n being '$' alone) are first sorted by their first 21
 // characters, packed 3 bits each ('$' and the end of text as 0, A..T as 1..4).  Sorted positions
 // with equal keys form groups; every suffix gets the rank of its group (the sorted index of the
-// group's first member).  Round h then sorts by the pair (rank[i], rank[i+h] + 1, or 0 past the
+// group's first member).  Doubling step h then sorts by the pair (rank[i], rank[i+h] + 1, or 0 past the
 // end), which orders suffixes by their first 2h characters; h doubles from 21 until every group is
 // a single suffix.  The sort is stable, so ties keep the previous order, as the method requires.
 //
@@ -279,7 +279,7 @@ __global__ void set_rank(const uint32_t *__restrict__ sa, const uint32_t *__rest
     if (i < N) rank[sa[i]] = gstart[i];
 }
 
-// key of sorted position i for round h: (rank of the suffix, rank of the suffix h further + 1, or 0)
+// key of sorted position i for doubling step h: (rank of the suffix, rank of the suffix h further + 1, or 0)
 __global__ void pair_keys(const uint32_t *__restrict__ sa, const uint32_t *__restrict__ rank, uint32_t N, uint32_t h,
                           uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -429,7 +429,7 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
         set_error("quadfm_index_device: a text code is above 3");
         return QR_EINVAL;
     }
-    // round 0: the first 21 characters
+    // initial sort: the first 21 characters
     if (e == hipSuccess) {
         hipLaunchKernelGGL(init_keys, dim3(blocks_for(N, 256)), dim3(256), 0, s, d_text, (uint32_t)n, B.k0, B.v0);
         e = hipGetLastError();
@@ -437,7 +437,7 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
     if (e == hipSuccess) e = radix_sort(B, N, 3 * KEY_CHARS, s);
     uint64_t groups = 0;
     if (e == hipSuccess) e = regroup(B, N, s, groups);
-    // rounds h = 21, 42, 84, ...: sort by (rank[i], rank[i+h]) until every suffix is alone
+    // doubling steps h = 21, 42, 84, ...: sort by (rank[i], rank[i+h]) until every suffix is alone
     const uint32_t rbits = bit_length(N);  // ranks < N; second component < N + 1
     for (uint64_t h = KEY_CHARS; e == hipSuccess && groups < N; h *= 2) {
         if (h > 2ull * N) {

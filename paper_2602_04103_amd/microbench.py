@@ -85,7 +85,8 @@ def lanes(args):
 
 
 def rankws(args):
-    """Rank throughput against structure size (cache-resident to HBM-resident)."""
+    """Rank throughput against structure size (cache-resident to HBM-resident), per inline layout;
+    the best of 1 and 2 queries per lane pair is printed."""
     import numpy as np
     import torch
 
@@ -93,33 +94,37 @@ def rankws(args):
     import paper_2602_04103_amd as qr
     nq = 1 << 24
     out = torch.empty(4 * nq, dtype=torch.int64, device="cuda")
+    layouts = {16: qr.QR_LAYOUT_16, 32: qr.QR_LAYOUT_32}
     for lg in args.qr_log_n:
         n = 1 << lg
         d = torch.from_numpy(datagen.bits(lg, 2 * n, 0.5).view(np.int64)).cuda()
-        h = qr.QuadRank(d, n)
-        del d
         q = torch.from_numpy(datagen.queries(lg + 1, n, nq).view(np.int64)).cuda()
         c = torch.from_numpy(datagen.symbols(lg + 2, nq)).cuda()
-        for pl in (1, 2):
-            h.set_tuning(lanes=2, per_lane=pl, block=256, grid_waves=0)
-            t1 = _time(lambda: h.rank(q, c, out[:nq]))
-            t4 = _time(lambda: h.rank4(q, out))
-            print("quadrank n=2^%d (%.2f GiB) per_pair=%d: rank %.2f G q/s, rank4 %.2f G q/s"
-                  % (lg, h.nbytes / 2**30, pl, nq / t1 / 1e9, nq / t4 / 1e9), flush=True)
-        h.free()
+        for L in args.layouts:
+            h = qr.QuadRank(d, n, layout=layouts[L])
+            t1 = t4 = float("inf")
+            for pl in (1, 2):
+                h.set_tuning(lanes=2, per_lane=pl, block=256, grid_waves=0)
+                t1 = min(t1, _time(lambda: h.rank(q, c, out[:nq])))
+                t4 = min(t4, _time(lambda: h.rank4(q, out)))
+            print("quadrank L%d n=2^%d (%.2f GiB): rank %.2f G q/s, rank4 %.2f G q/s"
+                  % (L, lg, h.nbytes / 2**30, nq / t1 / 1e9, nq / t4 / 1e9), flush=True)
+            h.free()
+        del d
         torch.cuda.empty_cache()
     for lg in args.br_log_n:
         n = 1 << lg
         d = torch.from_numpy(datagen.bits(lg, n, 0.5).view(np.int64)).cuda()
-        h = qr.BiRank(d, n)
-        del d
         q = torch.from_numpy(datagen.queries(lg + 1, n, nq).view(np.int64)).cuda()
-        for pl in (1, 2):
-            h.set_tuning(lanes=2, per_lane=pl, block=256, grid_waves=0)
-            t = _time(lambda: h.rank(q, out[:nq]))
-            print("birank n=2^%d (%.2f GiB) per_pair=%d: rank %.2f G q/s" % (lg, h.nbytes / 2**30, pl, nq / t / 1e9),
-                  flush=True)
-        h.free()
+        for L in args.layouts:
+            h = qr.BiRank(d, n, layout=layouts[L])
+            t = float("inf")
+            for pl in (1, 2):
+                h.set_tuning(lanes=2, per_lane=pl, block=256, grid_waves=0)
+                t = min(t, _time(lambda: h.rank(q, out[:nq])))
+            print("birank L%d n=2^%d (%.2f GiB): rank %.2f G q/s" % (L, lg, h.nbytes / 2**30, nq / t / 1e9), flush=True)
+            h.free()
+        del d
         torch.cuda.empty_cache()
 
 
@@ -133,8 +138,9 @@ def main(argv=None):
     l = sub.add_parser("lanes")
     l.add_argument("--log-n", type=int, default=36)
     r = sub.add_parser("rankws")
-    r.add_argument("--qr-log-n", type=int, nargs="+", default=[24, 28, 30, 31, 32, 33])
-    r.add_argument("--br-log-n", type=int, nargs="+", default=[28, 31, 33, 34, 35, 36])
+    r.add_argument("--qr-log-n", type=int, nargs="+", default=[24, 26, 28, 30, 31, 32, 33])
+    r.add_argument("--br-log-n", type=int, nargs="+", default=[24, 28, 31, 33, 34, 35, 36])
+    r.add_argument("--layouts", type=int, nargs="+", default=[16, 32], choices=[16, 32])
     a = ap.parse_args(argv)
     {"gather": gather, "glanes": glanes, "lanes": lanes, "rankws": rankws}[a.what](a)
 

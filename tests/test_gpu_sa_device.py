@@ -2,7 +2,7 @@
 radix sort, then the BWT and the locate sample) against the oracle's comparison-sort suffix array,
 bit-exact: packed BWT words, the row of '$', the mark bits and the sampled SA values, on texts
 around the sort's tile size (4096 suffixes), degenerate texts whose suffixes share very long
-prefixes (many doubling rounds), and texts with planted repeats.  Larger texts are compared with
+prefixes (many doubling steps), and texts with planted repeats.  Larger texts are compared with
 the host SA-IS output, and the count test at 2^28 bases builds its index this way."""
 import numpy as np
 import pytest
@@ -64,7 +64,7 @@ def test_device_sa_random_texts(n):
 
 @pytest.mark.parametrize("kind", ["allA", "allT", "period7", "tiled37", "halves"])
 def test_device_sa_degenerate_texts(kind):
-    """Suffixes sharing prefixes of thousands of characters: many doubling rounds."""
+    """Suffixes sharing prefixes of thousands of characters: many doubling steps."""
     qr = require_gpu()
     n = 30_001
     if kind == "allA":
