@@ -120,3 +120,57 @@ def test_arena_blocks_never_overlap_and_bytes_balance(size, ops):
     for s0, n0 in live:
         a.release(s0, n0)
     assert a.free == [(0, size)]
+
+
+# ------------------------------------------------------------------ serving scheduler (CPU stand-in)
+_SERVE_TEXT = None
+
+
+def _serve_text():
+    global _SERVE_TEXT
+    if _SERVE_TEXT is None:
+        _SERVE_TEXT = datagen.dna_codes(5151, 3000)
+    return _SERVE_TEXT
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 10_000), st.integers(1, 6), st.integers(8, 64), st.integers(0, 3), st.floats(1e3, 1e6),
+       st.integers(1, 5))
+def test_scheduler_serves_everything_within_limits(seed, slots, max_batch, budget_shift, rate, hold):
+    """Arbitrary workloads, slot counts, batch caps and budgets (as small as a few requests): every
+    request is served with the oracle's counts; in-flight batches never exceed the slots, reserved
+    bytes never exceed the budget, nothing finishes before it arrives, and admission is FIFO."""
+    from paper_2602_04103_amd.serve import FakeExecutor, Server, make_workload
+    text = _serve_text()
+    w = make_workload(seed, text, rate, duration_s=0.05, max_requests=30, max_size=48)
+    one = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
+    budget = one * (1 + budget_shift)
+    polls = {}
+
+    def ready(slot):  # a batch completes only after being polled `hold` times: overlap and reordering
+        polls[slot] = polls.get(slot, 0) + 1
+        if polls[slot] >= hold:
+            polls[slot] = 0
+            return True
+        return False
+
+    ex = FakeExecutor(w, lambda pat, off: oracle.count_naive(text, pat, off).astype(np.uint32), ready=ready)
+    t = [0.0]
+
+    def clock():
+        t[0] += 1e-3
+        return t[0]
+
+    srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=max_batch)
+    res = srv.run(w, clock=clock, deadline_s=1e6)
+    assert res.max_inflight <= slots and res.max_reserved_bytes <= budget
+    assert np.all(res.finish_s >= w.arrival)
+    for r in range(w.nreq):
+        p0, p1 = int(w.req_off[r]), int(w.req_off[r + 1])
+        want = oracle.count_naive(text, w.pat[int(w.off[p0]):int(w.off[p1])],
+                                  (w.off[p0:p1 + 1] - w.off[p0]).astype(np.uint64)).astype(np.uint32)
+        assert np.array_equal(srv.counts_of(w, r), want)
+    starts = [r0 for _, r0, _, _ in ex.submitted]
+    assert starts == sorted(starts) and starts[0] == 0          # batches cover the requests in order
+    assert all(r1 == nxt for (_, _, r1, _), (_, nxt, _, _) in zip(ex.submitted, ex.submitted[1:]))
+    assert ex.submitted[-1][2] == w.nreq
