@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import statistics
@@ -96,6 +97,7 @@ def main():
     ap.add_argument("--layouts", default="16,32",
                     help="inline-delta widths to build for each rank row; the tuner picks one per row")
     ap.add_argument("--no-extra", action="store_true", help="skip the prefix_rank row timed outside the step")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing of the steps")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tuning-from", default=None,
                     help="apply the launch settings recorded in an earlier bench JSON line instead of tuning")
@@ -221,9 +223,14 @@ def main():
             tuning[row] = "default"
             continue
         best_t = None
+        # every timed launch of a candidate takes the next full batch, as the timed steps do: replaying
+        # one batch leaves its queries and translations cached and can rank candidates differently
+        full = [k for k, (_, cnt) in enumerate(bl) if cnt == BATCH]
+        turn = itertools.count()
         for L in layouts:
             h = handle(row, L)
-            best, table = autotune.tune("%s|L%d" % (row, L), h.n, h.set_tuning, lambda r=row, L=L: launch(r, 0, L),
+            best, table = autotune.tune("%s|L%d" % (row, L), h.n, h.set_tuning,
+                                        lambda r=row, L=L: launch(r, full[next(turn) % len(full)], L),
                                         autotune.RANK_CANDIDATES, use_cache=False)
             t_best = min(t for _, t in table)
             by_layout[row][str(L)] = {"tuned_launch_ms": round(t_best * 1e3, 4), "tuning": best,
@@ -314,6 +321,31 @@ def main():
         "bytes_per_query": BYTES_PER_QUERY[dom],
     }
 
+    # ------------------------------------------------------------------ the same steps from a HIP graph
+    # the K timed steps (every row, every batch) captured once and replayed with one launch
+    graph_res = None
+    if not args.no_graph and rows:
+        gs = torch.cuda.Stream()
+        g = qr.Graph(gs)
+        with torch.cuda.stream(gs):
+            with g:
+                for k in range(args.steps):
+                    for row in rows:
+                        apply(row)  # the launch settings are frozen into the captured launches
+                        launch(row, k)
+        g.launch(gs)  # untimed first replay
+        gs.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.launch(gs)
+        gs.synchronize()
+        t_g = time.perf_counter() - t0
+        g.free()
+        graph_res = {"rank_queries_per_s": step_queries / t_g, "ms_per_step": t_g / args.steps * 1e3,
+                     "launches": args.steps * len(rows)}
+        log("graph replay of the %d steps: %.2f G q/s (%.3f ms/step)" % (args.steps, step_queries / t_g / 1e9,
+                                                                      t_g / args.steps * 1e3))
+
     # ------------------------------------------------------------------ extra rows (not in the step)
     # prefix_rank(q, c) on the QuadRank row's queries, structure and launch settings
     extra = {}
@@ -354,7 +386,10 @@ def main():
     # ------------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
     if not args.no_cpu_baseline and packed_q is not None and "quadrank_rank" in qsets:
-        cpu = cpu_baseline(packed_q, n_qr, datagen, np)
+        cpu = cpu_baseline(packed_q, n_qr, datagen, np, with_birank="birank_rank_p0.5" in rows)
+        log("cpu baseline (oracle, %d threads): rank %.1f M q/s, rank4 %.1f M q/s%s" % (
+            cpu["cores"], cpu["value"] / 1e6, cpu["rank4_queries_per_s"] / 1e6,
+            ", BiRank %.1f M q/s" % (cpu["birank_queries_per_s"] / 1e6) if "birank_queries_per_s" in cpu else ""))
 
     out = {
         "metric": "rank queries/s + % HBM random-line roofline; FM count patterns/s, p99 latency",
@@ -379,6 +414,7 @@ def main():
         },
         "rows": row_res,
         "extra_rows": extra,
+        "graph": graph_res,
         "builds": builds,
         "roofline": roofline,
         "fm": fm_res,
@@ -604,26 +640,51 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     return res
 
 
-def cpu_baseline(packed, n, datagen, np):
-    """The oracle (plain C, OpenMP over queries) on the host cores: build its prefix table over the
-    whole 2^32-base text once per call, then answer a bounded sample of the same queries."""
+def cpu_baseline(packed, n, datagen, np, with_birank=True):
+    """The oracle (plain C, OpenMP over queries) on the host cores, on bounded samples of the same
+    workloads.  Every oracle call first builds its prefix table over the whole structure (serially),
+    which the GPU timing has no counterpart of, so each rate is differential: one call on a sample
+    of S queries and one on its first S/4, and the rate is (3/4 S) / (t_S - t_{S/4}); the build
+    cancels."""
     import oracle
-    S = 10 ** 7
+
+    def rate(fn, q_all, *rest):
+        S = q_all.size
+        s = S // 4
+        t0 = time.perf_counter()
+        fn(q_all[:s], *[r[:s] for r in rest])
+        t_small = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fn(q_all, *rest)
+        t_big = time.perf_counter() - t0
+        return (S - s) / max(t_big - t_small, 1e-9), t_small, t_big
+
+    S = 2 * 10 ** 8
     q = datagen.queries(3204, n, S)
     c = datagen.symbols(3205, S)
-    t0 = time.perf_counter()
-    oracle.rank_dna(packed, n, q[:1], c[:1])
-    t_build = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.rank_dna(packed, n, q, c)
-    t_all = time.perf_counter() - t0
-    t_q = max(t_all - t_build, 1e-9)
+    r_q, ts, tb = rate(lambda qq, cc: oracle.rank_dna(packed, n, qq, cc), q, c)
+    del c
+    S4 = 10 ** 8
+    r_4, ts4, tb4 = rate(lambda qq: oracle.rank4_dna(packed, n, qq), q[:S4])
+    del q
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": S / t_q, "unit": "rank queries/s", "cores": cores, "kind": "oracle",
-            "sample": "first 10^7 of the QuadRank rank(q,c) queries on the same 2^32-base text; the oracle's "
-                      "prefix table over the whole text (%.1f s, built per call) is subtracted, as the GPU build "
-                      "is outside the GPU timing" % t_build,
-            "prefix_build_s": t_build}
+    res = {"value": r_q, "unit": "rank queries/s", "cores": cores, "kind": "oracle",
+           "sample": "2*10^8 uniform rank(q,c) queries on the same 2^32-base text, timed against its first "
+                     "5*10^7 (%.2f s vs %.2f s); the difference removes the oracle's per-call prefix table "
+                     "build, as the GPU build is outside the GPU timing" % (tb, ts),
+           "rank4_queries_per_s": r_4,
+           "rank4_sample": "10^8 uniform rank4 queries vs their first 2.5*10^7 (%.2f s vs %.2f s), same text"
+                           % (tb4, ts4)}
+    if with_birank:
+        nb = 1 << 36
+        bits = datagen.bits(3636, nb, 0.5)
+        qb = datagen.queries(3736, nb, S)
+        r_b, tsb, tbb = rate(lambda qq: oracle.rank_bits(bits, nb, qq), qb)
+        res["birank_queries_per_s"] = r_b
+        res["birank_sample"] = ("2*10^8 uniform BiRank queries on a 2^36-bit vector of density 0.5 vs their "
+                                "first 5*10^7 (%.2f s vs %.2f s)" % (tbb, tsb))
+        del bits, qb
+    return res
 
 
 if __name__ == "__main__":
