@@ -387,8 +387,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and packed_q is not None and "quadrank_rank" in qsets:
         cpu = cpu_baseline(packed_q, n_qr, datagen, np, with_birank="birank_rank_p0.5" in rows)
-        log("cpu baseline (oracle, %d threads): rank %.1f M q/s, rank4 %.1f M q/s%s" % (
-            cpu["cores"], cpu["value"] / 1e6, cpu["rank4_queries_per_s"] / 1e6,
+        log("cpu baseline (oracle, %d threads, %s): rank %.1f M q/s (one thread %.1f), rank4 %.1f M q/s%s" % (
+            cpu["cores"], cpu["cpu_model"], cpu["value"] / 1e6, cpu["one_thread_queries_per_s"] / 1e6,
+            cpu["rank4_queries_per_s"] / 1e6,
             ", BiRank %.1f M q/s" % (cpu["birank_queries_per_s"] / 1e6) if "birank_queries_per_s" in cpu else ""))
 
     out = {
@@ -640,6 +641,17 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     return res
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(packed, n, datagen, np, with_birank=True):
     """The oracle (plain C, OpenMP over queries) on the host cores, on bounded samples of the same
     workloads.  Every oracle call first builds its prefix table over the whole structure (serially),
@@ -663,15 +675,24 @@ def cpu_baseline(packed, n, datagen, np, with_birank=True):
     q = datagen.queries(3204, n, S)
     c = datagen.symbols(3205, S)
     r_q, ts, tb = rate(lambda qq, cc: oracle.rank_dna(packed, n, qq, cc), q, c)
+    S1 = 2 * 10 ** 7
+    cores = oracle.set_threads(1)
+    try:
+        r_1, ts1, tb1 = rate(lambda qq, cc: oracle.rank_dna(packed, n, qq, cc), q[:S1], c[:S1])
+    finally:
+        oracle.set_threads(cores)
     del c
     S4 = 10 ** 8
     r_4, ts4, tb4 = rate(lambda qq: oracle.rank4_dna(packed, n, qq), q[:S4])
     del q
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     res = {"value": r_q, "unit": "rank queries/s", "cores": cores, "kind": "oracle",
            "sample": "2*10^8 uniform rank(q,c) queries on the same 2^32-base text, timed against its first "
                      "5*10^7 (%.2f s vs %.2f s); the difference removes the oracle's per-call prefix table "
                      "build, as the GPU build is outside the GPU timing" % (tb, ts),
+           "one_thread_queries_per_s": r_1,
+           "one_thread_sample": "2*10^7 of the same rank(q,c) queries vs their first 5*10^6 on one thread "
+                                "(%.2f s vs %.2f s)" % (tb1, ts1),
+           "cpu_model": cpu_model(),
            "rank4_queries_per_s": r_4,
            "rank4_sample": "10^8 uniform rank4 queries vs their first 2.5*10^7 (%.2f s vs %.2f s), same text"
                            % (tb4, ts4)}

@@ -68,8 +68,16 @@ def _load():
         lib.or_count_backward.argtypes = [vp, u64, vp, vp, u64, vp]
         lib.or_kmer_intervals.restype = C.c_int
         lib.or_kmer_intervals.argtypes = [vp, u64, C.c_int, vp, vp]
+        lib.or_set_threads.restype = C.c_int
+        lib.or_set_threads.argtypes = [C.c_int]
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads used by the query loops from now on (n <= 0 keeps the setting); returns the previous
+    count.  Results do not depend on it."""
+    return int(_load().or_set_threads(int(n)))
 
 
 def _p(a: np.ndarray) -> int:

@@ -29,6 +29,16 @@
 
 #define OR_BAD UINT64_MAX
 
+#include <omp.h>
+
+/* Threads of the OpenMP loops over queries from now on; returns the previous setting.  The loops'
+   results do not depend on it (each query is answered on its own). */
+int or_set_threads(int n) {
+    int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+}
+
 /* ---- binary rank: rank(q) = #{ i < q : t_i = 1 }, 0 <= q <= n ---------------------------------- */
 
 static uint64_t word_masked(const uint64_t *words, uint64_t n, uint64_t w) {
