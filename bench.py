@@ -18,7 +18,6 @@ sample at rate 32).  The CPU baseline times the oracle on the host cores on a bo
 from __future__ import annotations
 
 import argparse
-import hashlib
 import itertools
 import json
 import os
@@ -41,13 +40,6 @@ BYTES_PER_QUERY = {
     "birank_rank_p0.5": 128 + 8 + 8,
     "birank_rank_p0.05": 128 + 8 + 8,
 }
-KERNEL_NAMES = {
-    "quadrank_rank": "qr_rank1_pair_kernel",
-    "quadrank_rank4": "qr_rank4_pair_kernel",
-    "quadrank_prefix_rank": "qr_prefix_pair_kernel",
-    "birank_rank_p0.5": "br_rank_pair_kernel",
-    "birank_rank_p0.05": "br_rank_pair_kernel",
-}
 
 
 def log(*a):
@@ -60,14 +52,6 @@ def batches(total: int, batch: int):
         out.append((o, min(batch, total - o)))
         o += batch
     return out
-
-
-def source_hash(*names) -> str:
-    h = hashlib.sha256()
-    for nme in names:
-        with open(os.path.join(ROOT, "paper_2602_04103_amd", "csrc", nme), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def main():
@@ -116,7 +100,7 @@ def main():
 
     import datagen
     import paper_2602_04103_amd as qr
-    from paper_2602_04103_amd import autotune
+    from paper_2602_04103_amd import autotune, profiling
 
     qr.lib()  # fail loudly when the HIP library is missing
     torch.cuda.init()
@@ -297,20 +281,22 @@ def main():
 
     # dominant kernel = largest share of the step's time
     dom = max(rows, key=lambda r: row_res[r]["avg_launch_ms"]) if rows else None
+    form = profiling.launch_form(tuning.get(dom)) if dom else None
     traffic = None
     prof_path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         if dom is None:
             raise KeyError("no rank rows")
         prof = json.load(open(prof_path))
-        ent = prof.get("kernels", {}).get("%s|L%d" % (dom, choice[dom]))
-        if ent and source_hash(*ent.get("sources", [])) == ent.get("source_hash"):
+        ent = prof.get("kernels", {}).get(profiling.traffic_key(dom, choice[dom], form))
+        if ent and profiling.source_hash(ent.get("sources", [])) == ent.get("source_hash"):
             traffic = ent["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
     roofline = None if dom is None else {
         "bound": "hbm",
-        "kernel": "%s<%s%d> (%s)" % (KERNEL_NAMES[dom], "QR" if dom.startswith("quadrank") else "BR", choice[dom], dom),
+        "kernel": "%s<%s%d> (%s)" % (profiling.ROW_KERNELS[dom][form], "QR" if dom.startswith("quadrank") else "BR",
+                                     choice[dom], dom),
         "row": dom,
         "layout": choice[dom],
         "achieved": round(row_res[dom]["algorithmic_GBps"], 1),

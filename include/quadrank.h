@@ -249,12 +249,19 @@ int quadfm_c_array(qr_quadfm h, uint64_t *h_C4);
  *   grid_waves resident waves per CU to launch (0 = enough lanes for every query, no grid-stride)
  *   lanes      lanes per query: 2 (default; each lane reads one 64-byte half of the line and the
  *              halves are combined by a cross-lane shuffle) or 1 (one lane reads what it needs)
+ *   sweep      0 (default) or the tile size 1024, 2048 or 4096 of the position-ordered form: each
+ *              workgroup of 256 threads sorts a tile of that many consecutive queries by position
+ *              in LDS and answers them in that order, so that the workgroups running together
+ *              load from a narrow band of the structure; results still go to the queries' own
+ *              slots.  Needs lanes = 2 and per_lane 1 or 2; block and grid_waves are ignored.
+ *              Outputs are identical to the other forms.
  * ---------------------------------------------------------------------------------------------- */
 typedef struct {
     int32_t block;
     int32_t per_lane;
     int32_t grid_waves;
     int32_t lanes;
+    int32_t sweep;
 } qr_tuning;
 
 int birank_set_tuning(qr_birank h, const qr_tuning *t);

@@ -32,7 +32,8 @@ class QRError(RuntimeError):
 
 
 class qr_tuning(C.Structure):
-    _fields_ = [("block", C.c_int32), ("per_lane", C.c_int32), ("grid_waves", C.c_int32), ("lanes", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("per_lane", C.c_int32), ("grid_waves", C.c_int32), ("lanes", C.c_int32),
+                ("sweep", C.c_int32)]
 
 
 class qr_serve_stats(C.Structure):
@@ -427,8 +428,8 @@ class _Handle:
         except Exception:
             pass
 
-    def _tune(self, fn, block=0, per_lane=0, grid_waves=0, lanes=0):
-        t = qr_tuning(block, per_lane, grid_waves, lanes)
+    def _tune(self, fn, block=0, per_lane=0, grid_waves=0, lanes=0, sweep=0):
+        t = qr_tuning(block, per_lane, grid_waves, lanes, sweep)
         _check(fn(self.h, C.byref(t)), "set_tuning")
 
 

@@ -9,11 +9,13 @@ import statistics
 
 import torch
 
-# lanes per query, queries in flight per lane (pair), threads per workgroup, resident waves per CU
+# lanes per query, queries in flight per lane (pair), threads per workgroup, resident waves per CU,
+# and the tile size of the position-ordered (sweep) form
 RANK_CANDIDATES = (
     [dict(lanes=2, per_lane=p, block=b, grid_waves=0) for p in (1, 2, 4) for b in (128, 256)]
     + [dict(lanes=2, per_lane=p, block=256, grid_waves=g) for p in (2, 4, 8) for g in (8, 16, 32)]
     + [dict(lanes=1, per_lane=p, block=256, grid_waves=0) for p in (1, 2)]
+    + [dict(lanes=2, per_lane=p, block=256, grid_waves=0, sweep=t) for t in (1024, 2048, 4096) for p in (1, 2)]
 )
 FM_CANDIDATES = [dict(block=b, refill=r, waves_per_cu=w) for b in (64, 256) for r in (8, 32, 64) for w in (8, 16, 32)]
 

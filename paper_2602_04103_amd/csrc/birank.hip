@@ -24,6 +24,7 @@
 
 #include "common.hpp"
 #include "birank_dev.hpp"
+#include "sweep.hpp"
 
 using namespace qr;
 
@@ -189,6 +190,40 @@ __global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ 
 // each (measured on MI355X: far fewer address-translation misses on multi-GiB structures than one
 // lane issuing four loads).  The lane holding the half that contains q popcounts it; lane 0 adds
 // the superblock offset and delta; the two contributions are summed across the pair.
+// rank(q[u]) for one query per unroll slot u, valid in both lanes of the pair; bad[u] marks q > n.
+template <class L, int PER_PAIR>
+__device__ __forceinline__ void br_pair_compute(const uint4 *__restrict__ lines,
+                                                const typename L::Super *__restrict__ super, uint64_t n,
+                                                const uint64_t (&q)[PER_PAIR], uint32_t hf, uint64_t (&r)[PER_PAIR],
+                                                bool (&bad)[PER_PAIR]) {
+    uint64_t off[PER_PAIR];
+    uint32_t p[PER_PAIR];
+    uint32_t h[PER_PAIR][16];
+    // this lane's half line and the superblock offset
+#pragma unroll
+    for (int u = 0; u < PER_PAIR; ++u) {
+        bad[u] = q[u] > n;
+        const uint64_t qq = bad[u] ? 0 : q[u];
+        const uint64_t j = line_of<L>(qq);
+        p[u] = (uint32_t)(qq - j * L::DATA) + L::HDR;
+        const uint4 *H = lines + j * 8 + hf * 4;
+        const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
+        h[u][0] = a.x, h[u][1] = a.y, h[u][2] = a.z, h[u][3] = a.w;
+        h[u][4] = b.x, h[u][5] = b.y, h[u][6] = b.z, h[u][7] = b.w;
+        h[u][8] = c.x, h[u][9] = c.y, h[u][10] = c.z, h[u][11] = c.w;
+        h[u][12] = d.x, h[u][13] = d.y, h[u][14] = d.z, h[u][15] = d.w;
+        off[u] = L::offset(super, j);
+    }
+    // count and combine across the pair
+#pragma unroll
+    for (int u = 0; u < PER_PAIR; ++u) {
+        const bool up = p[u] >= L::MID;
+        const uint32_t cnt = half_count(h[u], up ? p[u] - L::MID : p[u], up) & (((uint32_t)up == hf) ? ~0u : 0u);
+        const uint64_t mine = hf == 0 ? off[u] + L::delta(h[u][0]) - cnt : (uint64_t)cnt;
+        r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
+    }
+}
+
 template <class L, int PER_PAIR>
 __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restrict__ lines,
                                                            const typename L::Super *__restrict__ super, uint64_t n,
@@ -197,37 +232,12 @@ __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restri
     const uint32_t hf = threadIdx.x & 1u;
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
-        uint64_t q[PER_PAIR], r[PER_PAIR], off[PER_PAIR];
-        uint32_t p[PER_PAIR];
-        uint32_t h[PER_PAIR][16];
+        uint64_t q[PER_PAIR], r[PER_PAIR];
         bool bad[PER_PAIR];
-        // 1: query positions (index clamped so every load is unconditional and in bounds)
+        // query positions (index clamped so every load is unconditional and in bounds)
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) q[u] = Q[min(i0 + u * pairs, nq - 1)];
-        // 2: this lane's half line and the superblock offset
-#pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) {
-            bad[u] = q[u] > n;
-            const uint64_t qq = bad[u] ? 0 : q[u];
-            const uint64_t j = line_of<L>(qq);
-            p[u] = (uint32_t)(qq - j * L::DATA) + L::HDR;
-            const uint4 *H = lines + j * 8 + hf * 4;
-            const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
-            h[u][0] = a.x, h[u][1] = a.y, h[u][2] = a.z, h[u][3] = a.w;
-            h[u][4] = b.x, h[u][5] = b.y, h[u][6] = b.z, h[u][7] = b.w;
-            h[u][8] = c.x, h[u][9] = c.y, h[u][10] = c.z, h[u][11] = c.w;
-            h[u][12] = d.x, h[u][13] = d.y, h[u][14] = d.z, h[u][15] = d.w;
-            off[u] = L::offset(super, j);
-        }
-        // 3: count and combine across the pair
-#pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) {
-            const bool up = p[u] >= L::MID;
-            const uint32_t cnt = half_count(h[u], up ? p[u] - L::MID : p[u], up) & (((uint32_t)up == hf) ? ~0u : 0u);
-            const uint64_t mine = hf == 0 ? off[u] + L::delta(h[u][0]) - cnt : (uint64_t)cnt;
-            r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
-        }
-        // 4: results
+        br_pair_compute<L, PER_PAIR>(lines, super, n, q, hf, r, bad);
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = i0 + u * pairs;
@@ -237,6 +247,39 @@ __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restri
             }
         }
     }
+}
+
+// Sweep form: one tile of 256*QPT queries per workgroup, answered in position order (sweep.hpp);
+// results replace the sorted positions in LDS and are written back in query order.
+template <class L, int PER_PAIR, int QPT>
+__global__ __launch_bounds__(SWEEP_BLOCK) void br_rank_sweep_kernel(const uint4 *__restrict__ lines,
+                                                                    const typename L::Super *__restrict__ super,
+                                                                    uint64_t n, const uint64_t *__restrict__ Q,
+                                                                    uint64_t nq, uint64_t *__restrict__ out,
+                                                                    uint32_t *__restrict__ err, uint32_t shift) {
+    __shared__ SweepLds<QPT, false> S;
+    constexpr uint32_t PAIRS = SWEEP_BLOCK / 2;
+    const uint64_t base = (uint64_t)blockIdx.x * (SWEEP_BLOCK * QPT);
+    const uint32_t m = (uint32_t)min<uint64_t>(SWEEP_BLOCK * QPT, nq - base);
+    sweep_sort<QPT, false>(Q, nullptr, base, m, shift, S);
+    const uint32_t hf = threadIdx.x & 1u;
+    for (uint32_t s0 = threadIdx.x >> 1; s0 < m; s0 += PAIRS * PER_PAIR) {
+        uint64_t q[PER_PAIR], r[PER_PAIR];
+        bool bad[PER_PAIR];
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) q[u] = S.q[min(s0 + u * PAIRS, m - 1)];  // past m: discarded
+        br_pair_compute<L, PER_PAIR>(lines, super, n, q, hf, r, bad);
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint32_t sl = s0 + u * PAIRS;
+            if (hf == 0 && sl < m) {
+                S.q[sl] = r[u];
+                if (bad[u]) atomicOr(err, 1u);
+            }
+        }
+    }
+    __syncthreads();
+    sweep_store<QPT, false>(out, base, m, S);
 }
 
 template <class L, int PL>
@@ -258,8 +301,26 @@ hipError_t launch_rank_t(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq,
     return hipGetLastError();
 }
 
+template <class L, int PL, int QPT>
+hipError_t launch_rank_sweep(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s) {
+    const dim3 g((uint32_t)((nq + SWEEP_BLOCK * QPT - 1) / (SWEEP_BLOCK * QPT))), b(SWEEP_BLOCK);
+    const uint4 *L4 = reinterpret_cast<const uint4 *>(h->lines);
+    const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
+    hipLaunchKernelGGL((br_rank_sweep_kernel<L, PL, QPT>), g, b, 0, s, L4, S, h->n, d_q, nq, d_out, h->err,
+                       sweep_shift(h->n));
+    return hipGetLastError();
+}
+
 template <class L>
 hipError_t launch_rank(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s) {
+    if (h->tune.sweep) {
+        const bool two = h->tune.per_lane == 2;
+        switch (h->tune.sweep / SWEEP_BLOCK) {
+            case 4: return two ? launch_rank_sweep<L, 2, 4>(h, d_q, nq, d_out, s) : launch_rank_sweep<L, 1, 4>(h, d_q, nq, d_out, s);
+            case 8: return two ? launch_rank_sweep<L, 2, 8>(h, d_q, nq, d_out, s) : launch_rank_sweep<L, 1, 8>(h, d_q, nq, d_out, s);
+            default: return two ? launch_rank_sweep<L, 2, 16>(h, d_q, nq, d_out, s) : launch_rank_sweep<L, 1, 16>(h, d_q, nq, d_out, s);
+        }
+    }
     switch (h->tune.per_lane ? h->tune.per_lane : 1) {
         case 1: return launch_rank_t<L, 1>(h, d_q, nq, d_out, s);
         case 2: return launch_rank_t<L, 2>(h, d_q, nq, d_out, s);
@@ -457,6 +518,10 @@ int birank_set_tuning(qr_birank h, const qr_tuning *t) {
     }
     if (t->lanes != 0 && t->lanes != 1 && t->lanes != 2) {
         set_error("tuning: lanes must be 1 or 2");
+        return QR_EINVAL;
+    }
+    if (!sweep_tuning_ok(t)) {
+        set_error("tuning: sweep must be 0, 1024, 2048 or 4096, with lanes 2 and per_lane 1 or 2");
         return QR_EINVAL;
     }
     h->tune = *t;

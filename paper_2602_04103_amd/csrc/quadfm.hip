@@ -868,8 +868,8 @@ uint64_t quadfm_bytes(qr_quadfm h) {
 int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t) {
     if (!h || !t) return QR_EINVAL;
     if ((t->block && (t->block < 64 || t->block > 256 || t->block % 64)) || t->per_lane < 0 || t->per_lane > 64 ||
-        t->grid_waves < 0 || t->grid_waves > 64) {
-        set_error("quadfm_set_tuning: block 64..256 step 64, refill threshold 0..64, waves per CU 0..64");
+        t->grid_waves < 0 || t->grid_waves > 64 || t->sweep != 0) {
+        set_error("quadfm_set_tuning: block 64..256 step 64, refill threshold 0..64, waves per CU 0..64, sweep 0");
         return QR_EINVAL;
     }
     h->tune = *t;

@@ -29,6 +29,7 @@
 
 #include "common.hpp"
 #include "quadrank_dev.hpp"
+#include "sweep.hpp"
 
 using namespace qr;
 
@@ -297,6 +298,35 @@ __global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__
 // Lanes 2k, 2k+1 serve one query, lane hf loading half hf of the line (64 contiguous bytes), so each
 // wave load instruction touches 32 lines.  The lane holding q's half counts; lane 0 adds offset and
 // delta; the two contributions are summed across the pair.
+// rank(q[u], c[u]) (or the count of symbols <= c[u] when PREFIX) for one query per unroll slot u,
+// valid in both lanes of the pair; bad[u] marks q > n or c > 3 (result UINT64_MAX).
+template <class L, int PER_PAIR, bool PREFIX>
+__device__ __forceinline__ void sym_pair_compute(const uint4 *__restrict__ lines,
+                                                 const typename L::Super *__restrict__ super, uint64_t n,
+                                                 const uint64_t (&q)[PER_PAIR], const uint32_t (&c)[PER_PAIR],
+                                                 uint32_t hf, uint64_t (&r)[PER_PAIR], bool (&bad)[PER_PAIR]) {
+    uint64_t off[PER_PAIR];
+    PairHalf ph[PER_PAIR];
+#pragma unroll
+    for (int u = 0; u < PER_PAIR; ++u) {
+        bad[u] = q[u] > n || c[u] > 3;
+        load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
+        off[u] = PREFIX ? offset_le<L>(super, ph[u].j, c[u] & 3u) : L::offset1(super, ph[u].j, c[u] & 3u);
+    }
+#pragma unroll
+    for (int u = 0; u < PER_PAIR; ++u) {
+        const uint32_t cc = c[u] & 3u;
+        const uint32_t cnt = PREFIX ? pair_count_le(ph[u], hf, cc) : pair_count1(ph[u], hf, cc);
+        uint64_t mine = cnt;
+        if (hf == 0) {
+            const uint64_t d = PREFIX ? delta_le<L>(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc)
+                                      : (uint64_t)L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc);
+            mine = off[u] + d - cnt;
+        }
+        r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
+    }
+}
+
 template <class L, int PER_PAIR, bool PREFIX>
 __device__ __forceinline__ void sym_pair_body(const uint4 *__restrict__ lines, const typename L::Super *__restrict__ super,
                                               uint64_t n, const uint64_t *__restrict__ Q,
@@ -305,34 +335,16 @@ __device__ __forceinline__ void sym_pair_body(const uint4 *__restrict__ lines, c
     const uint32_t hf = threadIdx.x & 1u;
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
-        uint64_t q[PER_PAIR], r[PER_PAIR], off[PER_PAIR];
+        uint64_t q[PER_PAIR], r[PER_PAIR];
         uint32_t c[PER_PAIR];
         bool bad[PER_PAIR];
-        PairHalf ph[PER_PAIR];
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = min(i0 + u * pairs, nq - 1);
             q[u] = Q[i];
             c[u] = Cs[i];
         }
-#pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) {
-            bad[u] = q[u] > n || c[u] > 3;
-            load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
-            off[u] = PREFIX ? offset_le<L>(super, ph[u].j, c[u] & 3u) : L::offset1(super, ph[u].j, c[u] & 3u);
-        }
-#pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) {
-            const uint32_t cc = c[u] & 3u;
-            const uint32_t cnt = PREFIX ? pair_count_le(ph[u], hf, cc) : pair_count1(ph[u], hf, cc);
-            uint64_t mine = cnt;
-            if (hf == 0) {
-                const uint64_t d = PREFIX ? delta_le<L>(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc)
-                                          : (uint64_t)L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc);
-                mine = off[u] + d - cnt;
-            }
-            r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
-        }
+        sym_pair_compute<L, PER_PAIR, PREFIX>(lines, super, n, q, c, hf, r, bad);
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = i0 + u * pairs;
@@ -342,6 +354,40 @@ __device__ __forceinline__ void sym_pair_body(const uint4 *__restrict__ lines, c
             }
         }
     }
+}
+
+// Sweep form: one tile of 256*QPT queries per workgroup, answered in position order (sweep.hpp);
+// results replace the sorted positions in LDS and are written back in query order.
+template <class L, int PER_PAIR, bool PREFIX, int QPT>
+__global__ __launch_bounds__(SWEEP_BLOCK) void qr_sym_sweep_kernel(QR_SYM_ARGS, uint32_t shift) {
+    __shared__ SweepLds<QPT, true> S;
+    constexpr uint32_t PAIRS = SWEEP_BLOCK / 2;
+    const uint64_t base = (uint64_t)blockIdx.x * (SWEEP_BLOCK * QPT);
+    const uint32_t m = (uint32_t)min<uint64_t>(SWEEP_BLOCK * QPT, nq - base);
+    sweep_sort<QPT, true>(Q, Cs, base, m, shift, S);
+    const uint32_t hf = threadIdx.x & 1u;
+    for (uint32_t s0 = threadIdx.x >> 1; s0 < m; s0 += PAIRS * PER_PAIR) {
+        uint64_t q[PER_PAIR], r[PER_PAIR];
+        uint32_t c[PER_PAIR];
+        bool bad[PER_PAIR];
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint32_t sl = min(s0 + u * PAIRS, m - 1);  // slots past m: discarded, any value is safe
+            q[u] = S.q[sl];
+            c[u] = S.c[sl];
+        }
+        sym_pair_compute<L, PER_PAIR, PREFIX>(lines, super, n, q, c, hf, r, bad);
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint32_t sl = s0 + u * PAIRS;
+            if (hf == 0 && sl < m) {
+                S.q[sl] = r[u];
+                if (bad[u]) atomicOr(err, 1u);
+            }
+        }
+    }
+    __syncthreads();
+    sweep_store<QPT, true>(out, base, m, S);
 }
 
 template <class L, int PER_PAIR>
@@ -354,6 +400,38 @@ __global__ __launch_bounds__(256) void qr_prefix_pair_kernel(QR_SYM_ARGS) {
     sym_pair_body<L, PER_PAIR, true>(lines, super, n, Q, Cs, nq, out, err);
 }
 
+// rank4 of one query per unroll slot u: lane 0 ends with (A, C) in (ra, rb), lane 1 with (G, T).
+template <class L, int PER_PAIR>
+__device__ __forceinline__ void rank4_pair_compute(const uint4 *__restrict__ lines,
+                                                   const typename L::Super *__restrict__ super, uint64_t n,
+                                                   const uint64_t (&q)[PER_PAIR], uint32_t hf, uint64_t (&ra)[PER_PAIR],
+                                                   uint64_t (&rb)[PER_PAIR], bool (&bad)[PER_PAIR]) {
+    uint64_t off[PER_PAIR][4];
+    PairHalf ph[PER_PAIR];
+#pragma unroll
+    for (int u = 0; u < PER_PAIR; ++u) {
+        bad[u] = q[u] > n;
+        load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
+        L::offset4(super, ph[u].j, off[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < PER_PAIR; ++u) {
+        uint32_t cnt[4];
+        pair_count4(ph[u], hf, cnt);
+        uint64_t r[4];
+#pragma unroll
+        for (uint32_t cc = 0; cc < 4; ++cc) {
+            const uint64_t mine =
+                hf == 0 ? off[u][cc] + L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc) - cnt[cc]
+                        : (uint64_t)cnt[cc];
+            r[cc] = mine + pair_swap64(mine);
+        }
+        // lane 0 writes symbols A, C and lane 1 writes G, T of the row
+        ra[u] = bad[u] ? ~0ull : (hf == 0 ? r[0] : r[2]);
+        rb[u] = bad[u] ? ~0ull : (hf == 0 ? r[1] : r[3]);
+    }
+}
+
 template <class L, int PER_PAIR>
 __global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restrict__ lines,
                                                             const typename L::Super *__restrict__ super, uint64_t n,
@@ -363,37 +441,45 @@ __global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restr
     const uint64_t pairs = ((uint64_t)gridDim.x * blockDim.x) >> 1;
     for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1; i0 < nq; i0 += pairs * PER_PAIR) {
         uint64_t q[PER_PAIR], ra[PER_PAIR], rb[PER_PAIR];
-        uint64_t off[PER_PAIR][4];
         bool bad[PER_PAIR];
-        PairHalf ph[PER_PAIR];
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) q[u] = Q[min(i0 + u * pairs, nq - 1)];
-#pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) {
-            bad[u] = q[u] > n;
-            load_pair_half<L>(lines, bad[u] ? 0 : q[u], hf, ph[u]);
-            L::offset4(super, ph[u].j, off[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) {
-            uint32_t cnt[4];
-            pair_count4(ph[u], hf, cnt);
-            uint64_t r[4];
-#pragma unroll
-            for (uint32_t cc = 0; cc < 4; ++cc) {
-                const uint64_t mine =
-                    hf == 0 ? off[u][cc] + L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc) - cnt[cc]
-                            : (uint64_t)cnt[cc];
-                r[cc] = mine + pair_swap64(mine);
-            }
-            // lane 0 writes symbols A, C and lane 1 writes G, T of the row
-            ra[u] = bad[u] ? ~0ull : (hf == 0 ? r[0] : r[2]);
-            rb[u] = bad[u] ? ~0ull : (hf == 0 ? r[1] : r[3]);
-        }
+        rank4_pair_compute<L, PER_PAIR>(lines, super, n, q, hf, ra, rb, bad);
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = i0 + u * pairs;
             if (i < nq) {
+                reinterpret_cast<ulonglong2 *>(out4 + 4 * i)[hf] = make_ulonglong2(ra[u], rb[u]);
+                if (bad[u] && hf == 0) atomicOr(err, 1u);
+            }
+        }
+    }
+}
+
+// Sweep form of rank4: each query's 32-byte row is written straight to its own slot.
+template <class L, int PER_PAIR, int QPT>
+__global__ __launch_bounds__(SWEEP_BLOCK) void qr_rank4_sweep_kernel(const uint4 *__restrict__ lines,
+                                                                     const typename L::Super *__restrict__ super,
+                                                                     uint64_t n, const uint64_t *__restrict__ Q,
+                                                                     uint64_t nq, uint64_t *__restrict__ out4,
+                                                                     uint32_t *__restrict__ err, uint32_t shift) {
+    __shared__ SweepLds<QPT, false> S;
+    constexpr uint32_t PAIRS = SWEEP_BLOCK / 2;
+    const uint64_t base = (uint64_t)blockIdx.x * (SWEEP_BLOCK * QPT);
+    const uint32_t m = (uint32_t)min<uint64_t>(SWEEP_BLOCK * QPT, nq - base);
+    sweep_sort<QPT, false>(Q, nullptr, base, m, shift, S);
+    const uint32_t hf = threadIdx.x & 1u;
+    for (uint32_t s0 = threadIdx.x >> 1; s0 < m; s0 += PAIRS * PER_PAIR) {
+        uint64_t q[PER_PAIR], ra[PER_PAIR], rb[PER_PAIR];
+        bool bad[PER_PAIR];
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) q[u] = S.q[min(s0 + u * PAIRS, m - 1)];
+        rank4_pair_compute<L, PER_PAIR>(lines, super, n, q, hf, ra, rb, bad);
+#pragma unroll
+        for (int u = 0; u < PER_PAIR; ++u) {
+            const uint32_t sl = s0 + u * PAIRS;
+            if (sl < m) {
+                const uint64_t i = base + S.tile_of[sl];
                 reinterpret_cast<ulonglong2 *>(out4 + 4 * i)[hf] = make_ulonglong2(ra[u], rb[u]);
                 if (bad[u] && hf == 0) atomicOr(err, 1u);
             }
@@ -451,8 +537,48 @@ hipError_t build_t(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, void 
     return e;
 }
 
+template <class L, bool PREFIX, int QPT>
+void launch_rank1_sweep(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
+                        hipStream_t s) {
+    const dim3 g((uint32_t)((nq + SWEEP_BLOCK * QPT - 1) / (SWEEP_BLOCK * QPT))), b(SWEEP_BLOCK);
+    const uint4 *Ln = reinterpret_cast<const uint4 *>(h->lines);
+    const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
+    const uint32_t shift = sweep_shift(h->n);
+    if (h->tune.per_lane == 2)
+        hipLaunchKernelGGL((qr_sym_sweep_kernel<L, 2, PREFIX, QPT>), g, b, 0, s, Ln, S, h->n, d_q, d_c, nq, d_out, h->err,
+                           shift);
+    else
+        hipLaunchKernelGGL((qr_sym_sweep_kernel<L, 1, PREFIX, QPT>), g, b, 0, s, Ln, S, h->n, d_q, d_c, nq, d_out, h->err,
+                           shift);
+}
+
+template <class L>
+void launch_rank4_sweep(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t s) {
+    const uint4 *Ln = reinterpret_cast<const uint4 *>(h->lines);
+    const auto *S = reinterpret_cast<const typename L::Super *>(h->super);
+    const uint32_t shift = sweep_shift(h->n);
+    const int qpt = h->tune.sweep / SWEEP_BLOCK;
+    const dim3 g((uint32_t)((nq + h->tune.sweep - 1) / h->tune.sweep)), b(SWEEP_BLOCK);
+#define QR_R4S(P, Q) hipLaunchKernelGGL((qr_rank4_sweep_kernel<L, P, Q>), g, b, 0, s, Ln, S, h->n, d_q, nq, d_out4, h->err, shift)
+    if (h->tune.per_lane == 2) {
+        if (qpt == 4) QR_R4S(2, 4); else if (qpt == 8) QR_R4S(2, 8); else QR_R4S(2, 16);
+    } else {
+        if (qpt == 4) QR_R4S(1, 4); else if (qpt == 8) QR_R4S(1, 8); else QR_R4S(1, 16);
+    }
+#undef QR_R4S
+}
+
 template <class L, bool PREFIX>
 int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out, hipStream_t s) {
+    if (h->tune.sweep) {
+        switch (h->tune.sweep / SWEEP_BLOCK) {
+            case 4: launch_rank1_sweep<L, PREFIX, 4>(h, d_q, d_c, nq, d_out, s); break;
+            case 8: launch_rank1_sweep<L, PREFIX, 8>(h, d_q, d_c, nq, d_out, s); break;
+            default: launch_rank1_sweep<L, PREFIX, 16>(h, d_q, d_c, nq, d_out, s); break;
+        }
+        QR_HIP(hipGetLastError());
+        return QR_OK;
+    }
     const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
     const int lanes = h->tune.lanes == 1 ? 1 : 2;
     const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
@@ -487,6 +613,11 @@ int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_
 
 template <class L>
 int launch_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t s) {
+    if (h->tune.sweep) {
+        launch_rank4_sweep<L>(h, d_q, nq, d_out4, s);
+        QR_HIP(hipGetLastError());
+        return QR_OK;
+    }
     const int block = h->tune.block ? h->tune.block : 256, pl = h->tune.per_lane ? h->tune.per_lane : 1;
     const int lanes = h->tune.lanes == 1 ? 1 : 2;
     const dim3 g((uint32_t)grid_for(nq, pl, block, h->tune.grid_waves, lanes)), b(block);
@@ -695,6 +826,10 @@ int quadrank_set_tuning(qr_quadrank h, const qr_tuning *t) {
         (t->per_lane && t->per_lane != 1 && t->per_lane != 2 && t->per_lane != 4 && t->per_lane != 8) ||
         t->grid_waves < 0 || t->grid_waves > 64 || (t->lanes != 0 && t->lanes != 1 && t->lanes != 2)) {
         set_error("quadrank_set_tuning: block 64..256 step 64, per_lane 1/2/4/8, grid_waves 0..64, lanes 1/2");
+        return QR_EINVAL;
+    }
+    if (!sweep_tuning_ok(t)) {
+        set_error("quadrank_set_tuning: sweep must be 0, 1024, 2048 or 4096, with lanes 2 and per_lane 1 or 2");
         return QR_EINVAL;
     }
     h->tune = *t;

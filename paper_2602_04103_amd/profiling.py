@@ -3,12 +3,12 @@
   python -m paper_2602_04103_amd.profiling stats DIR [--cmd "..."]        kernel-trace statistics table
   python -m paper_2602_04103_amd.profiling counters DIR COUNTER [...]     per-kernel mean of PMC counters
   python -m paper_2602_04103_amd.profiling traffic FETCH_DIR WRITE_DIR --row ROW --layout 16|32 \
-      --copy-bytes B --out JSON
+      --form pair|lane|sweep --copy-bytes B --out JSON
 
 `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM bytes per launch of the rank
 kernel of one benchmark row and layout (the profiled run runs only that row), scaled by what the
 same counters read for a plain device copy of known size in the same runs (the calibration
-factor).  Entries are merged into JSON under the key "ROW|L<layout>", each with a hash of the
+factor).  Entries are merged into JSON under the key "ROW|L<layout>|<form>", each with a hash of the
 kernel sources it was taken with; entries whose sources have changed since are dropped."""
 from __future__ import annotations
 
@@ -23,14 +23,40 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # the kernel sources each row's counters depend on (a record goes stale when any of them changes)
-ROW_SOURCES = {"birank": ["birank.hip", "common.hpp"], "quadrank": ["quadrank.hip", "quadrank_dev.hpp", "common.hpp"]}
+ROW_SOURCES = {"birank": ["birank.hip", "birank_dev.hpp", "sweep.hpp", "common.hpp"],
+               "quadrank": ["quadrank.hip", "quadrank_dev.hpp", "sweep.hpp", "common.hpp"]}
+# kernel of each row for each launch form: lane pairs, one lane per query, position-ordered tiles
 ROW_KERNELS = {
-    "quadrank_rank": "qr_rank1_pair_kernel",
-    "quadrank_rank4": "qr_rank4_pair_kernel",
-    "quadrank_prefix_rank": "qr_prefix_pair_kernel",
-    "birank_rank_p0.5": "br_rank_pair_kernel",
-    "birank_rank_p0.05": "br_rank_pair_kernel",
+    "quadrank_rank": {"pair": "qr_rank1_pair_kernel", "lane": "qr_rank1_kernel", "sweep": "qr_sym_sweep_kernel"},
+    "quadrank_rank4": {"pair": "qr_rank4_pair_kernel", "lane": "qr_rank4_kernel", "sweep": "qr_rank4_sweep_kernel"},
+    "quadrank_prefix_rank": {"pair": "qr_prefix_pair_kernel", "lane": "qr_prefix_kernel", "sweep": "qr_sym_sweep_kernel"},
+    "birank_rank_p0.5": {"pair": "br_rank_pair_kernel", "lane": "br_rank_kernel", "sweep": "br_rank_sweep_kernel"},
+    "birank_rank_p0.05": {"pair": "br_rank_pair_kernel", "lane": "br_rank_kernel", "sweep": "br_rank_sweep_kernel"},
 }
+
+
+def launch_form(tuning) -> str:
+    """'sweep', 'lane' or 'pair': which kernel a row's launch settings select."""
+    t = tuning if isinstance(tuning, dict) else {}
+    if t.get("sweep"):
+        return "sweep"
+    return "lane" if t.get("lanes") == 1 else "pair"
+
+
+def traffic_key(row: str, layout: int, form: str) -> str:
+    return "%s|L%d|%s" % (row, layout, form)
+
+
+def kernel_matches(name: str, row: str, form: str, layout: int) -> bool:
+    """Whether a (demangled) kernel name from a profile is the given row's kernel in that form and
+    layout.  rank and prefix_rank share the sweep kernel; its PREFIX argument tells them apart."""
+    fam = ROW_KERNELS[row][form]
+    token = ("QR" if row.startswith("quadrank") else "BR") + str(layout)
+    if fam + "<" not in name or token not in name:
+        return False
+    if fam == "qr_sym_sweep_kernel":
+        return (", true," in name) == (row == "quadrank_prefix_rank")
+    return True
 
 
 def _csvs(d: str, suffix: str):
@@ -120,13 +146,13 @@ def cmd_traffic(a):
     except (OSError, ValueError):
         pass
     srcs = ROW_SOURCES["quadrank" if a.row.startswith("quadrank") else "birank"]
-    kname = ROW_KERNELS[a.row]
     token = ("QR" if a.row.startswith("quadrank") else "BR") + str(a.layout)
-    sel = lambda d: [x for k, v in d.items() if kname in k and token in k for x in v]  # noqa: E731
+    sel = lambda d: [x for k, v in d.items() if kernel_matches(k, a.row, a.form, a.layout) for x in v]  # noqa: E731
     fv, wv = sel(fetch), sel(write)
+    kname = ROW_KERNELS[a.row][a.form]
     if not fv or not wv:
         sys.exit("no dispatches of %s for layout %s in the counter output" % (kname, a.layout))
-    out["kernels"]["%s|L%d" % (a.row, a.layout)] = {
+    out["kernels"][traffic_key(a.row, a.layout, a.form)] = {
         "kernel": "%s<%s>" % (kname, token),
         "sources": srcs,
         "source_hash": source_hash(srcs),
@@ -158,6 +184,8 @@ def main(argv=None):
     t.add_argument("write_dir")
     t.add_argument("--row", required=True, choices=sorted(ROW_KERNELS))
     t.add_argument("--layout", type=int, required=True, choices=(16, 32))
+    t.add_argument("--form", default="pair", choices=("pair", "lane", "sweep"),
+                   help="launch form the profiled run used (its tuning)")
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--copy-kernel", default="elementwise")
     t.add_argument("--out", required=True)

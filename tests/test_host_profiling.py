@@ -1,0 +1,33 @@
+"""Host logic of the profile records: which kernel a row's launch settings select, and which
+rocprofv3 kernel names belong to which row (rank and prefix_rank share one sweep kernel)."""
+from paper_2602_04103_amd import profiling as P
+
+
+def test_launch_form():
+    assert P.launch_form(None) == "pair"
+    assert P.launch_form("default") == "pair"
+    assert P.launch_form(dict(lanes=2, per_lane=1)) == "pair"
+    assert P.launch_form(dict(lanes=1, per_lane=2)) == "lane"
+    assert P.launch_form(dict(lanes=2, per_lane=2, sweep=1024)) == "sweep"
+    assert P.launch_form(dict(lanes=2, sweep=0)) == "pair"
+    assert P.traffic_key("quadrank_rank", 32, "sweep") == "quadrank_rank|L32|sweep"
+
+
+def test_kernel_matches():
+    rank_sweep = "void (anonymous namespace)::qr_sym_sweep_kernel<qr::QR32, 1, false, 4>(HIP_vector_type<unsigned int"
+    pre_sweep = "void (anonymous namespace)::qr_sym_sweep_kernel<qr::QR32, 2, true, 8>(HIP_vector_type<unsigned int"
+    pair = "void (anonymous namespace)::qr_rank1_pair_kernel<qr::QR16, 1>(HIP_vector_type<unsigned int, 4u>"
+    lane = "void (anonymous namespace)::qr_rank1_kernel<qr::QR16, 1>(HIP_vector_type<unsigned int, 4u>"
+    br = "void (anonymous namespace)::br_rank_sweep_kernel<qr::BR32, 2, 4>(HIP_vector_type<unsigned int"
+    assert P.kernel_matches(rank_sweep, "quadrank_rank", "sweep", 32)
+    assert not P.kernel_matches(rank_sweep, "quadrank_prefix_rank", "sweep", 32)
+    assert P.kernel_matches(pre_sweep, "quadrank_prefix_rank", "sweep", 32)
+    assert not P.kernel_matches(pre_sweep, "quadrank_rank", "sweep", 32)
+    assert not P.kernel_matches(rank_sweep, "quadrank_rank", "sweep", 16)
+    assert P.kernel_matches(pair, "quadrank_rank", "pair", 16)
+    assert not P.kernel_matches(pair, "quadrank_rank", "lane", 16)  # qr_rank1_kernel is not a prefix of it
+    assert P.kernel_matches(lane, "quadrank_rank", "lane", 16)
+    assert not P.kernel_matches(lane, "quadrank_rank", "pair", 16)
+    assert P.kernel_matches(br, "birank_rank_p0.5", "sweep", 32)
+    assert not P.kernel_matches(br, "birank_rank_p0.5", "pair", 32)
+    assert not P.kernel_matches(br, "quadrank_rank4", "sweep", 32)
