@@ -266,6 +266,8 @@ def main():
         row_res[row] = {
             "queries_per_s": qps,
             "avg_launch_ms": per_launch * 1e3,
+            "launch_ms_min_p50_max": [round(min(secs) * 1e3, 4), round(statistics.median(secs) * 1e3, 4),
+                                      round(max(secs) * 1e3, 4)],
             "lines_per_query": 1,
             "roofline_frac_hbm": achieved / HBM_PEAK_GBS,
             "algorithmic_GBps": achieved,

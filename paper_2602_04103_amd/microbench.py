@@ -6,6 +6,8 @@
                                                      (several 16-byte loads per lane) vs lane pairs
   python -m paper_2602_04103_amd.microbench glanes   whole-line random gathers read by 1/2/4/8 lanes
                                                      per line, against working set
+  python -m paper_2602_04103_amd.microbench order    rank time against the order of a batch's queries
+                                                     (and the sweep form)
 """
 from __future__ import annotations
 
@@ -128,6 +130,83 @@ def rankws(args):
         torch.cuda.empty_cache()
 
 
+def order(args):
+    """Rank time against the order of a batch's queries (2^24 uniform queries, 32-bit layouts):
+    uniform; reordered with torch.sort so that the plain kernel sees (a) chunks sorted in place,
+    (b) every tile's sorted queries interleaved, as if all workgroups swept their tiles in step,
+    (c) the whole batch bucketed by position; the sweep form on the original order; and the cost of
+    a random 8-byte scatter of 2^24 results back to query order."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    nq = 1 << 24
+    ar = torch.arange(nq, device="cuda", dtype=torch.int64)
+
+    def run(name, h, nbits, q, c, rank4):
+        out = torch.empty(nq * (4 if rank4 else 1), dtype=torch.int64, device="cuda")
+
+        def go(qq, cc):
+            if rank4:
+                h.rank4(qq, out)
+            elif c is not None:
+                h.rank(qq, cc, out)
+            else:
+                h.rank(qq, out)
+
+        def timed(label, order):
+            qq = q[order].contiguous()
+            cc = c[order].contiguous() if c is not None else None
+            t = _time(lambda: go(qq, cc), 7)
+            print("%s %s: %.3f ms, %.2f G q/s" % (name, label, t * 1e3, nq / t / 1e9), flush=True)
+
+        h.set_tuning(lanes=2, per_lane=1, block=256, grid_waves=0)
+        t = _time(lambda: go(q, c), 7)
+        print("%s uniform order: %.3f ms, %.2f G q/s" % (name, t * 1e3, nq / t / 1e9), flush=True)
+        for lc in (10, 13, 16):
+            _, perm = torch.sort(((ar >> lc) << 40) | q)
+            timed("chunks of 2^%d sorted in place" % lc, perm)
+        for lc in (10, 12, 13):
+            _, perm = torch.sort(((ar >> lc) << 40) | q)
+            _, inter = torch.sort(((ar & ((1 << lc) - 1)) << 20) | (ar >> lc))
+            timed("tiles of 2^%d swept in step" % lc, perm[inter])
+        for bits in (6, 8, 12):
+            _, perm = torch.sort(q >> (nbits - bits), stable=True)
+            timed("batch bucketed by the top %d bits" % bits, perm)
+        for tile in (1024, 2048, 4096):
+            for pl in (1, 2):
+                h.set_tuning(lanes=2, per_lane=pl, sweep=tile)
+                t = _time(lambda: go(q, c), 7)
+                print("%s sweep form, tile %d, %d per pair: %.3f ms, %.2f G q/s"
+                      % (name, tile, pl, t * 1e3, nq / t / 1e9), flush=True)
+        h.set_tuning(lanes=2, per_lane=1, block=256, grid_waves=0)
+        w = 4 if rank4 else 1
+        src = out.view(nq, w)
+        dst = torch.empty_like(src)
+        _, perm = torch.sort(q)
+        t = _time(lambda: dst.index_copy_(0, perm, src), 7)
+        print("%s scatter of %d-byte results to query order: %.3f ms" % (name, 8 * w, t * 1e3), flush=True)
+
+    n = 1 << 32
+    d = torch.from_numpy(datagen.pack2(datagen.dna_codes(3202, n)).view(np.int64)).cuda()
+    h = qr.QuadRank(d, n, layout=qr.QR_LAYOUT_32)
+    del d
+    q = torch.from_numpy(datagen.queries(11, n, nq).view(np.int64)).cuda()
+    c = torch.from_numpy(datagen.symbols(12, nq)).cuda()
+    run("quadrank rank 2^32", h, 32, q, c, False)
+    run("quadrank rank4 2^32", h, 32, q, None, True)
+    h.free()
+    torch.cuda.empty_cache()
+    nb = 1 << 36
+    d = torch.from_numpy(datagen.bits(3636, nb, 0.5).view(np.int64)).cuda()
+    hb = qr.BiRank(d, nb, layout=qr.QR_LAYOUT_32)
+    del d
+    torch.cuda.empty_cache()
+    qb = torch.from_numpy(datagen.queries(13, nb, nq).view(np.int64)).cuda()
+    run("birank 2^36", hb, 36, qb, None, False)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -141,8 +220,9 @@ def main(argv=None):
     r.add_argument("--qr-log-n", type=int, nargs="+", default=[24, 26, 28, 30, 31, 32, 33])
     r.add_argument("--br-log-n", type=int, nargs="+", default=[24, 28, 31, 33, 34, 35, 36])
     r.add_argument("--layouts", type=int, nargs="+", default=[16, 32], choices=[16, 32])
+    sub.add_parser("order")
     a = ap.parse_args(argv)
-    {"gather": gather, "glanes": glanes, "lanes": lanes, "rankws": rankws}[a.what](a)
+    {"gather": gather, "glanes": glanes, "lanes": lanes, "rankws": rankws, "order": order}[a.what](a)
 
 
 if __name__ == "__main__":
