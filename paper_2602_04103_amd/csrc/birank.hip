@@ -398,7 +398,7 @@ int birank_build_ex(const uint64_t *d_bits, uint64_t n, int layout, hipStream_t 
     h->n = n;
     h->n_lines = n / data + 1;
     h->n_sb = (h->n_lines - 1) / sb_lines + 1;
-    h->tune = qr_tuning{256, 1, 0, 2};
+    h->tune = qr_tuning{256, 1, 0, 2, 0};
     const uint64_t n_groups = (h->n_lines - 1) / GROUP_LINES + 1;
     uint32_t *cnt = nullptr;
     uint64_t *base = nullptr;

@@ -559,7 +559,7 @@ int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t d
     const uint64_t entries = 1ull << (2 * kmer);
     h->n_lines = n_plus_1 / QR_DATA_BASES + 1;
     h->n_sb = n_plus_1 / QR_SB_BASES + 1;
-    h->tune = qr_tuning{256, 16, 16, 0};
+    h->tune = qr_tuning{256, 16, 16, 0, 0};
     unsigned long long *tot = nullptr;
     if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 16) != hipSuccess ||
         hipMalloc(&h->table, entries * sizeof(uint2)) != hipSuccess || hipMalloc(&h->head, 8) != hipSuccess ||

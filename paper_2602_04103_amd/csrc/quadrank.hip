@@ -697,7 +697,7 @@ int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStre
     h->n = n;
     h->n_lines = n / (l32 ? QR32::DATA : QR16::DATA) + 1;
     h->n_sb = (h->n_lines - 1) / (l32 ? QR32::SB_LINES : QR16::SB_LINES) + 1;
-    h->tune = qr_tuning{256, 1, 0, 2};
+    h->tune = qr_tuning{256, 1, 0, 2, 0};
     const size_t super_bytes = h->n_sb * 4 * (l32 ? 8 : 4);
     if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, super_bytes) != hipSuccess ||
         hipMalloc(&h->err, 4) != hipSuccess) {
