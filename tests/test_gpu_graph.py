@@ -107,3 +107,39 @@ def test_graph_replays_prefix_rank_intervals_and_locate():
         assert torch.equal(ost, est) and torch.equal(opos, epos)
     fm.check()
     g.free()
+
+
+def test_graph_replays_sweep_form():
+    """The position-ordered (sweep) launches of rank, prefix_rank, rank4 and BiRank rank, captured
+    with the tile sizes the tuner offers, replayed three times."""
+    qr = require_gpu()
+    n = 3 * 57344 + 5
+    codes = datagen.dna_codes(81, n)
+    h = qr.QuadRank(to_dev(datagen.pack2(codes)), n, layout=qr.QR_LAYOUT_32)
+    q = to_dev(datagen.queries(82, n, 250_001))
+    c = to_dev(datagen.symbols(83, 250_001))
+    br = qr.BiRank(to_dev(datagen.bits(84, 500_000)), 500_000, layout=qr.QR_LAYOUT_32)
+    qb = to_dev(datagen.queries(85, 500_000, 120_007))
+    h.set_tuning(lanes=2, per_lane=1, sweep=1024)
+    br.set_tuning(lanes=2, per_lane=2, sweep=4096)
+    e1, ep, e4, eb = h.rank(q, c).clone(), h.prefix_rank(q, c).clone(), h.rank4(q).clone(), br.rank(qb).clone()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    o1, op, o4, ob = (torch.empty_like(t) for t in (e1, ep, e4, eb))
+    announce("graph capture sweep")
+    with torch.cuda.stream(s):
+        g = qr.Graph(s)
+        with g:
+            h.rank(q, c, o1, stream=s)
+            h.prefix_rank(q, c, op, stream=s)
+            h.rank4(q, o4, stream=s)
+            br.rank(qb, ob, stream=s)
+    for rep in range(3):
+        for t in (o1, op, o4, ob):
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        announce("graph replay sweep", rep)
+        g.launch(s)
+        s.synchronize()
+        assert torch.equal(o1, e1) and torch.equal(op, ep) and torch.equal(o4, e4) and torch.equal(ob, eb)
+    g.free()
