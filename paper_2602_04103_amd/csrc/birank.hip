@@ -55,19 +55,35 @@ __device__ __forceinline__ uint64_t masked_word(const uint64_t *__restrict__ bit
     return x;
 }
 
-// Pass 1: number of 1 bits in each group of 64 lines (GROUP_LINES * DATA / 64 input words).
+// Pass 1: number of 1 bits in each group of 64 lines (GROUP_LINES * DATA / 64 input words), one
+// wavefront per group and COUNT_GROUPS groups per workgroup.  Groups made only of whole words below
+// n are read with 16-byte loads when the input is 16-byte aligned (a group is an even number of
+// words); the last group, or an input aligned to 8 bytes only, takes the masked word path.
+constexpr uint32_t COUNT_GROUPS = 4;
+
 template <class L>
-__global__ __launch_bounds__(256) void br_count_kernel(const uint64_t *__restrict__ bits, uint64_t n,
-                                                       uint64_t n_words, uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(64 * COUNT_GROUPS) void br_count_kernel(const uint64_t *__restrict__ bits, uint64_t n,
+                                                                     uint64_t n_words, uint64_t n_groups,
+                                                                     uint32_t *__restrict__ cnt) {
     constexpr uint32_t W = GROUP_LINES * L::DATA / 64;
-    const uint64_t g = blockIdx.x;
+    static_assert(W % 2 == 0, "a group must be a whole number of 16-byte chunks");
+    const uint64_t g = (uint64_t)blockIdx.x * COUNT_GROUPS + threadIdx.x / 64;
+    if (g >= n_groups) return;
+    const uint32_t lane = __lane_id();
+    const uint64_t w0 = g * W;
     uint32_t c = 0;
-    for (uint32_t k = threadIdx.x; k < W; k += 256) c += __popcll(masked_word(bits, g * W + k, n, n_words));
+    if (((uintptr_t)bits & 15) == 0 && w0 + W <= n / 64) {
+        const uint4 *v = reinterpret_cast<const uint4 *>(bits + w0);
+#pragma unroll 4
+        for (uint32_t k = lane; k < W / 2; k += 64) {
+            const uint4 x = v[k];
+            c += __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+        }
+    } else {
+        for (uint32_t k = lane; k < W; k += 64) c += __popcll(masked_word(bits, w0 + k, n, n_words));
+    }
     c = wave_sum(c);
-    __shared__ uint32_t part[4];
-    if (__lane_id() == 0) part[threadIdx.x / 64] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) cnt[g] = part[0] + part[1] + part[2] + part[3];
+    if (lane == 0) cnt[g] = c;
 }
 
 // Offsets of the 32-bit layout: s_i = exact rank at the first line of superblock i.
@@ -333,7 +349,8 @@ template <class L>
 hipError_t build_t(qr_birank_s *h, const uint64_t *d_bits, uint32_t *cnt, uint64_t *base, uint64_t n_groups,
                    hipStream_t stream) {
     const uint64_t n_words = (h->n + 63) / 64;
-    hipLaunchKernelGGL(br_count_kernel<L>, dim3((uint32_t)n_groups), dim3(256), 0, stream, d_bits, h->n, n_words, cnt);
+    hipLaunchKernelGGL(br_count_kernel<L>, dim3((uint32_t)((n_groups + COUNT_GROUPS - 1) / COUNT_GROUPS)),
+                       dim3(64 * COUNT_GROUPS), 0, stream, d_bits, h->n, n_words, n_groups, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (L::SHIFT) {  // 16-bit layout: a group is a superblock, the scan writes the shifted offsets

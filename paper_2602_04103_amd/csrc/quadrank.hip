@@ -65,25 +65,40 @@ __device__ __forceinline__ void word_counts(uint64_t x, uint32_t &cC, uint32_t &
     cG += __popcll(hi) - t;
 }
 
-// Pass 1: symbol counts of each group of 128 lines (padded with A).
+// Pass 1: symbol counts of each group of 128 lines (padded with A), one wavefront per group and
+// COUNT_GROUPS groups per workgroup.  Groups made only of whole packed words below n are read with
+// 16-byte loads when the input is 16-byte aligned; the last group, or an input aligned to 8 bytes
+// only, takes the masked word path.
+constexpr uint32_t COUNT_GROUPS = 4;
+
 template <class L>
-__global__ __launch_bounds__(256) void qr_count_kernel(const uint64_t *__restrict__ packed, uint64_t n,
-                                                       uint64_t n_words, uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(64 * COUNT_GROUPS) void qr_count_kernel(const uint64_t *__restrict__ packed, uint64_t n,
+                                                                     uint64_t n_words, uint64_t n_groups,
+                                                                     uint32_t *__restrict__ cnt) {
     constexpr uint32_t W = GROUP_LINES * L::WORDS;
-    const uint64_t g = blockIdx.x;
+    static_assert(W % 2 == 0, "a group must be a whole number of 16-byte chunks");
+    const uint64_t g = (uint64_t)blockIdx.x * COUNT_GROUPS + threadIdx.x / 64;
+    if (g >= n_groups) return;
+    const uint32_t lane = __lane_id();
+    const uint64_t w0 = g * W;
     uint32_t cC = 0, cG = 0, cT = 0;
-    for (uint32_t k = threadIdx.x; k < W; k += 256) word_counts(masked_packed(packed, g * W + k, n, n_words), cC, cG, cT);
+    if (((uintptr_t)packed & 15) == 0 && w0 + W <= n / 32) {
+        const uint4 *v = reinterpret_cast<const uint4 *>(packed + w0);
+#pragma unroll 4
+        for (uint32_t k = lane; k < W / 2; k += 64) {
+            const uint4 x = v[k];
+            word_counts((uint64_t)x.x | ((uint64_t)x.y << 32), cC, cG, cT);
+            word_counts((uint64_t)x.z | ((uint64_t)x.w << 32), cC, cG, cT);
+        }
+    } else {
+        for (uint32_t k = lane; k < W; k += 64) word_counts(masked_packed(packed, w0 + k, n, n_words), cC, cG, cT);
+    }
     cC = wave_sum(cC), cG = wave_sum(cG), cT = wave_sum(cT);
-    __shared__ uint32_t part[4][3];
-    if (__lane_id() == 0) part[threadIdx.x / 64][0] = cC, part[threadIdx.x / 64][1] = cG, part[threadIdx.x / 64][2] = cT;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t C = 0, G = 0, T = 0;
-        for (int w = 0; w < 4; ++w) C += part[w][0], G += part[w][1], T += part[w][2];
-        cnt[4 * g + 0] = GROUP_LINES * L::DATA - C - G - T;
-        cnt[4 * g + 1] = C;
-        cnt[4 * g + 2] = G;
-        cnt[4 * g + 3] = T;
+    if (lane == 0) {
+        cnt[4 * g + 0] = GROUP_LINES * L::DATA - cC - cG - cT;
+        cnt[4 * g + 1] = cC;
+        cnt[4 * g + 2] = cG;
+        cnt[4 * g + 3] = cT;
     }
 }
 
@@ -512,7 +527,8 @@ hipError_t build_t(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, void 
         if (cnt) (void)hipFree(cnt);
         return hipErrorOutOfMemory;
     }
-    hipLaunchKernelGGL(qr_count_kernel<L>, dim3((uint32_t)n_groups), dim3(256), 0, stream, d_packed2, n, n_words, cnt);
+    hipLaunchKernelGGL(qr_count_kernel<L>, dim3((uint32_t)((n_groups + COUNT_GROUPS - 1) / COUNT_GROUPS)),
+                       dim3(64 * COUNT_GROUPS), 0, stream, d_packed2, n, n_words, n_groups, cnt);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         if (L::SHIFT) {

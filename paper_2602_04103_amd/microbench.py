@@ -8,12 +8,14 @@
                                                      per line, against working set
   python -m paper_2602_04103_amd.microbench order    rank time against the order of a batch's queries
                                                      (and the sweep form)
+  python -m paper_2602_04103_amd.microbench stream   streaming-bandwidth references and the builds
 """
 from __future__ import annotations
 
 import argparse
 import os
 import sys
+import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
@@ -207,6 +209,55 @@ def order(args):
     run("birank 2^36", hb, 36, qb, None, False)
 
 
+def stream(args):
+    """Streaming bandwidth references for the build kernels: a device copy, a read-only reduction
+    and a write-only fill of 4 GiB (HIP events, median of 5), then the BiRank (2^36 bits) and
+    QuadRank (2^32 bases) builds; run under rocprofv3 --kernel-trace for the build kernels' times."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2602_04103_amd as qr
+    nb = 4 << 30
+    src = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    t = _time(lambda: dst.copy_(src))
+    print("copy 4 GiB: %.3f ms, %.0f GB/s (read + write)" % (t * 1e3, 2 * nb / t / 1e9), flush=True)
+    t = _time(lambda: torch.bitwise_not(src, out=dst))
+    print("bitwise_not 4 GiB: %.3f ms, %.0f GB/s (read + write)" % (t * 1e3, 2 * nb / t / 1e9), flush=True)
+    acc = torch.empty(1, dtype=torch.int64, device="cuda")
+    t = _time(lambda: torch.sum(src, dim=0, out=acc))
+    print("sum 4 GiB: %.3f ms, %.0f GB/s (read)" % (t * 1e3, nb / t / 1e9), flush=True)
+    t = _time(lambda: dst.fill_(7))
+    print("fill 4 GiB: %.3f ms, %.0f GB/s (write)" % (t * 1e3, nb / t / 1e9), flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+    n = 1 << 36
+    d = torch.from_numpy(datagen.bits(3636, n, 0.5).view(np.int64)).cuda()
+    for L in (qr.QR_LAYOUT_32, qr.QR_LAYOUT_16):
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = qr.BiRank(d, n, layout=L)
+            t1 = time.perf_counter()
+            print("birank build 2^36 layout %d: %.2f ms wall" % (16 if L == qr.QR_LAYOUT_16 else 32, (t1 - t0) * 1e3),
+                  flush=True)
+            h.free()
+    del d
+    torch.cuda.empty_cache()
+    n = 1 << 32
+    d = torch.from_numpy(datagen.pack2(datagen.dna_codes(3202, n)).view(np.int64)).cuda()
+    for L in (qr.QR_LAYOUT_32, qr.QR_LAYOUT_16):
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = qr.QuadRank(d, n, layout=L)
+            t1 = time.perf_counter()
+            print("quadrank build 2^32 layout %d: %.2f ms wall" % (16 if L == qr.QR_LAYOUT_16 else 32, (t1 - t0) * 1e3),
+                  flush=True)
+            h.free()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -221,8 +272,9 @@ def main(argv=None):
     r.add_argument("--br-log-n", type=int, nargs="+", default=[24, 28, 31, 33, 34, 35, 36])
     r.add_argument("--layouts", type=int, nargs="+", default=[16, 32], choices=[16, 32])
     sub.add_parser("order")
+    sub.add_parser("stream")
     a = ap.parse_args(argv)
-    {"gather": gather, "glanes": glanes, "lanes": lanes, "rankws": rankws, "order": order}[a.what](a)
+    {"gather": gather, "glanes": glanes, "lanes": lanes, "rankws": rankws, "order": order, "stream": stream}[a.what](a)
 
 
 if __name__ == "__main__":
