@@ -105,11 +105,19 @@ __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict
     constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
     // one LDS buffer holds the group's input words, then (after a barrier) the staged output lines
     constexpr uint32_t BUF = (W + 2 > 64 * OUT_STRIDE) ? W + 2 : 64 * OUT_STRIDE;
-    __shared__ uint64_t buf[BUF];
+    __shared__ __align__(16) uint64_t buf[BUF];
     uint64_t *in = buf, *stage = buf;
     const uint64_t g = blockIdx.x;
     const int t = threadIdx.x;
-    for (int k = t; k < (int)W + 2; k += 64) in[k] = k < (int)W ? masked_word(bits, g * W + k, n, n_words) : 0ull;
+    if (((uintptr_t)bits & 15) == 0 && g * W + W <= n / 64) {  // whole words only: 16-byte loads
+        const uint4 *v = reinterpret_cast<const uint4 *>(bits + g * W);
+        uint4 *d = reinterpret_cast<uint4 *>(in);
+#pragma unroll 4
+        for (uint32_t k = t; k < W / 2; k += 64) d[k] = v[k];
+        if (t < 2) in[W + t] = 0ull;
+    } else {
+        for (int k = t; k < (int)W + 2; k += 64) in[k] = k < (int)W ? masked_word(bits, g * W + k, n, n_words) : 0ull;
+    }
     __syncthreads();
 
     auto get64 = [&](uint32_t b) -> uint64_t {  // input bits [b, b+64) of this group

@@ -123,12 +123,19 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
     constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
     // one LDS buffer holds the group's input words, then (after a barrier) the staged output lines
     constexpr uint32_t BUF = (W > 128 * OUT_STRIDE) ? W : 128 * OUT_STRIDE;
-    __shared__ uint64_t buf[BUF];
+    __shared__ __align__(16) uint64_t buf[BUF];
     __shared__ uint64_t wave_tot[2];
     uint64_t *in = buf, *stage = buf;
     const uint64_t g = blockIdx.x;
     const int t = threadIdx.x;
-    for (uint32_t k = t; k < W; k += 128) in[k] = masked_packed(packed, g * W + k, n, n_words);
+    if (((uintptr_t)packed & 15) == 0 && g * W + W <= n / 32) {  // whole words only: 16-byte loads
+        const uint4 *v = reinterpret_cast<const uint4 *>(packed + g * W);
+        uint4 *d = reinterpret_cast<uint4 *>(in);
+#pragma unroll 4
+        for (uint32_t k = t; k < W / 2; k += 128) d[k] = v[k];
+    } else {
+        for (uint32_t k = t; k < W; k += 128) in[k] = masked_packed(packed, g * W + k, n, n_words);
+    }
     __syncthreads();
 
     uint32_t lo[L::WORDS], hi[L::WORDS];
