@@ -254,7 +254,8 @@ int quadfm_c_array(qr_quadfm h, uint64_t *h_C4);
  *              in LDS and answers them in that order, so that the workgroups running together
  *              load from a narrow band of the structure; results still go to the queries' own
  *              slots.  Needs lanes = 2 and per_lane 1 or 2; block and grid_waves are ignored.
- *              Outputs are identical to the other forms.
+ *              Outputs are identical to the other forms (a call with more than 2^31 - 1 tiles
+ *              runs the plain form).
  * ---------------------------------------------------------------------------------------------- */
 typedef struct {
     int32_t block;

@@ -337,7 +337,7 @@ hipError_t launch_rank_sweep(const qr_birank_s *h, const uint64_t *d_q, uint64_t
 
 template <class L>
 hipError_t launch_rank(const qr_birank_s *h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t s) {
-    if (h->tune.sweep) {
+    if (sweep_fits(h->tune.sweep, nq)) {
         const bool two = h->tune.per_lane == 2;
         switch (h->tune.sweep / SWEEP_BLOCK) {
             case 4: return two ? launch_rank_sweep<L, 2, 4>(h, d_q, nq, d_out, s) : launch_rank_sweep<L, 1, 4>(h, d_q, nq, d_out, s);

@@ -593,7 +593,7 @@ void launch_rank4_sweep(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_
 
 template <class L, bool PREFIX>
 int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out, hipStream_t s) {
-    if (h->tune.sweep) {
+    if (sweep_fits(h->tune.sweep, nq)) {
         switch (h->tune.sweep / SWEEP_BLOCK) {
             case 4: launch_rank1_sweep<L, PREFIX, 4>(h, d_q, d_c, nq, d_out, s); break;
             case 8: launch_rank1_sweep<L, PREFIX, 8>(h, d_q, d_c, nq, d_out, s); break;
@@ -636,7 +636,7 @@ int launch_rank1(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_
 
 template <class L>
 int launch_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t s) {
-    if (h->tune.sweep) {
+    if (sweep_fits(h->tune.sweep, nq)) {
         launch_rank4_sweep<L>(h, d_q, nq, d_out4, s);
         QR_HIP(hipGetLastError());
         return QR_OK;

@@ -23,6 +23,12 @@ __host__ __forceinline__ bool sweep_tuning_ok(const qr_tuning *t) {
     return (t->lanes == 0 || t->lanes == 2) && (t->per_lane == 0 || t->per_lane == 1 || t->per_lane == 2);
 }
 
+// Whether a launch takes the sweep form: it is selected and its one-tile-per-workgroup grid fits
+// the grid limit (otherwise the plain grid-stride form answers, with the same results).
+__host__ __forceinline__ bool sweep_fits(int32_t sweep, uint64_t nq) {
+    return sweep > 0 && (nq + (uint64_t)sweep - 1) / (uint64_t)sweep <= 0x7fffffffull;
+}
+
 // Right shift that maps every valid position q <= n to a bucket below 256.
 __host__ __forceinline__ uint32_t sweep_shift(uint64_t n) {
     uint32_t bits = 0;
