@@ -58,6 +58,13 @@ __host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
 }
 __host__ __device__ __forceinline__ uint64_t qr_line_of(uint64_t q) { return mulhi64(q, QR_MAGIC) >> QR_MAGIC_T; }
 
+// floor(q / 480) for every 32-bit q, with one 32-bit multiply-high: q / 480 = (q >> 5) / 15, and
+// m = ceil(2^32 / 15) = 0x11111112 has e = 14, so floor(y * m / 2^32) = floor(y / 15) for
+// y < 2^32 / 14, which covers y = q >> 5 < 2^27.  (Checked against division for all 2^32 values.)
+__host__ __device__ __forceinline__ uint32_t qr_line_of32(uint32_t q) {
+    return (uint32_t)(((uint64_t)(q >> 5) * 0x11111112ull) >> 32);
+}
+
 // Mask selecting bit positions [0, t) of the 32-bit word that covers positions [32k, 32k+32).
 __device__ __forceinline__ uint32_t prefix_mask32(uint32_t t, uint32_t k) {
     int32_t r = (int32_t)t - (int32_t)(32u * k);

@@ -89,26 +89,33 @@ __device__ __forceinline__ uint64_t rank_bwt(const FmDev &f, const HalfLine &h, 
     return r;
 }
 
+// The search works in 32-bit positions and ranks: the build admits at most 2^32 - 1 BWT rows.
+__device__ __forceinline__ uint32_t rank_bwt32(const FmDev &f, const HalfLine &h, uint32_t q, uint32_t c) {
+    uint32_t r = rank1_from_half32(h, c);
+    if (c == 0) r -= q > f.dollar;
+    return r;
+}
+
 // One backward step of the interval [sp, ep) with symbol c.  When sp and ep lie in the same half
 // line (most steps once the interval is small) both ranks come from one load: the second load is
 // issued only by the lanes whose ep lies elsewhere.
-__device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint64_t &sp, uint64_t &ep) {
+__device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint32_t &sp, uint32_t &ep) {
     HalfLine a;
-    load_half(f.lines, f.super, sp, a);
-    const uint64_t js = qr_line_of(sp), je = qr_line_of(ep);
-    const bool ups = (uint32_t)(sp - js * QR_DATA_BASES) + QR_HDR >= QR_MID;
-    const bool upe = (uint32_t)(ep - je * QR_DATA_BASES) + QR_HDR >= QR_MID;
-    const uint64_t base = fm_C(f, c);
-    const uint64_t rs = rank_bwt(f, a, sp, c);
-    uint64_t re;
+    load_half32(f.lines, f.super, sp, a);
+    const uint32_t js = qr_line_of32(sp), je = qr_line_of32(ep);
+    const uint32_t ps = sp - js * (uint32_t)QR_DATA_BASES + QR_HDR, pe = ep - je * (uint32_t)QR_DATA_BASES + QR_HDR;
+    const bool ups = ps >= QR_MID, upe = pe >= QR_MID;
+    const uint32_t base = (uint32_t)fm_C(f, c);
+    const uint32_t rs = rank_bwt32(f, a, sp, c);
+    uint32_t re;
     if (js == je && ups == upe) {
         HalfLine b = a;
-        b.t = upe ? (uint32_t)(ep - je * QR_DATA_BASES) + QR_HDR - QR_MID : (uint32_t)(ep - je * QR_DATA_BASES) + QR_HDR;
-        re = rank_bwt(f, b, ep, c);
+        b.t = upe ? pe - QR_MID : pe;
+        re = rank_bwt32(f, b, ep, c);
     } else {
         HalfLine b;
-        load_half(f.lines, f.super, ep, b);
-        re = rank_bwt(f, b, ep, c);
+        load_half32(f.lines, f.super, ep, b);
+        re = rank_bwt32(f, b, ep, c);
     }
     sp = base + rs;
     ep = base + re;
@@ -117,7 +124,7 @@ __device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint64_t &sp
 __global__ __launch_bounds__(256) void fm_table_kernel(FmDev f, uint2 *__restrict__ table) {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= (1u << (2 * f.kmer))) return;
-    uint64_t sp = 0, ep = f.n1;
+    uint32_t sp = 0, ep = (uint32_t)f.n1;
     for (uint32_t k = 0; k < f.kmer && sp < ep; ++k) fm_step(f, (w >> (2 * k)) & 3u, sp, ep);
     if (sp >= ep) sp = ep = 0;
     table[w] = make_uint2((uint32_t)sp, (uint32_t)ep);
@@ -143,16 +150,16 @@ __global__ void fm_totals_kernel(FmDev f, unsigned long long *__restrict__ out4)
 // Per-lane search state.  The backward search over a pattern P reads P from its end; over the
 // reverse complement of P it reads P from its start and complements every code (c -> 3 - c).
 struct Search {
-    uint64_t sp, ep;
+    uint32_t sp, ep;   // the current BWT interval (every row index is below 2^32)
     const uint8_t *P;  // pattern start
     uint32_t m;        // pattern length
     uint32_t left;     // characters still to process
     uint32_t pos;      // index in P of the next character to read
     uint32_t rc;       // 0: P itself, 1: its reverse complement
     uint32_t acc;      // count of the first strand, when counting both
-    uint64_t buf;      // bytes [buf_at, buf_end) of the pattern (8 of them, or 1 near the pattern ends)
-    uintptr_t buf_at, buf_end;
-    uintptr_t lo, hi;  // the pattern's byte range [lo, hi): no read leaves it
+    uint64_t buf;      // pattern bytes [win, win + wlen) (8 of them, or 1 near the pattern ends)
+    uint32_t win;      // index in P of buf's first byte; ~0u before the first fetch
+    uint32_t wlen;     // 8 or 1
 };
 
 __device__ __forceinline__ uint32_t strand_code(uint32_t c, uint32_t rc) { return (rc && c <= 3u) ? 3u - c : c; }
@@ -166,7 +173,7 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
 // Start the search of one strand; returns true if its count is already known (written to cnt).
 __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc, uint32_t &cnt) {
     s.rc = rc;
-    s.buf_at = ~(uintptr_t)0;
+    s.win = ~0u;
     const uint32_t m = s.m;
     const uint32_t K = f.kmer;
     if (m >= K) {
@@ -189,7 +196,7 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
         s.pos = rc ? K : m - K - 1;
     } else {
         s.sp = 0;
-        s.ep = f.n1;
+        s.ep = (uint32_t)f.n1;
         s.left = m;
         s.pos = rc ? 0 : m - 1;
     }
@@ -214,8 +221,6 @@ __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restric
     const uint64_t m = e - o;
     s.P = pat + o;
     s.m = (uint32_t)m;
-    s.lo = (uintptr_t)s.P;
-    s.hi = s.lo + m;
     s.acc = 0;
     if (m == 0) {  // the empty pattern matches at every position 0..n (counted once)
         cnt = (uint32_t)f.n1;
@@ -230,23 +235,24 @@ __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restric
 }
 
 // Next character of the current strand.  Characters are fetched 8 at a time with one aligned load
-// when the whole aligned 8-byte window lies inside the pattern, else one byte at a time.
+// when the whole aligned 8-byte window lies inside the pattern [P, P + m), else one byte at a time.
 __device__ __forceinline__ uint32_t next_char(Search &s) {
-    const uintptr_t a = (uintptr_t)(s.P + s.pos);
-    if (s.buf_at == ~(uintptr_t)0 || a < s.buf_at || a >= s.buf_end) {
+    const uint32_t i = s.pos;
+    if (s.win == ~0u || i < s.win || i - s.win >= s.wlen) {
+        const uintptr_t lo = (uintptr_t)s.P, a = lo + i;
         const uintptr_t w = a & ~(uintptr_t)7;
-        if (w >= s.lo && w + 8 <= s.hi) {
-            s.buf_at = w;
-            s.buf_end = w + 8;
+        if (w >= lo && w + 8 <= lo + s.m) {
+            s.win = (uint32_t)(w - lo);
+            s.wlen = 8;
             s.buf = *reinterpret_cast<const uint64_t *>(w);
         } else {
-            s.buf_at = a;
-            s.buf_end = a + 1;
+            s.win = i;
+            s.wlen = 1;
             s.buf = *reinterpret_cast<const uint8_t *>(a);
         }
     }
-    const uint32_t c = (uint32_t)(s.buf >> (8 * (a - s.buf_at))) & 0xffu;
-    s.pos = s.rc ? s.pos + 1 : s.pos - 1;
+    const uint32_t c = (uint32_t)(s.buf >> (8 * (i - s.win))) & 0xffu;
+    s.pos = s.rc ? i + 1 : i - 1;
     return strand_code(c, s.rc);
 }
 
@@ -318,9 +324,8 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
     s.P = pat;
     s.m = s.left = s.pos = s.rc = s.acc = 0;
     s.buf = 0;
-    s.buf_at = ~(uintptr_t)0;
-    s.buf_end = 0;
-    s.lo = s.hi = 0;
+    s.win = ~0u;
+    s.wlen = 0;
     while (true) {
         if (!drained) {
             const uint64_t idle = __ballot(!active);

@@ -38,6 +38,30 @@ __device__ __forceinline__ void load_half(const uint4 *__restrict__ lines, const
     hl.s = reinterpret_cast<const uint4 *>(super)[j / QR_LINES_PER_SB];
 }
 
+// load_half for positions below 2^32 (every position of an FM-index, whose BWT has fewer than 2^32
+// rows), with 32-bit line arithmetic.
+__device__ __forceinline__ void load_half32(const uint4 *__restrict__ lines, const uint32_t *__restrict__ super,
+                                            uint32_t q, HalfLine &hl) {
+    const uint32_t j = qr_line_of32(q);
+    const uint32_t p = q - j * (uint32_t)QR_DATA_BASES + QR_HDR;
+    hl.up = p >= QR_MID;
+    hl.t = hl.up ? p - QR_MID : p;
+    const uint4 *L = lines + (uint64_t)j * 8;
+    const uint4 *H = L + (hl.up ? 4 : 0);
+    const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
+    hl.w[0] = a.x, hl.w[1] = a.y, hl.w[2] = a.z, hl.w[3] = a.w;
+    hl.w[4] = b.x, hl.w[5] = b.y, hl.w[6] = b.z, hl.w[7] = b.w;
+    hl.w[8] = c.x, hl.w[9] = c.y, hl.w[10] = c.z, hl.w[11] = c.w;
+    hl.w[12] = d.x, hl.w[13] = d.y, hl.w[14] = d.z, hl.w[15] = d.w;
+    if (hl.up) {
+        const uint4 h0 = L[0];
+        hl.dAC = h0.x, hl.dGT = h0.z;
+    } else {
+        hl.dAC = a.x, hl.dGT = a.z;
+    }
+    hl.s = reinterpret_cast<const uint4 *>(super)[j / QR_LINES_PER_SB];
+}
+
 // v.{x,y,z,w}[c] by mask arithmetic: a runtime-indexed select chain would be lowered to a
 // stack array (scratch memory) once several queries are unrolled per lane.
 __device__ __forceinline__ uint32_t sel4(const uint4 &v, uint32_t c) {
@@ -71,6 +95,14 @@ __device__ __forceinline__ uint32_t half_count1(const HalfLine &hl, uint32_t c) 
 
 __device__ __forceinline__ uint64_t rank1_from_half(const HalfLine &hl, uint32_t c) {
     const uint64_t mid = ((uint64_t)sel4(hl.s, c) << QR_SHIFT) + delta_of(hl, c);
+    const uint32_t cnt = half_count1(hl, c);
+    return hl.up ? mid + cnt : mid - cnt;
+}
+
+// rank1_from_half in 32-bit arithmetic, for structures whose every rank is below 2^32 (then the
+// shifted offset, the mid-line rank and the result all fit).
+__device__ __forceinline__ uint32_t rank1_from_half32(const HalfLine &hl, uint32_t c) {
+    const uint32_t mid = (sel4(hl.s, c) << QR_SHIFT) + delta_of(hl, c);
     const uint32_t cnt = half_count1(hl, c);
     return hl.up ? mid + cnt : mid - cnt;
 }
