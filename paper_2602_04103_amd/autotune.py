@@ -17,7 +17,7 @@ RANK_CANDIDATES = (
     + [dict(lanes=1, per_lane=p, block=256, grid_waves=0) for p in (1, 2)]
     + [dict(lanes=2, per_lane=p, block=256, grid_waves=0, sweep=t) for t in (1024, 2048, 4096) for p in (1, 2)]
 )
-FM_CANDIDATES = [dict(block=b, refill=r, waves_per_cu=w) for b in (64, 256) for r in (8, 32, 64) for w in (8, 16, 32)]
+FM_CANDIDATES = [dict(block=b, refill=r, waves_per_cu=w) for b in (64, 256) for r in (8, 32, 64) for w in (8, 12, 16, 20, 24)]
 
 _CACHE_PATH = os.environ.get("QR_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), ".tune_cache.json"))
 
