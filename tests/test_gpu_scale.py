@@ -13,8 +13,11 @@ from tests.gpu_util import announce, require_gpu, to_dev, to_host_u64
 pytestmark = pytest.mark.gpu
 
 BATCH = 1 << 24
+# the settings the tuner chooses on these structures (lane pairs, and the sweep form with tiles of
+# 1024) and a few neighbours; the last one also runs prefix_rank
 BENCH_TUNINGS = [dict(lanes=2, per_lane=2, block=256, grid_waves=0), dict(lanes=2, per_lane=2, block=256, grid_waves=8),
-                 dict(lanes=2, per_lane=8, block=256, grid_waves=8), dict(lanes=2, per_lane=1, block=128, grid_waves=0)]
+                 dict(lanes=2, per_lane=8, block=256, grid_waves=8), dict(lanes=2, per_lane=2, block=256, sweep=1024),
+                 dict(lanes=2, per_lane=2, block=128, grid_waves=0), dict(lanes=2, per_lane=1, block=256, sweep=1024)]
 
 
 def boundary_queries(n, sb, line, mid):
