@@ -23,7 +23,8 @@
  *   of u64 word i/32.  Bits/bases at positions >= n in the last word are
  *   ignored (may hold anything).
  * - Device arrays of u64 must be 8-byte aligned and d_out4 (rank4) 16-byte aligned; a misaligned
- *   pointer is rejected with QR_EINVAL.
+ *   pointer is rejected with QR_EINVAL.  Build inputs aligned to 16 bytes are read with 16-byte
+ *   loads (the faster path); 8-byte alignment is enough for a correct build.
  * - Positions are zero-based and a query position q ranges over 0 <= q <= n
  *   (paper Section 1: rank(q, c) counts c among the first q characters).
  * - Work is enqueued on `stream` (0 = the null stream).  Query entry points
