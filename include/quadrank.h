@@ -335,7 +335,8 @@ int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, const uint64_t 
 
 /* Host-side reference of the library's exact division by the line payloads (for tests):
  * which = 0 -> floor(x / 1008) (BiRank), 1 -> floor(x / 480) (QuadRank), 2 -> floor(x / 992)
- * (BiRank, QR_LAYOUT_32), 3 -> floor(x / 448) (QuadRank, QR_LAYOUT_32); other values give ~0. */
+ * (BiRank, QR_LAYOUT_32), 3 -> floor(x / 448) (QuadRank, QR_LAYOUT_32), 4 -> floor(x / 480) by the
+ * FM-index search's 32-bit form (x < 2^32; ~0 above); other values give ~0. */
 uint64_t qr_line_of(uint64_t x, int which);
 
 #ifdef __cplusplus
