@@ -170,6 +170,28 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
     return t > 0xffffffffull ? 0xffffffffu : (uint32_t)t;
 }
 
+// Next character of the current strand.  Characters are fetched 8 at a time with one aligned load
+// when the whole aligned 8-byte window lies inside the pattern [P, P + m), else one byte at a time.
+__device__ __forceinline__ uint32_t next_char(Search &s) {
+    const uint32_t i = s.pos;
+    if (s.win == ~0u || i < s.win || i - s.win >= s.wlen) {
+        const uintptr_t lo = (uintptr_t)s.P, a = lo + i;
+        const uintptr_t w = a & ~(uintptr_t)7;
+        if (w >= lo && w + 8 <= lo + s.m) {
+            s.win = (uint32_t)(w - lo);
+            s.wlen = 8;
+            s.buf = *reinterpret_cast<const uint64_t *>(w);
+        } else {
+            s.win = i;
+            s.wlen = 1;
+            s.buf = *reinterpret_cast<const uint8_t *>(a);
+        }
+    }
+    const uint32_t c = (uint32_t)(s.buf >> (8 * (i - s.win))) & 0xffu;
+    s.pos = s.rc ? i + 1 : i - 1;
+    return strand_code(c, s.rc);
+}
+
 // Start the search of one strand; returns true if its count is already known (written to cnt).
 __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc, uint32_t &cnt) {
     s.rc = rc;
@@ -177,13 +199,17 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
     const uint32_t m = s.m;
     const uint32_t K = f.kmer;
     if (m >= K) {
-        // the first K characters searched: P[m-K..m) for P, the complement of P[0..K) reversed for rc(P)
+        // The first K characters searched: P[m-K..m) for P, the complement of P[0..K) reversed for
+        // rc(P).  Their table index is the sum of code_j * 4^j over the characters in the order the
+        // search reads them (j = 0 first), so they are read through the same 8-byte window as the
+        // later steps, which then continue from where it stands.
+        s.pos = rc ? 0 : m - 1;
         uint32_t w = 0;
         bool bad = false;
-        for (uint32_t t = 0; t < K; ++t) {
-            const uint32_t c = strand_code(s.P[rc ? K - 1 - t : m - K + t], rc);
+        for (uint32_t j = 0; j < K; ++j) {
+            const uint32_t c = next_char(s);
             bad |= c > 3;
-            w = (w << 2) | (c & 3u);
+            w |= (c & 3u) << (2 * j);
         }
         if (bad) {
             cnt = 0;
@@ -193,7 +219,6 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
         s.sp = iv.x;
         s.ep = iv.y;
         s.left = m - K;
-        s.pos = rc ? K : m - K - 1;
     } else {
         s.sp = 0;
         s.ep = (uint32_t)f.n1;
@@ -232,28 +257,6 @@ __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restric
     if (!fm_start(f, s, 1, cnt)) return false;
     cnt = sat_add(cnt, s.acc);
     return true;
-}
-
-// Next character of the current strand.  Characters are fetched 8 at a time with one aligned load
-// when the whole aligned 8-byte window lies inside the pattern [P, P + m), else one byte at a time.
-__device__ __forceinline__ uint32_t next_char(Search &s) {
-    const uint32_t i = s.pos;
-    if (s.win == ~0u || i < s.win || i - s.win >= s.wlen) {
-        const uintptr_t lo = (uintptr_t)s.P, a = lo + i;
-        const uintptr_t w = a & ~(uintptr_t)7;
-        if (w >= lo && w + 8 <= lo + s.m) {
-            s.win = (uint32_t)(w - lo);
-            s.wlen = 8;
-            s.buf = *reinterpret_cast<const uint64_t *>(w);
-        } else {
-            s.win = i;
-            s.wlen = 1;
-            s.buf = *reinterpret_cast<const uint8_t *>(a);
-        }
-    }
-    const uint32_t c = (uint32_t)(s.buf >> (8 * (i - s.win))) & 0xffu;
-    s.pos = s.rc ? i + 1 : i - 1;
-    return strand_code(c, s.rc);
 }
 
 // Advance one character; returns true when the pattern's count is final (in cnt).
