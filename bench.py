@@ -18,6 +18,7 @@ sample at rate 32).  The CPU baseline times the oracle on the host cores on a bo
 from __future__ import annotations
 
 import argparse
+import gc
 import itertools
 import json
 import os
@@ -241,19 +242,33 @@ def main():
         for row in rows:
             apply(row)
             launch(row, k)
+    # The timing events are created (first recorded) before the timed region: creating HIP events
+    # inside it would put event-pool growth, a host-side stall, between a launch's two records.
+    ev_pairs = {row: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(args.steps)] for row in rows}
+    for row in rows:
+        for a, b in ev_pairs[row]:
+            a.record(stream)
+            b.record(stream)
     torch.cuda.synchronize()
     ev = {row: [] for row in rows}
+    gc.collect()
+    gc.disable()  # no collector pause between a launch's two event records
     t_start = time.perf_counter()
+    host_max = {row: 0.0 for row in rows}  # longest host time spent issuing one launch
     for k in range(args.steps):
         for row in rows:
+            h0 = time.perf_counter()
             apply(row)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a, b = ev_pairs[row][k]
             a.record(stream)
             launch(row, k)
             b.record(stream)
             ev[row].append((a, b, bl[k % len(bl)][1]))
+            host_max[row] = max(host_max[row], time.perf_counter() - h0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    gc.enable()
     step_queries = sum(bl[k % len(bl)][1] for k in range(args.steps)) * len(rows)
     row_res = {}
     for row in rows:
@@ -268,6 +283,8 @@ def main():
             "avg_launch_ms": per_launch * 1e3,
             "launch_ms_min_p50_max": [round(min(secs) * 1e3, 4), round(statistics.median(secs) * 1e3, 4),
                                       round(max(secs) * 1e3, 4)],
+            "slowest_launch_step": int(max(range(len(secs)), key=lambda i: secs[i])),
+            "host_issue_ms_max": round(host_max[row] * 1e3, 4),
             "lines_per_query": 1,
             "roofline_frac_hbm": achieved / HBM_PEAK_GBS,
             "algorithmic_GBps": achieved,
