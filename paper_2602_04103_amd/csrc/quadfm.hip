@@ -82,12 +82,6 @@ __device__ __forceinline__ uint64_t fm_C(const FmDev &f, uint32_t c) {
     return (lo & ~m2) | (hi & m2);
 }
 
-// rank(q, c) over the BWT from the half line holding q, with the '$' correction for A.
-__device__ __forceinline__ uint64_t rank_bwt(const FmDev &f, const HalfLine &h, uint64_t q, uint32_t c) {
-    uint64_t r = rank1_from_half(h, c);
-    if (c == 0) r -= q > f.dollar;
-    return r;
-}
 
 // The search works in 32-bit positions and ranks: the build admits at most 2^32 - 1 BWT rows.
 __device__ __forceinline__ uint32_t rank_bwt32(const FmDev &f, const HalfLine &h, uint32_t q, uint32_t c) {
@@ -456,7 +450,9 @@ struct LocDev {
 
 // SA[row] by LF steps to the nearest marked row (at most rate - 1 of them); false if none is
 // reached within rate steps, which only inconsistent sample data can cause.
-__device__ __forceinline__ bool sa_of_row(const FmDev &f, const LocDev &d, uint64_t row, uint32_t &pos) {
+__device__ __forceinline__ bool sa_of_row(const FmDev &f, const LocDev &d, uint64_t row64, uint32_t &pos) {
+    if (row64 >= f.n1) return false;
+    uint32_t row = (uint32_t)row64;  // rows of an FM-index are below 2^32
     for (uint32_t steps = 0; steps < d.rate && row < f.n1; ++steps) {
         uint32_t marked = 0;
         const uint64_t k = br_rank_bit<BR16>(d.mlines, d.msuper, row, marked);
@@ -465,9 +461,9 @@ __device__ __forceinline__ bool sa_of_row(const FmDev &f, const LocDev &d, uint6
             return true;
         }
         HalfLine h;
-        load_half(f.lines, f.super, row, h);
+        load_half32(f.lines, f.super, row, h);
         const uint32_t c = symbol_from_half(h);
-        row = fm_C(f, c) + rank_bwt(f, h, row, c);
+        row = (uint32_t)fm_C(f, c) + rank_bwt32(f, h, row, c);
     }
     return false;
 }
