@@ -14,10 +14,11 @@
 //
 // Two count kernels:
 //   fm_batch_kernel       one lane per pattern; the host launches it once per batch of patterns;
-//   fm_persistent_kernel  CUs x waves resident wavefronts pull patterns from a device queue: when
-//                         lanes finish, the wave claims as many new patterns as it has idle lanes
-//                         with one atomic add on the queue head, so no lane idles while work remains
-//                         (the GPU counterpart of the paper's active list with swap-pop).
+//   fm_persistent_kernel  CUs x waves resident wavefronts pull patterns from a device queue: once
+//                         at least `refill` lanes of a wave have finished (a tuning choice), the wave
+//                         claims as many new patterns as it has idle lanes with one atomic add on
+//                         the queue head, so lanes are refilled in batches while work remains (the
+//                         GPU counterpart of the paper's active list with swap-pop).
 // Both can write the final BWT interval [sp, ep) instead of its size (the paper's query_batch
 // returns intervals).
 //
