@@ -429,6 +429,9 @@ class _Handle:
             pass
 
     def _tune(self, fn, block=0, per_lane=0, grid_waves=0, lanes=0, sweep=0):
+        """Query-kernel launch settings (qr_tuning): threads per workgroup, queries in flight per lane
+        (pair), resident waves per CU (0: one pass over the queries), lanes per query (2: lane pairs)
+        and the sweep tile (0, or 1024/2048/4096 queries sorted by position per workgroup)."""
         t = qr_tuning(block, per_lane, grid_waves, lanes, sweep)
         _check(fn(self.h, C.byref(t)), "set_tuning")
 
