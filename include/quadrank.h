@@ -332,6 +332,10 @@ int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx
  * each reading 128/lanes contiguous bytes; the group's sum is written to d_out[i]. */
 int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
                           uint32_t lanes, uint64_t *d_out, hipStream_t stream);
+/* Same with flags: QR_GATHER_NONTEMPORAL gives the line loads the non-temporal cache hint. */
+#define QR_GATHER_NONTEMPORAL 1u
+int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
+                             uint32_t lanes, uint32_t flags, uint64_t *d_out, hipStream_t stream);
 
 /* Host-side reference of the library's exact division by the line payloads (for tests):
  * which = 0 -> floor(x / 1008) (BiRank), 1 -> floor(x / 480) (QuadRank), 2 -> floor(x / 992)

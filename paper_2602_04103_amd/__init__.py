@@ -83,6 +83,7 @@ def lib():
             "quadrank_export": (ci, [vp, vp, vp]),
             "qr_gather_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
             "qr_gather_lanes_bench": (ci, [vp, u64, vp, u64, C.c_uint32, vp, vp]),
+            "qr_gather_lanes_bench_ex": (ci, [vp, u64, vp, u64, C.c_uint32, C.c_uint32, vp, vp]),
             "qr_server_create": (ci, [vp, ci, u64, u64, C.c_uint32, C.POINTER(vp)]),
             "qr_server_run": (ci, [vp, vp, vp, vp, u64, vp, vp, vp, C.c_double, C.POINTER(qr_serve_stats)]),
             "qr_server_free": (ci, [vp]),
@@ -237,11 +238,15 @@ def qr_gather_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, bytes_
     return out
 
 
+QR_GATHER_NONTEMPORAL = 1
+
+
 def qr_gather_lanes_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, lanes: int, out: torch.Tensor,
-                          stream=None):
+                          stream=None, flags: int = 0):
     nq = idx.numel()
-    _check(lib().qr_gather_lanes_bench(_dev(lines, "lines", W64, n_lines * 16), n_lines, _dev(idx, "idx", W64), nq,
-                                       lanes, _dev(out, "out", W64, nq), _stream(stream)), "qr_gather_lanes_bench")
+    _check(lib().qr_gather_lanes_bench_ex(_dev(lines, "lines", W64, n_lines * 16), n_lines, _dev(idx, "idx", W64), nq,
+                                          lanes, flags, _dev(out, "out", W64, nq), _stream(stream)),
+           "qr_gather_lanes_bench")
     return out
 
 

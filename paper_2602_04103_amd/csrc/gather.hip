@@ -26,9 +26,12 @@ __global__ __launch_bounds__(256) void gather_kernel(const uint4 *__restrict__ l
     out[i] = s;
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // LANES lanes share one query: lane t of the group reads 16-byte segments [t S, t S + S) of the line,
 // S = 8 / LANES, and the group's sum is reduced across its lanes; the group's first lane writes it.
-template <int LANES>
+// NT: the line loads carry the non-temporal hint.
+template <int LANES, bool NT>
 __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restrict__ lines, uint64_t n_lines,
                                                            const uint64_t *__restrict__ idx, uint64_t nq,
                                                            uint64_t *__restrict__ out) {
@@ -40,7 +43,14 @@ __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restri
     const uint4 *L = lines + l * 8 + t * S;
     uint4 v[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) v[k] = L[k];
+    for (int k = 0; k < S; ++k) {
+        if (NT) {
+            const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(L + k));
+            v[k] = make_uint4(x.x, x.y, x.z, x.w);
+        } else {
+            v[k] = L[k];
+        }
+    }
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < S; ++k) s += v[k].x + v[k].y + v[k].z + v[k].w;
@@ -51,10 +61,11 @@ __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restri
 
 }  // namespace
 
-extern "C" int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
-                                     uint32_t lanes, uint64_t *d_out, hipStream_t stream) {
+extern "C" int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
+                                        uint32_t lanes, uint32_t flags, uint64_t *d_out, hipStream_t stream) {
     if (!d_lines || !n_lines || (nq && (!d_idx || !d_out)) || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) ||
-        ((uintptr_t)d_lines & 15) || ((uintptr_t)d_idx & 7) || ((uintptr_t)d_out & 7)) {
+        (flags & ~QR_GATHER_NONTEMPORAL) || ((uintptr_t)d_lines & 15) || ((uintptr_t)d_idx & 7) ||
+        ((uintptr_t)d_out & 7)) {
         set_error("qr_gather_lanes_bench: bad arguments");
         return QR_EINVAL;
     }
@@ -66,14 +77,22 @@ extern "C" int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, cons
     }
     const uint4 *L = reinterpret_cast<const uint4 *>(d_lines);
     const dim3 g((uint32_t)blocks), b(256);
+#define QR_GL(N, T) hipLaunchKernelGGL((gather_lanes_kernel<N, T>), g, b, 0, stream, L, n_lines, d_idx, nq, d_out)
+    const bool nt = flags & QR_GATHER_NONTEMPORAL;
     switch (lanes) {
-        case 1: hipLaunchKernelGGL(gather_lanes_kernel<1>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
-        case 2: hipLaunchKernelGGL(gather_lanes_kernel<2>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
-        case 4: hipLaunchKernelGGL(gather_lanes_kernel<4>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
-        default: hipLaunchKernelGGL(gather_lanes_kernel<8>, g, b, 0, stream, L, n_lines, d_idx, nq, d_out); break;
+        case 1: if (nt) QR_GL(1, true); else QR_GL(1, false); break;
+        case 2: if (nt) QR_GL(2, true); else QR_GL(2, false); break;
+        case 4: if (nt) QR_GL(4, true); else QR_GL(4, false); break;
+        default: if (nt) QR_GL(8, true); else QR_GL(8, false); break;
     }
+#undef QR_GL
     QR_HIP(hipGetLastError());
     return QR_OK;
+}
+
+extern "C" int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
+                                     uint32_t lanes, uint64_t *d_out, hipStream_t stream) {
+    return qr_gather_lanes_bench_ex(d_lines, n_lines, d_idx, nq, lanes, 0, d_out, stream);
 }
 
 extern "C" int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,

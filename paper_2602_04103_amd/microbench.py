@@ -59,10 +59,10 @@ def glanes(args):
     for gib in args.gib:
         nl = int(gib * (1 << 30)) // 128
         buf = torch.ones(nl * 16, dtype=torch.int64, device="cuda")
-        for ln in (1, 2, 4, 8):
-            t = _time(lambda: qr.qr_gather_lanes_bench(buf, nl, idx, ln, out))
-            print("glanes ws=%.3f GiB lanes=%d: %.2f G lines/s (%.0f GB/s of 128-byte lines)"
-                  % (gib, ln, nq / t / 1e9, nq * 128 / t / 1e9), flush=True)
+        for ln in args.lanes:
+            t = _time(lambda: qr.qr_gather_lanes_bench(buf, nl, idx, ln, out, flags=args.flags))
+            print("glanes ws=%.3f GiB lanes=%d flags=%d: %.2f G lines/s (%.0f GB/s of 128-byte lines)"
+                  % (gib, ln, args.flags, nq / t / 1e9, nq * 128 / t / 1e9), flush=True)
         del buf
         torch.cuda.empty_cache()
 
@@ -265,6 +265,8 @@ def main(argv=None):
     g.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 2, 3, 4, 8])
     gl = sub.add_parser("glanes")
     gl.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 4, 8, 16])
+    gl.add_argument("--lanes", type=int, nargs="+", default=[1, 2, 4, 8], choices=[1, 2, 4, 8])
+    gl.add_argument("--flags", type=int, default=0, help="1: non-temporal line loads")
     l = sub.add_parser("lanes")
     l.add_argument("--log-n", type=int, default=36)
     r = sub.add_parser("rankws")
