@@ -164,6 +164,8 @@ def cmd_traffic(a):
         "copy_bytes": a.copy_bytes,
         "hbm_bytes_per_launch": statistics.mean(fv) * 1024.0 * f_fac + statistics.mean(wv) * 1024.0 * w_fac,
     }
+    if a.cmd:
+        out["kernels"][traffic_key(a.row, a.layout, a.form)]["command"] = a.cmd
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
@@ -186,6 +188,7 @@ def main(argv=None):
     t.add_argument("--layout", type=int, required=True, choices=(16, 32))
     t.add_argument("--form", default="pair", choices=("pair", "lane", "sweep"),
                    help="launch form the profiled run used (its tuning)")
+    t.add_argument("--cmd", default="", help="the profiled command, stored with the record")
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--copy-kernel", default="elementwise")
     t.add_argument("--out", required=True)
