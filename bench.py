@@ -238,10 +238,6 @@ def main():
         del src, dst
 
     # ------------------------------------------------------------------ timed steps
-    for k in range(args.warmup):
-        for row in rows:
-            apply(row)
-            launch(row, k)
     # The timing events are created (first recorded) before the timed region: creating HIP events
     # inside it would put event-pool growth, a host-side stall, between a launch's two records.
     ev_pairs = {row: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -253,6 +249,11 @@ def main():
     torch.cuda.synchronize()
     ev = {row: [] for row in rows}
     gc.collect()
+    for k in range(args.warmup):  # the warm-up steps run right before the timed ones
+        for row in rows:
+            apply(row)
+            launch(row, k)
+    torch.cuda.synchronize()
     gc.disable()  # no collector pause between a launch's two event records
     t_start = time.perf_counter()
     host_max = {row: 0.0 for row in rows}  # longest host time spent issuing one launch
