@@ -19,7 +19,8 @@ TUNES = [dict(), dict(per_lane=2), dict(per_lane=4, grid_waves=4), dict(lanes=1,
 
 
 @SETTINGS
-@given(st.integers(0, 400_000), st.floats(0.0, 1.0), st.integers(1, 30_000), st.sampled_from(TUNES),
+@given(st.one_of(st.integers(0, 3000), st.integers(50_000, 400_000)), st.floats(0.0, 1.0),
+       st.one_of(st.integers(1, 300), st.integers(5_000, 30_000)), st.sampled_from(TUNES),
        st.booleans(), st.integers(0, 2 ** 31))
 def test_birank_random(n, p, nq, tune, l32, s):
     qr = require_gpu()
@@ -32,7 +33,8 @@ def test_birank_random(n, p, nq, tune, l32, s):
 
 
 @SETTINGS
-@given(st.integers(0, 300_000), st.integers(1, 30_000), st.sampled_from(TUNES), st.booleans(),
+@given(st.one_of(st.integers(0, 3000), st.integers(50_000, 300_000)),
+       st.one_of(st.integers(1, 300), st.integers(5_000, 30_000)), st.sampled_from(TUNES), st.booleans(),
        st.integers(0, 2 ** 31))
 def test_quadrank_random(n, nq, tune, l32, s):
     qr = require_gpu()
@@ -51,7 +53,8 @@ def test_quadrank_random(n, nq, tune, l32, s):
 
 @settings(max_examples=15, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
-@given(st.integers(1, 20_000), st.integers(1, 600), st.integers(1, 9), st.sampled_from([1, 4, 8, 12]),
+@given(st.one_of(st.integers(1, 300), st.integers(3_000, 20_000)), st.integers(1, 600), st.integers(1, 9),
+       st.sampled_from([1, 4, 8, 12]),
        st.integers(0, 2 ** 31))
 def test_fm_random(n, npat, maxlen_div, kmer, s):
     qr = require_gpu()
