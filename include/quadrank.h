@@ -332,8 +332,11 @@ int qr_gather_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx
  * each reading 128/lanes contiguous bytes; the group's sum is written to d_out[i]. */
 int qr_gather_lanes_bench(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
                           uint32_t lanes, uint64_t *d_out, hipStream_t stream);
-/* Same with flags: QR_GATHER_NONTEMPORAL gives the line loads the non-temporal cache hint. */
+/* Same with flags: QR_GATHER_NONTEMPORAL gives the line loads the non-temporal cache hint, and
+ * QR_GATHER_STREAM_IO gives it to the index loads and result stores (as the rank kernels do for
+ * their queries and results). */
 #define QR_GATHER_NONTEMPORAL 1u
+#define QR_GATHER_STREAM_IO 2u
 int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
                              uint32_t lanes, uint32_t flags, uint64_t *d_out, hipStream_t stream);
 

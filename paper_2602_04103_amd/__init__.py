@@ -239,6 +239,7 @@ def qr_gather_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, bytes_
 
 
 QR_GATHER_NONTEMPORAL = 1
+QR_GATHER_STREAM_IO = 2
 
 
 def qr_gather_lanes_bench(lines: torch.Tensor, n_lines: int, idx: torch.Tensor, lanes: int, out: torch.Tensor,

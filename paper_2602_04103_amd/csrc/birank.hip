@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ 
         bool bad[PER_LANE];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
-            q[u] = Q[min(i0 + u * stride, nq - 1)];
+            q[u] = load_once(Q + min(i0 + u * stride, nq - 1));
             bad[u] = q[u] > n;
             if (bad[u]) q[u] = 0;  // line 0 always exists; the output is overwritten below
         }
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ 
         for (int u = 0; u < PER_LANE; ++u) {
             const uint64_t i = i0 + u * stride;
             if (i < nq) {
-                out[i] = r[u];
+                store_once(out + i, r[u]);
                 if (bad[u]) atomicOr(err, 1u);
             }
         }
@@ -260,13 +260,13 @@ __global__ __launch_bounds__(256) void br_rank_pair_kernel(const uint4 *__restri
         bool bad[PER_PAIR];
         // query positions (index clamped so every load is unconditional and in bounds)
 #pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) q[u] = Q[min(i0 + u * pairs, nq - 1)];
+        for (int u = 0; u < PER_PAIR; ++u) q[u] = load_once(Q + min(i0 + u * pairs, nq - 1));
         br_pair_compute<L, PER_PAIR>(lines, super, n, q, hf, r, bad);
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = i0 + u * pairs;
             if (hf == 0 && i < nq) {
-                out[i] = r[u];
+                store_once(out + i, r[u]);
                 if (bad[u]) atomicOr(err, 1u);
             }
         }

@@ -104,6 +104,24 @@ __device__ __forceinline__ uint64_t pair_swap64(uint64_t x) {
     return (uint64_t)pair_swap32((uint32_t)x) | ((uint64_t)pair_swap32((uint32_t)(x >> 32)) << 32);
 }
 
+// Query batches and results stream through a rank launch once.  They are loaded and stored with the
+// non-temporal hint, so they do not displace the structure's lines from L2 and from the memory-side
+// cache (256 MB, a fifth of a 2^32-base QuadRank), whose hits on those lines lift the gather rate.
+template <typename T>
+__device__ __forceinline__ T load_once(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void store_once(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+typedef uint64_t u64x2_t __attribute__((ext_vector_type(2)));
+// Two results to a 16-byte aligned address.
+__device__ __forceinline__ void store_once2(uint64_t *p, uint64_t a, uint64_t b) {
+    const u64x2_t v = {a, b};
+    __builtin_nontemporal_store(v, reinterpret_cast<u64x2_t *>(p));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

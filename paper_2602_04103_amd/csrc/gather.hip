@@ -30,8 +30,8 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // LANES lanes share one query: lane t of the group reads 16-byte segments [t S, t S + S) of the line,
 // S = 8 / LANES, and the group's sum is reduced across its lanes; the group's first lane writes it.
-// NT: the line loads carry the non-temporal hint.
-template <int LANES, bool NT>
+// NT: the line loads carry the non-temporal hint; IO: the index loads and result stores do.
+template <int LANES, bool NT, bool IO>
 __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restrict__ lines, uint64_t n_lines,
                                                            const uint64_t *__restrict__ idx, uint64_t nq,
                                                            uint64_t *__restrict__ out) {
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restri
     const uint64_t g = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / LANES;
     const int t = threadIdx.x % LANES;
     const uint64_t i = g < nq ? g : nq - 1;  // whole groups stay active for the reduction
-    const uint64_t l = mulhi64(idx[i], n_lines);
+    const uint64_t l = mulhi64(IO ? load_once(idx + i) : idx[i], n_lines);
     const uint4 *L = lines + l * 8 + t * S;
     uint4 v[S];
 #pragma unroll
@@ -56,7 +56,12 @@ __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restri
     for (int k = 0; k < S; ++k) s += v[k].x + v[k].y + v[k].z + v[k].w;
 #pragma unroll
     for (int m = 1; m < LANES; m <<= 1) s += __shfl_xor(s, m, 64);
-    if (t == 0 && g < nq) out[g] = s;
+    if (t == 0 && g < nq) {
+        if (IO)
+            store_once(out + g, (uint64_t)s);
+        else
+            out[g] = s;
+    }
 }
 
 }  // namespace
@@ -64,7 +69,7 @@ __global__ __launch_bounds__(256) void gather_lanes_kernel(const uint4 *__restri
 extern "C" int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, const uint64_t *d_idx, uint64_t nq,
                                         uint32_t lanes, uint32_t flags, uint64_t *d_out, hipStream_t stream) {
     if (!d_lines || !n_lines || (nq && (!d_idx || !d_out)) || (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) ||
-        (flags & ~QR_GATHER_NONTEMPORAL) || ((uintptr_t)d_lines & 15) || ((uintptr_t)d_idx & 7) ||
+        (flags & ~(QR_GATHER_NONTEMPORAL | QR_GATHER_STREAM_IO)) || ((uintptr_t)d_lines & 15) || ((uintptr_t)d_idx & 7) ||
         ((uintptr_t)d_out & 7)) {
         set_error("qr_gather_lanes_bench: bad arguments");
         return QR_EINVAL;
@@ -77,14 +82,23 @@ extern "C" int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, c
     }
     const uint4 *L = reinterpret_cast<const uint4 *>(d_lines);
     const dim3 g((uint32_t)blocks), b(256);
-#define QR_GL(N, T) hipLaunchKernelGGL((gather_lanes_kernel<N, T>), g, b, 0, stream, L, n_lines, d_idx, nq, d_out)
-    const bool nt = flags & QR_GATHER_NONTEMPORAL;
-    switch (lanes) {
-        case 1: if (nt) QR_GL(1, true); else QR_GL(1, false); break;
-        case 2: if (nt) QR_GL(2, true); else QR_GL(2, false); break;
-        case 4: if (nt) QR_GL(4, true); else QR_GL(4, false); break;
-        default: if (nt) QR_GL(8, true); else QR_GL(8, false); break;
+#define QR_GL(N, T, I) hipLaunchKernelGGL((gather_lanes_kernel<N, T, I>), g, b, 0, stream, L, n_lines, d_idx, nq, d_out)
+#define QR_GL2(N)                                   \
+    if (nt) {                                       \
+        if (io) QR_GL(N, true, true);               \
+        else QR_GL(N, true, false);                 \
+    } else {                                        \
+        if (io) QR_GL(N, false, true);              \
+        else QR_GL(N, false, false);                \
     }
+    const bool nt = flags & QR_GATHER_NONTEMPORAL, io = flags & QR_GATHER_STREAM_IO;
+    switch (lanes) {
+        case 1: QR_GL2(1); break;
+        case 2: QR_GL2(2); break;
+        case 4: QR_GL2(4); break;
+        default: QR_GL2(8); break;
+    }
+#undef QR_GL2
 #undef QR_GL
     QR_HIP(hipGetLastError());
     return QR_OK;

@@ -231,8 +231,8 @@ __device__ __forceinline__ void sym_lane_body(const uint4 *__restrict__ lines, c
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const uint64_t i = min(i0 + u * stride, nq - 1);
-            q[u] = Q[i];
-            c[u] = Cs[i];
+            q[u] = load_once(Q + i);
+            c[u] = load_once(Cs + i);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
@@ -253,7 +253,7 @@ __device__ __forceinline__ void sym_lane_body(const uint4 *__restrict__ lines, c
         for (int u = 0; u < PER_LANE; ++u) {
             const uint64_t i = i0 + u * stride;
             if (i < nq) {
-                out[i] = r[u];
+                store_once(out + i, r[u]);
                 if (bad[u]) atomicOr(err, 1u);
             }
         }
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__
         uint4 hdr[PER_LANE];
         uint64_t off[PER_LANE][4];
 #pragma unroll
-        for (int u = 0; u < PER_LANE; ++u) q[u] = Q[min(i0 + u * stride, nq - 1)];
+        for (int u = 0; u < PER_LANE; ++u) q[u] = load_once(Q + min(i0 + u * stride, nq - 1));
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             bad[u] = q[u] > n;
@@ -307,9 +307,8 @@ __global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__
             }
             const uint64_t i = i0 + u * stride;
             if (i < nq) {
-                ulonglong2 *o = reinterpret_cast<ulonglong2 *>(out4 + 4 * i);
-                o[0] = make_ulonglong2(r[0], r[1]);
-                o[1] = make_ulonglong2(r[2], r[3]);
+                store_once2(out4 + 4 * i, r[0], r[1]);
+                store_once2(out4 + 4 * i + 2, r[2], r[3]);
                 if (bad[u]) atomicOr(err, 1u);
             }
         }
@@ -363,15 +362,15 @@ __device__ __forceinline__ void sym_pair_body(const uint4 *__restrict__ lines, c
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = min(i0 + u * pairs, nq - 1);
-            q[u] = Q[i];
-            c[u] = Cs[i];
+            q[u] = load_once(Q + i);
+            c[u] = load_once(Cs + i);
         }
         sym_pair_compute<L, PER_PAIR, PREFIX>(lines, super, n, q, c, hf, r, bad);
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = i0 + u * pairs;
             if (hf == 0 && i < nq) {
-                out[i] = r[u];
+                store_once(out + i, r[u]);
                 if (bad[u]) atomicOr(err, 1u);
             }
         }
@@ -465,27 +464,31 @@ __global__ __launch_bounds__(256) void qr_rank4_pair_kernel(const uint4 *__restr
         uint64_t q[PER_PAIR], ra[PER_PAIR], rb[PER_PAIR];
         bool bad[PER_PAIR];
 #pragma unroll
-        for (int u = 0; u < PER_PAIR; ++u) q[u] = Q[min(i0 + u * pairs, nq - 1)];
+        for (int u = 0; u < PER_PAIR; ++u) q[u] = load_once(Q + min(i0 + u * pairs, nq - 1));
         rank4_pair_compute<L, PER_PAIR>(lines, super, n, q, hf, ra, rb, bad);
 #pragma unroll
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint64_t i = i0 + u * pairs;
             if (i < nq) {
-                reinterpret_cast<ulonglong2 *>(out4 + 4 * i)[hf] = make_ulonglong2(ra[u], rb[u]);
+                store_once2(out4 + 4 * i + 2 * hf, ra[u], rb[u]);
                 if (bad[u] && hf == 0) atomicOr(err, 1u);
             }
         }
     }
 }
 
-// Sweep form of rank4: each query's 32-byte row is written straight to its own slot.
+// Sweep form of rank4.  With tiles of 1024 queries the 32-byte rows are staged in LDS in query
+// order (32 KB beside the 13 KB of the sort) and written back coalesced; with larger tiles, whose
+// rows would not fit, each row goes straight to its own slot (a scatter: slower).
 template <class L, int PER_PAIR, int QPT>
 __global__ __launch_bounds__(SWEEP_BLOCK) void qr_rank4_sweep_kernel(const uint4 *__restrict__ lines,
                                                                      const typename L::Super *__restrict__ super,
                                                                      uint64_t n, const uint64_t *__restrict__ Q,
                                                                      uint64_t nq, uint64_t *__restrict__ out4,
                                                                      uint32_t *__restrict__ err, uint32_t shift) {
+    constexpr bool STAGE = QPT <= 4;
     __shared__ SweepLds<QPT, false> S;
+    __shared__ u64x2_t R[STAGE ? 2 * SWEEP_BLOCK * QPT : 1];  // half-row k of the tile's query k / 2
     constexpr uint32_t PAIRS = SWEEP_BLOCK / 2;
     const uint64_t base = (uint64_t)blockIdx.x * (SWEEP_BLOCK * QPT);
     const uint32_t m = (uint32_t)min<uint64_t>(SWEEP_BLOCK * QPT, nq - base);
@@ -501,11 +504,20 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void qr_rank4_sweep_kernel(const uint4
         for (int u = 0; u < PER_PAIR; ++u) {
             const uint32_t sl = s0 + u * PAIRS;
             if (sl < m) {
-                const uint64_t i = base + S.tile_of[sl];
-                reinterpret_cast<ulonglong2 *>(out4 + 4 * i)[hf] = make_ulonglong2(ra[u], rb[u]);
+                const uint32_t ti = S.tile_of[sl];
+                if (STAGE) {
+                    const u64x2_t v = {ra[u], rb[u]};
+                    R[2 * ti + hf] = v;
+                } else {  // a lone 32-byte row: a plain store, which L2 can merge with its neighbours
+                    reinterpret_cast<ulonglong2 *>(out4 + 4 * (base + ti))[hf] = make_ulonglong2(ra[u], rb[u]);
+                }
                 if (bad[u] && hf == 0) atomicOr(err, 1u);
             }
         }
+    }
+    if (STAGE) {
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < 2 * m; k += SWEEP_BLOCK) store_once2(out4 + 4 * base + 2 * k, R[k].x, R[k].y);
     }
 }
 

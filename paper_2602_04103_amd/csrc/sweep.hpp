@@ -82,8 +82,8 @@ __device__ __forceinline__ void sweep_sort(const uint64_t *__restrict__ Q, const
     for (int k = 0; k < QPT; ++k) {
         const uint32_t i = k * SWEEP_BLOCK + t;
         if (i < m) {
-            q[k] = Q[base + i];
-            c[k] = HAS_C ? Cs[base + i] : 0u;
+            q[k] = load_once(Q + base + i);
+            c[k] = HAS_C ? load_once(Cs + base + i) : 0u;
             const uint64_t hi = q[k] >> shift;
             const uint32_t b = hi < SWEEP_BUCKETS ? (uint32_t)hi : SWEEP_BUCKETS - 1;  // q > n: last bucket
             key[k] = b << 16 | atomicAdd(&S.start[b], 1u);
@@ -113,7 +113,7 @@ __device__ __forceinline__ void sweep_store(uint64_t *__restrict__ out, uint64_t
 #pragma unroll
     for (int k = 0; k < QPT; ++k) {
         const uint32_t i = k * SWEEP_BLOCK + threadIdx.x;
-        if (i < m) out[base + i] = S.q[S.slot_of[i]];
+        if (i < m) store_once(out + base + i, S.q[S.slot_of[i]]);
     }
 }
 

@@ -266,7 +266,7 @@ def main(argv=None):
     gl = sub.add_parser("glanes")
     gl.add_argument("--gib", type=float, nargs="+", default=[0.25, 1, 4, 8, 16])
     gl.add_argument("--lanes", type=int, nargs="+", default=[1, 2, 4, 8], choices=[1, 2, 4, 8])
-    gl.add_argument("--flags", type=int, default=0, help="1: non-temporal line loads")
+    gl.add_argument("--flags", type=int, default=0, help="1: non-temporal line loads, 2: non-temporal index loads and result stores")
     l = sub.add_parser("lanes")
     l.add_argument("--log-n", type=int, default=36)
     r = sub.add_parser("rankws")
