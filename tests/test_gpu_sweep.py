@@ -130,13 +130,14 @@ def test_quadrank_sweep_query_shapes(tune, L):
         h.check()
 
 
+@pytest.mark.parametrize("tile", [1024, 2048])  # rank4: rows staged in LDS, then rows written one by one
 @pytest.mark.parametrize("L", [0, 1])
-def test_quadrank_sweep_out_of_range(L):
+def test_quadrank_sweep_out_of_range(L, tile):
     qr = require_gpu()
     n = 7000
     codes, packed = qr_inputs(n, 3)
     h = qr.QuadRank(to_dev(packed), n, layout=layouts(qr)[L])
-    h.set_tuning(sweep=2048, per_lane=2)
+    h.set_tuning(sweep=tile, per_lane=2)
     q = np.concatenate([datagen.queries(4, n, 3000), np.array([n + 1, 2 ** 63, 5], np.uint64)])
     c = datagen.symbols(5, q.size)
     announce("quadrank-sweep-bad-q", L)
