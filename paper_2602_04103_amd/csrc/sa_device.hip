@@ -9,6 +9,13 @@
 // end), which orders suffixes by their first 2h characters; h doubles from 21 until every group is
 // a single suffix.  The sort is stable, so ties keep the previous order, as the method requires.
 //
+// A suffix alone in its group is in its final place, and its rank (that place) stays consistent
+// with every longer prefix, so a step only re-sorts the suffixes of groups with two or more members
+// (the "active" ones; discarding finished suffixes, as in Larsson and Sadakane's doubling).  Active
+// suffixes are kept as the list of their places in the suffix array, in order.  The members of a
+// group hold consecutive places and the sort key leads with the group's rank, so after a step's
+// sort the k-th key still belongs to the k-th listed place.
+//
 // Radix sort: 8-bit digits, least significant first.  Per pass: (1) per tile of 4096 keys a 256-bin
 // histogram in LDS, stored digit-major; (2) an exclusive scan of all histograms gives every
 // (digit, tile) its output base; (3) each tile walks its keys in order, ranks equal digits within a
@@ -235,56 +242,51 @@ __global__ void init_keys(const uint8_t *__restrict__ text, uint32_t n, uint64_t
     val[i] = (uint32_t)i;
 }
 
-// g[i] = i where sorted key i starts a group (differs from key i-1), else 0; the number of group
-// starts of each tile of 4096 goes to tcount[tile] (summed by sum_u32, not by a shared atomic)
-__global__ __launch_bounds__(BLK) void group_heads(const uint64_t *__restrict__ key, uint32_t N,
-                                                   uint32_t *__restrict__ g, uint32_t *__restrict__ tcount) {
-    __shared__ uint32_t wsum[BLK / 64];
-    const uint64_t i0 = (uint64_t)blockIdx.x * TILE + threadIdx.x;
-    uint32_t c = 0;
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t i = i0 + (uint64_t)j * BLK;
-        if (i < N) {
-            const bool h = i == 0 || key[i] != key[i - 1];
-            g[i] = h ? (uint32_t)i : 0u;
-            c += h;
-        }
-    }
-    c = wave_sum(c);
-    if (__lane_id() == 0) wsum[threadIdx.x / 64] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) tcount[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+// One pass over the U sorted keys of a step (place pos[i] in the suffix array, suffix v[i]):
+// store the suffix at its place; g[i] = its place if key i starts a new group, else 0 (a max-scan
+// then gives every key its group's first place); act[i] = 1 unless key i is alone in its group.
+__global__ void settle(const uint64_t *__restrict__ key, const uint32_t *__restrict__ v, const uint32_t *__restrict__ pos,
+                       uint32_t U, uint32_t *__restrict__ sa, uint32_t *__restrict__ g, uint32_t *__restrict__ act) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= U) return;
+    const uint64_t k = key[i];
+    const bool head = i == 0 || k != key[i - 1];
+    const bool tail = i + 1 == U || k != key[i + 1];
+    sa[pos[i]] = v[i];
+    g[i] = head ? pos[i] : 0u;
+    act[i] = (head && tail) ? 0u : 1u;
 }
 
-// *out = sum of x[0..n) (one workgroup)
-__global__ __launch_bounds__(TOP) void sum_u32(const uint32_t *__restrict__ x, uint64_t n,
-                                               unsigned long long *__restrict__ out) {
-    __shared__ unsigned long long wsum[TOP / 64];
-    unsigned long long c = 0;
-    for (uint64_t i = threadIdx.x; i < n; i += TOP) c += x[i];
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-    if (__lane_id() == 0) wsum[threadIdx.x / 64] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < TOP / 64; ++w) t += wsum[w];
-        *out = t;
-    }
-}
-
-__global__ void set_rank(const uint32_t *__restrict__ sa, const uint32_t *__restrict__ gstart, uint32_t N,
+// rank[v[i]] = first place of key i's group
+__global__ void set_rank(const uint32_t *__restrict__ v, const uint32_t *__restrict__ gstart, uint32_t U,
                          uint32_t *__restrict__ rank) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) rank[sa[i]] = gstart[i];
+    if (i < U) rank[v[i]] = gstart[i];
 }
 
-// key of sorted position i for doubling step h: (rank of the suffix, rank of the suffix h further + 1, or 0)
-__global__ void pair_keys(const uint32_t *__restrict__ sa, const uint32_t *__restrict__ rank, uint32_t N, uint32_t h,
-                          uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+// The places of the keys still active, in order (at[i] = exclusive count of active keys before i);
+// the number of them goes to *count.
+__global__ void compact_active(const uint32_t *__restrict__ pos, const uint32_t *__restrict__ act,
+                               const uint32_t *__restrict__ at, uint32_t U, uint32_t *__restrict__ pos_out,
+                               unsigned long long *__restrict__ count) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const uint32_t s = sa[i];
+    if (i >= U) return;
+    if (act[i]) pos_out[at[i]] = pos[i];
+    if (i + 1 == U) *count = (unsigned long long)at[i] + act[i];
+}
+
+__global__ void iota_u32(uint32_t *__restrict__ x, uint32_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (uint32_t)i;
+}
+
+// key of active suffix i for doubling step h: (rank of the suffix, rank of the suffix h further + 1,
+// or 0 past the end)
+__global__ void pair_keys(const uint32_t *__restrict__ sa, const uint32_t *__restrict__ pos, const uint32_t *__restrict__ rank,
+                          uint32_t U, uint32_t N, uint32_t h, uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= U) return;
+    const uint32_t s = sa[pos[i]];
     const uint64_t s2 = (uint64_t)s + h;
     const uint32_t r2 = s2 < N ? rank[s2] + 1u : 0u;
     key[i] = ((uint64_t)rank[s] << 32) | r2;
@@ -336,11 +338,13 @@ uint32_t blocks_for(uint64_t n, uint32_t bs) { return (uint32_t)((n + bs - 1) / 
 struct Buffers {
     uint64_t *k0 = nullptr, *k1 = nullptr;
     uint32_t *v0 = nullptr, *v1 = nullptr, *rank = nullptr, *g = nullptr, *hist = nullptr, *offs = nullptr,
-             *aux = nullptr, *bad = nullptr;
+             *aux = nullptr, *bad = nullptr, *sa = nullptr, *pos = nullptr, *pos2 = nullptr, *act = nullptr,
+             *at = nullptr;
     unsigned long long *cnt = nullptr;
     ~Buffers() {
         for (void *p : {(void *)k0, (void *)k1, (void *)v0, (void *)v1, (void *)rank, (void *)g, (void *)hist,
-                        (void *)offs, (void *)aux, (void *)bad, (void *)cnt})
+                        (void *)offs, (void *)aux, (void *)bad, (void *)cnt, (void *)sa, (void *)pos, (void *)pos2,
+                        (void *)act, (void *)at})
             if (p) (void)hipFree(p);
     }
 };
@@ -363,20 +367,30 @@ hipError_t radix_sort(Buffers &B, uint32_t N, uint32_t bits, hipStream_t s) {
     return hipSuccess;
 }
 
-// sorted keys in k0 -> group starts (max-scan of heads) -> rank[]; returns the number of groups
-hipError_t regroup(Buffers &B, uint32_t N, hipStream_t s, uint64_t &groups) {
-    const uint32_t nt = blocks_for(N, TILE);
-    hipLaunchKernelGGL(group_heads, dim3(nt), dim3(BLK), 0, s, B.k0, N, B.g, B.hist);
-    hipLaunchKernelGGL(sum_u32, dim3(1), dim3(TOP), 0, s, B.hist, (uint64_t)nt, B.cnt);
+// After a step's sort of the U active keys (k0, v0) whose places are pos[0..U): store the suffixes
+// at their places, give each its group's first place as rank, and keep in pos the places of the
+// suffixes whose groups still have two or more members; returns their number in U.
+hipError_t settle_step(Buffers &B, uint32_t &U, hipStream_t s) {
+    const uint32_t nb = blocks_for(U, 256);
+    hipLaunchKernelGGL(settle, dim3(nb), dim3(256), 0, s, B.k0, B.v0, B.pos, U, B.sa, B.g, B.act);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = scan_u32<OpMax, true>(B.g, N, B.g, B.aux, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(set_rank, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.v0, B.g, N, B.rank);
-    e = hipGetLastError();
+    if (e == hipSuccess) e = scan_u32<OpMax, true>(B.g, U, B.g, B.aux, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(set_rank, dim3(nb), dim3(256), 0, s, B.v0, B.g, U, B.rank);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = scan_u32<OpAdd, false>(B.act, U, B.at, B.aux, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(compact_active, dim3(nb), dim3(256), 0, s, B.pos, B.act, B.at, U, B.pos2, B.cnt);
+        e = hipGetLastError();
+    }
     unsigned long long c = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&c, B.cnt, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    groups = c;
+    if (e == hipSuccess) {
+        std::swap(B.pos, B.pos2);
+        U = (uint32_t)c;
+    }
     return e;
 }
 
@@ -411,9 +425,12 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
         hipMalloc(&B.v0, 4ull * N) != hipSuccess || hipMalloc(&B.v1, 4ull * N) != hipSuccess ||
         hipMalloc(&B.rank, 4ull * N) != hipSuccess || hipMalloc(&B.g, 4ull * N + 4) != hipSuccess ||
         hipMalloc(&B.hist, 4 * nh) != hipSuccess || hipMalloc(&B.offs, 4 * nh) != hipSuccess ||
-        hipMalloc(&B.aux, 4 * naux) != hipSuccess || hipMalloc(&B.bad, 4) != hipSuccess || hipMalloc(&B.cnt, 8) != hipSuccess) {
+        hipMalloc(&B.aux, 4 * naux) != hipSuccess || hipMalloc(&B.bad, 4) != hipSuccess || hipMalloc(&B.cnt, 8) != hipSuccess ||
+        hipMalloc(&B.sa, 4ull * N) != hipSuccess || hipMalloc(&B.pos, 4ull * N) != hipSuccess ||
+        hipMalloc(&B.pos2, 4ull * N) != hipSuccess || hipMalloc(&B.act, 4ull * N) != hipSuccess ||
+        hipMalloc(&B.at, 4ull * N) != hipSuccess) {
         (void)hipGetLastError();
-        set_error("quadfm_index_device: device allocation failed (about %llu bytes)", (unsigned long long)(40ull * N + 8 * nh));
+        set_error("quadfm_index_device: device allocation failed (about %llu bytes)", (unsigned long long)(60ull * N + 8 * nh));
         return QR_ENOMEM;
     }
     hipStream_t s = stream;
@@ -429,34 +446,33 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
         set_error("quadfm_index_device: a text code is above 3");
         return QR_EINVAL;
     }
-    // initial sort: the first 21 characters
+    // initial sort: the first 21 characters, all N suffixes active at places 0..N-1
     if (e == hipSuccess) {
         hipLaunchKernelGGL(init_keys, dim3(blocks_for(N, 256)), dim3(256), 0, s, d_text, (uint32_t)n, B.k0, B.v0);
+        hipLaunchKernelGGL(iota_u32, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.pos, N);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = radix_sort(B, N, 3 * KEY_CHARS, s);
-    uint64_t groups = 0;
-    if (e == hipSuccess) e = regroup(B, N, s, groups);
-    // doubling steps h = 21, 42, 84, ...: sort by (rank[i], rank[i+h]) until every suffix is alone
+    uint32_t U = N;
+    if (e == hipSuccess) e = settle_step(B, U, s);
+    // doubling steps h = 21, 42, 84, ...: sort the active suffixes by (rank[i], rank[i+h]) until none is left
     const uint32_t rbits = bit_length(N);  // ranks < N; second component < N + 1
-    for (uint64_t h = KEY_CHARS; e == hipSuccess && groups < N; h *= 2) {
+    for (uint64_t h = KEY_CHARS; e == hipSuccess && U > 0; h *= 2) {
         if (h > 2ull * N) {
             set_error("quadfm_index_device: prefix doubling did not converge");
             return QR_EHIP;
         }
-        hipLaunchKernelGGL(pair_keys, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.v0, B.rank, N, (uint32_t)h, B.k0, B.v1);
+        hipLaunchKernelGGL(pair_keys, dim3(blocks_for(U, 256)), dim3(256), 0, s, B.sa, B.pos, B.rank, U, N, (uint32_t)h,
+                           B.k0, B.v0);
         e = hipGetLastError();
-        if (e == hipSuccess) {
-            std::swap(B.v0, B.v1);
-            // low word holds rank2 + 1 <= N in rbits bits; high word the first rank: sort bits [0, 32+rbits)
-            e = radix_sort(B, N, 32 + rbits, s);
-        }
-        if (e == hipSuccess) e = regroup(B, N, s, groups);
+        // low word holds rank2 + 1 <= N in rbits bits; high word the first rank: sort bits [0, 32+rbits)
+        if (e == hipSuccess) e = radix_sort(B, U, 32 + rbits, s);
+        if (e == hipSuccess) e = settle_step(B, U, s);
     }
-    // BWT and the locate sample from SA (in v0)
+    // BWT and the locate sample from the suffix array
     unsigned long long *d_dollar = B.cnt;
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(bwt_pack, dim3(blocks_for(((uint64_t)N + 31) / 32, 256)), dim3(256), 0, s, B.v0, d_text, N,
+        hipLaunchKernelGGL(bwt_pack, dim3(blocks_for(((uint64_t)N + 31) / 32, 256)), dim3(256), 0, s, B.sa, d_text, N,
                            d_bwt_packed2, d_dollar);
         e = hipGetLastError();
     }
@@ -464,11 +480,11 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
     if (e == hipSuccess) e = hipMemcpyAsync(&dol, d_dollar, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && rate) {
         const uint64_t nwv = ((uint64_t)N + 63) / 64;
-        hipLaunchKernelGGL(sample_marks, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.v0, N, rate, d_mark_bits, B.hist);
+        hipLaunchKernelGGL(sample_marks, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.sa, N, rate, d_mark_bits, B.hist);
         e = hipGetLastError();
         if (e == hipSuccess) e = scan_u32<OpAdd, false>(B.hist, nwv, B.offs, B.aux, s);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(sample_write, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.v0, N, rate, B.offs, d_samples);
+            hipLaunchKernelGGL(sample_write, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.sa, N, rate, B.offs, d_samples);
             e = hipGetLastError();
         }
     }
