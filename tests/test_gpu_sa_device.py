@@ -62,9 +62,31 @@ def test_device_sa_random_texts(n):
     check_against_oracle(qr, codes, 7 if n > 7 else 1)
 
 
-@pytest.mark.parametrize("kind", ["allA", "allT", "period7", "tiled37", "halves"])
+def fibonacci_word(n):
+    """The Fibonacci word over {A, C} (s_k = s_{k-1} s_{k-2}), cut to n characters."""
+    a, b = [0], [0, 1]
+    while len(b) < n:
+        a, b = b, b + a
+    return np.array(b[:n], np.uint8)
+
+
+def mixed_repeats(n):
+    """Random text with copies of segments of 30, 300, 3000 and 9000 characters, so that groups of
+    suffixes finish in different doubling steps."""
+    codes = datagen.dna_codes(12, n)
+    at = 0
+    for k, length in enumerate((30, 300, 3000, 9000)):
+        seg = datagen.dna_codes(13 + k, length)
+        for _ in range(2 if length > 1000 else 5):
+            codes[at:at + length] = seg
+            at += length + 7
+    return codes
+
+
+@pytest.mark.parametrize("kind", ["allA", "allT", "period7", "tiled37", "halves", "fibonacci", "mixed"])
 def test_device_sa_degenerate_texts(kind):
-    """Suffixes sharing prefixes of thousands of characters: many doubling steps."""
+    """Suffixes sharing prefixes of thousands of characters: many doubling steps; groups that
+    finish in different steps (only unfinished groups are sorted again)."""
     qr = require_gpu()
     n = 30_001
     if kind == "allA":
@@ -75,6 +97,10 @@ def test_device_sa_degenerate_texts(kind):
         codes = (np.arange(n) % 7 % 4).astype(np.uint8)
     elif kind == "tiled37":
         codes = np.tile(datagen.dna_codes(9, 37), n // 37 + 1)[:n].copy()
+    elif kind == "fibonacci":
+        codes = fibonacci_word(n)
+    elif kind == "mixed":
+        codes = mixed_repeats(n)
     else:
         h = datagen.dna_codes(10, n // 2)
         codes = np.concatenate([h, h, datagen.dna_codes(11, n - 2 * h.size)])
