@@ -101,3 +101,19 @@ def test_host_argument_validation():
     assert "null" in qr.last_error()
     for s in (0, -1, -2, -3, -4, -5):
         assert L.qr_status_string(s)
+
+
+def test_gather_bench_argument_validation():
+    """The gather microbenchmark rejects bad lane counts, unknown flags and misaligned pointers."""
+    import paper_2602_04103_amd as qr
+    L = qr.lib()
+    f16, f8 = C.c_void_p(0x10000), C.c_void_p(0x10008)  # never dereferenced: validation fails first
+    ok = qr.QR_GATHER_NONTEMPORAL | qr.QR_GATHER_STREAM_IO
+    for lanes in (0, 3, 16):
+        assert L.qr_gather_lanes_bench_ex(f16, 4, f16, 1, lanes, 0, f16, None) == qr.QR_EINVAL
+    assert L.qr_gather_lanes_bench_ex(f16, 4, f16, 1, 2, ok + 4, f16, None) == qr.QR_EINVAL
+    assert L.qr_gather_lanes_bench_ex(f8, 4, f16, 1, 2, 0, f16, None) == qr.QR_EINVAL   # lines not 16-byte aligned
+    assert L.qr_gather_lanes_bench_ex(f16, 0, f16, 1, 2, 0, f16, None) == qr.QR_EINVAL  # no lines
+    assert L.qr_gather_lanes_bench_ex(f16, 4, None, 1, 2, 0, f16, None) == qr.QR_EINVAL
+    assert L.qr_gather_lanes_bench_ex(f16, 4, f16, 0, 2, ok, f16, None) == qr.QR_OK      # nothing to do
+    assert L.qr_gather_bench(f16, 4, f16, 1, 96, f16, None) == qr.QR_EINVAL
