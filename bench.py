@@ -326,6 +326,32 @@ def main():
         "traffic": traffic,
         "bytes_per_query": BYTES_PER_QUERY[dom],
     }
+    if roofline is not None:
+        # context for the fraction: the random-line gather rate over the dominant row's own structure
+        # allocation (same size, same pages), two lanes per line, with the non-temporal index and result
+        # streams of the rank kernels; the rate a rank kernel would reach if its one random line per
+        # query were its only cost (untimed region, after the steps)
+        lines_ptr, n_lines, _, _ = handle(dom).raw_layout()
+        draws = torch.randint(-2 ** 63, 2 ** 63 - 1, (BATCH,), dtype=torch.int64, device=dev)
+
+        def gather():
+            rc = qr.lib().qr_gather_lanes_bench_ex(lines_ptr, n_lines, draws.data_ptr(), BATCH, 2,
+                                                   qr.QR_GATHER_STREAM_IO, outs.data_ptr(), stream.cuda_stream)
+            if rc:
+                raise RuntimeError("qr_gather_lanes_bench_ex failed: %d" % rc)
+
+        t_gather = autotune.time_launch(gather, reps=7)
+        del draws
+        ceiling = BATCH / t_gather
+        roofline["line_gather_ceiling"] = {
+            "lines_per_s": round(ceiling, 1),
+            "queries_per_s": round(row_res[dom]["queries_per_s"], 1),
+            "frac": round(row_res[dom]["queries_per_s"] / ceiling, 4),
+            "what": "2^24 uniform random 128-byte lines of the same structure allocation, two lanes per "
+                    "line, non-temporal index and result streams (qr_gather_lanes_bench_ex)",
+        }
+        log("%s: %.2f G q/s against %.2f G random lines/s over the same allocation (%.1f%%)" % (
+            dom, row_res[dom]["queries_per_s"] / 1e9, ceiling / 1e9, 100 * row_res[dom]["queries_per_s"] / ceiling))
 
     # ------------------------------------------------------------------ the same steps from a HIP graph
     # the K timed steps (every row, every batch) captured once and replayed with one launch
