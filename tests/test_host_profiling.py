@@ -31,3 +31,19 @@ def test_kernel_matches():
     assert P.kernel_matches(br, "birank_rank_p0.5", "sweep", 32)
     assert not P.kernel_matches(br, "birank_rank_p0.5", "pair", 32)
     assert not P.kernel_matches(br, "quadrank_rank4", "sweep", 32)
+
+
+def test_traffic_records_match_the_current_sources():
+    """Every committed HBM-traffic record was taken from the kernel sources as they stand (else the
+    bench reports its traffic as null), and the measured bytes per query equal the algorithmic
+    ones within 1 %."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles", "hbm_traffic.json")
+    recs = json.load(open(path))["kernels"]
+    algorithmic = {"quadrank_rank": 145, "quadrank_rank4": 168, "birank_rank_p0.5": 144, "birank_rank_p0.05": 144}
+    assert set(k.split("|")[0] for k in recs) == set(algorithmic)
+    for key, r in recs.items():
+        assert r["source_hash"] == P.source_hash(r["sources"]), key
+        per_query = r["hbm_bytes_per_launch"] / (1 << 24)
+        assert abs(per_query / algorithmic[key.split("|")[0]] - 1) < 0.01, (key, per_query)
