@@ -159,10 +159,11 @@ int quadfm_index_host(const uint8_t *h_text, uint64_t n, uint32_t rate, uint64_t
                       uint64_t *h_mark_bits, uint32_t *h_samples);
 
 /* The same outputs built on the device (the input preparation that quadfm_index_host does on the
- * host): the suffix array of T$ by prefix doubling over a radix sort, then the packed BWT
+ * host): the suffix array of T$ by prefix doubling over a radix sort (each doubling step re-sorts
+ * only the suffixes whose groups are not yet single), then the packed BWT
  * (d_bwt_packed2, ceil((n+1)/32) words) with the row of '$' returned in *dollar_pos (host), and
  * with rate > 0 the mark bits (ceil((n+1)/64) words) and samples (floor(n/rate)+1 u32).  d_text
- * holds n codes 0..3 on the device.  Synchronous; allocates about 40 (n+1) bytes of temporaries.
+ * holds n codes 0..3 on the device.  Synchronous; allocates about 53 (n+1) bytes of temporaries.
  * QR_EINVAL on a code > 3, QR_ERANGE if n+1 exceeds 2^32 - 4097, QR_ENOMEM if the temporaries do
  * not fit.  Results are identical to quadfm_index_host's. */
 int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t rate, uint64_t *d_bwt_packed2, uint64_t *dollar_pos,

@@ -430,7 +430,7 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
         hipMalloc(&B.pos2, 4ull * N) != hipSuccess || hipMalloc(&B.act, 4ull * N) != hipSuccess ||
         hipMalloc(&B.at, 4ull * N) != hipSuccess) {
         (void)hipGetLastError();
-        set_error("quadfm_index_device: device allocation failed (about %llu bytes)", (unsigned long long)(60ull * N + 8 * nh));
+        set_error("quadfm_index_device: device allocation failed (about %llu bytes)", (unsigned long long)(52ull * N + 8 * nh));
         return QR_ENOMEM;
     }
     hipStream_t s = stream;
