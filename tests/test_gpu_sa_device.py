@@ -7,6 +7,8 @@ the host SA-IS output, and the count test at 2^28 bases builds its index this wa
 import numpy as np
 import pytest
 import torch
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 
 import datagen
 import oracle
@@ -139,3 +141,33 @@ def test_device_sa_rejects_bad_codes():
     t = torch.from_numpy(np.array([0, 1, 4, 2], np.uint8)).cuda()
     with pytest.raises(qr.QRError):
         qr.quadfm_index_device(t, 0)
+
+
+@settings(max_examples=30, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(st.integers(0, 6000), st.sampled_from(["random", "periodic", "repeats", "runs"]), st.integers(1, 60),
+       st.sampled_from([0, 1, 3, 32]), st.integers(0, 2 ** 31))
+def test_device_sa_random_structures(n, kind, period, rate, seed):
+    """Randomised texts (hypothesis, derandomised): uniform, periodic with a random period, random
+    segments copied with substitutions, and long single-symbol runs, so groups of suffixes finish
+    after any number of doubling steps."""
+    qr = require_gpu()
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        codes = rng.integers(0, 4, n, dtype=np.uint8)
+    elif kind == "periodic":
+        codes = np.tile(rng.integers(0, 4, period, dtype=np.uint8), n // period + 1)[:n].copy()
+    elif kind == "repeats":
+        codes = rng.integers(0, 4, n, dtype=np.uint8)
+        seg = rng.integers(0, 4, max(1, n // 8), dtype=np.uint8)
+        for _ in range(4):
+            at = int(rng.integers(0, max(1, n - seg.size + 1)))
+            copy = seg.copy()
+            flip = rng.random(seg.size) < 0.01
+            copy[flip] = (copy[flip] + 1) % 4
+            codes[at:at + seg.size] = copy[:max(0, min(seg.size, n - at))]
+    else:
+        codes = np.repeat(rng.integers(0, 4, max(1, n // max(1, period * 20) + 1), dtype=np.uint8),
+                          period * 20)[:n].copy()
+    announce("device-sa-random", n, kind, period, rate, seed)
+    check_against_oracle(qr, codes, rate)
