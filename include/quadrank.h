@@ -162,12 +162,14 @@ int quadfm_index_host(const uint8_t *h_text, uint64_t n, uint32_t rate, uint64_t
  * host): the suffix array of T$ by prefix doubling over a radix sort (each doubling step re-sorts
  * only the suffixes whose groups are not yet single), then the packed BWT
  * (d_bwt_packed2, ceil((n+1)/32) words) with the row of '$' returned in *dollar_pos (host), and
- * with rate > 0 the mark bits (ceil((n+1)/64) words) and samples (floor(n/rate)+1 u32).  d_text
- * holds n codes 0..3 on the device.  Synchronous; allocates about 53 (n+1) bytes of temporaries.
+ * with rate > 0 the mark bits (ceil((n+1)/64) words) and samples (floor(n/rate)+1 u32).  When d_sa is
+ * not NULL it receives the suffix array itself (n+1 u32 row values, 4-byte aligned), so that a
+ * caller can check the index input independently.  d_text holds n codes 0..3 on the device.
+ * Synchronous; allocates about 53 (n+1) bytes of temporaries.
  * QR_EINVAL on a code > 3, QR_ERANGE if n+1 exceeds 2^32 - 4097, QR_ENOMEM if the temporaries do
  * not fit.  Results are identical to quadfm_index_host's. */
 int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t rate, uint64_t *d_bwt_packed2, uint64_t *dollar_pos,
-                        uint64_t *d_mark_bits, uint32_t *d_samples, hipStream_t stream);
+                        uint64_t *d_mark_bits, uint32_t *d_samples, uint32_t *d_sa, hipStream_t stream);
 
 /* Build the index from the packed BWT (n_plus_1 symbols at d_bwt_packed2, '$' stored as A at row
  * dollar_pos).  Builds QuadRank over the BWT, the C array and the 8-mer interval table. */
@@ -183,7 +185,9 @@ int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t d
  * the size of its BWT interval (u32).  An empty pattern counts n+1; a pattern with a code > 3
  * counts 0 (it cannot occur in an ACGT text).  The offsets must not decrease: a pattern with
  * d_off[p+1] < d_off[p] is not read, counts 0 and sets the sticky error (QR_EINVAL from
- * quadfm_check).  Runs the persistent work-queue kernel: resident
+ * quadfm_check).  This form takes no length for d_pat: the caller guarantees that every offset
+ * lies within the bytes at d_pat (a NULL d_pat holds none, so only empty patterns are read);
+ * quadfm_count_ex takes the length and checks it.  Runs the persistent work-queue kernel: resident
  * wavefronts pull patterns from a device queue until it drains.  Calls on one handle must not
  * overlap in time (they share the queue head); use one handle per concurrent stream. */
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
@@ -198,22 +202,27 @@ int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, ui
 #define QUADFM_BOTH_STRANDS 1u /* count P and its reverse complement (A<->T, C<->G, reversed): the
                                   result is count(P) + count(rc(P)), saturating at 2^32-1; the empty
                                   pattern still counts n+1 */
-/* The general persistent count: flags as above; d_workspace is an 8-byte queue head as for
- * quadfm_count_ws, or NULL to use the handle's own (then calls must not overlap). */
-int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t flags,
-                    uint32_t *d_count, void *d_workspace, hipStream_t stream);
+/* The general persistent count: pat_bytes is the number of bytes at d_pat (d_pat may be NULL only
+ * with pat_bytes = 0, QR_EINVAL otherwise), and a pattern whose offsets run past it is treated like
+ * a decreasing offset pair: not read, counted 0, sticky error; flags as above; d_workspace is an
+ * 8-byte queue head as for quadfm_count_ws, or NULL to use the handle's own (then calls must not
+ * overlap). */
+int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                    uint32_t flags, uint32_t *d_count, void *d_workspace, hipStream_t stream);
 /* Same result with one plain launch per batch of `batch` patterns, one lane per pattern
  * (batch = 0: a single launch over all patterns).  The baseline for the work-queue kernel. */
 int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
                          uint32_t *d_count, hipStream_t stream);
-int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
-                            uint32_t flags, uint32_t *d_count, hipStream_t stream);
+/* quadfm_count_batched with the pattern buffer length checked as in quadfm_count_ex, and flags. */
+int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                            uint64_t batch, uint32_t flags, uint32_t *d_count, hipStream_t stream);
 /* The backward search of quadfm_count (persistent kernel), writing each pattern's final BWT interval
  * instead of its size: d_iv[2i] = sp, d_iv[2i+1] = ep (u32 pairs, 8-byte aligned), [0, 0) when the
- * pattern does not occur (or holds a code > 3); the empty pattern gives [0, n+1).  The paper's
- * batched query returns these intervals (Appendix D). */
-int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_iv,
-                     hipStream_t stream);
+ * pattern does not occur (or holds a code > 3); the empty pattern gives [0, n+1).  pat_bytes bounds
+ * the offsets as in quadfm_count_ex.  The paper's batched query returns these intervals
+ * (Appendix D). */
+int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                     uint32_t *d_iv, hipStream_t stream);
 
 /* Locate (the extension the paper's closing section proposes): the text position of every
  * occurrence, from a text-position sample of the suffix array (quadfm_index_host's mark bits and
@@ -232,7 +241,8 @@ int quadfm_locate_offsets(qr_quadfm h, const uint32_t *d_iv, uint64_t npat, uint
 int quadfm_locate(qr_quadfm h, const uint32_t *d_iv, const uint64_t *d_start, uint64_t npat, uint64_t total,
                   uint32_t *d_pos, hipStream_t stream);
 /* Synchronise `stream` (counts, intervals and positions are then final); report and clear the sticky
- * error: QR_EINVAL if a pattern's offsets decreased, QR_ERANGE if a locate walk failed. */
+ * error: QR_EINVAL if a pattern's offsets decreased or ran past the pattern buffer, QR_ERANGE if a
+ * locate walk failed. */
 int quadfm_check(qr_quadfm h, hipStream_t stream);
 int quadfm_free(qr_quadfm h);
 uint64_t quadfm_len(qr_quadfm h);   /* n (text length, without '$') */

@@ -13,6 +13,8 @@ Functions cite the passage they follow:
                paper's closing section for a bidirectional FM-index)
   count_*    — Appendix D: count-only exact search; naive, suffix-array and
                textbook backward-search statements of the same count
+  check_sa   — whether given row values are the suffix array of T$ (the order the suffix-array
+               count searches), by direct comparison of neighbouring suffixes
   locate_sa  — the positions of every occurrence in suffix-array order (the locate query the
                paper's closing section proposes for its FM-index)
 """
@@ -57,7 +59,8 @@ def _load():
         lib.or_rank4_dna.argtypes = [vp, u64, vp, u64, vp]
         lib.or_prefix_rank_dna.restype = i64
         lib.or_prefix_rank_dna.argtypes = [vp, u64, vp, vp, u64, vp]
-        lib.or_unpack2.argtypes = [vp, u64, vp]
+        lib.or_check_sa.restype = C.c_int
+        lib.or_check_sa.argtypes = [vp, u64, vp]
         lib.or_count_naive.argtypes = [vp, u64, vp, vp, u64, vp]
         lib.or_suffix_array.argtypes = [vp, u64, vp]
         lib.or_bwt.restype = u64
@@ -139,13 +142,6 @@ def prefix_rank_dna(packed: np.ndarray, n: int, q: np.ndarray, c: np.ndarray) ->
     return out[: q.size]
 
 
-def unpack2(packed: np.ndarray, n: int) -> np.ndarray:
-    out = np.empty(max(n, 1), dtype=np.uint8)
-    if n:
-        _load().or_unpack2(_p(_nonempty(packed, np.uint64)), n, _p(out))
-    return out[:n]
-
-
 def count_naive(text: np.ndarray, pat: np.ndarray, off: np.ndarray) -> np.ndarray:
     """Occurrences of each pattern (CSR: pat codes, off[npat+1]) in text, by direct comparison."""
     npat = off.size - 1
@@ -162,6 +158,20 @@ def suffix_array(text: np.ndarray) -> np.ndarray:
     sa = np.empty(n + 1, dtype=np.int64)
     _load().or_suffix_array(_p(_nonempty(text, np.uint8)), n, _p(sa))
     return sa
+
+
+def check_sa(text: np.ndarray, sa: np.ndarray) -> int:
+    """0 if sa (n+1 row values, any integer dtype) is the suffix array of text + '$': a permutation
+    of 0..n whose neighbouring rows hold strictly increasing suffixes by direct comparison ('$'
+    smallest); 1 if a value is out of range or repeated; 2 if a neighbouring pair is out of order."""
+    n = text.size
+    s = np.ascontiguousarray(sa, dtype=np.int64)
+    if s.size != n + 1:
+        return 1
+    rc = _load().or_check_sa(_p(_nonempty(text, np.uint8)), n, _p(s))
+    if rc < 0:
+        raise MemoryError("oracle check_sa")
+    return int(rc)
 
 
 def bwt(text: np.ndarray, sa: np.ndarray):

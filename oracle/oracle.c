@@ -172,10 +172,6 @@ int64_t or_prefix_rank_dna(const uint64_t *packed, uint64_t n, const uint64_t *q
 
 /* ---- FM-index count ------------------------------------------------------------------------------ */
 
-void or_unpack2(const uint64_t *packed, uint64_t n, uint8_t *codes) {
-    for (uint64_t i = 0; i < n; ++i) codes[i] = (uint8_t)base_at(packed, i);
-}
-
 /* count(P) = #{ i in [0, n-m] : T[i..i+m) = P } by direct comparison at every start.  A pattern
    code > 3 cannot match an ACGT text; m = 0 gives n+1 (every position 0..n, the FM full interval). */
 void or_count_naive(const uint8_t *text, uint64_t n, const uint8_t *pat, const uint64_t *off, uint64_t npat,
@@ -216,6 +212,39 @@ void or_suffix_array(const uint8_t *text, uint64_t n, int64_t *sa) {
     for (uint64_t i = 0; i <= n; ++i) sa[i] = (int64_t)i;
     const uint8_t *ctx[2] = {text, (const uint8_t *)(uintptr_t)n};
     qsort_r(sa, n + 1, sizeof(int64_t), cmp_suffix, (void *)ctx);
+}
+
+/* Check a suffix array of T$ given as n+1 row values, without building one: it must be a
+   permutation of 0..n, and each pair of neighbouring rows must hold two suffixes in strictly
+   increasing order, compared character by character with the end of the text ('$') smaller than
+   any character (the same order the comparison sort above uses).  Returns 0 if both hold, 1 if a
+   value is out of range or repeated (some row is then missing), 2 if a neighbouring pair is out of
+   order, -1 if memory runs out. */
+int or_check_sa(const uint8_t *text, uint64_t n, const int64_t *sa) {
+    uint64_t nw = (n + 1 + 63) / 64;
+    uint64_t *seen = (uint64_t *)calloc(nw, sizeof(uint64_t));
+    if (!seen) return -1;
+    int bad = 0;
+    for (uint64_t k = 0; k <= n && !bad; ++k) {
+        int64_t v = sa[k];
+        if (v < 0 || (uint64_t)v > n || (seen[(uint64_t)v / 64] >> ((uint64_t)v % 64) & 1)) bad = 1;
+        else seen[(uint64_t)v / 64] |= 1ULL << ((uint64_t)v % 64);
+    }
+    free(seen);
+    if (bad) return 1;
+    int disorder = 0;
+#pragma omp parallel for schedule(static) reduction(| : disorder)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+        uint64_t i = (uint64_t)sa[k], j = (uint64_t)sa[k + 1];
+        while (i < n && j < n && text[i] == text[j]) {
+            ++i;
+            ++j;
+        }
+        /* suffix i < suffix j iff i reached the end first, or both go on and T[i] < T[j] */
+        int less = (i == n && j < n) || (i < n && j < n && text[i] < text[j]);
+        disorder |= !less;
+    }
+    return disorder ? 2 : 0;
 }
 
 /* BWT[k] = T[SA[k]-1], or '$' (code 4 here) where SA[k] = 0.  Returns the row of '$'. */

@@ -22,7 +22,16 @@ LIB_PATH = os.path.join(_HERE, "libquadrank.so")
 QR_OK, QR_EINVAL, QR_ENOMEM, QR_EHIP, QR_ERANGE, QR_EDEVICE = 0, -1, -2, -3, -4, -5
 QUADFM_BOTH_STRANDS = 1
 QR_SERVE_CHECK_FREE_MEMORY = 1
-QR_LAYOUT_16, QR_LAYOUT_32 = 0, 1
+QR_LAYOUT_16, QR_LAYOUT_32, QR_LAYOUT_16P, QR_LAYOUT_64, QR_LAYOUT_16X2, QR_LAYOUT_24_8 = 0, 1, 2, 3, 4, 5
+LAYOUT_NAMES = {QR_LAYOUT_16: "16", QR_LAYOUT_32: "32", QR_LAYOUT_16P: "16p", QR_LAYOUT_64: "64",
+                QR_LAYOUT_16X2: "16x2", QR_LAYOUT_24_8: "24_8"}
+LAYOUT_BY_NAME = {v: k for k, v in LAYOUT_NAMES.items()}
+
+
+def _super_dtype(layout: int):
+    """Element type of a layout's offset array (exact u64 offsets, or shifted u32 ones)."""
+    import numpy as np
+    return np.uint64 if layout in (QR_LAYOUT_32, QR_LAYOUT_24_8) else np.uint32
 
 
 class QRError(RuntimeError):
@@ -95,8 +104,8 @@ def lib():
         optional = {
             "quadfm_bwt_host": (ci, [vp, u64, vp, C.POINTER(u64)]),
             "quadfm_index_host": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp]),
-            "quadfm_index_device": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp, vp]),
-            "quadfm_intervals": (ci, [vp, vp, vp, u64, vp, vp]),
+            "quadfm_index_device": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp, vp, vp]),
+            "quadfm_intervals": (ci, [vp, vp, u64, vp, u64, vp, vp]),
             "quadfm_build_ex": (ci, [vp, u64, u64, C.c_uint32, vp, C.POINTER(vp)]),
             "quadfm_locate_attach": (ci, [vp, vp, vp, u64, C.c_uint32, vp]),
             "quadfm_locate_offsets": (ci, [vp, vp, u64, vp, vp]),
@@ -105,8 +114,8 @@ def lib():
             "quadfm_count": (ci, [vp, vp, vp, u64, vp, vp]),
             "quadfm_count_batched": (ci, [vp, vp, vp, u64, u64, vp, vp]),
             "quadfm_count_ws": (ci, [vp, vp, vp, u64, vp, vp, vp]),
-            "quadfm_count_ex": (ci, [vp, vp, vp, u64, C.c_uint32, vp, vp, vp]),
-            "quadfm_count_batched_ex": (ci, [vp, vp, vp, u64, u64, C.c_uint32, vp, vp]),
+            "quadfm_count_ex": (ci, [vp, vp, u64, vp, u64, C.c_uint32, vp, vp, vp]),
+            "quadfm_count_batched_ex": (ci, [vp, vp, u64, vp, u64, u64, C.c_uint32, vp, vp]),
             "quadfm_check": (ci, [vp, vp]),
             "quadfm_free": (ci, [vp]),
             "quadfm_len": (u64, [vp]),
@@ -280,9 +289,10 @@ def quadfm_index_host(text_codes, rate: int):
     return out, int(d.value), marks, samples
 
 
-def quadfm_index_device(text: torch.Tensor, rate: int = 0, stream=None):
+def quadfm_index_device(text: torch.Tensor, rate: int = 0, stream=None, sa: torch.Tensor | None = None):
     """Device input preparation from n text codes on the device: (packed BWT, dollar row, mark bits,
-    samples) as device tensors (the last two None when rate == 0)."""
+    samples) as device tensors (the last two None when rate == 0).  With `sa` (n+1 int32 elements
+    on the device) the suffix array itself is written there as u32 row values."""
     n = text.numel()
     dev = text.device
     bwt = torch.empty(max(1, (n + 1 + 31) // 32), dtype=torch.int64, device=dev)
@@ -292,9 +302,10 @@ def quadfm_index_device(text: torch.Tensor, rate: int = 0, stream=None):
         marks = torch.empty(max(1, (n + 1 + 63) // 64), dtype=torch.int64, device=dev)
         samples = torch.empty(n // rate + 1, dtype=torch.int32, device=dev)
         mp, sp = _dev(marks, "marks", W64), _dev(samples, "samples", W32)
+    sap = _dev(sa, "sa", W32, n + 1) if sa is not None else None
     d = u64()
     _check(lib().quadfm_index_device(_dev(text, "text", W8) if n else None, n, rate, _dev(bwt, "bwt", W64), C.byref(d),
-                                     mp, sp, _stream(stream)), "quadfm_index_device")
+                                     mp, sp, sap, _stream(stream)), "quadfm_index_device")
     return bwt, int(d.value), marks, samples
 
 
@@ -305,50 +316,52 @@ def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stre
     return h.value
 
 
+def _pat(pat: torch.Tensor):
+    """(pointer, byte length) of a pattern buffer; the library checks every offset against the length."""
+    return _dev(pat, "pat", W8), pat.numel()
+
+
 def quadfm_count(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, stream=None):
-    npat = off.numel() - 1
-    _check(lib().quadfm_count(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, _dev(count, "count", W32, npat),
-                              _stream(stream)), "quadfm_count")
-    return count
+    """quadfm_count through its length-checked form (quadfm_count_ex with the handle's queue head)."""
+    return quadfm_count_ex(h, pat, off, count, 0, None, stream)
 
 
 def quadfm_count_ws(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, workspace: torch.Tensor,
                     stream=None):
-    npat = off.numel() - 1
-    _check(lib().quadfm_count_ws(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat,
-                                 _dev(count, "count", W32, npat), _dev(workspace, "workspace", W64, 1),
-                                 _stream(stream)), "quadfm_count_ws")
-    return count
+    """quadfm_count_ws through its length-checked form (quadfm_count_ex with a caller-owned head)."""
+    _dev(workspace, "workspace", W64, 1)
+    return quadfm_count_ex(h, pat, off, count, 0, workspace, stream)
 
 
 def quadfm_count_ex(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, flags: int = 0,
                     workspace: torch.Tensor | None = None, stream=None):
     npat = off.numel() - 1
     ws = _dev(workspace, "workspace", W64, 1) if workspace is not None else None
-    _check(lib().quadfm_count_ex(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, flags,
-                                 _dev(count, "count", W32, npat), ws, _stream(stream)), "quadfm_count_ex")
+    pp, pn = _pat(pat)
+    _check(lib().quadfm_count_ex(h, pp, pn, _dev(off, "off", W64), npat, flags, _dev(count, "count", W32, npat), ws,
+                                 _stream(stream)), "quadfm_count_ex")
     return count
 
 
 def quadfm_count_batched_ex(h: int, pat: torch.Tensor, off: torch.Tensor, batch: int, flags: int, count: torch.Tensor,
                             stream=None):
     npat = off.numel() - 1
-    _check(lib().quadfm_count_batched_ex(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, batch, flags,
+    pp, pn = _pat(pat)
+    _check(lib().quadfm_count_batched_ex(h, pp, pn, _dev(off, "off", W64), npat, batch, flags,
                                          _dev(count, "count", W32, npat), _stream(stream)), "quadfm_count_batched_ex")
     return count
 
 
 def quadfm_count_batched(h: int, pat: torch.Tensor, off: torch.Tensor, batch: int, count: torch.Tensor, stream=None):
-    npat = off.numel() - 1
-    _check(lib().quadfm_count_batched(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat, batch,
-                                      _dev(count, "count", W32, npat), _stream(stream)), "quadfm_count_batched")
-    return count
+    """quadfm_count_batched through its length-checked form (quadfm_count_batched_ex, no flags)."""
+    return quadfm_count_batched_ex(h, pat, off, batch, 0, count, stream)
 
 
 def quadfm_intervals(h: int, pat: torch.Tensor, off: torch.Tensor, iv: torch.Tensor, stream=None):
     npat = off.numel() - 1
-    _check(lib().quadfm_intervals(h, _dev(pat, "pat", W8), _dev(off, "off", W64), npat,
-                                  _dev(iv, "iv", W32, 2 * npat), _stream(stream)), "quadfm_intervals")
+    pp, pn = _pat(pat)
+    _check(lib().quadfm_intervals(h, pp, pn, _dev(off, "off", W64), npat, _dev(iv, "iv", W32, 2 * npat),
+                                  _stream(stream)), "quadfm_intervals")
     return iv
 
 
@@ -478,11 +491,12 @@ class BiRank(_Handle):
         return _layout(lib().birank_layout, self.h)
 
     def export(self):
-        """Host copies (numpy) of the raw layout: (lines u64[n_lines, 16], super u32[n_super])."""
+        """Host copies (numpy) of the raw layout: (lines u64[n_lines, 16], super[n_super] of the
+        layout's offset type)."""
         import numpy as np
         _, nl, _, ns = self.raw_layout()
         lines = np.empty((nl, 16), dtype=np.uint64)
-        sup = np.empty(ns, dtype=np.uint64 if self.layout == QR_LAYOUT_32 else np.uint32)
+        sup = np.empty(max(ns, 1), dtype=_super_dtype(self.layout))[:ns]
         _check(lib().birank_export(self.h, lines.ctypes.data, sup.ctypes.data), "birank_export")
         return lines, sup
 
@@ -532,7 +546,7 @@ class QuadRank(_Handle):
         import numpy as np
         _, nl, _, ns = self.raw_layout()
         lines = np.empty((nl, 16), dtype=np.uint64)
-        sup = np.empty((ns, 4), dtype=np.uint64 if self.layout == QR_LAYOUT_32 else np.uint32)
+        sup = np.empty((max(ns, 1), 4), dtype=_super_dtype(self.layout))[:ns]
         _check(lib().quadrank_export(self.h, lines.ctypes.data, sup.ctypes.data), "quadrank_export")
         return lines, sup
 

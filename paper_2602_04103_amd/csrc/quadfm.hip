@@ -71,8 +71,10 @@ struct FmDev {
     const uint2 *table;
     uint64_t n1, dollar;
     uint64_t C0, C1, C2, C3;
-    uint32_t *err;  // sticky error word: ERR_WALK (locate), ERR_OFFSETS (a decreasing offset pair)
-    uint32_t kmer;  // characters resolved by the start table
+    uint32_t *err;     // sticky error word: ERR_WALK (locate), ERR_OFFSETS (offsets that decrease or
+                       // run past the pattern buffer)
+    uint32_t kmer;     // characters resolved by the start table
+    uint64_t pat_len;  // bytes of the pattern buffer of this call: no pattern may end beyond it
 };
 
 constexpr uint32_t ERR_WALK = 1u, ERR_OFFSETS = 2u;
@@ -232,7 +234,7 @@ template <bool BOTH>
 __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restrict__ pat, const uint64_t *__restrict__ off,
                                         uint64_t p, Search &s, uint32_t &cnt) {
     const uint64_t o = off[p], e = off[p + 1];
-    if (e < o || e - o > 0xffffffffull) {  // not a pattern: nothing of it is read
+    if (e < o || e > f.pat_len || e - o > 0xffffffffull) {  // not a pattern: nothing of it is read
         atomicOr(f.err, ERR_OFFSETS);
         s.m = 0;
         cnt = 0;
@@ -515,20 +517,30 @@ FmDev dev_view(const qr_quadfm_s *h) {
     f.C0 = h->C[0], f.C1 = h->C[1], f.C2 = h->C[2], f.C3 = h->C[3];
     f.err = h->err;
     f.kmer = h->kmer;
+    f.pat_len = 0;
     return f;
 }
 
-int count_args(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
-               const char *what) {
+// Pattern buffer length for the calls without one: the caller vouches that the CSR lies inside
+// d_pat (unbounded), except that a NULL buffer holds no byte.
+uint64_t implied_len(const uint8_t *d_pat) { return d_pat ? ~0ull : 0ull; }
+
+int count_args(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+               uint32_t *d_count, const char *what) {
     if (!h || (npat && (!d_off || !d_count))) {
         set_error("%s: null handle or pointer", what);
+        return QR_EINVAL;
+    }
+    if (!d_pat && pat_bytes) {
+        set_error("%s: d_pat is NULL but pat_bytes = %llu", what, (unsigned long long)pat_bytes);
         return QR_EINVAL;
     }
     if (((uintptr_t)d_off & 7) || ((uintptr_t)d_count & 3)) {
         set_error("%s: d_off must be 8-byte and d_count 4-byte aligned", what);
         return QR_EINVAL;
     }
-    (void)d_pat;  // may be NULL when every pattern is empty
+    // d_pat may be NULL when every pattern is empty; the kernels treat any pattern ending beyond
+    // pat_bytes like a decreasing offset pair (counted 0, sticky error, nothing read)
     return check_device(h->device);
 }
 
@@ -623,8 +635,8 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
 }
 
 // flags: QUADFM_BOTH_STRANDS; iv: write intervals (uint2 per pattern) instead of counts
-static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
-                            unsigned long long *head, uint32_t flags, bool iv, hipStream_t stream) {
+static int count_persistent(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                            uint32_t *d_count, unsigned long long *head, uint32_t flags, bool iv, hipStream_t stream) {
     const int block = h->tune.block ? h->tune.block : 256;
     const uint32_t refill = h->tune.per_lane > 0 ? (uint32_t)h->tune.per_lane : 16u;
     const int wpc = h->tune.grid_waves > 0 ? h->tune.grid_waves : 16;
@@ -634,22 +646,24 @@ static int count_persistent(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d
     hipLaunchKernelGGL(fill_zero_u64, dim3(1), dim3(1), 0, stream, head);
     QR_HIP(hipGetLastError());
     const dim3 g((uint32_t)blocks), b(block);
+    FmDev f = dev_view(h);
+    f.pat_len = pat_bytes;
     if (iv)
-        hipLaunchKernelGGL((fm_persistent_kernel<false, true>), g, b, 0, stream, dev_view(h), d_pat, d_off, npat, d_count,
-                           head, refill);
+        hipLaunchKernelGGL((fm_persistent_kernel<false, true>), g, b, 0, stream, f, d_pat, d_off, npat, d_count, head,
+                           refill);
     else if (flags & QUADFM_BOTH_STRANDS)
-        hipLaunchKernelGGL((fm_persistent_kernel<true, false>), g, b, 0, stream, dev_view(h), d_pat, d_off, npat, d_count,
-                           head, refill);
+        hipLaunchKernelGGL((fm_persistent_kernel<true, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count, head,
+                           refill);
     else
-        hipLaunchKernelGGL((fm_persistent_kernel<false, false>), g, b, 0, stream, dev_view(h), d_pat, d_off, npat, d_count,
-                           head, refill);
+        hipLaunchKernelGGL((fm_persistent_kernel<false, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count, head,
+                           refill);
     QR_HIP(hipGetLastError());
     return QR_OK;
 }
 
-int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t flags,
-                    uint32_t *d_count, void *d_workspace, hipStream_t stream) {
-    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_ex");
+int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                    uint32_t flags, uint32_t *d_count, void *d_workspace, hipStream_t stream) {
+    int rc = count_args(h, d_pat, pat_bytes, d_off, npat, d_count, "quadfm_count_ex");
     if (rc) return rc;
     if (flags & ~QUADFM_BOTH_STRANDS) {
         set_error("quadfm_count_ex: unknown flag bits 0x%x", flags);
@@ -661,24 +675,24 @@ int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, ui
     }
     if (!npat) return QR_OK;
     unsigned long long *head = d_workspace ? reinterpret_cast<unsigned long long *>(d_workspace) : h->head;
-    return count_persistent(h, d_pat, d_off, npat, d_count, head, flags, false, stream);
+    return count_persistent(h, d_pat, pat_bytes, d_off, npat, d_count, head, flags, false, stream);
 }
 
-int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_iv,
-                     hipStream_t stream) {
-    int rc = count_args(h, d_pat, d_off, npat, d_iv, "quadfm_intervals");
+int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                     uint32_t *d_iv, hipStream_t stream) {
+    int rc = count_args(h, d_pat, pat_bytes, d_off, npat, d_iv, "quadfm_intervals");
     if (rc) return rc;
     if ((uintptr_t)d_iv & 7) {
         set_error("quadfm_intervals: d_iv must be 8-byte aligned");
         return QR_EINVAL;
     }
     if (!npat) return QR_OK;
-    return count_persistent(h, d_pat, d_off, npat, d_iv, h->head, 0u, true, stream);
+    return count_persistent(h, d_pat, pat_bytes, d_off, npat, d_iv, h->head, 0u, true, stream);
 }
 
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
                  hipStream_t stream) {
-    return quadfm_count_ex(h, d_pat, d_off, npat, 0u, d_count, nullptr, stream);
+    return quadfm_count_ex(h, d_pat, implied_len(d_pat), d_off, npat, 0u, d_count, nullptr, stream);
 }
 
 int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
@@ -687,19 +701,20 @@ int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, ui
         set_error("quadfm_count_ws: d_workspace is NULL");
         return QR_EINVAL;
     }
-    return quadfm_count_ex(h, d_pat, d_off, npat, 0u, d_count, d_workspace, stream);
+    return quadfm_count_ex(h, d_pat, implied_len(d_pat), d_off, npat, 0u, d_count, d_workspace, stream);
 }
 
-int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
-                            uint32_t flags, uint32_t *d_count, hipStream_t stream) {
-    int rc = count_args(h, d_pat, d_off, npat, d_count, "quadfm_count_batched");
+int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                            uint64_t batch, uint32_t flags, uint32_t *d_count, hipStream_t stream) {
+    int rc = count_args(h, d_pat, pat_bytes, d_off, npat, d_count, "quadfm_count_batched");
     if (rc) return rc;
     if (flags & ~QUADFM_BOTH_STRANDS) {
         set_error("quadfm_count_batched_ex: unknown flag bits 0x%x", flags);
         return QR_EINVAL;
     }
     if (!batch) batch = npat;
-    const FmDev f = dev_view(h);
+    FmDev f = dev_view(h);
+    f.pat_len = pat_bytes;
     for (uint64_t p0 = 0; p0 < npat; p0 += batch) {
         const uint64_t np = std::min(batch, npat - p0);
         const uint64_t blocks = (np + 255) / 256;
@@ -720,7 +735,7 @@ int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d
 
 int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
                          uint32_t *d_count, hipStream_t stream) {
-    return quadfm_count_batched_ex(h, d_pat, d_off, npat, batch, 0u, d_count, stream);
+    return quadfm_count_batched_ex(h, d_pat, implied_len(d_pat), d_off, npat, batch, 0u, d_count, stream);
 }
 
 int quadfm_check(qr_quadfm h, hipStream_t stream) {
@@ -732,7 +747,8 @@ int quadfm_check(qr_quadfm h, hipStream_t stream) {
     QR_HIP(hipMemcpy(&v, h->err, 4, hipMemcpyDeviceToHost));
     QR_HIP(hipMemset(h->err, 0, 4));
     if (v & ERR_OFFSETS) {
-        set_error("quadfm: a pattern's offsets decrease (d_off[p+1] < d_off[p]); it was counted as 0");
+        set_error("quadfm: a pattern's offsets decrease (d_off[p+1] < d_off[p]) or run past the pattern buffer; "
+                  "it was counted as 0");
         return QR_EINVAL;
     }
     if (v & ERR_WALK) {

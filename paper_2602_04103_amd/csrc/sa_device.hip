@@ -406,8 +406,9 @@ uint32_t bit_length(uint64_t x) {
 }  // namespace
 
 extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t rate, uint64_t *d_bwt_packed2,
-                                   uint64_t *dollar_pos, uint64_t *d_mark_bits, uint32_t *d_samples, hipStream_t stream) {
-    if ((!d_text && n) || !d_bwt_packed2 || !dollar_pos || ((uintptr_t)d_bwt_packed2 & 7) ||
+                                   uint64_t *dollar_pos, uint64_t *d_mark_bits, uint32_t *d_samples, uint32_t *d_sa,
+                                   hipStream_t stream) {
+    if ((!d_text && n) || !d_bwt_packed2 || !dollar_pos || ((uintptr_t)d_bwt_packed2 & 7) || ((uintptr_t)d_sa & 3) ||
         (rate && (!d_mark_bits || !d_samples || ((uintptr_t)d_mark_bits & 7) || ((uintptr_t)d_samples & 3)))) {
         set_error("quadfm_index_device: null or misaligned pointer");
         return QR_EINVAL;
@@ -478,6 +479,7 @@ extern "C" int quadfm_index_device(const uint8_t *d_text, uint64_t n, uint32_t r
     }
     unsigned long long dol = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&dol, d_dollar, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && d_sa) e = hipMemcpyAsync(d_sa, B.sa, 4ull * N, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && rate) {
         const uint64_t nwv = ((uint64_t)N + 63) / 64;
         hipLaunchKernelGGL(sample_marks, dim3(blocks_for(N, 256)), dim3(256), 0, s, B.sa, N, rate, d_mark_bits, B.hist);

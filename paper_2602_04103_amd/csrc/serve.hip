@@ -271,7 +271,7 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 err = QR_EHIP;
                 break;
             }
-            rc = quadfm_count_ws(s->fm, d_pat, d_off, npat, d_cnt, s->heads + k, st);
+            rc = quadfm_count_ex(s->fm, d_pat, chars, d_off, npat, 0u, d_cnt, s->heads + k, st);
             if (rc) {
                 err = rc;
                 break;

@@ -133,25 +133,38 @@ def test_fm_rejects_bad_dollar():
         qr.QuadFm(to_dev(bwt), 1001, 1001)
 
 
-def test_fm_config3_full_sampled():
+def test_fm_config3_full():
     """Text of 2^28 bases with 1000 planted 10-kb repeats x 20 copies; 10^7 patterns (lengths
-    20..250, 90% sampled with 1% substitutions, 10% iid).  All counts come from the persistent
-    kernel; 200 sampled patterns are recounted by the oracle's direct scan, and the per-batch
-    kernel must agree with the persistent one on every pattern.  Intervals and locate (SA sampled
-    at rate 32) are checked on the same index, whose input (suffix array, BWT, sample) is prepared
-    on the device."""
+    20..250, 90% sampled with 1% substitutions, 10% iid).  The index input (suffix array, BWT and
+    locate sample) is prepared on the device; its suffix array is handed out and checked by the
+    oracle directly (a permutation whose neighbouring suffixes increase).  Every one of the 10^7
+    persistent-kernel counts then equals the oracle's suffix-array binary search over the text, and
+    so does every per-batch count.  200 sampled patterns are also recounted by the oracle's direct
+    scan of the text.  Intervals and locate (SA sampled at rate 32) are checked on the same index."""
     qr = require_gpu()
     n = 1 << 28
     codes = datagen.dna_codes(2028, n)
     datagen.plant_repeats(2029, codes, nseg=1000, seglen=10_000, copies=20, sub=0.01)
     pat, off, kind = datagen.patterns(2030, codes, 10 ** 7)
     announce("fm-config3 build")
-    fm = qr.QuadFm.from_text(codes, locate_rate=32, device_sa=True)
+    d_sa = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    bwt, dollar, marks, samples = qr.quadfm_index_device(torch.from_numpy(codes).cuda(), 32, sa=d_sa)
+    fm = qr.QuadFm(bwt, n + 1, dollar)
+    fm.attach_locate(marks, samples, 32)
+    del bwt, marks, samples
+    sa = d_sa.cpu().numpy().view(np.uint32).astype(np.int64)
+    del d_sa
     announce("fm-config3 count")
     dp, do = to_dev(pat), to_dev(off)
     got = fm.count(dp, do).cpu().numpy().view(np.uint32)
     got_b = fm.count_batched(dp, do, 1 << 20).cpu().numpy().view(np.uint32)
-    assert np.array_equal(got, got_b)
+    fm.check()
+    announce("fm-config3 oracle: suffix-array check and 10^7 counts")
+    assert oracle.check_sa(codes, sa) == 0
+    want_all = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
+    assert np.array_equal(got, want_all)
+    assert np.array_equal(got_b, want_all)
+    assert sa[dollar] == 0                       # the '$' row of the BWT is the row of suffix 0
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(10 ** 7, 200, replace=False))
     sp = [pat[int(off[i]):int(off[i + 1])] for i in sample]
@@ -164,6 +177,9 @@ def test_fm_config3_full_sampled():
     iv_d = fm.intervals(dp, do)
     iv = iv_d.cpu().numpy().view(np.uint32).astype(np.int64)
     assert np.array_equal((iv[:, 1] - iv[:, 0]).astype(np.uint32), got)
+    lo, hi = oracle.interval_sa(codes, sa, pat[:int(off[100_000])], off[:100_001])
+    nz = hi > lo
+    assert np.array_equal(iv[:100_000][nz, 0], lo[nz].astype(np.int64))   # intervals are the SA ranges
     # output offsets over all 10^7 intervals (thousands of scan tiles) = running sum of the counts
     st = torch.empty(10 ** 7 + 1, dtype=torch.int64, device="cuda")
     qr.quadfm_locate_offsets(fm.h, iv_d, st)
@@ -172,13 +188,14 @@ def test_fm_config3_full_sampled():
     announce("fm-config3 locate")
     start, pos = fm.locate(to_dev(spat), to_dev(soff))
     start, pos = start.cpu().numpy(), pos.cpu().numpy().view(np.uint32).astype(np.int64)
+    w_start, w_pos = oracle.locate_sa(codes, sa, spat, soff)
+    assert np.array_equal(start.astype(np.uint64), w_start)
+    assert np.array_equal(pos.astype(np.uint64), w_pos)
     for k in range(len(sp)):
         ps = pos[start[k]:start[k + 1]]
         assert ps.size == want[k] and np.unique(ps).size == ps.size
         for x in ps:
             assert np.array_equal(codes[x:x + sp[k].size], sp[k])
-        sufs = [codes[x:x + 300].tobytes() for x in ps]          # 300 > pattern length: order by suffix
-        assert all(a <= b for a, b in zip(sufs, sufs[1:]))
 
 
 @pytest.mark.parametrize("n", [3, 5000, 200_000])
@@ -228,6 +245,73 @@ def test_fm_decreasing_offsets_count_zero_and_report():
             fm.check()
         assert ei.value.status == qr.QR_EINVAL
         fm.check()
+
+
+def test_fm_offsets_past_pattern_buffer():
+    """A pattern whose offsets run past the pattern buffer is not read: it counts 0 and the sticky
+    error reports it, in every count form; with an empty pattern buffer (a NULL pointer and length
+    0) only empty patterns are counted.  The length check happens before any pattern byte is
+    loaded, so no launch here reads outside its buffers."""
+    qr = require_gpu()
+    codes = make_text(9, 5000)
+    announce("fm-offsets-past-buffer")
+    fm = qr.QuadFm.from_text(codes)
+    pat = codes[200:230].copy()
+    off = np.array([0, 10, 20, 30, 31, 1 << 40], np.uint64)   # patterns 3 and 4 end beyond 30 bytes
+    good = oracle.count_naive(codes, pat, np.array([0, 10, 20, 30], np.uint64)).astype(np.uint32)
+    want = np.concatenate([good, [0, 0]]).astype(np.uint32)
+    dp, do = to_dev(pat), to_dev(off)
+    for kernel in ("persistent", "batched", "both", "intervals"):
+        if kernel == "persistent":
+            got = fm.count(dp, do).cpu().numpy().view(np.uint32)
+        elif kernel == "batched":
+            got = fm.count_batched(dp, do, 2).cpu().numpy().view(np.uint32)
+        elif kernel == "both":
+            got = fm.count(dp, do, both_strands=True).cpu().numpy().view(np.uint32)
+            w2 = oracle.count_both_strands(codes, oracle.suffix_array(codes), pat,
+                                           np.array([0, 10, 20, 30], np.uint64)).astype(np.uint32)
+            want = np.concatenate([w2, [0, 0]]).astype(np.uint32)
+        else:
+            iv = fm.intervals(dp, do).cpu().numpy().view(np.uint32)
+            got = (iv[:, 1] - iv[:, 0]).astype(np.uint32)
+            want = np.concatenate([good, [0, 0]]).astype(np.uint32)
+        assert np.array_equal(got, want), kernel
+        with pytest.raises(qr.QRError) as ei:
+            fm.check()
+        assert ei.value.status == qr.QR_EINVAL
+        fm.check()
+    # an empty pattern buffer: the binding passes a NULL pointer with length 0
+    empty = torch.empty(0, dtype=torch.uint8, device="cuda")
+    off2 = to_dev(np.array([0, 0, 4, 4], np.uint64))
+    got = fm.count(empty, off2).cpu().numpy().view(np.uint32)
+    assert got.tolist() == [codes.size + 1, 0, 0]   # [4, 4) lies past a buffer of 0 bytes as well
+    with pytest.raises(qr.QRError):
+        fm.check()
+    fm.check()
+
+
+def test_fm_plain_count_entry_point():
+    """quadfm_count and quadfm_count_batched as the C ABI declares them (no buffer length), called
+    directly: the same counts as the oracle on a well-formed CSR."""
+    qr = require_gpu()
+    import ctypes as C
+    codes = make_text(12, 30_000)
+    pat, off, _ = datagen.patterns(13, codes, 3000, minlen=1, maxlen=40, frac_sampled=0.8, sub=0.02)
+    announce("fm-plain-entry")
+    fm = qr.QuadFm.from_text(codes)
+    want = oracle.count_sa(codes, oracle.suffix_array(codes), pat, off).astype(np.uint32)
+    dp, do = to_dev(pat), to_dev(off)
+    out = torch.empty(off.size - 1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert qr.lib().quadfm_count(C.c_void_p(fm.h), C.c_void_p(dp.data_ptr()), C.c_void_p(do.data_ptr()),
+                                 C.c_uint64(off.size - 1), C.c_void_p(out.data_ptr()), C.c_void_p(s)) == 0
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want)
+    out.zero_()
+    assert qr.lib().quadfm_count_batched(C.c_void_p(fm.h), C.c_void_p(dp.data_ptr()), C.c_void_p(do.data_ptr()),
+                                         C.c_uint64(off.size - 1), C.c_uint64(500), C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(s)) == 0
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want)
+    fm.check()
 
 
 @pytest.mark.parametrize("kmer", [1, 5, 10, 12])

@@ -37,21 +37,26 @@ def oracle_outputs(codes, rate):
     return words, dollar, marks, samples
 
 
-def device_outputs(qr, codes, rate):
+def device_outputs(qr, codes, rate, with_sa=False):
     t = torch.from_numpy(np.ascontiguousarray(codes)).cuda()
-    bwt, dollar, marks, samples = qr.quadfm_index_device(t, rate)
+    sa = torch.empty(codes.size + 1, dtype=torch.int32, device="cuda") if with_sa else None
+    bwt, dollar, marks, samples = qr.quadfm_index_device(t, rate, sa=sa)
     out = [bwt.cpu().numpy().view(np.uint64), dollar]
     out += [marks.cpu().numpy().view(np.uint64), samples.cpu().numpy().view(np.uint32)] if rate else [None, None]
+    out.append(sa.cpu().numpy().view(np.uint32) if with_sa else None)
     return out
 
 
 def check_against_oracle(qr, codes, rate):
-    got = device_outputs(qr, codes, rate)
+    got = device_outputs(qr, codes, rate, with_sa=rate > 0)
     want = oracle_outputs(codes, rate)
     assert got[1] == want[1]
     assert np.array_equal(got[0], want[0])
     if rate:
         assert np.array_equal(got[2], want[2]) and np.array_equal(got[3], want[3])
+        # the suffix array handed out is the oracle's (and passes the oracle's direct check)
+        assert np.array_equal(got[4].astype(np.int64), oracle.suffix_array(codes))
+        assert oracle.check_sa(codes, got[4]) == 0
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 20, 21, 22, 31, 32, 33, 100, 1000, 4094, 4095, 4096, 4097, 8191,

@@ -1,9 +1,11 @@
 """Serving at full size: the 2^30-base index (uniform ACGT with 1000 planted 10-kb segments x20 at
 1 % substitutions), built on the device with the 12-character start table, served by the native
 loop in the launch configuration the benchmark times (4 slots, 256 MiB arena, batches of up to
-2^18 patterns, live free-memory check) at 10^7 patterns/s.  Every served count must equal one
-direct count of all patterns and each sampled request counted alone; sampled patterns are checked
-against the oracle's direct substring count, one by one."""
+2^18 patterns, live free-memory check) at 10^7 patterns/s.  The suffix array behind the index is
+handed out by the device input preparation and checked by the oracle directly; every served count
+then equals the oracle's suffix-array binary search over the text, one direct count of all
+patterns, and each sampled request counted alone; sampled patterns are also recounted by the
+oracle's direct scan of the text."""
 import numpy as np
 import pytest
 import torch
@@ -22,9 +24,12 @@ def test_native_serve_2e30_sampled():
     text = datagen.dna_codes(3030, n)
     datagen.plant_repeats(3031, text, nseg=1000, seglen=10_000, copies=20, sub=0.01)
     announce("serve-2^30 index")
-    bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0)
+    d_sa = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0, sa=d_sa)
     fm = qr.QuadFm(bwt, n + 1, dollar, kmer=12)
-    del bwt
+    sa = d_sa.cpu().numpy().view(np.uint32)
+    del bwt, d_sa
+    torch.cuda.empty_cache()
     fm.set_tuning(block=64, refill=32, waves_per_cu=8)
     w = make_workload(5003, text, 1e7, 0.02, max_requests=200_000)
     announce("serve-2^30 run", w.nreq, int(w.req_off[-1]))
@@ -45,6 +50,11 @@ def test_native_serve_2e30_sampled():
         off = (w.off[p0:p1 + 1] - w.off[p0]).astype(np.uint64)
         alone = fm.count(to_dev(pat), to_dev(off)).cpu().numpy().view(np.uint32)
         assert np.array_equal(served[p0:p1], alone)
+    announce("serve-2^30 oracle: suffix-array check and every served count")
+    sa = sa.astype(np.int64)
+    assert oracle.check_sa(text, sa) == 0
+    assert np.array_equal(served, oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
+    del sa
     # oracle on sampled patterns (direct substring counting over the whole text)
     idx = np.sort(rng.choice(npat, 32, replace=False))
     pats = [w.pat[int(w.off[i]):int(w.off[i + 1])] for i in idx]

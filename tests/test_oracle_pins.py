@@ -219,6 +219,51 @@ def test_suffix_array_and_bwt_bruteforce(seed):
     assert d == want.index(0)
 
 
+@pytest.mark.parametrize("text", ["", "A", "AA", "ACA", "GATT", "TTTTT", "ACGTA", "CACAC"])
+def test_check_sa_accepts_exactly_the_sorted_order(text):
+    """Over every permutation of the rows of a tiny T$, exactly one passes the checker: the order
+    of sorting the suffixes of the string directly ('$' < A < C < G < T in ASCII)."""
+    import itertools
+    codes = codes_of(text)
+    s = text + "$"
+    want = sorted(range(len(s)), key=lambda i: s[i:])
+    passing = [p for p in itertools.permutations(range(len(s))) if oracle.check_sa(codes, np.array(p)) == 0]
+    assert passing == [tuple(want)]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_check_sa_rejects_broken_arrays(seed):
+    n = [50, 301, 1000, 4096, 20_000][seed]
+    codes = datagen.dna_codes(900 + seed, n)
+    if seed % 2:
+        datagen.plant_repeats(950 + seed, codes, nseg=2, seglen=n // 10, copies=3, sub=0.01)
+        codes[: n // 4] = 3                       # a long run: neighbours share long prefixes
+    sa = oracle.suffix_array(codes)
+    assert oracle.check_sa(codes, sa) == 0
+    assert oracle.check_sa(codes, sa.astype(np.uint32)) == 0
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(0, n))
+    swapped = sa.copy()
+    swapped[[k, k + 1]] = swapped[[k + 1, k]]     # neighbouring rows exchanged
+    assert oracle.check_sa(codes, swapped) == 2
+    far = sa.copy()
+    j = int(rng.integers(k + 2, n + 1)) if k + 2 <= n else 0
+    far[[k, j]] = far[[j, k]]                       # two distant rows exchanged
+    assert oracle.check_sa(codes, far) == 2
+    dup = sa.copy()
+    dup[k] = dup[(k + 7) % (n + 1)]                 # a value twice, so a row is missing
+    assert oracle.check_sa(codes, dup) == 1
+    out = sa.copy()
+    out[k] = n + 1                                  # a value beyond the last row
+    assert oracle.check_sa(codes, out) == 1
+    assert oracle.check_sa(codes, sa[:-1]) == 1     # one row short
+    neg = sa.copy()
+    neg[k] = -1
+    assert oracle.check_sa(codes, neg) == 1
+    shifted = np.roll(sa, 1)                        # a permutation, but '$' no longer first
+    assert oracle.check_sa(codes, shifted) == 2
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_count_three_ways_vs_bruteforce(seed):
     n = 400 + 37 * seed
