@@ -12,7 +12,7 @@ device.  A request completes when the host observes its batch's completion event
 completion time minus arrival time.
 
 The scheduler is written against a small executor interface (`submit`, `poll`, `counts`), with the
-GPU executor below and a CPU stand-in for tests of the scheduling logic.  `NativeServer` runs the
+GPU executor below (the tests drive it with a CPU stand-in of their own).  `NativeServer` runs the
 same policy in the library's native loop (qr_server_*), which is what the benchmark measures.
 """
 from __future__ import annotations
@@ -20,7 +20,7 @@ from __future__ import annotations
 import bisect
 import dataclasses
 import time
-from typing import Callable, List, Optional
+from typing import Callable, Optional
 
 import numpy as np
 
@@ -156,33 +156,6 @@ class GpuExecutor:
 
     def sync(self):
         self.torch.cuda.synchronize()
-
-
-class FakeExecutor:
-    """CPU stand-in: counts with `count_fn(pat, off)` and completes a batch once `ready(slot)` says so
-    (tests use it to force out-of-order completion)."""
-
-    def __init__(self, workload: Workload, count_fn: Callable, ready: Optional[Callable] = None):
-        self.w, self.count_fn = workload, count_fn
-        self.ready = ready or (lambda slot: True)
-        self.cnt = np.zeros(int(workload.off.size - 1), dtype=np.uint32)
-        self.submitted: List[tuple] = []
-
-    def submit(self, slot: int, r0: int, r1: int, base: int):
-        w = self.w
-        p0, p1 = int(w.req_off[r0]), int(w.req_off[r1])
-        off = (w.off[p0:p1 + 1] - w.off[p0]).astype(np.uint64)
-        self.cnt[p0:p1] = self.count_fn(w.pat[int(w.off[p0]):int(w.off[p1])], off)
-        self.submitted.append((slot, r0, r1, base))
-
-    def poll(self, slot: int) -> bool:
-        return bool(self.ready(slot))
-
-    def counts(self, p0: int, p1: int) -> np.ndarray:
-        return self.cnt[p0:p1]
-
-    def sync(self):
-        pass
 
 
 # ------------------------------------------------------------------------------------------ native loop

@@ -140,7 +140,8 @@ def test_scheduler_serves_everything_within_limits(seed, slots, max_batch, budge
     """Arbitrary workloads, slot counts, batch caps and budgets (as small as a few requests): every
     request is served with the oracle's counts; in-flight batches never exceed the slots, reserved
     bytes never exceed the budget, nothing finishes before it arrives, and admission is FIFO."""
-    from paper_2602_04103_amd.serve import FakeExecutor, Server, make_workload
+    from paper_2602_04103_amd.serve import Server, make_workload
+    from tests.serve_fakes import FakeExecutor
     text = _serve_text()
     w = make_workload(seed, text, rate, duration_s=0.05, max_requests=30, max_size=48)
     one = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))

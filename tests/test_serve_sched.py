@@ -6,7 +6,8 @@ import pytest
 
 import datagen
 import oracle
-from paper_2602_04103_amd.serve import Arena, FakeExecutor, Server, Workload, make_workload
+from paper_2602_04103_amd.serve import Arena, Server, Workload, make_workload
+from tests.serve_fakes import FakeExecutor
 
 
 def small_workload(seed=1, nreq=40, n=5000, rate=2e5):
