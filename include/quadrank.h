@@ -70,9 +70,14 @@ const char *qr_last_error(void);
 /* Library version string. */
 const char *qr_version(void);
 
-/* Inline-delta width of a layout (the paper's 16-bit default and its 32-bit variant, Sections 3/4). */
-#define QR_LAYOUT_16 0 /* 16-bit deltas + a shifted 32-bit offset per small superblock (default) */
-#define QR_LAYOUT_32 1 /* 32-bit deltas + an exact 64-bit offset per ~4e9-position superblock */
+/* Line layouts (the paper's 16-bit structures and its variants, Sections 3 and 4 and the appendix on
+ * pairing superblocks); each is described with the build call of its structure. */
+#define QR_LAYOUT_16 0   /* 16-bit deltas + a shifted 32-bit offset per small superblock (default) */
+#define QR_LAYOUT_32 1   /* 32-bit deltas + an exact 64-bit offset per ~4e9-position superblock */
+#define QR_LAYOUT_16P 2  /* 16-bit deltas + paired superblocks: one shifted offset per two superblocks */
+#define QR_LAYOUT_64 3   /* a 64-bit absolute rank per line (per symbol for QuadRank): no offset array */
+#define QR_LAYOUT_16X2 4 /* BiRank only: two 16-bit deltas per line, a quarter line counted per query */
+#define QR_LAYOUT_24_8 5 /* QuadRank only: a 24-bit and two 8-bit deltas per symbol, 64 bases counted */
 
 /* ------------------------------------------------------------------------------------------------
  * BiRank (paper Section 3).  rank(q) = number of 1 bits among t_0 .. t_{q-1}.
@@ -84,11 +89,21 @@ typedef struct qr_birank_s *qr_birank;
 
 /* Build from n_bits bits at d_bits (ceil(n_bits/64) u64 words; may be NULL iff n_bits == 0). */
 int birank_build(const uint64_t *d_bits, uint64_t n_bits, hipStream_t stream, qr_birank *out);
-/* Same with a layout choice.  QR_LAYOUT_32 (the BiRank32 variant): each line holds a 32-bit delta
- * and 992 data bits, 2^22 lines share one exact u64 offset (3.23 % overhead instead of 1.64 %, and an
- * offset array small enough to stay in cache); n < 2^48. */
+/* Same with a layout choice (QR_EINVAL for QR_LAYOUT_24_8 or an unknown value):
+ *   QR_LAYOUT_32 (the BiRank32 variant): each line holds a 32-bit delta and 992 data bits, 2^22
+ *     lines share one exact u64 offset (3.23 % overhead instead of 1.64 %, and an offset array
+ *     small enough to stay in cache); n < 2^48.
+ *   QR_LAYOUT_16P (paired superblocks, the paper's appendix on pairing superblocks): the 16-bit
+ *     lines, with one shifted u32 offset per 128 lines taken at their middle (line 64), so half the
+ *     offsets of QR_LAYOUT_16; lines in the lower 64 store their delta plus 64*1008 - 496, which the
+ *     query removes; n < 2^42.
+ *   QR_LAYOUT_64 (the BiRank64 variant): the line's first 64 bits hold the absolute rank at its
+ *     middle and 960 data bits follow; no offset array (6.67 % overhead); n < 2^48.
+ *   QR_LAYOUT_16X2 (the BiRank16x2 variant): two 16-bit deltas per line, to line bits 256 and 768,
+ *     and 992 data bits; a query counts at most a quarter line from the nearer one; 64 lines share
+ *     a shifted u32 offset as in QR_LAYOUT_16; n < 2^42. */
 int birank_build_ex(const uint64_t *d_bits, uint64_t n_bits, int layout, hipStream_t stream, qr_birank *out);
-/* QR_LAYOUT_16 or QR_LAYOUT_32, or -1 for a NULL handle. */
+/* The layout the handle was built with, or -1 for a NULL handle. */
 int birank_layout_kind(qr_birank h);
 /* d_out[i] = rank(d_q[i]) for i < nq (u64 in, u64 out; d_q and d_out may alias). */
 int birank_rank(qr_birank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, hipStream_t stream);
@@ -99,8 +114,9 @@ int birank_free(qr_birank h);
 uint64_t birank_len(qr_birank h);
 uint64_t birank_bytes(qr_birank h);
 int birank_layout(qr_birank h, const void **d_lines, uint64_t *n_lines, const void **d_super, uint64_t *n_super);
-/* Copy the structure to host memory: n_lines*128 bytes to h_lines, and n_super offsets (u32 for
- * QR_LAYOUT_16, u64 for QR_LAYOUT_32) to h_super (synchronous; either pointer may be NULL). */
+/* Copy the structure to host memory: n_lines*128 bytes to h_lines, and n_super offsets (u64 for
+ * QR_LAYOUT_32, u32 for the other layouts; QR_LAYOUT_64 has none) to h_super (synchronous; either
+ * pointer may be NULL). */
 int birank_export(qr_birank h, void *h_lines, void *h_super);
 
 /* ------------------------------------------------------------------------------------------------
@@ -113,11 +129,24 @@ typedef struct qr_quadrank_s *qr_quadrank;
 
 /* Build from n bases, 2-bit packed at d_packed2 (ceil(n/32) u64 words; NULL iff n == 0). */
 int quadrank_build(const uint64_t *d_packed2, uint64_t n, hipStream_t stream, qr_quadrank *out);
-/* Same with a layout choice.  QR_LAYOUT_32 (the QuadRank32 variant): each line holds four 32-bit
- * deltas and 448 bases, 2^23 lines share four exact u64 offsets (14.3 % overhead instead of 6.7 %,
- * and an offset array small enough to stay in cache); n < 2^48. */
+/* Same with a layout choice (QR_EINVAL for QR_LAYOUT_16X2 or an unknown value):
+ *   QR_LAYOUT_32 (the QuadRank32 variant): each line holds four 32-bit deltas and 448 bases, 2^23
+ *     lines share four exact u64 offsets (14.3 % overhead instead of 6.7 %, and an offset array
+ *     small enough to stay in cache); n < 2^48.
+ *   QR_LAYOUT_16P (paired superblocks, the paper's appendix on pairing superblocks): the 16-bit
+ *     lines, with one row of four shifted u32 offsets per 256 lines taken at their middle (line
+ *     128), half the offsets of QR_LAYOUT_16; lines in the lower 128 store their deltas plus
+ *     128*480 - 224, which the query removes; n < 2^44.
+ *   QR_LAYOUT_64 (the QuadRank64 variant): u64 words 0..3 of each line hold the absolute ranks of
+ *     A, C, G, T at its middle (base 128 of the line) and 384 bases follow; no offset array (33 %
+ *     overhead); n < 2^48.
+ *   QR_LAYOUT_24_8 (the QuadRank24_8 variant on 128-byte lines): 384 bases per line with three
+ *     anchors (bases 64, 192, 320 of the line): per symbol a 24-bit delta to the first (u32 word c,
+ *     bits 0..23) and 8-bit deltas from the first to the second (bits 24..31) and from the second
+ *     to the third (u32 word 4 + c); 2^15 lines share four exact u64 offsets; a query counts at most
+ *     64 bases; n < 2^48. */
 int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStream_t stream, qr_quadrank *out);
-/* QR_LAYOUT_16 or QR_LAYOUT_32, or -1 for a NULL handle. */
+/* The layout the handle was built with, or -1 for a NULL handle. */
 int quadrank_layout_kind(qr_quadrank h);
 /* d_out[i] = rank(d_q[i], d_c[i]). */
 int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
@@ -135,8 +164,9 @@ uint64_t quadrank_len(qr_quadrank h);
 uint64_t quadrank_bytes(qr_quadrank h);
 int quadrank_layout(qr_quadrank h, const void **d_lines, uint64_t *n_lines, const void **d_super,
                     uint64_t *n_super);
-/* Copy the structure to host memory: n_lines*128 bytes, and n_super rows of four offsets (u32 for
- * QR_LAYOUT_16, u64 for QR_LAYOUT_32) (synchronous; either pointer may be NULL). */
+/* Copy the structure to host memory: n_lines*128 bytes, and n_super rows of four offsets (u64 for
+ * QR_LAYOUT_32 and QR_LAYOUT_24_8, u32 for the other layouts; QR_LAYOUT_64 has none) (synchronous;
+ * either pointer may be NULL). */
 int quadrank_export(qr_quadrank h, void *h_lines, void *h_super);
 
 /* ------------------------------------------------------------------------------------------------

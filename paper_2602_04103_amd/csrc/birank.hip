@@ -12,6 +12,10 @@
 //     line j: bits [0,32) b_j, bits [32,1024) input bits [992 j, 992 j + 992)
 //     b_j = rank(992 j + 480) - s_{j/2^22};  s_i = rank(992 * 2^22 * i) (u64, exact)
 //     bounds: b_j <= (2^22 - 1)*992 + 480 < 2^32; the offset array has one entry per 4.16e9 bits
+//   BR16P (BR16 with paired superblocks: one offset per 128 lines, at the pair's middle)
+//   BR64 (the paper's BiRank64: an absolute 64-bit rank per line, no offset array)
+//   BR16X2 (the paper's BiRank16x2: deltas to line bits 256 and 768, a quarter line counted)
+//     the last three are defined, with their bounds, beside their layout traits (birank_dev.hpp)
 //
 // floor(n/B) + 1 lines, so q = n always has a line; bits past n are stored as zero and every
 // delta is taken over that zero-padded text.
@@ -19,6 +23,7 @@
 // Query: j = floor(q/B), p = q - B j + HDR (line bit of q);
 //   rank(q) = offset_j + b_j + popcount(line bits [512, p))   if p >= 512
 //   rank(q) = offset_j + b_j - popcount(line bits [p, 512))   if p <  512
+// (BR16X2 counts between p and its anchor, line bit 256 or 768, with that anchor's delta.)
 #include <algorithm>
 #include <new>
 
@@ -36,10 +41,10 @@ constexpr uint32_t GROUP_LINES = 64;  // lines per build workgroup (BR16: one su
 
 struct qr_birank_s {
     int device;
-    int layout;  // QR_LAYOUT_16 or QR_LAYOUT_32
+    int layout;  // QR_LAYOUT_16, _32, _16P, _64 or _16X2
     uint64_t n, n_lines, n_sb;
     uint64_t *lines;  // n_lines * 16 words
-    void *super;      // n_sb entries of u32 (16-bit layout) or u64 (32-bit layout)
+    void *super;      // n_sb offsets (u32 for the 16-bit layouts, u64 for the 32-bit one; none for BR64)
     uint32_t *err;    // sticky device error word
     qr_tuning tune;
 };
@@ -94,15 +99,28 @@ __global__ void br32_super_kernel(const uint64_t *__restrict__ base, uint64_t n_
     if (i < n_sb) super[i] = base[std::min(i * GPS, n_groups - 1)];
 }
 
+// Offsets of paired superblocks: s'_i = the rank at the start of group 2i + 1 (the pair's middle),
+// shifted.  A last pair without its upper group takes the rank after its lower group, whose count
+// covers all 64 of its (zero-padded) lines.
+__global__ void br_paired_super_kernel(const uint64_t *__restrict__ base, const uint32_t *__restrict__ cnt,
+                                       uint64_t n_groups, uint64_t n_sb, uint32_t shift, uint32_t *__restrict__ super) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_sb) return;
+    const uint64_t g = 2 * i + 1;
+    const uint64_t r = g < n_groups ? base[g] : base[g - 1] + cnt[g - 1];
+    super[i] = (uint32_t)(r >> shift);
+}
+
 // Pass 3: one 64-lane workgroup per group of 64 lines; lane t forms line 64 g + t.
 constexpr int OUT_STRIDE = 17;  // padded LDS row (u64) for the staged lines: avoids bank conflicts
 
 template <class L>
 __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict__ bits, uint64_t n, uint64_t n_words,
-                                                      const uint64_t *__restrict__ base, uint64_t n_lines,
+                                                      const uint64_t *__restrict__ base,
+                                                      const uint32_t *__restrict__ paired_super, uint64_t n_lines,
                                                       uint64_t *__restrict__ lines) {
     constexpr uint32_t W = GROUP_LINES * L::DATA / 64;
-    constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
+    constexpr uint64_t GPS = L::SB_LINES >= GROUP_LINES ? L::SB_LINES / GROUP_LINES : 1;  // groups per superblock
     // one LDS buffer holds the group's input words, then (after a barrier) the staged output lines
     constexpr uint32_t BUF = (W + 2 > 64 * OUT_STRIDE) ? W + 2 : 64 * OUT_STRIDE;
     __shared__ __align__(16) uint64_t buf[BUF];
@@ -127,21 +145,36 @@ __global__ __launch_bounds__(64) void br_write_kernel(const uint64_t *__restrict
     };
     const uint32_t b0 = L::DATA * (uint32_t)t;
     uint64_t o[16];
-    o[0] = get64(b0) << L::HDR;
+    o[0] = L::HDR < 64 ? get64(b0) << (L::HDR & 63u) : 0ull;  // the header bits stay zero for now
 #pragma unroll
     for (int k = 1; k < 16; ++k) o[k] = get64(b0 + 64u * k - L::HDR);
-    uint32_t c_first = 0, c_second = 0;
+    // ones before each anchor of the line: line bit 512 (middle), or 256 and 768 (quarter anchors)
+    uint32_t c_q1 = 0, c_q2 = 0, c_q3 = 0, c_q4 = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) c_first += __popcll(o[k]);
+    for (int k = 0; k < 4; ++k) c_q1 += __popcll(o[k]);
 #pragma unroll
-    for (int k = 8; k < 16; ++k) c_second += __popcll(o[k]);
-    const uint32_t c_tot = c_first + c_second;
+    for (int k = 4; k < 8; ++k) c_q2 += __popcll(o[k]);
+#pragma unroll
+    for (int k = 8; k < 12; ++k) c_q3 += __popcll(o[k]);
+#pragma unroll
+    for (int k = 12; k < 16; ++k) c_q4 += __popcll(o[k]);
+    const uint32_t c_tot = c_q1 + c_q2 + c_q3 + c_q4;
     const uint32_t before = wave_inclusive_scan<uint32_t>(c_tot) - c_tot;
+    const uint64_t start = base[g] + before;  // rank at the line's first data bit
     // offset of this line's superblock as the query reconstructs it
-    const uint64_t sb_base = base[(g / GPS) * GPS];
-    const uint64_t off = (sb_base >> L::SHIFT) << L::SHIFT;
-    const uint64_t delta = base[g] - off + before + c_first;
-    o[0] |= delta;
+    uint64_t off = 0;
+    if constexpr (L::ID == QR_LAYOUT_16P) {
+        off = ((uint64_t)paired_super[g >> 1] << L::SHIFT) - ((g & 1) ? 0ull : L::BIAS);
+    } else if constexpr (L::SB_LINES != 0) {
+        const uint64_t sb_base = base[(g / GPS) * GPS];
+        off = (sb_base >> L::SHIFT) << L::SHIFT;
+    }
+    if constexpr (L::QUARTER) {
+        const uint64_t d0 = start + c_q1 - off, d1 = start + c_q1 + c_q2 + c_q3 - off;
+        o[0] |= d0 | (d1 << 16);
+    } else {
+        o[0] |= start + c_q1 + c_q2 - off;  // fills the HDR header bits (all 64 of them for BR64)
+    }
     __syncthreads();  // every lane has read its input words: the buffer now takes the output
 #pragma unroll
     for (int k = 0; k < 16; ++k) stage[t * OUT_STRIDE + k] = o[k];
@@ -167,7 +200,8 @@ __global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nq; i0 += stride * PER_LANE) {
         uint64_t q[PER_LANE], off[PER_LANE];
-        uint32_t p[PER_LANE], hdr[PER_LANE];
+        uint32_t p[PER_LANE];
+        uint2 hdr[PER_LANE];
         uint32_t h[PER_LANE][16];
         bool bad[PER_LANE];
 #pragma unroll
@@ -187,16 +221,18 @@ __global__ __launch_bounds__(256) void br_rank_kernel(const uint4 *__restrict__ 
             h[u][4] = b.x, h[u][5] = b.y, h[u][6] = b.z, h[u][7] = b.w;
             h[u][8] = c.x, h[u][9] = c.y, h[u][10] = c.z, h[u][11] = c.w;
             h[u][12] = d.x, h[u][13] = d.y, h[u][14] = d.z, h[u][15] = d.w;
-            hdr[u] = up ? reinterpret_cast<const uint32_t *>(lines)[j * 32] : a.x;
+            hdr[u] = up ? reinterpret_cast<const uint2 *>(lines)[j * 16] : make_uint2(a.x, a.y);
             off[u] = L::offset(super, j);
         }
         uint64_t r[PER_LANE];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const bool up = p[u] >= L::MID;
-            const uint32_t cnt = half_count(h[u], up ? p[u] - L::MID : p[u], up);
-            const uint64_t mid = off[u] + L::delta(hdr[u]);
-            r[u] = bad[u] ? ~0ull : (up ? mid + cnt : mid - cnt);
+            bool fwd;
+            const uint32_t cnt = br_count<L>(h[u], up ? p[u] - L::MID : p[u], up, fwd);
+            const uint64_t j = line_of<L>(q[u]);
+            const uint64_t anchor = off[u] + L::delta(hdr[u].x, hdr[u].y, up, j);
+            r[u] = bad[u] ? ~0ull : (fwd ? anchor + cnt : anchor - cnt);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
@@ -220,7 +256,7 @@ __device__ __forceinline__ void br_pair_compute(const uint4 *__restrict__ lines,
                                                 const typename L::Super *__restrict__ super, uint64_t n,
                                                 const uint64_t (&q)[PER_PAIR], uint32_t hf, uint64_t (&r)[PER_PAIR],
                                                 bool (&bad)[PER_PAIR]) {
-    uint64_t off[PER_PAIR];
+    uint64_t off[PER_PAIR], jj[PER_PAIR];
     uint32_t p[PER_PAIR];
     uint32_t h[PER_PAIR][16];
     // this lane's half line and the superblock offset
@@ -237,13 +273,17 @@ __device__ __forceinline__ void br_pair_compute(const uint4 *__restrict__ lines,
         h[u][8] = c.x, h[u][9] = c.y, h[u][10] = c.z, h[u][11] = c.w;
         h[u][12] = d.x, h[u][13] = d.y, h[u][14] = d.z, h[u][15] = d.w;
         off[u] = L::offset(super, j);
+        jj[u] = j;
     }
-    // count and combine across the pair
+    // count and combine across the pair: the lane holding q's half adds or subtracts its count,
+    // lane 0 (which holds the header) adds the anchor's rank
 #pragma unroll
     for (int u = 0; u < PER_PAIR; ++u) {
         const bool up = p[u] >= L::MID;
-        const uint32_t cnt = half_count(h[u], up ? p[u] - L::MID : p[u], up) & (((uint32_t)up == hf) ? ~0u : 0u);
-        const uint64_t mine = hf == 0 ? off[u] + L::delta(h[u][0]) - cnt : (uint64_t)cnt;
+        bool fwd;
+        const uint32_t cnt = br_count<L>(h[u], up ? p[u] - L::MID : p[u], up, fwd) & (((uint32_t)up == hf) ? ~0u : 0u);
+        uint64_t mine = fwd ? (uint64_t)cnt : 0ull - (uint64_t)cnt;
+        if (hf == 0) mine += off[u] + L::delta(h[u][0], h[u][1], up, jj[u]);
         r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
     }
 }
@@ -361,20 +401,58 @@ hipError_t build_t(qr_birank_s *h, const uint64_t *d_bits, uint32_t *cnt, uint64
                        dim3(64 * COUNT_GROUPS), 0, stream, d_bits, h->n, n_words, n_groups, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (L::SHIFT) {  // 16-bit layout: a group is a superblock, the scan writes the shifted offsets
+    if constexpr (L::SHIFT != 0 && L::SB_LINES == GROUP_LINES) {
+        // a group is a superblock: the scan writes the shifted offsets
         e = launch_scan_counts(cnt, n_groups, 1, L::SHIFT, base, reinterpret_cast<uint32_t *>(h->super), stream);
-    } else {  // 32-bit layout: scan into base, then pick one exact offset per superblock
+    } else {  // scan into base, then the offsets of the layout (none for BR64)
         e = launch_scan_counts(cnt, n_groups, 1, 0, base, nullptr, stream);
-        if (e == hipSuccess) {
+        if (e == hipSuccess && L::ID == QR_LAYOUT_32) {
             hipLaunchKernelGGL(br32_super_kernel, dim3((uint32_t)((h->n_sb + 255) / 256)), dim3(256), 0, stream, base,
                                n_groups, h->n_sb, reinterpret_cast<uint64_t *>(h->super));
+            e = hipGetLastError();
+        } else if (e == hipSuccess && L::ID == QR_LAYOUT_16P) {
+            hipLaunchKernelGGL(br_paired_super_kernel, dim3((uint32_t)((h->n_sb + 255) / 256)), dim3(256), 0, stream, base,
+                               cnt, n_groups, h->n_sb, L::SHIFT, reinterpret_cast<uint32_t *>(h->super));
             e = hipGetLastError();
         }
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(br_write_kernel<L>, dim3((uint32_t)n_groups), dim3(64), 0, stream, d_bits, h->n, n_words, base,
-                       h->n_lines, h->lines);
+                       reinterpret_cast<const uint32_t *>(h->super), h->n_lines, h->lines);
     return hipGetLastError();
+}
+
+// Geometry of each layout as the host needs it.
+struct BrGeom {
+    uint64_t data, sb_lines, max_n, super_elem;  // super_elem: bytes per offset (0: no offset array)
+};
+
+bool br_geom(int layout, BrGeom &g) {
+    switch (layout) {
+        case QR_LAYOUT_16: g = {BR16::DATA, BR16::SB_LINES, BR16::MAX_N, 4}; return true;
+        case QR_LAYOUT_32: g = {BR32::DATA, BR32::SB_LINES, BR32::MAX_N, 8}; return true;
+        case QR_LAYOUT_16P: g = {BR16P::DATA, BR16P::SB_LINES, BR16P::MAX_N, 4}; return true;
+        case QR_LAYOUT_64: g = {BR64::DATA, BR64::SB_LINES, BR64::MAX_N, 0}; return true;
+        case QR_LAYOUT_16X2: g = {BR16X2::DATA, BR16X2::SB_LINES, BR16X2::MAX_N, 4}; return true;
+        default: return false;
+    }
+}
+
+// f(L{}) for the layout's trait type.
+template <class F>
+hipError_t br_dispatch(int layout, F &&f) {
+    switch (layout) {
+        case QR_LAYOUT_32: return f(BR32{});
+        case QR_LAYOUT_16P: return f(BR16P{});
+        case QR_LAYOUT_64: return f(BR64{});
+        case QR_LAYOUT_16X2: return f(BR16X2{});
+        default: return f(BR16{});
+    }
+}
+
+uint64_t super_bytes_of(const qr_birank_s *h) {
+    BrGeom g{};
+    return br_geom(h->layout, g) ? h->n_sb * g.super_elem : 0;
 }
 
 void release(qr_birank_s *h) {
@@ -399,12 +477,12 @@ int birank_build_ex(const uint64_t *d_bits, uint64_t n, int layout, hipStream_t 
         set_error("birank_build: d_bits is NULL (with n = %llu) or not 8-byte aligned", (unsigned long long)n);
         return QR_EINVAL;
     }
-    if (layout != QR_LAYOUT_16 && layout != QR_LAYOUT_32) {
+    BrGeom geo{};
+    if (!br_geom(layout, geo)) {
         set_error("birank_build: unknown layout %d", layout);
         return QR_EINVAL;
     }
-    const bool l32 = layout == QR_LAYOUT_32;
-    const uint64_t max_n = l32 ? BR32::MAX_N : BR16::MAX_N;
+    const uint64_t max_n = geo.max_n;
     if (n > max_n) {
         set_error("birank_build: n = %llu exceeds the layout limit %llu", (unsigned long long)n,
                   (unsigned long long)max_n);
@@ -417,12 +495,10 @@ int birank_build_ex(const uint64_t *d_bits, uint64_t n, int layout, hipStream_t 
         set_error("hipGetDevice failed");
         return QR_EHIP;
     }
-    const uint64_t data = l32 ? BR32::DATA : BR16::DATA;
-    const uint64_t sb_lines = l32 ? BR32::SB_LINES : BR16::SB_LINES;
     h->layout = layout;
     h->n = n;
-    h->n_lines = n / data + 1;
-    h->n_sb = (h->n_lines - 1) / sb_lines + 1;
+    h->n_lines = n / geo.data + 1;
+    h->n_sb = geo.sb_lines ? (h->n_lines - 1) / geo.sb_lines + 1 : 0;
     h->tune = qr_tuning{256, 1, 0, 2, 0};
     const uint64_t n_groups = (h->n_lines - 1) / GROUP_LINES + 1;
     uint32_t *cnt = nullptr;
@@ -433,8 +509,9 @@ int birank_build_ex(const uint64_t *d_bits, uint64_t n, int layout, hipStream_t 
         release(h);
         return code;
     };
-    const size_t super_bytes = h->n_sb * (l32 ? 8 : 4);
-    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, super_bytes) != hipSuccess ||
+    const size_t super_bytes = h->n_sb * geo.super_elem;
+    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess ||
+        (super_bytes && hipMalloc(&h->super, super_bytes) != hipSuccess) ||
         hipMalloc(&h->err, 4) != hipSuccess || hipMalloc(&cnt, n_groups * 4) != hipSuccess ||
         hipMalloc(&base, n_groups * 8) != hipSuccess) {
         (void)hipGetLastError();
@@ -443,8 +520,7 @@ int birank_build_ex(const uint64_t *d_bits, uint64_t n, int layout, hipStream_t 
         return fail(QR_ENOMEM);
     }
     if (hipMemsetAsync(h->err, 0, 4, stream) != hipSuccess) return fail(QR_EHIP);
-    hipError_t e = l32 ? build_t<BR32>(h, d_bits, cnt, base, n_groups, stream)
-                       : build_t<BR16>(h, d_bits, cnt, base, n_groups, stream);
+    hipError_t e = br_dispatch(layout, [&](auto tag) { return build_t<decltype(tag)>(h, d_bits, cnt, base, n_groups, stream); });
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         set_error("birank_build: %s", hipGetErrorString(e));
@@ -472,8 +548,8 @@ int birank_rank(qr_birank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out, 
     int rc = check_device(h->device);
     if (rc) return rc;
     if (!nq) return QR_OK;
-    const hipError_t e = h->layout == QR_LAYOUT_32 ? launch_rank<BR32>(h, d_q, nq, d_out, stream)
-                                                   : launch_rank<BR16>(h, d_q, nq, d_out, stream);
+    const hipError_t e =
+        br_dispatch(h->layout, [&](auto tag) { return launch_rank<decltype(tag)>(h, d_q, nq, d_out, stream); });
     if (e != hipSuccess) {
         set_error("birank_rank launch: %s", hipGetErrorString(e));
         return QR_EHIP;
@@ -504,7 +580,7 @@ int birank_free(qr_birank h) {
 
 uint64_t birank_len(qr_birank h) { return h ? h->n : 0; }
 uint64_t birank_bytes(qr_birank h) {
-    return h ? h->n_lines * 128 + h->n_sb * (h->layout == QR_LAYOUT_32 ? 8 : 4) : 0;
+    return h ? h->n_lines * 128 + super_bytes_of(h) : 0;
 }
 int birank_layout_kind(qr_birank h) { return h ? h->layout : -1; }
 
@@ -522,8 +598,7 @@ int birank_export(qr_birank h, void *h_lines, void *h_super) {
     int rc = check_device(h->device);
     if (rc) return rc;
     if (h_lines) QR_HIP(hipMemcpy(h_lines, h->lines, h->n_lines * 128, hipMemcpyDeviceToHost));
-    if (h_super)
-        QR_HIP(hipMemcpy(h_super, h->super, h->n_sb * (h->layout == QR_LAYOUT_32 ? 8 : 4), hipMemcpyDeviceToHost));
+    if (h_super && super_bytes_of(h)) QR_HIP(hipMemcpy(h_super, h->super, super_bytes_of(h), hipMemcpyDeviceToHost));
     return QR_OK;
 }
 

@@ -15,6 +15,10 @@
 //   QR32 (a 32-bit inline variant): HDR = 64 slots, lo_0 = b_A | b_C << 32, hi_0 = b_G | b_T << 32;
 //     DATA = 448; middle = base 192; b_{j,c} = rank(448 j + 192, c) - s_{j/2^23, c} (s exact, u64)
 //     bounds: b <= (2^23 - 1)*448 + 192 < 2^32
+//   QR16P (QR16 with paired superblocks), QR64 (the paper's QuadRank64: absolute u64 ranks, no
+//   offset array) and QR24_8 (the paper's QuadRank24_8 on 128-byte lines: three anchors per line, a
+//   query counts at most 64 bases) are defined, with their bounds, beside their layout traits
+//   (quadrank_dev.hpp)
 //
 // floor(n/DATA) + 1 lines; bases past n are stored as A (code 0) and every delta is taken over that
 // padded text, so the padding cancels for every q <= n.
@@ -35,10 +39,10 @@ using namespace qr;
 
 struct qr_quadrank_s {
     int device;
-    int layout;  // QR_LAYOUT_16 or QR_LAYOUT_32
+    int layout;  // QR_LAYOUT_16, _32, _16P, _64 or _24_8
     uint64_t n, n_lines, n_sb;
     uint64_t *lines;  // n_lines * 16 words
-    void *super;      // n_sb * 4 offsets: u32 (16-bit layout) or u64 (32-bit layout)
+    void *super;      // n_sb * 4 offsets: u32 (16-bit layouts) or u64 (32-bit and 24_8 layouts); none for QR64
     uint32_t *err;
     qr_tuning tune;
 };
@@ -102,12 +106,24 @@ __global__ __launch_bounds__(64 * COUNT_GROUPS) void qr_count_kernel(const uint6
     }
 }
 
-// Offsets of the 32-bit layout: s_{i,c} = exact rank at the first line of superblock i.
-__global__ void qr32_super_kernel(const uint64_t *__restrict__ base, uint64_t n_groups, uint64_t n_sb,
-                                  uint64_t *__restrict__ super) {
+// Exact offsets (QR32, QR24_8): s_{i,c} = the rank at the first line of superblock i, which is the
+// first line of build group gps * i (gps = groups per superblock).
+__global__ void qr_exact_super_kernel(const uint64_t *__restrict__ base, uint64_t n_groups, uint64_t n_sb, uint64_t gps,
+                                      uint64_t *__restrict__ super) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    constexpr uint64_t GPS = QR32::SB_LINES / GROUP_LINES;
-    if (e < 4 * n_sb) super[e] = base[4 * std::min((e / 4) * GPS, n_groups - 1) + (e & 3)];
+    if (e < 4 * n_sb) super[e] = base[4 * std::min((e / 4) * gps, n_groups - 1) + (e & 3)];
+}
+
+// Offsets of paired superblocks (QR16P): s'_{i,c} = the rank at the start of group 2i + 1 (the
+// pair's middle), shifted; a last pair without its upper group takes the rank after its lower
+// group, whose counts cover all of its (A-padded) lines.
+__global__ void qr_paired_super_kernel(const uint64_t *__restrict__ base, const uint32_t *__restrict__ cnt,
+                                       uint64_t n_groups, uint64_t n_sb, uint32_t shift, uint32_t *__restrict__ super) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 4 * n_sb) return;
+    const uint64_t g = 2 * (e / 4) + 1, c = e & 3;
+    const uint64_t r = g < n_groups ? base[4 * g + c] : base[4 * (g - 1) + c] + cnt[4 * (g - 1) + c];
+    super[e] = (uint32_t)(r >> shift);
 }
 
 // Pass 3: one 128-lane workgroup per group; lane t forms line 128 g + t from packed words
@@ -117,10 +133,14 @@ constexpr int OUT_STRIDE = 17;
 template <class L>
 __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restrict__ packed, uint64_t n,
                                                        uint64_t n_words, const uint64_t *__restrict__ base,
-                                                       uint64_t n_lines, uint64_t *__restrict__ lines) {
+                                                       const uint32_t *__restrict__ paired_super, uint64_t n_lines,
+                                                       uint64_t *__restrict__ lines) {
     constexpr uint32_t W = GROUP_LINES * L::WORDS;
-    constexpr uint32_t FIRST = (L::MID - L::HDR) / 32;   // packed words in the lower half
-    constexpr uint64_t GPS = L::SB_LINES / GROUP_LINES;  // groups per superblock
+    // packed words before the anchor(s): the lower half for middle-anchored layouts; for QR24_8 the
+    // words before data bases 64, 192 and 320 (slots 192, 320, 448)
+    constexpr uint32_t FIRST = L::MULTI ? 2 : (L::MID - L::HDR) / 32;
+    constexpr uint32_t SECOND = L::MULTI ? 6 : FIRST, THIRD = L::MULTI ? 10 : FIRST;
+    constexpr uint64_t GPS = L::SB_LINES >= GROUP_LINES ? L::SB_LINES / GROUP_LINES : 1;  // groups per superblock
     // one LDS buffer holds the group's input words, then (after a barrier) the staged output lines
     constexpr uint32_t BUF = (W > 128 * OUT_STRIDE) ? W : 128 * OUT_STRIDE;
     __shared__ __align__(16) uint64_t buf[BUF];
@@ -139,13 +159,16 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
     __syncthreads();
 
     uint32_t lo[L::WORDS], hi[L::WORDS];
-    uint32_t fC = 0, fG = 0, fT = 0, aC = 0, aG = 0, aT = 0;  // lower-half and whole-line counts
+    uint32_t fC = 0, fG = 0, fT = 0, aC = 0, aG = 0, aT = 0;  // counts before the (first) anchor, whole line
+    uint32_t sC = 0, sG = 0, sT = 0, tC = 0, tG = 0, tT = 0;  // QR24_8: words [FIRST, SECOND), [SECOND, THIRD)
 #pragma unroll
     for (int k = 0; k < (int)L::WORDS; ++k) {
         const uint64_t x = in[L::WORDS * t + k];
         lo[k] = even_bits(x);
         hi[k] = even_bits(x >> 1);
         if (k < (int)FIRST) word_counts(x, fC, fG, fT);
+        if (L::MULTI && k >= (int)FIRST && k < (int)SECOND) word_counts(x, sC, sG, sT);
+        if (L::MULTI && k >= (int)SECOND && k < (int)THIRD) word_counts(x, tC, tG, tT);
         word_counts(x, aC, aG, aT);
     }
     const uint32_t fA = 32 * FIRST - fC - fG - fT, aA = L::DATA - aC - aG - aT;
@@ -161,13 +184,40 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
     uint64_t d[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const uint64_t sb_base = base[4 * ((g / GPS) * GPS) + c];
-        const uint64_t off = (sb_base >> L::SHIFT) << L::SHIFT;  // the offset the query reconstructs
+        uint64_t off = 0;  // the offset the query reconstructs
+        if constexpr (L::ID == QR_LAYOUT_16P) {
+            off = ((uint64_t)paired_super[4 * (g >> 1) + c] << L::SHIFT) - ((g & 1) ? 0ull : L::BIAS);
+        } else if constexpr (L::SB_LINES != 0) {
+            const uint64_t sb_base = base[4 * ((g / GPS) * GPS) + c];
+            off = (sb_base >> L::SHIFT) << L::SHIFT;
+        }
         d[c] = base[4 * g + c] - off + ((before >> (16 * c)) & 0xffffu) + first[c];
     }
 
     uint64_t o[16];
-    if (L::HDR == 32) {  // deltas in the low 32 slots of pair 0, bases 0..31 in its high 32 slots
+    if constexpr (L::MULTI) {  // u32 word c: L1_c | d1_c << 24; u32 word 4 + c: d2_c
+        const uint32_t d1[4] = {32 * (SECOND - FIRST) - sC - sG - sT, sC, sG, sT};
+        const uint32_t d2[4] = {32 * (THIRD - SECOND) - tC - tG - tT, tC, tG, tT};
+        uint32_t w[8];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            w[c] = (uint32_t)d[c] | (d1[c] << 24);
+            w[4 + c] = d2[c];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = (uint64_t)w[2 * k] | ((uint64_t)w[2 * k + 1] << 32);
+    }
+    if constexpr (L::HDR == 128) {  // header in pairs 0 and 1; pair k >= 2 holds packed words 2k-4, 2k-3
+        if constexpr (!L::MULTI) {  // QR64: the absolute ranks of A, C, G, T as u64 words 0..3
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] = d[c];
+        }
+#pragma unroll
+        for (int k = 2; k < 8; ++k) {
+            o[2 * k] = (uint64_t)lo[2 * k - 4] | ((uint64_t)lo[2 * k - 3] << 32);
+            o[2 * k + 1] = (uint64_t)hi[2 * k - 4] | ((uint64_t)hi[2 * k - 3] << 32);
+        }
+    } else if constexpr (L::HDR == 32) {  // deltas in the low 32 slots of pair 0, bases 0..31 in its high 32 slots
         o[0] = (d[0] | (d[1] << 16)) | ((uint64_t)lo[0] << 32);
         o[1] = (d[2] | (d[3] << 16)) | ((uint64_t)hi[0] << 32);
 #pragma unroll
@@ -175,7 +225,7 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
             o[2 * k] = (uint64_t)lo[2 * k - 1] | ((uint64_t)lo[2 * k] << 32);
             o[2 * k + 1] = (uint64_t)hi[2 * k - 1] | ((uint64_t)hi[2 * k] << 32);
         }
-    } else {  // deltas fill pair 0; pair k >= 1 holds packed words 2k-2 and 2k-1
+    } else {  // QR32: deltas fill pair 0; pair k >= 1 holds packed words 2k-2 and 2k-1
         o[0] = d[0] | (d[1] << 32);
         o[1] = d[2] | (d[3] << 32);
 #pragma unroll
@@ -200,7 +250,8 @@ __global__ __launch_bounds__(128) void qr_write_kernel(const uint64_t *__restric
 
 // ---- one lane per query (lanes = 1) --------------------------------------------------------------
 template <class L>
-__device__ __forceinline__ void load_lane_half(const uint4 *__restrict__ lines, uint64_t q, PairHalf &ph, uint4 &hdr) {
+__device__ __forceinline__ void load_lane_half(const uint4 *__restrict__ lines, uint64_t q, PairHalf &ph, uint4 &hdr,
+                                               uint4 &hdr1) {
     ph.j = qline_of<L>(q);
     const uint32_t p = (uint32_t)(q - ph.j * L::DATA) + L::HDR;
     ph.up = p >= L::MID;
@@ -211,8 +262,20 @@ __device__ __forceinline__ void load_lane_half(const uint4 *__restrict__ lines, 
     ph.w[4] = b.x, ph.w[5] = b.y, ph.w[6] = b.z, ph.w[7] = b.w;
     ph.w[8] = c.x, ph.w[9] = c.y, ph.w[10] = c.z, ph.w[11] = c.w;
     ph.w[12] = d.x, ph.w[13] = d.y, ph.w[14] = d.z, ph.w[15] = d.w;
-    hdr = ph.up ? lines[ph.j * 8] : a;
+    // The header: u32 words 0..3 of the line, and words 4..7 for the layouts with 128 header slots.
+    // Those layouts read it from the line in both halves: selecting between that load and the
+    // register copies a, b would be compiled into a load through stack copies of a and b.
+    if constexpr (L::HDR > 64) {
+        hdr = lines[ph.j * 8];
+        hdr1 = lines[ph.j * 8 + 1];
+    } else {
+        hdr = ph.up ? lines[ph.j * 8] : a;
+        hdr1 = make_uint4(0u, 0u, 0u, 0u);
+    }
 }
+
+// The line slot of q from its half and the slot inside it.
+__device__ __forceinline__ uint32_t line_slot(const PairHalf &ph) { return ph.up ? ph.t + QR_MID : ph.t; }
 
 // rank(q, c) (PREFIX = false) or prefix_rank(q, c) = #{i < q : t_i <= c} (PREFIX = true): the same
 // walk with the symbol test, the delta and the offset replaced by their sums over the symbols <= c.
@@ -227,7 +290,7 @@ __device__ __forceinline__ void sym_lane_body(const uint4 *__restrict__ lines, c
         uint32_t c[PER_LANE];
         bool bad[PER_LANE];
         PairHalf ph[PER_LANE];
-        uint4 hdr[PER_LANE];
+        uint4 hdr[PER_LANE], hdr1[PER_LANE];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const uint64_t i = min(i0 + u * stride, nq - 1);
@@ -237,17 +300,19 @@ __device__ __forceinline__ void sym_lane_body(const uint4 *__restrict__ lines, c
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             bad[u] = q[u] > n || c[u] > 3;
-            load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u]);
+            load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u], hdr1[u]);
             off[u] = PREFIX ? offset_le<L>(super, ph[u].j, c[u] & 3u) : L::offset1(super, ph[u].j, c[u] & 3u);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             const uint32_t cc = c[u] & 3u, hu = (uint32_t)ph[u].up;
-            const uint32_t cnt = PREFIX ? pair_count_le(ph[u], hu, cc) : pair_count1(ph[u], hu, cc);
-            const uint64_t d = PREFIX ? delta_le<L>(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc)
-                                      : (uint64_t)L::delta(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc);
-            const uint64_t mid = off[u] + d;
-            r[u] = bad[u] ? ~0ull : (ph[u].up ? mid + cnt : mid - cnt);
+            bool fwd;
+            const uint32_t cnt = PREFIX ? count_le<L>(ph[u], hu, cc, fwd) : count1<L>(ph[u], hu, cc, fwd);
+            const uint32_t p = line_slot(ph[u]);
+            const uint64_t d = PREFIX ? delta_le<L>(hdr[u], hdr1[u], cc, p, ph[u].j)
+                                      : L::delta(hdr[u], hdr1[u], cc, p, ph[u].j);
+            const uint64_t anchor = off[u] + d;
+            r[u] = bad[u] ? ~0ull : (fwd ? anchor + cnt : anchor - cnt);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
@@ -285,25 +350,27 @@ __global__ __launch_bounds__(256) void qr_rank4_kernel(const uint4 *__restrict__
         uint64_t q[PER_LANE];
         bool bad[PER_LANE];
         PairHalf ph[PER_LANE];
-        uint4 hdr[PER_LANE];
+        uint4 hdr[PER_LANE], hdr1[PER_LANE];
         uint64_t off[PER_LANE][4];
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) q[u] = load_once(Q + min(i0 + u * stride, nq - 1));
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             bad[u] = q[u] > n;
-            load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u]);
+            load_lane_half<L>(lines, bad[u] ? 0 : q[u], ph[u], hdr[u], hdr1[u]);
             L::offset4(super, ph[u].j, off[u]);
         }
 #pragma unroll
         for (int u = 0; u < PER_LANE; ++u) {
             uint32_t cnt[4];
-            pair_count4(ph[u], (uint32_t)ph[u].up, cnt);
+            bool fwd;
+            count4<L>(ph[u], (uint32_t)ph[u].up, cnt, fwd);
+            const uint32_t p = line_slot(ph[u]);
             uint64_t r[4];
 #pragma unroll
             for (uint32_t cc = 0; cc < 4; ++cc) {
-                const uint64_t mid = off[u][cc] + L::delta(hdr[u].x, hdr[u].y, hdr[u].z, hdr[u].w, cc);
-                r[cc] = bad[u] ? ~0ull : (ph[u].up ? mid + cnt[cc] : mid - cnt[cc]);
+                const uint64_t anchor = off[u][cc] + L::delta(hdr[u], hdr1[u], cc, p, ph[u].j);
+                r[cc] = bad[u] ? ~0ull : (fwd ? anchor + cnt[cc] : anchor - cnt[cc]);
             }
             const uint64_t i = i0 + u * stride;
             if (i < nq) {
@@ -337,12 +404,13 @@ __device__ __forceinline__ void sym_pair_compute(const uint4 *__restrict__ lines
 #pragma unroll
     for (int u = 0; u < PER_PAIR; ++u) {
         const uint32_t cc = c[u] & 3u;
-        const uint32_t cnt = PREFIX ? pair_count_le(ph[u], hf, cc) : pair_count1(ph[u], hf, cc);
-        uint64_t mine = cnt;
-        if (hf == 0) {
-            const uint64_t d = PREFIX ? delta_le<L>(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc)
-                                      : (uint64_t)L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc);
-            mine = off[u] + d - cnt;
+        bool fwd;
+        const uint32_t cnt = PREFIX ? count_le<L>(ph[u], hf, cc, fwd) : count1<L>(ph[u], hf, cc, fwd);
+        uint64_t mine = fwd ? (uint64_t)cnt : 0ull - (uint64_t)cnt;
+        if (hf == 0) {  // lane 0 holds the header (the first eight words of the line)
+            const uint32_t p = line_slot(ph[u]);
+            const uint4 a = hdr_lo(ph[u].w), b = hdr_hi(ph[u].w);
+            mine += off[u] + (PREFIX ? delta_le<L>(a, b, cc, p, ph[u].j) : L::delta(a, b, cc, p, ph[u].j));
         }
         r[u] = bad[u] ? ~0ull : mine + pair_swap64(mine);
     }
@@ -438,13 +506,14 @@ __device__ __forceinline__ void rank4_pair_compute(const uint4 *__restrict__ lin
 #pragma unroll
     for (int u = 0; u < PER_PAIR; ++u) {
         uint32_t cnt[4];
-        pair_count4(ph[u], hf, cnt);
+        bool fwd;
+        count4<L>(ph[u], hf, cnt, fwd);
+        const uint32_t p = line_slot(ph[u]);
         uint64_t r[4];
 #pragma unroll
         for (uint32_t cc = 0; cc < 4; ++cc) {
-            const uint64_t mine =
-                hf == 0 ? off[u][cc] + L::delta(ph[u].w[0], ph[u].w[1], ph[u].w[2], ph[u].w[3], cc) - cnt[cc]
-                        : (uint64_t)cnt[cc];
+            uint64_t mine = fwd ? (uint64_t)cnt[cc] : 0ull - (uint64_t)cnt[cc];
+            if (hf == 0) mine += off[u][cc] + L::delta(hdr_lo(ph[u].w), hdr_hi(ph[u].w), cc, p, ph[u].j);
             r[cc] = mine + pair_swap64(mine);
         }
         // lane 0 writes symbols A, C and lane 1 writes G, T of the row
@@ -521,6 +590,39 @@ __global__ __launch_bounds__(SWEEP_BLOCK) void qr_rank4_sweep_kernel(const uint4
     }
 }
 
+// Geometry of each layout as the host needs it.
+struct QrGeom {
+    uint64_t data, sb_lines, max_n, super_elem;  // super_elem: bytes per offset (0: no offset array)
+};
+
+bool qr_geom(int layout, QrGeom &g) {
+    switch (layout) {
+        case QR_LAYOUT_16: g = {QR16::DATA, QR16::SB_LINES, QR16::MAX_N, 4}; return true;
+        case QR_LAYOUT_32: g = {QR32::DATA, QR32::SB_LINES, QR32::MAX_N, 8}; return true;
+        case QR_LAYOUT_16P: g = {QR16P::DATA, QR16P::SB_LINES, QR16P::MAX_N, 4}; return true;
+        case QR_LAYOUT_64: g = {QR64::DATA, QR64::SB_LINES, QR64::MAX_N, 0}; return true;
+        case QR_LAYOUT_24_8: g = {QR24_8::DATA, QR24_8::SB_LINES, QR24_8::MAX_N, 8}; return true;
+        default: return false;
+    }
+}
+
+// f(L{}) for the layout's trait type.
+template <class F>
+auto qr_dispatch(int layout, F &&f) {
+    switch (layout) {
+        case QR_LAYOUT_32: return f(QR32{});
+        case QR_LAYOUT_16P: return f(QR16P{});
+        case QR_LAYOUT_64: return f(QR64{});
+        case QR_LAYOUT_24_8: return f(QR24_8{});
+        default: return f(QR16{});
+    }
+}
+
+uint64_t super_bytes_of(const qr_quadrank_s *h) {
+    QrGeom g{};
+    return qr_geom(h->layout, g) ? h->n_sb * 4 * g.super_elem : 0;
+}
+
 void release(qr_quadrank_s *h) {
     if (!h) return;
     if (h->lines) (void)hipFree(h->lines);
@@ -537,7 +639,7 @@ uint64_t grid_for(uint64_t nq, int pl, int block, int grid_waves, int lanes) {
 
 template <class L>
 hipError_t build_t(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, void *super, hipStream_t stream) {
-    const uint64_t n_lines = n / L::DATA + 1, n_sb = (n_lines - 1) / L::SB_LINES + 1;
+    const uint64_t n_lines = n / L::DATA + 1, n_sb = L::SB_LINES ? (n_lines - 1) / L::SB_LINES + 1 : 0;
     const uint64_t n_groups = (n_lines - 1) / GROUP_LINES + 1, n_words = (n + 31) / 32;
     uint32_t *cnt = nullptr;
     uint64_t *base = nullptr;
@@ -550,20 +652,25 @@ hipError_t build_t(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, void 
                        dim3(64 * COUNT_GROUPS), 0, stream, d_packed2, n, n_words, n_groups, cnt);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        if (L::SHIFT) {
+        if constexpr (L::SHIFT != 0 && L::SB_LINES == GROUP_LINES) {  // a group is a superblock
             e = launch_scan_counts(cnt, n_groups, 4, L::SHIFT, base, reinterpret_cast<uint32_t *>(super), stream);
         } else {
             e = launch_scan_counts(cnt, n_groups, 4, 0, base, nullptr, stream);
-            if (e == hipSuccess) {
-                hipLaunchKernelGGL(qr32_super_kernel, dim3((uint32_t)((4 * n_sb + 255) / 256)), dim3(256), 0, stream, base,
-                                   n_groups, n_sb, reinterpret_cast<uint64_t *>(super));
+            if (e == hipSuccess && L::ID == QR_LAYOUT_16P) {
+                hipLaunchKernelGGL(qr_paired_super_kernel, dim3((uint32_t)((4 * n_sb + 255) / 256)), dim3(256), 0, stream,
+                                   base, cnt, n_groups, n_sb, L::SHIFT, reinterpret_cast<uint32_t *>(super));
+                e = hipGetLastError();
+            } else if (e == hipSuccess && L::SB_LINES != 0) {
+                hipLaunchKernelGGL(qr_exact_super_kernel, dim3((uint32_t)((4 * n_sb + 255) / 256)), dim3(256), 0, stream,
+                                   base, n_groups, n_sb, (uint64_t)(L::SB_LINES / GROUP_LINES),
+                                   reinterpret_cast<uint64_t *>(super));
                 e = hipGetLastError();
             }
         }
     }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(qr_write_kernel<L>, dim3((uint32_t)n_groups), dim3(128), 0, stream, d_packed2, n, n_words, base,
-                           n_lines, lines);
+                           reinterpret_cast<const uint32_t *>(super), n_lines, lines);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -711,12 +818,12 @@ int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStre
         set_error("quadrank_build: d_packed2 is NULL (with n = %llu) or not 8-byte aligned", (unsigned long long)n);
         return QR_EINVAL;
     }
-    if (layout != QR_LAYOUT_16 && layout != QR_LAYOUT_32) {
+    QrGeom geo{};
+    if (!qr_geom(layout, geo)) {
         set_error("quadrank_build: unknown layout %d", layout);
         return QR_EINVAL;
     }
-    const bool l32 = layout == QR_LAYOUT_32;
-    const uint64_t max_n = l32 ? QR32::MAX_N : QR16::MAX_N;
+    const uint64_t max_n = geo.max_n;
     if (n > max_n) {
         set_error("quadrank_build: n = %llu exceeds the layout limit %llu", (unsigned long long)n,
                   (unsigned long long)max_n);
@@ -730,12 +837,12 @@ int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStre
     }
     h->layout = layout;
     h->n = n;
-    h->n_lines = n / (l32 ? QR32::DATA : QR16::DATA) + 1;
-    h->n_sb = (h->n_lines - 1) / (l32 ? QR32::SB_LINES : QR16::SB_LINES) + 1;
+    h->n_lines = n / geo.data + 1;
+    h->n_sb = geo.sb_lines ? (h->n_lines - 1) / geo.sb_lines + 1 : 0;
     h->tune = qr_tuning{256, 1, 0, 2, 0};
-    const size_t super_bytes = h->n_sb * 4 * (l32 ? 8 : 4);
-    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, super_bytes) != hipSuccess ||
-        hipMalloc(&h->err, 4) != hipSuccess) {
+    const size_t super_bytes = h->n_sb * 4 * geo.super_elem;
+    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess ||
+        (super_bytes && hipMalloc(&h->super, super_bytes) != hipSuccess) || hipMalloc(&h->err, 4) != hipSuccess) {
         (void)hipGetLastError();
         set_error("quadrank_build: device allocation of %llu bytes failed",
                   (unsigned long long)(h->n_lines * 128 + super_bytes));
@@ -746,8 +853,8 @@ int quadrank_build_ex(const uint64_t *d_packed2, uint64_t n, int layout, hipStre
         release(h);
         return QR_EHIP;
     }
-    const hipError_t e = l32 ? build_t<QR32>(d_packed2, n, h->lines, h->super, stream)
-                             : build_t<QR16>(d_packed2, n, h->lines, h->super, stream);
+    const hipError_t e =
+        qr_dispatch(layout, [&](auto tag) { return build_t<decltype(tag)>(d_packed2, n, h->lines, h->super, stream); });
     if (e != hipSuccess) {
         set_error("quadrank_build: %s", hipGetErrorString(e));
         release(h);
@@ -784,8 +891,7 @@ int quadrank_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64
         return QR_EINVAL;
     }
     if (!nq) return QR_OK;
-    return h->layout == QR_LAYOUT_32 ? launch_rank1<QR32, false>(h, d_q, d_c, nq, d_out, stream)
-                                     : launch_rank1<QR16, false>(h, d_q, d_c, nq, d_out, stream);
+    return qr_dispatch(h->layout, [&](auto tag) { return launch_rank1<decltype(tag), false>(h, d_q, d_c, nq, d_out, stream); });
 }
 
 int quadrank_prefix_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c, uint64_t nq, uint64_t *d_out,
@@ -797,16 +903,14 @@ int quadrank_prefix_rank(qr_quadrank h, const uint64_t *d_q, const uint8_t *d_c,
         return QR_EINVAL;
     }
     if (!nq) return QR_OK;
-    return h->layout == QR_LAYOUT_32 ? launch_rank1<QR32, true>(h, d_q, d_c, nq, d_out, stream)
-                                     : launch_rank1<QR16, true>(h, d_q, d_c, nq, d_out, stream);
+    return qr_dispatch(h->layout, [&](auto tag) { return launch_rank1<decltype(tag), true>(h, d_q, d_c, nq, d_out, stream); });
 }
 
 int quadrank_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_out4, hipStream_t stream) {
     int rc = qr_launch_common(h, nq, d_q, d_out4, 16, "quadrank_rank4");
     if (rc) return rc;
     if (!nq) return QR_OK;
-    return h->layout == QR_LAYOUT_32 ? launch_rank4<QR32>(h, d_q, nq, d_out4, stream)
-                                     : launch_rank4<QR16>(h, d_q, nq, d_out4, stream);
+    return qr_dispatch(h->layout, [&](auto tag) { return launch_rank4<decltype(tag)>(h, d_q, nq, d_out4, stream); });
 }
 
 int quadrank_check(qr_quadrank h, hipStream_t stream) {
@@ -831,7 +935,7 @@ int quadrank_free(qr_quadrank h) {
 
 uint64_t quadrank_len(qr_quadrank h) { return h ? h->n : 0; }
 uint64_t quadrank_bytes(qr_quadrank h) {
-    return h ? h->n_lines * 128 + h->n_sb * 4 * (h->layout == QR_LAYOUT_32 ? 8 : 4) : 0;
+    return h ? h->n_lines * 128 + super_bytes_of(h) : 0;
 }
 int quadrank_layout_kind(qr_quadrank h) { return h ? h->layout : -1; }
 
@@ -850,8 +954,7 @@ int quadrank_export(qr_quadrank h, void *h_lines, void *h_super) {
     int rc = check_device(h->device);
     if (rc) return rc;
     if (h_lines) QR_HIP(hipMemcpy(h_lines, h->lines, h->n_lines * 128, hipMemcpyDeviceToHost));
-    if (h_super)
-        QR_HIP(hipMemcpy(h_super, h->super, h->n_sb * 4 * (h->layout == QR_LAYOUT_32 ? 8 : 4), hipMemcpyDeviceToHost));
+    if (h_super && super_bytes_of(h)) QR_HIP(hipMemcpy(h_super, h->super, super_bytes_of(h), hipMemcpyDeviceToHost));
     return QR_OK;
 }
 

@@ -148,24 +148,34 @@ __device__ __forceinline__ void rank4_from_half(const HalfLine &hl, uint64_t (&r
 }
 
 // ---- layouts -------------------------------------------------------------------------------------
+// Each layout gives HDR (header slots at the line start), DATA (bases per line), MID (slot 256, the
+// 64-byte half boundary), WORDS (packed input words per line), the offset-array geometry
+// (SB_LINES, SB_LOG, SHIFT, Super), the exact division by DATA (MAGIC, MAGIC_T), and
+//   MULTI    false: a query counts between its slot p and the middle (within p's 64-byte half);
+//            true:  between p and the nearest of three anchors, within p's 64-slot pair (24_8);
+//   offset1(s, j, c) / offset4 + delta(a, b, c, p, j) = rank(anchor of p, c), where a and b hold the
+//            line's first eight u32 words (the header) and p is the query's line slot.
+// The arithmetic is modulo 2^64: a paired layout's offset may exceed the anchor rank (its delta
+// carries a negative bias), and the sum is still exact.
+//
 // QR16: four 16-bit deltas in slots [0,32) (lo_0 low half = A | C << 16, hi_0 low half = G | T << 16),
 //       480 bases, 128 lines per superblock, offsets s = floor(rank / 2^12) as u32.
 // QR32: four 32-bit deltas in slots [0,64) (lo_0 = A | C << 32, hi_0 = G | T << 32), 448 bases,
 //       2^23 lines per superblock, exact u64 offsets.  floor(x/448) = mulhi(x, ceil(2^72/448)) >> 8,
 //       exact for x < 2^63 (e = 384 < 448).
 struct QR16 {
+    static constexpr int ID = QR_LAYOUT_16;
     static constexpr uint32_t HDR = 32, DATA = 480, MID = 256, WORDS = 15;
+    static constexpr bool MULTI = false;
     static constexpr uint64_t SB_LINES = 128;
     static constexpr uint32_t SB_LOG = 7, SHIFT = 12;
     static constexpr uint64_t MAGIC = QR_MAGIC;
     static constexpr uint32_t MAGIC_T = QR_MAGIC_T;
     static constexpr uint64_t MAX_N = (1ull << 44) - 1;
     using Super = uint32_t;
-    // delta of symbol c from the line's first four u32 words
-    __device__ __forceinline__ static uint32_t delta(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t c) {
-        (void)w1, (void)w3;
+    __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &, uint32_t c, uint32_t, uint64_t) {
         const uint32_t m2 = 0u - ((c >> 1) & 1u);
-        const uint32_t d = (w0 & ~m2) | (w2 & m2);
+        const uint32_t d = (a.x & ~m2) | (a.z & m2);
         return (d >> (16u * (c & 1u))) & 0xffffu;
     }
     __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__ s, uint64_t j, uint32_t c) {
@@ -178,18 +188,111 @@ struct QR16 {
     }
 };
 
+// QR16 with paired superblocks (the paper's appendix on pairing superblocks): one row of four
+// shifted offsets per 256 lines, taken at the pair's middle (line 128 of the 256), so half the
+// offsets of QR16.  Lines of the lower 128 store their delta plus BIAS = 128 * 480 - 224 (the most
+// bases between a lower line's middle and the pair's middle), removed again by the query.
+//   b_{j,c} = rank(480 j + 224, c) - 2^12 s'_{j/256, c} + [j mod 256 < 128] BIAS
+//   s'_{i,c} = floor(rank(480 (256 i + 128), c) / 2^12)
+//   bounds: lower lines 0 <= b <= BIAS + 4095 = 65311; upper lines b <= 127*480 + 224 + 4095 = 65279
+struct QR16P {
+    static constexpr int ID = QR_LAYOUT_16P;
+    static constexpr uint32_t HDR = 32, DATA = 480, MID = 256, WORDS = 15;
+    static constexpr bool MULTI = false;
+    static constexpr uint64_t SB_LINES = 256;
+    static constexpr uint32_t SB_LOG = 8, SHIFT = 12;
+    static constexpr uint64_t BIAS = 128 * 480 - 224;
+    static constexpr uint64_t MAGIC = QR_MAGIC;
+    static constexpr uint32_t MAGIC_T = QR_MAGIC_T;
+    static constexpr uint64_t MAX_N = (1ull << 44) - 1;
+    using Super = uint32_t;
+    __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &b, uint32_t c, uint32_t p, uint64_t j) {
+        return QR16::delta(a, b, c, p, j) - ((j & 128u) ? 0ull : BIAS);
+    }
+    __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__ s, uint64_t j, uint32_t c) {
+        return (uint64_t)sel4(reinterpret_cast<const uint4 *>(s)[j >> SB_LOG], c) << SHIFT;
+    }
+    __device__ __forceinline__ static void offset4(const Super *__restrict__ s, uint64_t j, uint64_t (&o)[4]) {
+        const uint4 v = reinterpret_cast<const uint4 *>(s)[j >> SB_LOG];
+        o[0] = (uint64_t)v.x << SHIFT, o[1] = (uint64_t)v.y << SHIFT, o[2] = (uint64_t)v.z << SHIFT,
+        o[3] = (uint64_t)v.w << SHIFT;
+    }
+};
+
 struct QR32 {
+    static constexpr int ID = QR_LAYOUT_32;
     static constexpr uint32_t HDR = 64, DATA = 448, MID = 256, WORDS = 14;
+    static constexpr bool MULTI = false;
     static constexpr uint64_t SB_LINES = 1ull << 23;
     static constexpr uint32_t SB_LOG = 23, SHIFT = 0;
     static constexpr uint64_t MAGIC = 0x924924924924924aull;  // ceil(2^72 / 448)
     static constexpr uint32_t MAGIC_T = 8;
     static constexpr uint64_t MAX_N = (1ull << 48) - 1;
     using Super = uint64_t;
-    __device__ __forceinline__ static uint32_t delta(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t c) {
-        const uint32_t m1 = 0u - (c & 1u), m2 = 0u - ((c >> 1) & 1u);
-        const uint32_t lo = (w0 & ~m1) | (w1 & m1), hi = (w2 & ~m1) | (w3 & m1);
-        return (lo & ~m2) | (hi & m2);
+    __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &, uint32_t c, uint32_t, uint64_t) {
+        return sel4(a, c);
+    }
+    __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__ s, uint64_t j, uint32_t c) {
+        return s[4 * (j >> SB_LOG) + (c & 3u)];
+    }
+    __device__ __forceinline__ static void offset4(const Super *__restrict__ s, uint64_t j, uint64_t (&o)[4]) {
+        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(s + 4 * (j >> SB_LOG));
+        const ulonglong2 a = p[0], b = p[1];
+        o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+    }
+};
+
+// 64-bit word x of the header (u32 words 2x, 2x+1 of a.xyzw, b.xyzw) for a runtime x in 0..3.
+__device__ __forceinline__ uint64_t hdr64(const uint4 &a, const uint4 &b, uint32_t x) {
+    const uint32_t m1 = 0u - (x & 1u), m2 = 0u - ((x >> 1) & 1u);
+    const uint32_t lo = (((a.x & ~m1) | (a.z & m1)) & ~m2) | (((b.x & ~m1) | (b.z & m1)) & m2);
+    const uint32_t hi = (((a.y & ~m1) | (a.w & m1)) & ~m2) | (((b.y & ~m1) | (b.w & m1)) & m2);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// The paper's QuadRank64: the line's first two pairs (slots [0,128), u64 words 0..3) hold the
+// absolute ranks of A, C, G, T at the line's middle (slot 256 = data base 128), then 384 bases in
+// pairs 2..7; no offset array.  floor(x/384) = mulhi(x, ceil(2^72/384)) >> 8, exact for x < 2^63
+// (e = 128 < 384).
+struct QR64 {
+    static constexpr int ID = QR_LAYOUT_64;
+    static constexpr uint32_t HDR = 128, DATA = 384, MID = 256, WORDS = 12;
+    static constexpr bool MULTI = false;
+    static constexpr uint64_t SB_LINES = 0;  // no offset array
+    static constexpr uint32_t SB_LOG = 0, SHIFT = 0;
+    static constexpr uint64_t MAGIC = 0xaaaaaaaaaaaaaaabull;  // ceil(2^72 / 384)
+    static constexpr uint32_t MAGIC_T = 8;
+    static constexpr uint64_t MAX_N = (1ull << 48) - 1;
+    using Super = uint64_t;
+    __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &b, uint32_t c, uint32_t, uint64_t) {
+        return hdr64(a, b, c);
+    }
+    __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__, uint64_t, uint32_t) { return 0; }
+    __device__ __forceinline__ static void offset4(const Super *__restrict__, uint64_t, uint64_t (&o)[4]) {
+        o[0] = o[1] = o[2] = o[3] = 0;
+    }
+};
+
+// The paper's QuadRank24_8 on 128-byte lines: the header (slots [0,128)) holds per symbol a 24-bit
+// delta L1 to the anchor at slot 192 and two 8-bit deltas d1 (from slot 192 to 320) and d2 (from 320
+// to 448); 384 bases fill pairs 2..7, and a query counts at most one 64-slot pair, backwards to the
+// anchor at its end (pairs 2, 4, 6) or forwards from the anchor at its start (pairs 3, 5, 7).
+//   u32 word c (c = A..T): L1_c | d1_c << 24;  u32 word 4 + c: d2_c
+//   L1_{j,c} = rank(384 j + 64, c) - S_{j/2^15, c};  d1 = #c in bases [64, 192) of the line, d2 in
+//   [192, 320) (each <= 128);  S exact (u64) per 2^15 lines;  L1 <= (2^15 - 1)*384 + 64 < 2^24
+struct QR24_8 {
+    static constexpr int ID = QR_LAYOUT_24_8;
+    static constexpr uint32_t HDR = 128, DATA = 384, MID = 256, WORDS = 12;
+    static constexpr bool MULTI = true;
+    static constexpr uint64_t SB_LINES = 1ull << 15;
+    static constexpr uint32_t SB_LOG = 15, SHIFT = 0;
+    static constexpr uint64_t MAGIC = QR64::MAGIC;
+    static constexpr uint32_t MAGIC_T = QR64::MAGIC_T;
+    static constexpr uint64_t MAX_N = (1ull << 48) - 1;
+    using Super = uint64_t;
+    __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &b, uint32_t c, uint32_t p, uint64_t) {
+        const uint32_t w = sel4(a, c), d2 = sel4(b, c) & 0xffu;
+        return (uint64_t)(w & 0xffffffu) + (p >= 256 ? (w >> 24) : 0u) + (p >= 384 ? d2 : 0u);
     }
     __device__ __forceinline__ static uint64_t offset1(const Super *__restrict__ s, uint64_t j, uint32_t c) {
         return s[4 * (j >> SB_LOG) + (c & 3u)];
@@ -268,15 +371,20 @@ __device__ __forceinline__ uint32_t pair_count_le(const PairHalf &ph, uint32_t h
 
 // Sums over the symbols x <= c of the line deltas and of the superblock offsets.
 template <class L>
-__device__ __forceinline__ uint64_t delta_le(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t c) {
+__device__ __forceinline__ uint64_t delta_le(const uint4 &a, const uint4 &b, uint32_t c, uint32_t p, uint64_t j) {
     uint64_t d = 0;
 #pragma unroll
-    for (uint32_t x = 0; x < 4; ++x) d += x <= c ? (uint64_t)L::delta(w0, w1, w2, w3, x) : 0ull;
+    for (uint32_t x = 0; x < 4; ++x) d += x <= c ? L::delta(a, b, x, p, j) : 0ull;
     return d;
 }
 
+// The header words (line u32 words 0..7) of a lane pair's lower half.
+__device__ __forceinline__ uint4 hdr_lo(const uint32_t (&w)[16]) { return make_uint4(w[0], w[1], w[2], w[3]); }
+__device__ __forceinline__ uint4 hdr_hi(const uint32_t (&w)[16]) { return make_uint4(w[4], w[5], w[6], w[7]); }
+
 template <class L>
 __device__ __forceinline__ uint64_t offset_le(const typename L::Super *__restrict__ s, uint64_t j, uint32_t c) {
+    if constexpr (L::SB_LINES == 0) return 0;  // no offset array
     uint64_t o[4];
     L::offset4(s, j, o);
     return o[0] + (c >= 1 ? o[1] : 0ull) + (c >= 2 ? o[2] : 0ull) + (c >= 3 ? o[3] : 0ull);
@@ -305,6 +413,90 @@ __device__ __forceinline__ void pair_count4(const PairHalf &ph, uint32_t hf, uin
     cnt[1] = cL - cT;
     cnt[2] = cH - cT;
     cnt[3] = cT;
+}
+
+// ---- counts of any layout ------------------------------------------------------------------------
+// The four words (lo low, lo high, hi low, hi high) of pair k (0..3) of a half line, picked with
+// masks.
+__device__ __forceinline__ void pick_pair(const uint32_t (&w)[16], uint32_t k, uint32_t (&o)[4]) {
+    o[0] = o[1] = o[2] = o[3] = 0u;
+#pragma unroll
+    for (uint32_t s = 0; s < 4; ++s) {
+        const uint32_t m = (k == s) ? 0xffffffffu : 0u;
+        o[0] |= w[4 * s] & m, o[1] |= w[4 * s + 1] & m, o[2] |= w[4 * s + 2] & m, o[3] |= w[4 * s + 3] & m;
+    }
+}
+
+// The counted range of a multi-anchor layout: pair k = t / 64 of q's half, slots [u, 64) of it
+// before an anchor (k even) or [0, u) after one (k odd), u = t mod 64.  Masks of its two 32-slot
+// words, and whether the range follows its anchor.
+__device__ __forceinline__ bool multi_masks(uint32_t t, uint32_t &m0, uint32_t &m1) {
+    const bool fwd = (t >> 6) & 1u;
+    const uint32_t u = t & 63u, inv = fwd ? 0u : 0xffffffffu;
+    m0 = prefix_mask32(u, 0) ^ inv;
+    m1 = prefix_mask32(u, 1) ^ inv;
+    return fwd;
+}
+
+// Occurrences of c in this lane's share of the counted range (zero unless the lane holds q's half),
+// and whether the range follows the anchor (add) or precedes it (subtract).
+template <class L>
+__device__ __forceinline__ uint32_t count1(const PairHalf &ph, uint32_t hf, uint32_t c, bool &fwd) {
+    if constexpr (L::MULTI) {
+        uint32_t m0, m1, v[4];
+        fwd = multi_masks(ph.t, m0, m1);
+        if ((uint32_t)ph.up != hf) return 0u;
+        pick_pair(ph.w, ph.t >> 6, v);
+        const uint32_t xl = (c & 1) ? 0u : 0xffffffffu, xh = (c & 2) ? 0u : 0xffffffffu;
+        return __popc((v[0] ^ xl) & (v[2] ^ xh) & m0) + __popc((v[1] ^ xl) & (v[3] ^ xh) & m1);
+    } else {
+        fwd = ph.up;
+        return pair_count1(ph, hf, c);
+    }
+}
+
+// Slots of the counted range whose symbol is at most c (see pair_count_le).
+template <class L>
+__device__ __forceinline__ uint32_t count_le(const PairHalf &ph, uint32_t hf, uint32_t c, bool &fwd) {
+    if constexpr (L::MULTI) {
+        uint32_t m0, m1, v[4];
+        fwd = multi_masks(ph.t, m0, m1);
+        if ((uint32_t)ph.up != hf) return 0u;
+        pick_pair(ph.w, ph.t >> 6, v);
+        const uint32_t ma = 0u - (c & 1u), mb = 0u - ((c >> 1) & 1u);
+        const uint32_t a0 = (mb & v[0] & v[2] & ~ma) | (~mb & (v[2] | (v[0] & ~ma)));
+        const uint32_t a1 = (mb & v[1] & v[3] & ~ma) | (~mb & (v[3] | (v[1] & ~ma)));
+        const uint32_t len = fwd ? (ph.t & 63u) : 64u - (ph.t & 63u);
+        return len - __popc(a0 & m0) - __popc(a1 & m1);
+    } else {
+        fwd = ph.up;
+        return pair_count_le(ph, hf, c);
+    }
+}
+
+// The four symbol counts of the counted range (zero unless the lane holds q's half).
+template <class L>
+__device__ __forceinline__ void count4(const PairHalf &ph, uint32_t hf, uint32_t (&cnt)[4], bool &fwd) {
+    if constexpr (L::MULTI) {
+        uint32_t m0, m1, v[4];
+        fwd = multi_masks(ph.t, m0, m1);
+        if ((uint32_t)ph.up != hf) {
+            cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0u;
+            return;
+        }
+        pick_pair(ph.w, ph.t >> 6, v);
+        const uint32_t l0 = v[0] & m0, l1 = v[1] & m1, h0 = v[2] & m0, h1 = v[3] & m1;
+        const uint32_t cT = __popc(l0 & h0) + __popc(l1 & h1), cL = __popc(l0) + __popc(l1),
+                       cH = __popc(h0) + __popc(h1);
+        const uint32_t len = fwd ? (ph.t & 63u) : 64u - (ph.t & 63u);
+        cnt[0] = len - cL - cH + cT;
+        cnt[1] = cL - cT;
+        cnt[2] = cH - cT;
+        cnt[3] = cT;
+    } else {
+        fwd = ph.up;
+        pair_count4(ph, hf, cnt);
+    }
 }
 
 }  // namespace qr

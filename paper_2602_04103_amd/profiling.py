@@ -43,16 +43,24 @@ def launch_form(tuning) -> str:
     return "lane" if t.get("lanes") == 1 else "pair"
 
 
-def traffic_key(row: str, layout: int, form: str) -> str:
-    return "%s|L%d|%s" % (row, layout, form)
+# layout name -> the suffix of its trait type in kernel names (qr::BR16P, qr::QR24_8, ...)
+LAYOUT_TOKENS = {"16": "16", "32": "32", "16p": "16P", "64": "64", "16x2": "16X2", "24_8": "24_8"}
 
 
-def kernel_matches(name: str, row: str, form: str, layout: int) -> bool:
+def traffic_key(row: str, layout, form: str) -> str:
+    return "%s|L%s|%s" % (row, layout, form)
+
+
+def layout_token(row: str, layout) -> str:
+    return ("QR" if row.startswith("quadrank") else "BR") + LAYOUT_TOKENS[str(layout)]
+
+
+def kernel_matches(name: str, row: str, form: str, layout) -> bool:
     """Whether a (demangled) kernel name from a profile is the given row's kernel in that form and
     layout.  rank and prefix_rank share the sweep kernel; its PREFIX argument tells them apart."""
+    import re
     fam = ROW_KERNELS[row][form]
-    token = ("QR" if row.startswith("quadrank") else "BR") + str(layout)
-    if fam + "<" not in name or token not in name:
+    if fam + "<" not in name or not re.search(r"\b%s\b" % re.escape(layout_token(row, layout)), name):
         return False
     if fam == "qr_sym_sweep_kernel":
         return (", true," in name) == (row == "quadrank_prefix_rank")
@@ -85,6 +93,22 @@ def counter_values(d: str, counter: str):
                 continue
             k = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
             res.setdefault(k, []).append(float(r.get("Counter_Value") or r.get("Counter-Value") or 0))
+    return res
+
+
+def counter_dispatches(d: str, counter: str):
+    """{kernel name: [(dispatch id, value)] in dispatch order} for one counter."""
+    res = {}
+    for p in _csvs(d, "counter_collection.csv"):
+        for r in _rows(p):
+            name = r.get("Counter_Name") or r.get("Counter-Name")
+            if name != counter:
+                continue
+            k = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
+            did = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id") or 0)
+            res.setdefault(k, []).append((did, float(r.get("Counter_Value") or r.get("Counter-Value") or 0)))
+    for v in res.values():
+        v.sort()
     return res
 
 
@@ -126,6 +150,20 @@ def cmd_counters(a):
             print("%-24s %-80s dispatches=%-5d mean=%.4g" % (c, k[:80], len(v), statistics.mean(v)))
 
 
+def cmd_dispatches(a):
+    """Each dispatch's counter value, in dispatch order, for the kernels whose names contain a given
+    text: for runs that launch one kernel on several inputs in turn (the bench's gather sweep)."""
+    print("# rocprofv3 --pmc per-dispatch values, in dispatch order")
+    if a.cmd:
+        print("# command: " + a.cmd)
+    for c in a.counter:
+        for k, v in sorted(counter_dispatches(a.dir, c).items()):
+            if a.kernel and a.kernel not in k:
+                continue
+            print("%-24s %s" % (c, k[:100]))
+            print("    " + " ".join("%.4g" % x for _, x in v))
+
+
 def cmd_traffic(a):
     fetch = counter_values(a.fetch_dir, "FETCH_SIZE")
     write = counter_values(a.write_dir, "WRITE_SIZE")
@@ -146,7 +184,7 @@ def cmd_traffic(a):
     except (OSError, ValueError):
         pass
     srcs = ROW_SOURCES["quadrank" if a.row.startswith("quadrank") else "birank"]
-    token = ("QR" if a.row.startswith("quadrank") else "BR") + str(a.layout)
+    token = layout_token(a.row, a.layout)
     sel = lambda d: [x for k, v in d.items() if kernel_matches(k, a.row, a.form, a.layout) for x in v]  # noqa: E731
     fv, wv = sel(fetch), sel(write)
     kname = ROW_KERNELS[a.row][a.form]
@@ -181,11 +219,16 @@ def main(argv=None):
     c.add_argument("dir")
     c.add_argument("counter", nargs="+")
     c.add_argument("--cmd", default="")
+    dsp = sub.add_parser("dispatches")
+    dsp.add_argument("dir")
+    dsp.add_argument("counter", nargs="+")
+    dsp.add_argument("--kernel", default="", help="only kernels whose name contains this text")
+    dsp.add_argument("--cmd", default="")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
     t.add_argument("--row", required=True, choices=sorted(ROW_KERNELS))
-    t.add_argument("--layout", type=int, required=True, choices=(16, 32))
+    t.add_argument("--layout", required=True, choices=tuple(LAYOUT_TOKENS))
     t.add_argument("--form", default="pair", choices=("pair", "lane", "sweep"),
                    help="launch form the profiled run used (its tuning)")
     t.add_argument("--cmd", default="", help="the profiled command, stored with the record")
@@ -193,7 +236,7 @@ def main(argv=None):
     t.add_argument("--copy-kernel", default="elementwise")
     t.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "counters": cmd_counters, "traffic": cmd_traffic}[a.what](a)
+    {"stats": cmd_stats, "counters": cmd_counters, "dispatches": cmd_dispatches, "traffic": cmd_traffic}[a.what](a)
 
 
 if __name__ == "__main__":

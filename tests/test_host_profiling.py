@@ -31,6 +31,16 @@ def test_kernel_matches():
     assert P.kernel_matches(br, "birank_rank_p0.5", "sweep", 32)
     assert not P.kernel_matches(br, "birank_rank_p0.5", "pair", 32)
     assert not P.kernel_matches(br, "quadrank_rank4", "sweep", 32)
+    # named layouts: a 16-bit token does not match the paired or quarter-anchored variants
+    paired = "void (anonymous namespace)::br_rank_sweep_kernel<qr::BR16P, 2, 4>(HIP_vector_type<unsigned int"
+    quarter = "void (anonymous namespace)::br_rank_pair_kernel<qr::BR16X2, 1>(HIP_vector_type<unsigned int"
+    multi = "void (anonymous namespace)::qr_rank4_pair_kernel<qr::QR24_8, 2>(HIP_vector_type<unsigned int"
+    assert P.kernel_matches(paired, "birank_rank_p0.5", "sweep", "16p")
+    assert not P.kernel_matches(paired, "birank_rank_p0.5", "sweep", 16)
+    assert P.kernel_matches(quarter, "birank_rank_p0.05", "pair", "16x2")
+    assert not P.kernel_matches(quarter, "birank_rank_p0.05", "pair", "16")
+    assert P.kernel_matches(multi, "quadrank_rank4", "pair", "24_8")
+    assert P.traffic_key("birank_rank_p0.5", "16p", "pair") == "birank_rank_p0.5|L16p|pair"
 
 
 def test_traffic_records_match_the_current_sources():
