@@ -384,7 +384,8 @@ int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, const uint64
 /* Host-side reference of the library's exact division by the line payloads (for tests):
  * which = 0 -> floor(x / 1008) (BiRank), 1 -> floor(x / 480) (QuadRank), 2 -> floor(x / 992)
  * (BiRank, QR_LAYOUT_32), 3 -> floor(x / 448) (QuadRank, QR_LAYOUT_32), 4 -> floor(x / 480) by the
- * FM-index search's 32-bit form (x < 2^32; ~0 above); other values give ~0. */
+ * FM-index search's 32-bit form (x < 2^32; ~0 above), 5 -> floor(x / 960) (BiRank, QR_LAYOUT_64),
+ * 6 -> floor(x / 384) (QuadRank, QR_LAYOUT_64 and QR_LAYOUT_24_8); other values give ~0. */
 uint64_t qr_line_of(uint64_t x, int which);
 
 #ifdef __cplusplus

@@ -71,6 +71,8 @@ uint64_t qr_line_of(uint64_t x, int which) {
         case 2: return qr::line_of<qr::BR32>(x);
         case 3: return qr::qline_of<qr::QR32>(x);
         case 4: return x <= 0xffffffffull ? qr::qr_line_of32((uint32_t)x) : ~0ull;
+        case 5: return qr::line_of<qr::BR64>(x);
+        case 6: return qr::qline_of<qr::QR64>(x);
         default: return ~0ull;
     }
 }

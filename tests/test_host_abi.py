@@ -34,7 +34,8 @@ def test_library_exports_every_declared_symbol():
 def test_line_division_is_exact():
     import paper_2602_04103_amd as qr
     rng = np.random.default_rng(1)
-    for which, d, limit in ((0, 1008, 1 << 42), (1, 480, 1 << 44), (2, 992, 1 << 48), (3, 448, 1 << 48)):
+    for which, d, limit in ((0, 1008, 1 << 42), (1, 480, 1 << 44), (2, 992, 1 << 48), (3, 448, 1 << 48),
+                            (5, 960, 1 << 48), (6, 384, 1 << 48)):
         xs = list(range(0, 5000)) + [int(x) for x in rng.integers(0, limit, 20000, dtype=np.int64)]
         for k in (1, 2, 63, 64, 127, 128, (limit // d) - 1, (1 << 40) // d, (1 << 62) // d):
             xs += [k * d - 1, k * d, k * d + 1]
