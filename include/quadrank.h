@@ -228,6 +228,17 @@ int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint6
  * serving loop use. */
 int quadfm_count_ws(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
                     void *d_workspace, hipStream_t stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): quadfm_count_ex with the handle's or a caller's queue
+ * head replaced by one kept in a fixed 256-byte device array of the library (one per device, held
+ * until the process ends), so the call allocates nothing and takes no workspace.  Arguments,
+ * results and errors are those of quadfm_count_ex.  The array holds a single 8-byte queue head
+ * whatever npat is, so no input size exceeds it.  Every call on a device shares that device's
+ * head and resets it on `stream` when it starts: calls that overlap in time on one device race
+ * (wrong counts), so serialise them, e.g. on one stream.  The first call on each device looks up
+ * the array's device address (hipGetSymbolAddress) with that device current. */
+int quadfm_count_noalloc(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                         uint32_t flags, uint32_t *d_count, hipStream_t stream);
 /* Count flags for the *_ex calls. */
 #define QUADFM_BOTH_STRANDS 1u /* count P and its reverse complement (A<->T, C<->G, reversed): the
                                   result is count(P) + count(rc(P)), saturating at 2^32-1; the empty

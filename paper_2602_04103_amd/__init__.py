@@ -115,6 +115,7 @@ def lib():
             "quadfm_count_batched": (ci, [vp, vp, vp, u64, u64, vp, vp]),
             "quadfm_count_ws": (ci, [vp, vp, vp, u64, vp, vp, vp]),
             "quadfm_count_ex": (ci, [vp, vp, u64, vp, u64, C.c_uint32, vp, vp, vp]),
+            "quadfm_count_noalloc": (ci, [vp, vp, u64, vp, u64, C.c_uint32, vp, vp]),
             "quadfm_count_batched_ex": (ci, [vp, vp, u64, vp, u64, u64, C.c_uint32, vp, vp]),
             "quadfm_check": (ci, [vp, vp]),
             "quadfm_free": (ci, [vp]),
@@ -340,6 +341,17 @@ def quadfm_count_ex(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.T
     pp, pn = _pat(pat)
     _check(lib().quadfm_count_ex(h, pp, pn, _dev(off, "off", W64), npat, flags, _dev(count, "count", W32, npat), ws,
                                  _stream(stream)), "quadfm_count_ex")
+    return count
+
+
+def quadfm_count_noalloc(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.Tensor, flags: int = 0,
+                         stream=None):
+    """quadfm_count_ex with the queue head in the library's fixed device array: no allocation and no
+    workspace; calls that overlap on one device race."""
+    npat = off.numel() - 1
+    pp, pn = _pat(pat)
+    _check(lib().quadfm_count_noalloc(h, pp, pn, _dev(off, "off", W64), npat, flags, _dev(count, "count", W32, npat),
+                                      _stream(stream)), "quadfm_count_noalloc")
     return count
 
 

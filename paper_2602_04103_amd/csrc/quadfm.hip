@@ -29,6 +29,7 @@
 // back), until a marked row: SA[k] = sample + steps, at most s - 1 steps.  The row of '$' has
 // SA = 0 and is always marked, so the walk never steps through '$'.
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "birank_dev.hpp"
@@ -688,6 +689,58 @@ int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, cons
     }
     if (!npat) return QR_OK;
     return count_persistent(h, d_pat, pat_bytes, d_off, npat, d_iv, h->head, 0u, true, stream);
+}
+
+// ---- quadfm_count_noalloc -------------------------------------------------------------------------
+// The persistent count's only memory beyond its inputs and outputs is the 8-byte work-queue head.
+// For callers that cannot allocate, the head lives in this file-scope device array: every device
+// the library runs on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol): the device address
+// of each device's copy is looked up once, with that device current, and kept.
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 256;  // one queue head is used; the rest pads the array
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_SCRATCH_BYTES / 8];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Device address of the current device's scratch array (looked up on the first call per device).
+static int scratch_address(unsigned long long **out) {
+    static std::mutex mu;
+    static unsigned long long *addr[NOALLOC_MAX_DEVICES] = {nullptr};
+    int dev = -1;
+    QR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("quadfm_count_noalloc: device %d is beyond the %d devices the library tracks", dev,
+                  NOALLOC_MAX_DEVICES);
+        return QR_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("quadfm_count_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return QR_EHIP;
+        }
+        addr[dev] = reinterpret_cast<unsigned long long *>(ptr);
+    }
+    *out = addr[dev];
+    return QR_OK;
+}
+
+int quadfm_count_noalloc(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
+                         uint32_t flags, uint32_t *d_count, hipStream_t stream) {
+    int rc = count_args(h, d_pat, pat_bytes, d_off, npat, d_count, "quadfm_count_noalloc");
+    if (rc) return rc;
+    if (flags & ~QUADFM_BOTH_STRANDS) {
+        set_error("quadfm_count_noalloc: unknown flag bits 0x%x", flags);
+        return QR_EINVAL;
+    }
+    unsigned long long *head = nullptr;
+    rc = scratch_address(&head);
+    if (rc) return rc;
+    if (!npat) return QR_OK;
+    // the head is cleared by a one-lane kernel on `stream` (count_persistent), not by a memset
+    return count_persistent(h, d_pat, pat_bytes, d_off, npat, d_count, head, flags, false, stream);
 }
 
 int quadfm_count(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint32_t *d_count,
