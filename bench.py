@@ -33,13 +33,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 BATCH = 1 << 24
 TOTAL_Q = 10 ** 9
 
-# algorithmic bytes per query: one random 128-byte line + the coalesced query/result streams
-BYTES_PER_QUERY = {
-    "quadrank_rank": 128 + 8 + 1 + 8,
-    "quadrank_rank4": 128 + 8 + 32,
-    "quadrank_prefix_rank": 128 + 8 + 1 + 8,
-    "birank_rank_p0.5": 128 + 8 + 8,
-    "birank_rank_p0.05": 128 + 8 + 8,
+# The roofline counts the algorithmic lines: one random 128-byte line per rank query.  The coalesced
+# query and result streams each query also moves are reported beside it, not inside it.
+LINE_BYTES = 128
+STREAM_BYTES_PER_QUERY = {
+    "quadrank_rank": 8 + 1 + 8,
+    "quadrank_rank4": 8 + 32,
+    "quadrank_prefix_rank": 8 + 1 + 8,
+    "birank_rank_p0.5": 8 + 8,
+    "birank_rank_p0.05": 8 + 8,
 }
 
 
@@ -71,21 +73,29 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
-    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8", help="offered loads, patterns/s")
+    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8,2e8,4e8",
+                    help="offered loads, patterns/s (past 10^8 the 200 000-request cap shortens the run)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--serve-kmer", type=int, default=12, help="start-table size of the served index")
+    ap.add_argument("--no-fm-hbm", action="store_true",
+                    help="skip the FM count measurement on the served (HBM-resident) index")
+    ap.add_argument("--fm-hbm-patterns", type=int, default=4 * 10 ** 6)
     ap.add_argument("--serve-python", action="store_true",
                     help="run the sweep with the Python scheduling loop instead of the native one")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
     ap.add_argument("--rows", default="quadrank_rank,quadrank_rank4,birank_rank_p0.5,birank_rank_p0.05",
                     help="comma-separated rank rows of the step; quadrank_prefix_rank is an optional extra row")
-    ap.add_argument("--layouts", default="16,32",
-                    help="inline-delta widths to build for each rank row; the tuner picks one per row")
+    ap.add_argument("--layouts", default="16,32,16p,64,16x2,24_8",
+                    help="line layouts to build for each rank row (16x2 is BiRank's only, 24_8 QuadRank's); "
+                         "the tuner picks one per row")
     ap.add_argument("--no-extra", action="store_true", help="skip the prefix_rank row timed outside the step")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing of the steps")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tuning-from", default=None,
                     help="apply the launch settings recorded in an earlier bench JSON line instead of tuning")
+    ap.add_argument("--gather-gib", default="",
+                    help="comma-separated sizes in GiB: measure the random-line gather ceiling over a fresh "
+                         "allocation of each size (after the steps; reported under gather_sweep)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -108,8 +118,10 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     rows = [r for r in args.rows.split(",") if r]
-    layouts = [int(x) for x in args.layouts.split(",") if x]
-    layout_id = {16: qr.QR_LAYOUT_16, 32: qr.QR_LAYOUT_32}
+    layouts = [x for x in args.layouts.split(",") if x]
+    layout_id = qr.LAYOUT_BY_NAME
+    qr_layouts = [L for L in layouts if L != "16x2"]    # QuadRank has no 16x2 layout
+    br_layouts = [L for L in layouts if L != "24_8"]    # BiRank has no 24_8 layout
     t_setup = time.time()
 
     def to_dev(a):
@@ -120,6 +132,16 @@ def main():
 
     # ------------------------------------------------------------------ structures + queries
     structs, qsets, builds = {}, {}, {}
+
+    def build_rate(key, in_bytes, out_bytes, secs):
+        """Streaming rate of a build: its algorithmic bytes (the packed input read by the count pass
+        and again by the line writer, the structure written once) over the host time of the build
+        call, which also holds its device allocations and final synchronisation (a lower bound on
+        the kernels' own rate)."""
+        algo = 2 * in_bytes + out_bytes
+        builds[key + "_algorithmic_bytes"] = algo
+        builds[key + "_GBps"] = round(algo / secs / 1e9, 1)
+        builds[key + "_frac_of_hbm_peak"] = round(algo / secs / 1e9 / HBM_PEAK_GBS, 4)
     packed_q = None
     n_qr = 1 << 32
     if any(r.startswith("quadrank") for r in rows):
@@ -131,12 +153,13 @@ def main():
         d = to_dev(packed_q)
         log("quadrank text generated %.1fs" % (time.time() - t0))
         structs["quadrank"] = {}
-        for L in layouts:
+        for L in qr_layouts:
             torch.cuda.synchronize()
             t0 = time.time()
             structs["quadrank"][L] = qr.QuadRank(d, n_qr, layout=layout_id[L])
-            builds["quadrank%d_build_s" % L] = time.time() - t0
-            builds["quadrank%d_bytes" % L] = structs["quadrank"][L].nbytes
+            builds["quadrank%s_build_s" % L] = time.time() - t0
+            builds["quadrank%s_bytes" % L] = structs["quadrank"][L].nbytes
+            build_rate("quadrank%s" % L, n_qr // 4, structs["quadrank"][L].nbytes, time.time() - t0)
         del d
         if "quadrank_rank" in rows:
             qsets["quadrank_rank"] = (to_dev(datagen.queries(3204, n_qr, TOTAL_Q)), to_dev(datagen.symbols(3205, TOTAL_Q)))
@@ -154,12 +177,13 @@ def main():
         d = to_dev(datagen.bits(seed, n_br, dens))
         t1 = time.time()
         structs[row] = {}
-        for L in layouts:
+        for L in br_layouts:
             torch.cuda.synchronize()
             t2 = time.time()
             structs[row][L] = qr.BiRank(d, n_br, layout=layout_id[L])
-            builds["birank%d_build_p%g_s" % (L, dens)] = time.time() - t2
-            builds["birank%d_bytes" % L] = structs[row][L].nbytes
+            builds["birank%s_build_p%g_s" % (L, dens)] = time.time() - t2
+            builds["birank%s_bytes" % L] = structs[row][L].nbytes
+            build_rate("birank%s_p%g" % (L, dens), n_br // 8, structs[row][L].nbytes, time.time() - t2)
         del d
         qsets[row] = (to_dev(datagen.queries(seed + 100, n_br, TOTAL_Q)), None)
         log("%s ready (gen %.1fs)" % (row, t1 - t0))
@@ -168,7 +192,10 @@ def main():
     outs = torch.empty(BATCH * 4, dtype=torch.int64, device=dev)
     bl = batches(TOTAL_Q, BATCH)
 
-    choice = {row: layouts[0] for row in rows}  # layout each row runs on (set by the tuner)
+    def row_layouts(row):
+        return qr_layouts if row.startswith("quadrank") else br_layouts
+
+    choice = {row: row_layouts(row)[0] for row in rows}  # layout each row runs on (set by the tuner)
 
     def handle(row, L=None):
         return structs["quadrank" if row.startswith("quadrank") else row][choice[row] if L is None else L]
@@ -198,8 +225,8 @@ def main():
     for row in rows:
         if fixed and isinstance(fixed.get(row), dict):
             t = dict(fixed[row])
-            L = int(t.pop("layout", 16))
-            choice[row] = L if L in layouts else layouts[0]
+            L = str(t.pop("layout", "16"))
+            choice[row] = L if L in row_layouts(row) else row_layouts(row)[0]
             handle(row).set_tuning(**t)
             tuning[row] = t
             continue
@@ -212,15 +239,16 @@ def main():
         # one batch leaves its queries and translations cached and can rank candidates differently
         full = [k for k, (_, cnt) in enumerate(bl) if cnt == BATCH]
         turn = itertools.count()
-        for L in layouts:
+        for L in row_layouts(row):
             h = handle(row, L)
-            best, table = autotune.tune("%s|L%d" % (row, L), h.n, h.set_tuning,
+            best, table = autotune.tune("%s|L%s" % (row, L), h.n, h.set_tuning,
                                         lambda r=row, L=L: launch(r, full[next(turn) % len(full)], L),
                                         autotune.RANK_CANDIDATES, use_cache=False)
             t_best = min(t for _, t in table)
-            by_layout[row][str(L)] = {"tuned_launch_ms": round(t_best * 1e3, 4), "tuning": best,
-                                      "queries_per_s": BATCH / t_best}
-            log("tuned %s layout %d -> %s %.3f ms (%s)" % (row, L, best, t_best * 1e3,
+            by_layout[row][L] = {"tuned_launch_ms": round(t_best * 1e3, 4), "tuning": best,
+                                 "queries_per_s": BATCH / t_best, "structure_bytes": h.nbytes,
+                                 "roofline_frac_hbm": BATCH / t_best * LINE_BYTES / 1e9 / HBM_PEAK_GBS}
+            log("tuned %s layout %s -> %s %.3f ms (%s)" % (row, L, best, t_best * 1e3,
                                                           ", ".join("%.3f" % (t * 1e3) for _, t in table[:6])))
             if best_t is None or t_best < best_t:
                 best_t, choice[row], tuning[row] = t_best, L, best
@@ -277,8 +305,8 @@ def main():
         nq = sum(c for _, _, c in ev[row])
         per_launch = statistics.mean(secs)
         qps = nq / sum(secs)
-        bpq = BYTES_PER_QUERY[row]
-        achieved = bpq * nq / sum(secs) / 1e9
+        achieved = LINE_BYTES * nq / sum(secs) / 1e9
+        with_streams = (LINE_BYTES + STREAM_BYTES_PER_QUERY[row]) * nq / sum(secs) / 1e9
         row_res[row] = {
             "queries_per_s": qps,
             "avg_launch_ms": per_launch * 1e3,
@@ -289,13 +317,16 @@ def main():
             "lines_per_query": 1,
             "roofline_frac_hbm": achieved / HBM_PEAK_GBS,
             "algorithmic_GBps": achieved,
+            "stream_bytes_per_query": STREAM_BYTES_PER_QUERY[row],
+            "frac_incl_streams": with_streams / HBM_PEAK_GBS,
             "tuning": (dict(tuning[row], layout=choice[row]) if isinstance(tuning.get(row), dict)
                        else tuning.get(row)),
             "layout": choice[row],
             "by_layout": by_layout[row],
         }
-        log("%-20s L%d %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline" % (
-            row, choice[row], qps / 1e9, per_launch * 1e3, 100 * achieved / HBM_PEAK_GBS))
+        log("%-20s L%s %.2f G q/s  %.3f ms/launch  lines %.1f%% of HBM (%.1f%% with the query/result streams)" % (
+            row, choice[row], qps / 1e9, per_launch * 1e3, 100 * achieved / HBM_PEAK_GBS,
+            100 * with_streams / HBM_PEAK_GBS))
     ms_per_step = wall / args.steps * 1e3
     value = step_queries / wall if rows else None
 
@@ -315,8 +346,7 @@ def main():
         pass
     roofline = None if dom is None else {
         "bound": "hbm",
-        "kernel": "%s<%s%d> (%s)" % (profiling.ROW_KERNELS[dom][form], "QR" if dom.startswith("quadrank") else "BR",
-                                     choice[dom], dom),
+        "kernel": "%s<%s> (%s)" % (profiling.ROW_KERNELS[dom][form], profiling.layout_token(dom, choice[dom]), dom),
         "row": dom,
         "layout": choice[dom],
         "achieved": round(row_res[dom]["algorithmic_GBps"], 1),
@@ -324,7 +354,9 @@ def main():
         "unit": "GB/s",
         "frac": round(row_res[dom]["roofline_frac_hbm"], 4),
         "traffic": traffic,
-        "bytes_per_query": BYTES_PER_QUERY[dom],
+        "bytes_per_query": LINE_BYTES,
+        "stream_bytes_per_query": STREAM_BYTES_PER_QUERY[dom],
+        "frac_incl_streams": round(row_res[dom]["frac_incl_streams"], 4),
     }
     if roofline is not None:
         # context for the fraction: the random-line gather rate over the dominant row's own structure
@@ -352,6 +384,15 @@ def main():
         }
         log("%s: %.2f G q/s against %.2f G random lines/s over the same allocation (%.1f%%)" % (
             dom, row_res[dom]["queries_per_s"] / 1e9, ceiling / 1e9, 100 * row_res[dom]["queries_per_s"] / ceiling))
+
+    # ------------------------------------------------------------------ gather ceilings by working set
+    gather_sweep = None
+    if args.gather_gib:
+        gather_sweep = []
+        for gib in (float(x) for x in args.gather_gib.split(",") if x):
+            lps = gather_ceiling(qr, torch, dev, int(gib * (1 << 30)))
+            gather_sweep.append({"gib": gib, "lines_per_s": lps, "GBps_of_lines": lps * 128 / 1e9})
+            log("gather ceiling over %.2f GiB: %.2f G lines/s (%.0f GB/s of lines)" % (gib, lps / 1e9, lps * 128 / 1e9))
 
     # ------------------------------------------------------------------ the same steps from a HIP graph
     # the K timed steps (every row, every batch) captured once and replayed with one launch
@@ -397,11 +438,11 @@ def main():
         torch.cuda.synchronize()
         secs = sum(a.elapsed_time(b) / 1e3 for a, b, _ in evs)
         nq = sum(c_ for _, _, c_ in evs)
-        achieved = BYTES_PER_QUERY["quadrank_prefix_rank"] * nq / secs / 1e9
+        achieved = LINE_BYTES * nq / secs / 1e9
         extra["quadrank_prefix_rank"] = {"queries_per_s": nq / secs, "avg_launch_ms": secs / len(evs) * 1e3,
                                          "roofline_frac_hbm": achieved / HBM_PEAK_GBS, "algorithmic_GBps": achieved,
                                          "layout": choice["quadrank_rank"], "in_step": False}
-        log("%-20s L%d %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline (outside the step)" % (
+        log("%-20s L%s %.2f G q/s  %.3f ms/launch  %.1f%% of HBM roofline (outside the step)" % (
             "quadrank_prefix_rank", choice["quadrank_rank"], nq / secs / 1e9, secs / len(evs) * 1e3,
             100 * achieved / HBM_PEAK_GBS))
 
@@ -450,6 +491,7 @@ def main():
         "graph": graph_res,
         "builds": builds,
         "roofline": roofline,
+        "gather_sweep": gather_sweep,
         "fm": fm_res,
         "serve": serve_res,
         "cpu_baseline": cpu,
@@ -543,13 +585,20 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=kbest)
     achieved = npat / t_p * work["lines_per_pattern"] * 128 / 1e9
     res["work"] = work
-    res["roofline"] = {"bound": "hbm", "kernel": "fm_persistent_kernel", "achieved": round(achieved, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                       "note": "algorithmic 128-byte lines; the 72 MB index fits the 256 MB MALL, so the "
-                               "line reads are served mostly from cache and the fraction can exceed HBM's"}
-    log("fm work: %.1f steps, %.1f lines, %.1f half lines per pattern -> %.0f GB/s of lines (%.0f%% of HBM)" % (
-        work["steps_per_pattern"], work["lines_per_pattern"], work["half_lines_per_pattern"], achieved,
-        100 * achieved / HBM_PEAK_GBS))
+    line_bytes = ((n + 1) // 480 + 1) * 128
+    ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
+    lps = npat / t_p * work["lines_per_pattern"]
+    res["roofline"] = {"bound": "cache", "kernel": "fm_persistent_kernel", "achieved": round(achieved, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
+                       "lines_per_s": lps, "line_gather_ceiling_lines_per_s": ceil_lps,
+                       "frac": round(lps / ceil_lps, 4),
+                       "note": "algorithmic 128-byte lines; the %.0f MB of lines fit the 256 MB memory-side cache, "
+                               "so the fraction is taken against the measured random-line gather rate over an "
+                               "allocation of the same size, not against HBM" % (line_bytes / 1e6)}
+    log("fm work: %.1f steps, %.1f lines, %.1f half lines per pattern -> %.0f GB/s of lines (%.0f%% of HBM), "
+        "%.2f G lines/s against a gather ceiling of %.2f G lines/s over %.0f MB (%.0f%%)" % (
+            work["steps_per_pattern"], work["lines_per_pattern"], work["half_lines_per_pattern"], achieved,
+            100 * achieved / HBM_PEAK_GBS, lps / 1e9, ceil_lps / 1e9, line_bytes / 1e6, 100 * lps / ceil_lps))
     log("fm persistent %.1f M patterns/s; batched best %.1f M; gain %.2fx; equal=%s" % (
         npat / t_p / 1e6, best_b / 1e6, res["gain_vs_best_batched"], res["persistent_equals_batched"]))
     if rate:
@@ -570,6 +619,81 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
         log("fm locate (rate %d): %d positions, %.1f M positions/s; intervals %.2f ms, offsets %.2f ms, walks %.2f ms"
             % (rate, total, total / t_loc / 1e6, t_iv * 1e3, t_off * 1e3, t_loc * 1e3))
     fm.free()
+    return res
+
+
+def gather_ceiling(qr, torch, dev, nbytes, draws=1 << 24, reps=5):
+    """Random 128-byte lines per second over a fresh allocation of `nbytes` (2^24 uniform lines, two
+    lanes per line, non-temporal index and result streams): the rate a kernel that reads one random
+    line per unit of work over a structure of that size can reach."""
+    from paper_2602_04103_amd import autotune
+    n_lines = max(1, nbytes // 128)
+    buf = torch.ones(n_lines * 16, dtype=torch.int64, device=dev)
+    idx = torch.randint(-2 ** 63, 2 ** 63 - 1, (draws,), dtype=torch.int64, device=dev)
+    out = torch.empty(draws, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        rc = qr.lib().qr_gather_lanes_bench_ex(buf.data_ptr(), n_lines, idx.data_ptr(), draws, 2,
+                                               qr.QR_GATHER_STREAM_IO, out.data_ptr(), stream.cuda_stream)
+        if rc:
+            raise RuntimeError("qr_gather_lanes_bench_ex failed: %d" % rc)
+
+    t = autotune.time_launch(run, reps=reps)
+    del buf, idx, out
+    return draws / t
+
+
+def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt, dollar, fm_serve):
+    """The persistent count on the index the serving sweep uses (2^30 bases: its lines and start
+    table exceed the 256 MB memory-side cache, so most line reads go to HBM), against one launch per
+    batch, at the start-table size of the batched row (k = 8) and of the served index."""
+    n = text.size
+    npat = args.fm_hbm_patterns
+    pat, off, _ = datagen.patterns(4040, text, npat)
+    dp, do = to_dev(pat), to_dev(off)
+    cnt = torch.empty(npat, dtype=torch.int32, device=dev)
+    cnt_b = torch.empty(npat, dtype=torch.int32, device=dev)
+    line_bytes = ((n + 1) // 480 + 1) * 128
+    ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
+    res = {"workload": "QuadFm count on the 2^%d-base serving text (uniform ACGT, 1000 planted 10-kb segments x20, "
+                       "1%% subs) + sentinel; %d patterns, lengths 20..250, 90%% sampled with 1%% substitutions, "
+                       "10%% iid" % (int(np.log2(n)), npat),
+           "line_bytes": line_bytes, "line_gather_ceiling_lines_per_s": ceil_lps, "by_kmer": {}}
+    fms = {args.serve_kmer: fm_serve}
+    if args.serve_kmer != 8:
+        fms[8] = qr.QuadFm(bwt, n + 1, dollar, kmer=8)
+    for k, fm in sorted(fms.items()):
+        # the persistent kernel's launch settings tuned on this index (an HBM-resident index wants
+        # more patterns in flight than the cache-resident one), on the first 10^6 patterns
+        sub = min(npat, 1_000_000)
+        best, _ = autotune.tune("quadfm-hbm-k%d" % k, n, fm.set_tuning, lambda f=fm: f.count(dp, do[:sub + 1], cnt[:sub]),
+                                autotune.FM_CANDIDATES, reps=2, use_cache=False)
+        t_p = autotune.time_launch(lambda f=fm: f.count(dp, do, cnt), reps=args.fm_reps)
+        row = {"index_bytes": fm.nbytes, "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3,
+               "tuning": best}
+        for batch in (1 << 16, 1 << 20, 0):
+            t_b = autotune.time_launch(lambda f=fm: f.count_batched(dp, do, batch, cnt_b), reps=args.fm_reps)
+            row["batched_%s_patterns_per_s" % (batch or "all")] = npat / t_b
+        best_b = max(v for kk, v in row.items() if kk.startswith("batched_"))
+        row["gain_vs_best_batched"] = row["persistent_patterns_per_s"] / best_b
+        row["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
+        work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=k)
+        lps = npat / t_p * work["lines_per_pattern"]
+        row["work"] = work
+        row["roofline"] = {"bound": "hbm", "kernel": "fm_persistent_kernel", "achieved": round(lps * 128 / 1e9, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(lps * 128 / 1e9 / HBM_PEAK_GBS, 4),
+                           "lines_per_s": lps, "frac_of_line_gather_ceiling": round(lps / ceil_lps, 4)}
+        res["by_kmer"][str(k)] = row
+        log("fm 2^%d k=%d: persistent %.1f M patterns/s, best batched %.1f M (gain %.2fx), %.1f lines/pattern, "
+            "%.0f GB/s of lines = %.1f%% of HBM, %.0f%% of the gather ceiling (%.2f G lines/s), equal=%s" % (
+                int(np.log2(n)), k, npat / t_p / 1e6, best_b / 1e6, row["gain_vs_best_batched"],
+                work["lines_per_pattern"], lps * 128 / 1e9, 100 * lps * 128 / 1e9 / HBM_PEAK_GBS,
+                100 * lps / ceil_lps, ceil_lps / 1e9, row["persistent_equals_batched"]))
+        if k != args.serve_kmer:
+            fm.free()
+        else:
+            fm.set_tuning(block=64, refill=32, waves_per_cu=8)  # the serving loop's own settings
     return res
 
 
@@ -628,7 +752,13 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0)
     t1 = time.time()
     fm = qr.QuadFm(bwt, n + 1, dollar, kmer=args.serve_kmer)
+    hbm_row = None
+    if not args.no_fm_hbm:
+        from paper_2602_04103_amd import autotune
+        hbm_row = bench_fm_hbm(args, qr, autotune, datagen, np, torch, torch.device("cuda"), to_dev, text, bwt,
+                               dollar, fm)
     del bwt
+    torch.cuda.empty_cache()
     fm.set_tuning(block=64, refill=32, waves_per_cu=8)
     log("serve index 2^%d: text + %s SA+BWT %.1fs" % (args.serve_log_n, "host" if args.host_sa else "device", t1 - t0))
     slots, budget = 4, 256 << 20
@@ -637,7 +767,8 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
            "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "device_free_bytes_at_start": int(free),
-           "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": []}
+           "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": [],
+           "fm_count_hbm": hbm_row}
     # warm-up (untimed): first launches, pinned-memory pools, stream creation
     w0 = make_workload(4999, text, 1e6, 0.05, max_requests=200)
     ex0 = GpuExecutor(fm, w0, slots=slots, budget_bytes=budget)
@@ -665,23 +796,51 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         res["loads"].append(summ)
         if not args.serve_python:
             srv.free()
-        log("serve load %.0e: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, %d batches, max in flight %d, equal=%s"
+        log("serve load %.0e: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, %d batches (median %.0f, p99 %.0f patterns; "
+            "p99 requests in batches of median %.0f), max in flight %d, equal=%s"
             % (load, summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6, summ["batches"],
-               summ["max_inflight_batches"], summ["equal_to_direct_count"]))
+               summ.get("batch_patterns_p50", 0), summ.get("batch_patterns_p99", 0),
+               summ.get("batch_patterns_of_p99_requests_median", 0), summ["max_inflight_batches"],
+               summ["equal_to_direct_count"]))
         del ex, srv
     fm.free()
     return res
 
 
 def cpu_model():
+    """The host CPU as lscpu reports it (model name, family/model/stepping, sockets x cores, L3, and
+    the hypervisor when virtualised), falling back to /proc/cpuinfo."""
+    import subprocess
+    want = ("Model name", "Vendor ID", "CPU family", "Model", "Stepping", "Socket(s)", "Core(s) per socket",
+            "Thread(s) per core", "CPU(s)", "L3 cache", "Hypervisor vendor", "CPU max MHz")
+    info = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in want and k.strip() not in info:
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if not info.get("Model name"):
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        info["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return info or None
+
+
+def host_threads():
+    """(threads this process may run on, online CPUs)."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except OSError:
+        aff = os.cpu_count()
+    return aff, os.cpu_count()
 
 
 def cpu_baseline(packed, n, datagen, np, with_birank=True):
@@ -724,7 +883,10 @@ def cpu_baseline(packed, n, datagen, np, with_birank=True):
            "one_thread_queries_per_s": r_1,
            "one_thread_sample": "2*10^7 of the same rank(q,c) queries vs their first 5*10^6 on one thread "
                                 "(%.2f s vs %.2f s)" % (tb1, ts1),
-           "cpu_model": cpu_model(),
+           "cpu_model": (cpu_model() or {}).get("Model name"),
+           "lscpu": cpu_model(),
+           "nproc": host_threads()[0],
+           "online_cpus": host_threads()[1],
            "rank4_queries_per_s": r_4,
            "rank4_sample": "10^8 uniform rank4 queries vs their first 2.5*10^7 (%.2f s vs %.2f s), same text"
                            % (tb4, ts4)}

@@ -194,7 +194,8 @@ class NativeServer:
         self.counts_host = h_cnt.numpy()[: int(w.off.size - 1)]
         return ServeStats(latency_s=finish - arrival, finish_s=finish, batches=int(st.batches),
                           max_inflight=int(st.max_inflight), max_reserved_bytes=int(st.max_reserved_bytes),
-                          patterns=int(w.req_off[-1]), wall_s=float(st.wall_s))
+                          patterns=int(w.req_off[-1]), wall_s=float(st.wall_s),
+                          req_patterns=np.diff(np.asarray(w.req_off, dtype=np.int64)))
 
     def counts(self, p0: int, p1: int) -> np.ndarray:
         return self.counts_host[p0:p1]
@@ -221,6 +222,17 @@ class ServeStats:
     max_reserved_bytes: int
     patterns: int
     wall_s: float
+    req_patterns: Optional[np.ndarray] = None  # patterns of each request (for the batch sizes)
+
+    def batch_sizes(self) -> Optional[np.ndarray]:
+        """Patterns per batch, recovered from the finish times: a batch's requests are consecutive
+        (FIFO admission) and all finish when the host sees that batch complete (batches the host
+        sees complete at the same instant count as one)."""
+        if self.req_patterns is None or not self.finish_s.size:
+            return None
+        f = self.finish_s
+        starts = np.concatenate([[0], np.nonzero(f[1:] != f[:-1])[0] + 1])
+        return np.add.reduceat(self.req_patterns, starts)
 
     def summary(self) -> dict:
         lat = self.latency_s
@@ -235,7 +247,21 @@ class ServeStats:
             "batches": self.batches,
             "max_inflight_batches": self.max_inflight,
             "max_reserved_bytes": self.max_reserved_bytes,
+            **self._batch_summary(),
         }
+
+    def _batch_summary(self) -> dict:
+        b = self.batch_sizes()
+        if b is None or not b.size:
+            return {}
+        lat = self.latency_s
+        slow = lat >= np.percentile(lat, 99)   # the requests behind the p99
+        f = self.finish_s
+        starts = np.concatenate([[0], np.nonzero(f[1:] != f[:-1])[0] + 1])
+        owner = np.repeat(np.arange(b.size), np.diff(np.concatenate([starts, [f.size]])))
+        return {"batch_patterns_p50": float(np.percentile(b, 50)), "batch_patterns_p99": float(np.percentile(b, 99)),
+                "batch_patterns_max": int(b.max()),
+                "batch_patterns_of_p99_requests_median": float(np.median(b[owner[slow]]))}
 
 
 class Server:
