@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tuning-from", default=None,
                     help="apply the launch settings recorded in an earlier bench JSON line instead of tuning")
-    ap.add_argument("--gather-gib", default="",
+    ap.add_argument("--gather-gib", default="0.25,1,8",
                     help="comma-separated sizes in GiB: measure the random-line gather ceiling over a fresh "
                          "allocation of each size (after the steps; reported under gather_sweep)")
     ap.add_argument("--calibrate-copy", action="store_true",
