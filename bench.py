@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--gather-gib", default="0.25,1,8",
                     help="comma-separated sizes in GiB: measure the random-line gather ceiling over a fresh "
                          "allocation of each size (after the steps; reported under gather_sweep)")
+    ap.add_argument("--gather-lanes", default="2",
+                    help="lanes per line (1, 2, 4, 8) of the gather sweep: each size is measured with each")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -390,9 +392,11 @@ def main():
     if args.gather_gib:
         gather_sweep = []
         for gib in (float(x) for x in args.gather_gib.split(",") if x):
-            lps = gather_ceiling(qr, torch, dev, int(gib * (1 << 30)))
-            gather_sweep.append({"gib": gib, "lines_per_s": lps, "GBps_of_lines": lps * 128 / 1e9})
-            log("gather ceiling over %.2f GiB: %.2f G lines/s (%.0f GB/s of lines)" % (gib, lps / 1e9, lps * 128 / 1e9))
+            for lanes in (int(x) for x in args.gather_lanes.split(",") if x):
+                lps = gather_ceiling(qr, torch, dev, int(gib * (1 << 30)), lanes=lanes)
+                gather_sweep.append({"gib": gib, "lanes": lanes, "lines_per_s": lps, "GBps_of_lines": lps * 128 / 1e9})
+                log("gather ceiling over %.2f GiB, %d lanes per line: %.2f G lines/s (%.0f GB/s of lines)" % (
+                    gib, lanes, lps / 1e9, lps * 128 / 1e9))
 
     # ------------------------------------------------------------------ the same steps from a HIP graph
     # the K timed steps (every row, every batch) captured once and replayed with one launch
@@ -622,10 +626,10 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     return res
 
 
-def gather_ceiling(qr, torch, dev, nbytes, draws=1 << 24, reps=5):
-    """Random 128-byte lines per second over a fresh allocation of `nbytes` (2^24 uniform lines, two
-    lanes per line, non-temporal index and result streams): the rate a kernel that reads one random
-    line per unit of work over a structure of that size can reach."""
+def gather_ceiling(qr, torch, dev, nbytes, draws=1 << 24, reps=5, lanes=2):
+    """Random 128-byte lines per second over a fresh allocation of `nbytes` (2^24 uniform lines, read
+    by `lanes` lanes per line, non-temporal index and result streams): the rate a kernel that reads
+    one random line per unit of work over a structure of that size can reach."""
     from paper_2602_04103_amd import autotune
     n_lines = max(1, nbytes // 128)
     buf = torch.ones(n_lines * 16, dtype=torch.int64, device=dev)
@@ -634,7 +638,7 @@ def gather_ceiling(qr, torch, dev, nbytes, draws=1 << 24, reps=5):
     stream = torch.cuda.current_stream()
 
     def run():
-        rc = qr.lib().qr_gather_lanes_bench_ex(buf.data_ptr(), n_lines, idx.data_ptr(), draws, 2,
+        rc = qr.lib().qr_gather_lanes_bench_ex(buf.data_ptr(), n_lines, idx.data_ptr(), draws, lanes,
                                                qr.QR_GATHER_STREAM_IO, out.data_ptr(), stream.cuda_stream)
         if rc:
             raise RuntimeError("qr_gather_lanes_bench_ex failed: %d" % rc)
