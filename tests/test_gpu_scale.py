@@ -13,11 +13,13 @@ from tests.gpu_util import announce, require_gpu, to_dev, to_host_u64
 pytestmark = pytest.mark.gpu
 
 BATCH = 1 << 24
-# the settings the tuner chooses on these structures (lane pairs, and the sweep form with tiles of
-# 1024) and a few neighbours; the last one also runs prefix_rank
+# the settings the tuner chooses on these structures (lane pairs with 2 queries per pair, in blocks
+# of 128 or 256; the sweep form with tiles of 1024 or 4096) and a few neighbours; the last one also
+# runs prefix_rank
 BENCH_TUNINGS = [dict(lanes=2, per_lane=2, block=256, grid_waves=0), dict(lanes=2, per_lane=2, block=256, grid_waves=8),
                  dict(lanes=2, per_lane=8, block=256, grid_waves=8), dict(lanes=2, per_lane=2, block=256, sweep=1024),
-                 dict(lanes=2, per_lane=2, block=128, grid_waves=0), dict(lanes=2, per_lane=1, block=256, sweep=1024)]
+                 dict(lanes=2, per_lane=2, block=128, grid_waves=0), dict(lanes=2, per_lane=1, block=256, sweep=4096),
+                 dict(lanes=2, per_lane=1, block=256, sweep=1024)]
 
 
 def boundary_queries(n, sb, line, mid):
@@ -31,19 +33,24 @@ def boundary_queries(n, sb, line, mid):
 
 @pytest.mark.parametrize("p,seed", [(0.5, 3636), (0.05, 3637)])
 def test_birank_2e36(p, seed):
-    """Both layouts: the 16-bit one (superblocks of 64 lines) and the 32-bit one, whose 2^22-line
-    superblocks are crossed 16 times at this size."""
+    """Every layout the bench builds: the 16-bit one (superblocks of 64 lines), the 32-bit one
+    (2^22-line superblocks, crossed 16 times at this size), paired superblocks, the 64-bit
+    absolute lines and the quarter anchors."""
     qr = require_gpu()
     n = 1 << 36
     bits = datagen.bits(seed, n, p)
     total = int(np.unpackbits(bits.view(np.uint8)).sum(dtype=np.int64))
     q = datagen.queries(seed + 100, n, BATCH)
     fixed = np.concatenate([np.array([0, n, n - 1, 1 << 35], np.uint64), boundary_queries(n, (1 << 22) * 992, 992, 480),
-                            boundary_queries(min(n, 64 * 64512 * 3), 64 * 1008, 1008, 496)])
+                            boundary_queries(min(n, 64 * 64512 * 3), 64 * 1008, 1008, 496),
+                            boundary_queries(min(n, 128 * 128 * 1008 * 3), 128 * 1008, 1008, 496),
+                            boundary_queries(min(n, 64 * 960 * 3), 64 * 960, 960, 448),
+                            boundary_queries(min(n, 64 * 63488 * 3), 64 * 992, 992, 224)])
     q[:fixed.size] = fixed
     dq = to_dev(q)
     want = oracle.rank_bits(bits, n, q)
-    for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32):
+    assert fixed.size < BATCH
+    for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32, qr.QR_LAYOUT_16P, qr.QR_LAYOUT_64, qr.QR_LAYOUT_16X2):
         announce("birank 2^36", p, "layout", layout)
         h = qr.BiRank(to_dev(bits), n, layout=layout)
         for tune in BENCH_TUNINGS:
@@ -58,8 +65,8 @@ def test_birank_2e36(p, seed):
 
 
 def test_quadrank_2e32_with_repeats():
-    """Both layouts (rank, rank4 and prefix_rank); the 32-bit layout has its superblock boundary at
-    2^23 lines = 3758096384 bases."""
+    """Every layout the bench builds (rank, rank4 and prefix_rank): the 32-bit layout has its
+    superblock boundary at 2^23 lines = 3758096384 bases, QuadRank24_8 one every 2^15 lines."""
     qr = require_gpu()
     n = 1 << 32
     codes = datagen.dna_codes(3202, n)
@@ -68,14 +75,17 @@ def test_quadrank_2e32_with_repeats():
     packed = datagen.pack2(codes)
     del codes
     q = datagen.queries(3204, n, BATCH)
-    fixed = np.concatenate([np.array([n, 0], np.uint64), boundary_queries(n, (1 << 23) * 448, 448, 192)])
+    fixed = np.concatenate([np.array([n, 0], np.uint64), boundary_queries(n, (1 << 23) * 448, 448, 192),
+                            boundary_queries(min(n, (1 << 15) * 384 * 4), (1 << 15) * 384, 384, 64),
+                            boundary_queries(min(n, 256 * 480 * 4), 256 * 480, 480, 224)])
     q[:fixed.size] = fixed
     c = datagen.symbols(3205, BATCH)
     dq, dc = to_dev(q), to_dev(c)
     want1 = oracle.rank_dna(packed, n, q, c)
     want4 = oracle.rank4_dna(packed, n, q)
     wantp = oracle.prefix_rank_dna(packed, n, q, c)
-    for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32):
+    assert fixed.size < BATCH
+    for layout in (qr.QR_LAYOUT_16, qr.QR_LAYOUT_32, qr.QR_LAYOUT_16P, qr.QR_LAYOUT_64, qr.QR_LAYOUT_24_8):
         announce("quadrank 2^32 layout", layout)
         h = qr.QuadRank(to_dev(packed), n, layout=layout)
         for tune in BENCH_TUNINGS:
