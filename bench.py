@@ -77,9 +77,13 @@ def main():
                     help="offered loads, patterns/s (past 10^8 the 200 000-request cap shortens the run)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--serve-kmer", type=int, default=12, help="start-table size of the served index")
+    ap.add_argument("--serve-layout", default="32",
+                    help="QuadRank layout of the served index (32: the fastest count over the 2^30-base index)")
     ap.add_argument("--no-fm-hbm", action="store_true",
                     help="skip the FM count measurement on the served (HBM-resident) index")
     ap.add_argument("--fm-hbm-patterns", type=int, default=4 * 10 ** 6)
+    ap.add_argument("--fm-layouts", default="16p,32,64,24_8",
+                    help="QuadRank layouts besides the 16-bit one to build the FM rows' indexes over (empty: none)")
     ap.add_argument("--serve-python", action="store_true",
                     help="run the sweep with the Python scheduling loop instead of the native one")
     ap.add_argument("--no-tune", action="store_true", help="use default launch settings")
@@ -545,6 +549,9 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     fm = fms.pop(kbest)
     for f in fms.values():
         f.free()
+    names = [name for name in args.fm_layouts.split(",") if name]
+    others = {name: qr.QuadFm(bwt, n + 1, dollar, kmer=kbest, layout=qr.LAYOUT_BY_NAME[name])
+              for name in (["16"] + names if names else [])}
     count_bytes = fm.nbytes
     if rate:
         fm.attach_locate(marks, samples, rate)
@@ -592,8 +599,9 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     line_bytes = ((n + 1) // 480 + 1) * 128
     ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
     lps = npat / t_p * work["lines_per_pattern"]
-    res["roofline"] = {"bound": "cache", "kernel": "fm_persistent_kernel", "achieved": round(achieved, 1),
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
+    res["roofline"] = {"bound": "cache", "kernel": "fm_persistent_kernel<QR16, false, false>",
+                       "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
                        "lines_per_s": lps, "line_gather_ceiling_lines_per_s": ceil_lps,
                        "frac": round(lps / ceil_lps, 4),
                        "note": "algorithmic 128-byte lines; the %.0f MB of lines fit the 256 MB memory-side cache, "
@@ -605,6 +613,13 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
             100 * achieved / HBM_PEAK_GBS, lps / 1e9, ceil_lps / 1e9, line_bytes / 1e6, 100 * lps / ceil_lps))
     log("fm persistent %.1f M patterns/s; batched best %.1f M; gain %.2fx; equal=%s" % (
         npat / t_p / 1e6, best_b / 1e6, res["gain_vs_best_batched"], res["persistent_equals_batched"]))
+    if others:
+        ref = cnt.clone()
+        res["by_layout"] = fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, others, ref, dp, do, cnt, pat,
+                                          off, npat, n, kbest, min(npat, 2_000_000))
+        res["best_layout"], _ = fm_best_layout(res["by_layout"])
+        for f in others.values():
+            f.free()
     if rate:
         # locate every occurrence of every pattern: intervals, output offsets, then the LF walks
         iv = torch.empty((npat, 2), dtype=torch.int32, device=dev)
@@ -651,22 +666,25 @@ def gather_ceiling(qr, torch, dev, nbytes, draws=1 << 24, reps=5, lanes=2):
 def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt, dollar, fm_serve):
     """The persistent count on the index the serving sweep uses (2^30 bases: its lines and start
     table exceed the 256 MB memory-side cache, so most line reads go to HBM), against one launch per
-    batch, at the start-table size of the batched row (k = 8) and of the served index."""
+    batch, at the start-table size of the batched row (k = 8) and of the served index, over the
+    served index's layout; then the same count over every layout (by_layout), whose fastest gives
+    the row's roofline."""
     n = text.size
     npat = args.fm_hbm_patterns
     pat, off, _ = datagen.patterns(4040, text, npat)
     dp, do = to_dev(pat), to_dev(off)
     cnt = torch.empty(npat, dtype=torch.int32, device=dev)
     cnt_b = torch.empty(npat, dtype=torch.int32, device=dev)
-    line_bytes = ((n + 1) // 480 + 1) * 128
+    line_bytes = ((n + 1) // FM_GEOMETRY[args.serve_layout][0] + 1) * 128
     ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
-    res = {"workload": "QuadFm count on the 2^%d-base serving text (uniform ACGT, 1000 planted 10-kb segments x20, "
+    res = {"layout": args.serve_layout,
+           "workload": "QuadFm count on the 2^%d-base serving text (uniform ACGT, 1000 planted 10-kb segments x20, "
                        "1%% subs) + sentinel; %d patterns, lengths 20..250, 90%% sampled with 1%% substitutions, "
                        "10%% iid" % (int(np.log2(n)), npat),
            "line_bytes": line_bytes, "line_gather_ceiling_lines_per_s": ceil_lps, "by_kmer": {}}
     fms = {args.serve_kmer: fm_serve}
     if args.serve_kmer != 8:
-        fms[8] = qr.QuadFm(bwt, n + 1, dollar, kmer=8)
+        fms[8] = qr.QuadFm(bwt, n + 1, dollar, kmer=8, layout=qr.LAYOUT_BY_NAME[args.serve_layout])
     for k, fm in sorted(fms.items()):
         # the persistent kernel's launch settings tuned on this index (an HBM-resident index wants
         # more patterns in flight than the cache-resident one), on the first 10^6 patterns
@@ -682,10 +700,12 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
         best_b = max(v for kk, v in row.items() if kk.startswith("batched_"))
         row["gain_vs_best_batched"] = row["persistent_patterns_per_s"] / best_b
         row["persistent_equals_batched"] = bool(torch.equal(cnt, cnt_b))
-        work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=k)
+        work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=k, layout=args.serve_layout)
         lps = npat / t_p * work["lines_per_pattern"]
         row["work"] = work
-        row["roofline"] = {"bound": "hbm", "kernel": "fm_persistent_kernel", "achieved": round(lps * 128 / 1e9, 1),
+        row["roofline"] = {"bound": "hbm",
+                           "kernel": "fm_persistent_kernel<%s, false, false>" % FM_TRAIT[args.serve_layout],
+                           "achieved": round(lps * 128 / 1e9, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(lps * 128 / 1e9 / HBM_PEAK_GBS, 4),
                            "lines_per_s": lps, "frac_of_line_gather_ceiling": round(lps / ceil_lps, 4)}
         res["by_kmer"][str(k)] = row
@@ -698,16 +718,84 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
             fm.free()
         else:
             fm.set_tuning(block=64, refill=32, waves_per_cu=8)  # the serving loop's own settings
+    names = [name for name in args.fm_layouts.split(",") if name]
+    if names:
+        k = args.serve_kmer
+        res["by_layout_kmer"] = k
+        ref = cnt.clone()
+        others = {name: qr.QuadFm(bwt, n + 1, dollar, kmer=k, layout=qr.LAYOUT_BY_NAME[name])
+                  for name in ["16"] + names}
+        res["by_layout"] = fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, others, ref, dp, do, cnt, pat, off,
+                                          npat, n, k, min(npat, 1_000_000))
+        res["best_layout"], res["roofline"] = fm_best_layout(res["by_layout"])
+        for f in others.values():
+            f.free()
     return res
 
 
-def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=8, sample=2000, seed=11):
+# bases per line and header slots of each QuadRank layout the FM-index runs on, and its trait's name
+FM_GEOMETRY = {"16": (480, 32), "16p": (480, 32), "32": (448, 64), "64": (384, 128), "24_8": (384, 128)}
+FM_TRAIT = {"16": "QR16", "16p": "QR16P", "32": "QR32", "64": "QR64", "24_8": "QR24_8"}
+
+
+def fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, fms, ref, dp, do, cnt, pat, off, npat, n, kmer,
+                   tune_sub):
+    """The persistent count of the same BWT's index over each QuadRank layout (size against
+    throughput, as the paper compares QuadFm over each rank structure): tuned launch settings, rate,
+    counts equal to the reference counts, lines per pattern in the layout's geometry and the
+    fraction of the random-line gather ceiling over an allocation of the layout's line bytes.  All
+    indexes are built before any is timed, and the rates are timed twice, in opposite orders (the
+    best of the two is reported): where an allocation lands in HBM moves a random-line rate by a
+    few per cent."""
+    rows, rates = {}, {name: [] for name in fms}
+    for name, fm in fms.items():
+        best, _ = autotune.tune("quadfm-%s-2^%d" % (name, int(np.log2(n))), n, fm.set_tuning,
+                                lambda f=fm: f.count(dp, do[:tune_sub + 1], cnt[:tune_sub]), autotune.FM_CANDIDATES,
+                                reps=2, use_cache=False)
+        rows[name] = {"tuning": best}
+    for order in (list(fms), list(fms)[::-1]):
+        for name in order:
+            rates[name].append(npat / autotune.time_launch(lambda f=fms[name]: f.count(dp, do, cnt), reps=args.fm_reps))
+            eq = bool(torch.equal(cnt, ref))
+            rows[name]["equal_to_reference"] = rows[name].get("equal_to_reference", True) and eq
+    for name, fm in fms.items():
+        rate = max(rates[name])
+        work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=kmer, layout=name)
+        data = FM_GEOMETRY[name][0]
+        line_bytes = ((n + 1) // data + 1) * 128
+        ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
+        lps = rate * work["lines_per_pattern"]
+        rows[name].update({"index_bytes": fm.nbytes, "bits_per_base": round(fm.nbytes * 8 / n, 3),
+                           "persistent_patterns_per_s": rate, "passes_patterns_per_s": rates[name],
+                           "persistent_ms": npat / rate * 1e3, "lines_per_pattern": work["lines_per_pattern"],
+                           "half_lines_per_pattern": work["half_lines_per_pattern"], "lines_per_s": lps,
+                           "line_gather_ceiling_lines_per_s": ceil_lps,
+                           "frac_of_line_gather_ceiling": round(lps / ceil_lps, 4)})
+        log("fm 2^%d k=%d layout %s: %.1f M patterns/s (passes %s), %.3f bits/base, %.1f lines/pattern, %.0f%% of the "
+            "gather ceiling (%.2f G lines/s), equal=%s" % (
+                int(np.log2(n)), kmer, name, rate / 1e6, " ".join("%.1f" % (r / 1e6) for r in rates[name]),
+                fm.nbytes * 8 / n, work["lines_per_pattern"], 100 * lps / ceil_lps, ceil_lps / 1e9,
+                rows[name]["equal_to_reference"]))
+    return rows
+
+
+def fm_best_layout(rows):
+    """The layout with the highest count rate, and a roofline object for its kernel."""
+    name = max(rows, key=lambda k: rows[k]["persistent_patterns_per_s"])
+    r = rows[name]
+    return name, {"bound": "hbm", "kernel": "fm_persistent_kernel<%s, false, false>" % FM_TRAIT[name],
+                  "layout": name, "achieved": round(r["lines_per_s"] * 128 / 1e9, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(r["lines_per_s"] * 128 / 1e9 / HBM_PEAK_GBS, 4),
+                  "lines_per_s": r["lines_per_s"], "frac_of_line_gather_ceiling": r["frac_of_line_gather_ceiling"]}
+
+
+def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=8, sample=2000, seed=11, layout="16"):
     """Backward steps, lines and half-line loads per pattern, on a sample of the workload: the
     search of P starts from the interval of its last K = kmer characters and step k (k = 1..m-K)
     turns the interval of the suffix P[m-K-k+1..m) into that of P[m-K-k..m), stopping once it is
     empty.  A step reads one 128-byte line when sp and ep share a line (else two), and one 64-byte
-    half when they share a half line (else two halves).  The suffix intervals come from
-    quadfm_intervals."""
+    half when they share a half line (else two halves), in the line geometry of the index's QuadRank
+    layout.  The suffix intervals come from quadfm_intervals."""
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(npat, min(sample, npat), replace=False))
     sufs, owner = [], []
@@ -720,7 +808,8 @@ def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=8, sample=2000, s
     soff = np.zeros(len(sufs) + 1, np.uint64)
     soff[1:] = np.cumsum([x.size for x in sufs])
     iv = fm.intervals(to_dev(np.concatenate(sufs)), to_dev(soff)).cpu().numpy().view(np.uint32).astype(np.int64)
-    DATA, HDR, MID = 480, 32, 256  # the FM index's 16-bit QuadRank layout
+    DATA, HDR = FM_GEOMETRY[layout]
+    MID = 256
     steps = lines = halves = 0
     i = 0
     for p in idx:
@@ -755,7 +844,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     else:
         bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0)
     t1 = time.time()
-    fm = qr.QuadFm(bwt, n + 1, dollar, kmer=args.serve_kmer)
+    fm = qr.QuadFm(bwt, n + 1, dollar, kmer=args.serve_kmer, layout=qr.LAYOUT_BY_NAME[args.serve_layout])
     hbm_row = None
     if not args.no_fm_hbm:
         from paper_2602_04103_amd import autotune
@@ -770,7 +859,8 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     res = {"workload": "QuadFm serving: 2^%d-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs); "
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
-           "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "device_free_bytes_at_start": int(free),
+           "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "layout": args.serve_layout,
+           "device_free_bytes_at_start": int(free),
            "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": [],
            "fm_count_hbm": hbm_row}
     # warm-up (untimed): first launches, pinned-memory pools, stream creation

@@ -210,6 +210,15 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
  * from it. */
 int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
                     hipStream_t stream, qr_quadfm *out);
+/* Same over another QuadRank layout (Appendix D: QuadFm is instantiated with each rank structure
+ * for the DNA alphabet): QR_LAYOUT_16 (the default of the calls above), QR_LAYOUT_16P,
+ * QR_LAYOUT_32, QR_LAYOUT_64 or QR_LAYOUT_24_8, each as described for quadrank_build_ex; the
+ * layout sets the index's size (quadfm_bytes) and which bytes each backward step reads, not its
+ * results.  QR_EINVAL for QR_LAYOUT_16X2 or an unknown value. */
+int quadfm_build_layout(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
+                        int layout, hipStream_t stream, qr_quadfm *out);
+/* The QR_LAYOUT_* value the index was built with (-1 for NULL). */
+int quadfm_layout_kind(qr_quadfm h);
 /* Count occurrences of npat patterns given in CSR form: pattern p is the codes
  * d_pat[d_off[p] .. d_off[p+1]) (u8 codes 0..3; u64 offsets, npat+1 of them); d_count[p] receives
  * the size of its BWT interval (u32).  An empty pattern counts n+1; a pattern with a code > 3
@@ -396,7 +405,8 @@ int qr_gather_lanes_bench_ex(const void *d_lines, uint64_t n_lines, const uint64
  * which = 0 -> floor(x / 1008) (BiRank), 1 -> floor(x / 480) (QuadRank), 2 -> floor(x / 992)
  * (BiRank, QR_LAYOUT_32), 3 -> floor(x / 448) (QuadRank, QR_LAYOUT_32), 4 -> floor(x / 480) by the
  * FM-index search's 32-bit form (x < 2^32; ~0 above), 5 -> floor(x / 960) (BiRank, QR_LAYOUT_64),
- * 6 -> floor(x / 384) (QuadRank, QR_LAYOUT_64 and QR_LAYOUT_24_8); other values give ~0. */
+ * 6 -> floor(x / 384) (QuadRank, QR_LAYOUT_64 and QR_LAYOUT_24_8), 7 -> floor(x / 448) and
+ * 8 -> floor(x / 384) by the 32-bit form (x < 2^32; ~0 above); other values give ~0. */
 uint64_t qr_line_of(uint64_t x, int which);
 
 #ifdef __cplusplus

@@ -107,6 +107,8 @@ def lib():
             "quadfm_index_device": (ci, [vp, u64, C.c_uint32, vp, C.POINTER(u64), vp, vp, vp, vp]),
             "quadfm_intervals": (ci, [vp, vp, u64, vp, u64, vp, vp]),
             "quadfm_build_ex": (ci, [vp, u64, u64, C.c_uint32, vp, C.POINTER(vp)]),
+            "quadfm_build_layout": (ci, [vp, u64, u64, C.c_uint32, ci, vp, C.POINTER(vp)]),
+            "quadfm_layout_kind": (ci, [vp]),
             "quadfm_locate_attach": (ci, [vp, vp, vp, u64, C.c_uint32, vp]),
             "quadfm_locate_offsets": (ci, [vp, vp, u64, vp, vp]),
             "quadfm_locate": (ci, [vp, vp, vp, u64, u64, vp, vp]),
@@ -310,10 +312,11 @@ def quadfm_index_device(text: torch.Tensor, rate: int = 0, stream=None, sa: torc
     return bwt, int(d.value), marks, samples
 
 
-def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None, kmer: int = 8) -> int:
+def quadfm_build(bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None, kmer: int = 8,
+                 layout: int = QR_LAYOUT_16) -> int:
     h = vp()
-    _check(lib().quadfm_build_ex(_dev(bwt_packed2, "bwt_packed2", W64, (n_plus_1 + 31) // 32), n_plus_1, dollar_pos,
-                                 kmer, _stream(stream), C.byref(h)), "quadfm_build")
+    _check(lib().quadfm_build_layout(_dev(bwt_packed2, "bwt_packed2", W64, (n_plus_1 + 31) // 32), n_plus_1,
+                                     dollar_pos, kmer, layout, _stream(stream), C.byref(h)), "quadfm_build")
     return h.value
 
 
@@ -567,31 +570,34 @@ class QuadFm(_Handle):
     """Count-only FM-index built from a packed BWT of T$ ('$' stored as A at row dollar_pos)."""
     _free = staticmethod(quadfm_free)
 
-    def __init__(self, bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None, kmer: int = 8):
-        super().__init__(quadfm_build(bwt_packed2, n_plus_1, dollar_pos, stream, kmer))
+    def __init__(self, bwt_packed2: torch.Tensor, n_plus_1: int, dollar_pos: int, stream=None, kmer: int = 8,
+                 layout: int = QR_LAYOUT_16):
+        super().__init__(quadfm_build(bwt_packed2, n_plus_1, dollar_pos, stream, kmer, layout))
         self.kmer = kmer
+        self.layout = layout
         self.n = n_plus_1 - 1
 
     @classmethod
-    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = True, kmer: int = 8):
+    def from_text(cls, text_codes, stream=None, locate_rate: int = 0, device_sa: bool = True, kmer: int = 8,
+                  layout: int = QR_LAYOUT_16):
         """Suffix array and BWT built on the device (device_sa=False: on the host with SA-IS), then
-        the index build; with locate_rate > 0 also the suffix-array sample at that rate, attached
-        for locate."""
+        the index build over the QuadRank layout `layout`; with locate_rate > 0 also the suffix-array
+        sample at that rate, attached for locate."""
         import numpy as np
         n1 = int(np.asarray(text_codes).size) + 1
         if device_sa:
             t = torch.from_numpy(np.ascontiguousarray(text_codes, dtype=np.uint8)).cuda()
             bwt, dollar, marks, samples = quadfm_index_device(t, locate_rate, stream)
             del t
-            fm = cls(bwt, n1, dollar, stream, kmer)
+            fm = cls(bwt, n1, dollar, stream, kmer, layout)
             if locate_rate:
                 fm.attach_locate(marks, samples, locate_rate, stream)
             return fm
         if not locate_rate:
             bwt, dollar = quadfm_bwt_host(text_codes)
-            return cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream, kmer)
+            return cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream, kmer, layout)
         bwt, dollar, marks, samples = quadfm_index_host(text_codes, locate_rate)
-        fm = cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream, kmer)
+        fm = cls(torch.from_numpy(bwt.view(np.int64)).cuda(), n1, dollar, stream, kmer, layout)
         fm.attach_locate(torch.from_numpy(marks.view(np.int64)).cuda(), torch.from_numpy(samples.view(np.int32)).cuda(),
                          locate_rate, stream)
         return fm

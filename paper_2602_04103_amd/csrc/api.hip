@@ -70,9 +70,11 @@ uint64_t qr_line_of(uint64_t x, int which) {
         case 1: return qr::qline_of<qr::QR16>(x);
         case 2: return qr::line_of<qr::BR32>(x);
         case 3: return qr::qline_of<qr::QR32>(x);
-        case 4: return x <= 0xffffffffull ? qr::qr_line_of32((uint32_t)x) : ~0ull;
+        case 4: return x <= 0xffffffffull ? qr::qline_of32<qr::QR16>((uint32_t)x) : ~0ull;
         case 5: return qr::line_of<qr::BR64>(x);
         case 6: return qr::qline_of<qr::QR64>(x);
+        case 7: return x <= 0xffffffffull ? qr::qline_of32<qr::QR32>((uint32_t)x) : ~0ull;
+        case 8: return x <= 0xffffffffull ? qr::qline_of32<qr::QR64>((uint32_t)x) : ~0ull;
         default: return ~0ull;
     }
 }

@@ -43,7 +43,7 @@ hipError_t launch_scan_counts(const uint32_t *cnt, uint64_t nrow, int ncol, uint
 //   1008 (BiRank payload):  s = 73, e = 880 -> exact for x < 2^63
 //    480 (QuadRank payload): s = 72, e = 224 -> exact for x < 2^63
 // The BiRank constants live with its layout traits (birank_dev.hpp); the 16-bit QuadRank constants
-// below serve the FM-index, whose BWT uses that layout.
+// below are those of its trait QR16 (quadrank_dev.hpp).
 constexpr uint64_t QR_DATA_BASES = 480;  // bases per QuadRank line
 constexpr uint64_t QR_LINES_PER_SB = 128;
 constexpr uint64_t QR_SB_BASES = QR_DATA_BASES * QR_LINES_PER_SB;  // 61440 = 1920 input words
@@ -57,13 +57,6 @@ __host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
     return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) >> 64);
 }
 __host__ __device__ __forceinline__ uint64_t qr_line_of(uint64_t q) { return mulhi64(q, QR_MAGIC) >> QR_MAGIC_T; }
-
-// floor(q / 480) for every 32-bit q, with one 32-bit multiply-high: q / 480 = (q >> 5) / 15, and
-// m = ceil(2^32 / 15) = 0x11111112 has e = 14, so floor(y * m / 2^32) = floor(y / 15) for
-// y < 2^32 / 14, which covers y = q >> 5 < 2^27.  (Checked against division for all 2^32 values.)
-__host__ __device__ __forceinline__ uint32_t qr_line_of32(uint32_t q) {
-    return (uint32_t)(((uint64_t)(q >> 5) * 0x11111112ull) >> 32);
-}
 
 // Mask selecting bit positions [0, t) of the 32-bit word that covers positions [32k, 32k+32).
 __device__ __forceinline__ uint32_t prefix_mask32(uint32_t t, uint32_t k) {

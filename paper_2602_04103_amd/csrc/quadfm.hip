@@ -1,5 +1,6 @@
 // QuadFm on gfx950 (paper Appendix D): a count-only FM-index over the DNA alphabet whose rank
-// queries run on the QuadRank layout.
+// queries run on a QuadRank layout: the 16-bit one by default, or any other QuadRank layout (the
+// paper instantiates QuadFm with each of its rank structures).
 //
 // Index over T$ (length n+1):
 //   - BWT of T$ with the single '$' stored as A at row dollar; rank_B(q, A) = rank(q, A) - [q > dollar]
@@ -39,7 +40,8 @@
 using namespace qr;
 
 namespace qr {
-int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, uint32_t *super, hipStream_t stream);
+int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, int layout, uint64_t *lines, void *super,
+                        hipStream_t stream);
 }
 
 struct qr_quadfm_s {
@@ -47,9 +49,10 @@ struct qr_quadfm_s {
     uint64_t n1;      // BWT length = n + 1
     uint64_t dollar;  // row of '$'
     uint64_t C[4];
-    uint64_t n_lines, n_sb;
+    int layout;              // QuadRank layout of the BWT's rank structure (QR_LAYOUT_*)
+    uint64_t n_lines, super_bytes;
     uint64_t *lines;
-    uint32_t *super;
+    void *super;             // the layout's offset array (a placeholder of 16 bytes when it has none)
     uint2 *table;                // 4^8 intervals (sp, ep)
     unsigned long long *head;    // device work-queue head
     uint32_t *err;               // sticky device error word (locate)
@@ -68,7 +71,7 @@ constexpr uint32_t KMER_DEFAULT = 8, KMER_MAX = 12;  // the start table holds 4^
 
 struct FmDev {
     const uint4 *lines;
-    const uint32_t *super;
+    const void *super;
     const uint2 *table;
     uint64_t n1, dollar;
     uint64_t C0, C1, C2, C3;
@@ -87,9 +90,15 @@ __device__ __forceinline__ uint64_t fm_C(const FmDev &f, uint32_t c) {
 }
 
 
+template <class L>
+__device__ __forceinline__ const typename L::Super *super_of(const FmDev &f) {
+    return reinterpret_cast<const typename L::Super *>(f.super);
+}
+
 // The search works in 32-bit positions and ranks: the build admits at most 2^32 - 1 BWT rows.
-__device__ __forceinline__ uint32_t rank_bwt32(const FmDev &f, const HalfLine &h, uint32_t q, uint32_t c) {
-    uint32_t r = rank1_from_half32(h, c);
+template <class L>
+__device__ __forceinline__ uint32_t rank_bwt32(const FmDev &f, const LaneHalf &h, uint32_t q, uint32_t c) {
+    uint32_t r = lane_rank<L>(h, lane_slot<L>(q, h.j), c);
     if (c == 0) r -= q > f.dollar;
     return r;
 }
@@ -97,52 +106,52 @@ __device__ __forceinline__ uint32_t rank_bwt32(const FmDev &f, const HalfLine &h
 // One backward step of the interval [sp, ep) with symbol c.  When sp and ep lie in the same half
 // line (most steps once the interval is small) both ranks come from one load: the second load is
 // issued only by the lanes whose ep lies elsewhere.
+template <class L>
 __device__ __forceinline__ void fm_step(const FmDev &f, uint32_t c, uint32_t &sp, uint32_t &ep) {
-    HalfLine a;
-    load_half32(f.lines, f.super, sp, a);
-    const uint32_t js = qr_line_of32(sp), je = qr_line_of32(ep);
-    const uint32_t ps = sp - js * (uint32_t)QR_DATA_BASES + QR_HDR, pe = ep - je * (uint32_t)QR_DATA_BASES + QR_HDR;
-    const bool ups = ps >= QR_MID, upe = pe >= QR_MID;
+    LaneHalf a;
+    load_lane_half<L>(f.lines, super_of<L>(f), sp, a);
+    const uint32_t je = qline_of32<L>(ep);
+    const bool same = a.j == je && (lane_slot<L>(sp, a.j) >= L::MID) == (lane_slot<L>(ep, je) >= L::MID);
     const uint32_t base = (uint32_t)fm_C(f, c);
-    const uint32_t rs = rank_bwt32(f, a, sp, c);
+    const uint32_t rs = rank_bwt32<L>(f, a, sp, c);
     uint32_t re;
-    if (js == je && ups == upe) {
-        HalfLine b = a;
-        b.t = upe ? pe - QR_MID : pe;
-        re = rank_bwt32(f, b, ep, c);
+    if (same) {
+        re = rank_bwt32<L>(f, a, ep, c);
     } else {
-        HalfLine b;
-        load_half32(f.lines, f.super, ep, b);
-        re = rank_bwt32(f, b, ep, c);
+        LaneHalf b;
+        load_lane_half<L>(f.lines, super_of<L>(f), ep, b);
+        re = rank_bwt32<L>(f, b, ep, c);
     }
     sp = base + rs;
     ep = base + re;
 }
 
+template <class L>
 __global__ __launch_bounds__(256) void fm_table_kernel(FmDev f, uint2 *__restrict__ table) {
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= (1u << (2 * f.kmer))) return;
     uint32_t sp = 0, ep = (uint32_t)f.n1;
-    for (uint32_t k = 0; k < f.kmer && sp < ep; ++k) fm_step(f, (w >> (2 * k)) & 3u, sp, ep);
+    for (uint32_t k = 0; k < f.kmer && sp < ep; ++k) fm_step<L>(f, (w >> (2 * k)) & 3u, sp, ep);
     if (sp >= ep) sp = ep = 0;
     table[w] = make_uint2((uint32_t)sp, (uint32_t)ep);
 }
 
 // Totals of each symbol in the BWT (rank at n+1) with '$' removed from A, and out4[4] = 1 iff
-// the row of '$' holds A as the layout requires.
+// the row of '$' holds A as the index requires.
+template <class L>
 __global__ void fm_totals_kernel(FmDev f, unsigned long long *__restrict__ out4) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    HalfLine h, d0, d1;
-    load_half(f.lines, f.super, f.n1, h);
-    uint64_t r[4];
-    rank4_from_half(h, r);
-    load_half(f.lines, f.super, f.dollar, d0);
-    load_half(f.lines, f.super, f.dollar + 1, d1);
-    out4[0] = r[0] - 1;
-    out4[1] = r[1];
-    out4[2] = r[2];
-    out4[3] = r[3];
-    out4[4] = rank1_from_half(d1, 0) - rank1_from_half(d0, 0);
+    const uint32_t n1 = (uint32_t)f.n1, d = (uint32_t)f.dollar;
+    LaneHalf h, d0, d1;
+    load_lane_half<L>(f.lines, super_of<L>(f), n1, h);
+    load_lane_half<L>(f.lines, super_of<L>(f), d, d0);
+    load_lane_half<L>(f.lines, super_of<L>(f), d + 1, d1);
+    const uint32_t p = lane_slot<L>(n1, h.j);
+    out4[0] = (uint64_t)lane_rank<L>(h, p, 0) - 1;
+    out4[1] = lane_rank<L>(h, p, 1);
+    out4[2] = lane_rank<L>(h, p, 2);
+    out4[3] = lane_rank<L>(h, p, 3);
+    out4[4] = lane_rank<L>(d1, lane_slot<L>(d + 1, d1.j), 0) - lane_rank<L>(d0, lane_slot<L>(d, d0.j), 0);
 }
 
 // Per-lane search state.  The backward search over a pattern P reads P from its end; over the
@@ -258,7 +267,7 @@ __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restric
 }
 
 // Advance one character; returns true when the pattern's count is final (in cnt).
-template <bool BOTH>
+template <class L, bool BOTH>
 __device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &cnt) {
     const uint32_t c = next_char(s);
     bool fin;
@@ -266,7 +275,7 @@ __device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &
         cnt = 0;
         fin = true;
     } else {
-        fm_step(f, c, s.sp, s.ep);
+        fm_step<L>(f, c, s.sp, s.ep);
         --s.left;
         fin = s.sp >= s.ep || s.left == 0;
         if (fin) cnt = s.sp < s.ep ? (uint32_t)(s.ep - s.sp) : 0u;
@@ -295,7 +304,7 @@ __device__ __forceinline__ void emit(const FmDev &f, uint32_t *__restrict__ out,
     reinterpret_cast<uint2 *>(out)[p] = v;
 }
 
-template <bool BOTH, bool IV>
+template <class L, bool BOTH, bool IV>
 __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                        const uint64_t *__restrict__ off, uint64_t p0, uint64_t np,
                                                        uint32_t *__restrict__ out) {
@@ -305,14 +314,14 @@ __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *_
     Search s;
     uint32_t cnt = 0;
     if (!fm_init<BOTH>(f, pat, off, p, s, cnt))
-        while (!fm_advance<BOTH>(f, s, cnt)) {
+        while (!fm_advance<L, BOTH>(f, s, cnt)) {
         }
     emit<IV>(f, out, p, s, cnt);
 }
 
 __global__ void fill_zero_u64(unsigned long long *p) { *p = 0ull; }
 
-template <bool BOTH, bool IV>
+template <class L, bool BOTH, bool IV>
 __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                             const uint64_t *__restrict__ off, uint64_t npat,
                                                             uint32_t *__restrict__ out,
@@ -355,7 +364,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
         }
         if (active) {
             uint32_t cnt = 0;
-            if (fm_advance<BOTH>(f, s, cnt)) {
+            if (fm_advance<L, BOTH>(f, s, cnt)) {
                 emit<IV>(f, out, p, s, cnt);
                 active = false;
             }
@@ -454,6 +463,7 @@ struct LocDev {
 
 // SA[row] by LF steps to the nearest marked row (at most rate - 1 of them); false if none is
 // reached within rate steps, which only inconsistent sample data can cause.
+template <class L>
 __device__ __forceinline__ bool sa_of_row(const FmDev &f, const LocDev &d, uint64_t row64, uint32_t &pos) {
     if (row64 >= f.n1) return false;
     uint32_t row = (uint32_t)row64;  // rows of an FM-index are below 2^32
@@ -464,16 +474,17 @@ __device__ __forceinline__ bool sa_of_row(const FmDev &f, const LocDev &d, uint6
             pos = d.samples[k] + steps;
             return true;
         }
-        HalfLine h;
-        load_half32(f.lines, f.super, row, h);
-        const uint32_t c = symbol_from_half(h);
-        row = (uint32_t)fm_C(f, c) + rank_bwt32(f, h, row, c);
+        LaneHalf h;
+        load_lane_half<L>(f.lines, super_of<L>(f), row, h);
+        const uint32_t c = lane_symbol(h, lane_slot<L>(row, h.j));
+        row = (uint32_t)fm_C(f, c) + rank_bwt32<L>(f, h, row, c);
     }
     return false;
 }
 
 // One lane per output: output g belongs to the last pattern p with start[p] <= g, and is
 // SA[sp_p + g - start[p]].
+template <class L>
 __global__ __launch_bounds__(256) void fm_locate_kernel(FmDev f, LocDev d, const uint2 *__restrict__ iv,
                                                         const unsigned long long *__restrict__ start, uint64_t npat,
                                                         uint64_t total, uint32_t *__restrict__ pos,
@@ -488,12 +499,29 @@ __global__ __launch_bounds__(256) void fm_locate_kernel(FmDev f, LocDev d, const
         }
         const uint64_t row = iv[lo].x + (g - start[lo]);
         uint32_t v = 0;
-        if (!sa_of_row(f, d, row, v)) {
+        if (!sa_of_row<L>(f, d, row, v)) {
             v = 0xffffffffu;
             atomicOr(err, ERR_WALK);
         }
         pos[g] = v;
     }
+}
+
+// f(L{}) for the trait type of a QuadRank layout the index can use (the 16-bit one by default).
+template <class F>
+auto fm_layout(int layout, F &&f) {
+    switch (layout) {
+        case QR_LAYOUT_16P: return f(QR16P{});
+        case QR_LAYOUT_32: return f(QR32{});
+        case QR_LAYOUT_64: return f(QR64{});
+        case QR_LAYOUT_24_8: return f(QR24_8{});
+        default: return f(QR16{});
+    }
+}
+
+bool fm_layout_ok(int layout) {
+    return layout == QR_LAYOUT_16 || layout == QR_LAYOUT_16P || layout == QR_LAYOUT_32 || layout == QR_LAYOUT_64 ||
+           layout == QR_LAYOUT_24_8;
 }
 
 void release(qr_quadfm_s *h) {
@@ -549,10 +577,15 @@ int count_args(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint
 
 extern "C" {
 
-int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
-                    hipStream_t stream, qr_quadfm *out) {
+int quadfm_build_layout(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
+                        int layout, hipStream_t stream, qr_quadfm *out) {
     if (!out) return QR_EINVAL;
     *out = nullptr;
+    if (!fm_layout_ok(layout)) {
+        set_error("quadfm_build: layout %d is not a QuadRank layout with one-lane queries (16, 16P, 32, 64, 24_8)",
+                  layout);
+        return QR_EINVAL;
+    }
     if (kmer < 1 || kmer > KMER_MAX) {
         set_error("quadfm_build: the start table resolves 1..%u characters, not %u", KMER_MAX, kmer);
         return QR_EINVAL;
@@ -574,12 +607,19 @@ int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t d
     h->n1 = n_plus_1;
     h->dollar = dollar_pos;
     h->kmer = kmer;
+    h->layout = layout;
     const uint64_t entries = 1ull << (2 * kmer);
-    h->n_lines = n_plus_1 / QR_DATA_BASES + 1;
-    h->n_sb = n_plus_1 / QR_SB_BASES + 1;
+    fm_layout(layout, [&](auto tag) {
+        using L = decltype(tag);
+        h->n_lines = n_plus_1 / L::DATA + 1;
+        const uint64_t n_sb = L::SB_LINES ? (h->n_lines - 1) / L::SB_LINES + 1 : 0;
+        h->super_bytes = n_sb * 4 * sizeof(typename L::Super);
+        return 0;
+    });
     h->tune = qr_tuning{256, 16, 16, 0, 0};
     unsigned long long *tot = nullptr;
-    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess || hipMalloc(&h->super, h->n_sb * 16) != hipSuccess ||
+    if (hipMalloc(&h->lines, h->n_lines * 128) != hipSuccess ||
+        hipMalloc(&h->super, std::max<uint64_t>(h->super_bytes, 16)) != hipSuccess ||
         hipMalloc(&h->table, entries * sizeof(uint2)) != hipSuccess || hipMalloc(&h->head, 8) != hipSuccess ||
         hipMalloc(&h->err, 4) != hipSuccess || hipMalloc(&tot, 40) != hipSuccess) {
         (void)hipGetLastError();
@@ -588,14 +628,17 @@ int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t d
         set_error("quadfm_build: device allocation failed");
         return QR_ENOMEM;
     }
-    int rc = quadrank_build_into(d_bwt_packed2, n_plus_1, h->lines, h->super, stream);
+    int rc = quadrank_build_into(d_bwt_packed2, n_plus_1, layout, h->lines, h->super, stream);
     if (rc) {
         (void)hipFree(tot);
         release(h);
         return rc;
     }
     FmDev f = dev_view(h);
-    hipLaunchKernelGGL(fm_totals_kernel, dim3(1), dim3(64), 0, stream, f, tot);
+    fm_layout(layout, [&](auto tag) {
+        hipLaunchKernelGGL(fm_totals_kernel<decltype(tag)>, dim3(1), dim3(64), 0, stream, f, tot);
+        return 0;
+    });
     unsigned long long t[5] = {0, 0, 0, 0, 0};
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(t, tot, 40, hipMemcpyDeviceToHost, stream);
@@ -617,7 +660,11 @@ int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t d
         return QR_EINVAL;
     }
     f = dev_view(h);
-    hipLaunchKernelGGL(fm_table_kernel, dim3((uint32_t)((entries + 255) / 256)), dim3(256), 0, stream, f, h->table);
+    fm_layout(layout, [&](auto tag) {
+        hipLaunchKernelGGL(fm_table_kernel<decltype(tag)>, dim3((uint32_t)((entries + 255) / 256)), dim3(256), 0, stream,
+                           f, h->table);
+        return 0;
+    });
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemsetAsync(h->err, 0, 4, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -630,10 +677,17 @@ int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t d
     return QR_OK;
 }
 
+int quadfm_build_ex(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, uint32_t kmer,
+                    hipStream_t stream, qr_quadfm *out) {
+    return quadfm_build_layout(d_bwt_packed2, n_plus_1, dollar_pos, kmer, QR_LAYOUT_16, stream, out);
+}
+
 int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t dollar_pos, hipStream_t stream,
                  qr_quadfm *out) {
-    return quadfm_build_ex(d_bwt_packed2, n_plus_1, dollar_pos, KMER_DEFAULT, stream, out);
+    return quadfm_build_layout(d_bwt_packed2, n_plus_1, dollar_pos, KMER_DEFAULT, QR_LAYOUT_16, stream, out);
 }
+
+int quadfm_layout_kind(qr_quadfm h) { return h ? h->layout : -1; }
 
 // flags: QUADFM_BOTH_STRANDS; iv: write intervals (uint2 per pattern) instead of counts
 static int count_persistent(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
@@ -649,15 +703,19 @@ static int count_persistent(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_byte
     const dim3 g((uint32_t)blocks), b(block);
     FmDev f = dev_view(h);
     f.pat_len = pat_bytes;
-    if (iv)
-        hipLaunchKernelGGL((fm_persistent_kernel<false, true>), g, b, 0, stream, f, d_pat, d_off, npat, d_count, head,
-                           refill);
-    else if (flags & QUADFM_BOTH_STRANDS)
-        hipLaunchKernelGGL((fm_persistent_kernel<true, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count, head,
-                           refill);
-    else
-        hipLaunchKernelGGL((fm_persistent_kernel<false, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count, head,
-                           refill);
+    fm_layout(h->layout, [&](auto tag) {
+        using L = decltype(tag);
+        if (iv)
+            hipLaunchKernelGGL((fm_persistent_kernel<L, false, true>), g, b, 0, stream, f, d_pat, d_off, npat, d_count,
+                               head, refill);
+        else if (flags & QUADFM_BOTH_STRANDS)
+            hipLaunchKernelGGL((fm_persistent_kernel<L, true, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count,
+                               head, refill);
+        else
+            hipLaunchKernelGGL((fm_persistent_kernel<L, false, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count,
+                               head, refill);
+        return 0;
+    });
     QR_HIP(hipGetLastError());
     return QR_OK;
 }
@@ -775,12 +833,16 @@ int quadfm_count_batched_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_byte
             set_error("quadfm_count_batched: batch too large");
             return QR_EINVAL;
         }
-        if (flags & QUADFM_BOTH_STRANDS)
-            hipLaunchKernelGGL((fm_batch_kernel<true, false>), dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat, d_off,
-                               p0, np, d_count);
-        else
-            hipLaunchKernelGGL((fm_batch_kernel<false, false>), dim3((uint32_t)blocks), dim3(256), 0, stream, f, d_pat,
-                               d_off, p0, np, d_count);
+        fm_layout(h->layout, [&](auto tag) {
+            using L = decltype(tag);
+            if (flags & QUADFM_BOTH_STRANDS)
+                hipLaunchKernelGGL((fm_batch_kernel<L, true, false>), dim3((uint32_t)blocks), dim3(256), 0, stream, f,
+                                   d_pat, d_off, p0, np, d_count);
+            else
+                hipLaunchKernelGGL((fm_batch_kernel<L, false, false>), dim3((uint32_t)blocks), dim3(256), 0, stream, f,
+                                   d_pat, d_off, p0, np, d_count);
+            return 0;
+        });
         QR_HIP(hipGetLastError());
     }
     return QR_OK;
@@ -920,9 +982,12 @@ int quadfm_locate(qr_quadfm h, const uint32_t *d_iv, const uint64_t *d_start, ui
     d.samples = h->samples;
     d.rate = h->rate;
     const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, (uint64_t)cu_count() * 32));
-    hipLaunchKernelGGL(fm_locate_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, dev_view(h), d,
-                       reinterpret_cast<const uint2 *>(d_iv), reinterpret_cast<const unsigned long long *>(d_start), npat,
-                       total, d_pos, h->err);
+    fm_layout(h->layout, [&](auto tag) {
+        hipLaunchKernelGGL(fm_locate_kernel<decltype(tag)>, dim3((uint32_t)blocks), dim3(256), 0, stream, dev_view(h), d,
+                           reinterpret_cast<const uint2 *>(d_iv), reinterpret_cast<const unsigned long long *>(d_start),
+                           npat, total, d_pos, h->err);
+        return 0;
+    });
     QR_HIP(hipGetLastError());
     return QR_OK;
 }
@@ -935,7 +1000,7 @@ int quadfm_free(qr_quadfm h) {
 uint64_t quadfm_len(qr_quadfm h) { return h ? h->n1 - 1 : 0; }
 uint64_t quadfm_bytes(qr_quadfm h) {
     if (!h) return 0;
-    return h->n_lines * 128 + h->n_sb * 16 + (1ull << (2 * h->kmer)) * sizeof(uint2) +
+    return h->n_lines * 128 + h->super_bytes + (1ull << (2 * h->kmer)) * sizeof(uint2) +
            (h->marks ? birank_bytes(h->marks) + h->n_samples * 4 : 0);
 }
 

@@ -790,9 +790,10 @@ int launch_rank4(qr_quadrank h, const uint64_t *d_q, uint64_t nq, uint64_t *d_ou
 
 namespace qr {
 
-// Build the 16-bit QuadRank layout into caller-provided arrays (used by the FM-index build).
-int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, uint64_t *lines, uint32_t *super, hipStream_t stream) {
-    hipError_t e = build_t<QR16>(d_packed2, n, lines, super, stream);
+// Build a QuadRank layout into caller-provided arrays (used by the FM-index build).
+int quadrank_build_into(const uint64_t *d_packed2, uint64_t n, int layout, uint64_t *lines, void *super,
+                        hipStream_t stream) {
+    hipError_t e = qr_dispatch(layout, [&](auto tag) { return build_t<decltype(tag)>(d_packed2, n, lines, super, stream); });
     if (e == hipErrorOutOfMemory) {
         set_error("quadrank build: temporary allocation failed");
         return QR_ENOMEM;

@@ -6,62 +6,6 @@
 
 namespace qr {
 
-// The half line that holds query position q, plus what is needed to finish rank(q, .).
-struct HalfLine {
-    uint32_t w[16];  // the 64-byte half: pair k (0..3) = lo_k (w[4k], w[4k+1]), hi_k (w[4k+2], w[4k+3])
-    uint32_t dAC;    // b_A | b_C << 16
-    uint32_t dGT;    // b_G | b_T << 16
-    uint4 s;         // the four superblock offsets s_{i,A..T}
-    uint32_t t;      // slot of q inside the half (0..255)
-    bool up;         // q lies in the upper half (count forward from the middle)
-};
-
-__device__ __forceinline__ void load_half(const uint4 *__restrict__ lines, const uint32_t *__restrict__ super,
-                                          uint64_t q, HalfLine &hl) {
-    const uint64_t j = qr_line_of(q);
-    const uint32_t p = (uint32_t)(q - j * QR_DATA_BASES) + QR_HDR;
-    hl.up = p >= QR_MID;
-    hl.t = hl.up ? p - QR_MID : p;
-    const uint4 *L = lines + j * 8;
-    const uint4 *H = L + (hl.up ? 4 : 0);
-    const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
-    hl.w[0] = a.x, hl.w[1] = a.y, hl.w[2] = a.z, hl.w[3] = a.w;
-    hl.w[4] = b.x, hl.w[5] = b.y, hl.w[6] = b.z, hl.w[7] = b.w;
-    hl.w[8] = c.x, hl.w[9] = c.y, hl.w[10] = c.z, hl.w[11] = c.w;
-    hl.w[12] = d.x, hl.w[13] = d.y, hl.w[14] = d.z, hl.w[15] = d.w;
-    if (hl.up) {
-        const uint4 h0 = L[0];
-        hl.dAC = h0.x, hl.dGT = h0.z;
-    } else {
-        hl.dAC = a.x, hl.dGT = a.z;
-    }
-    hl.s = reinterpret_cast<const uint4 *>(super)[j / QR_LINES_PER_SB];
-}
-
-// load_half for positions below 2^32 (every position of an FM-index, whose BWT has fewer than 2^32
-// rows), with 32-bit line arithmetic.
-__device__ __forceinline__ void load_half32(const uint4 *__restrict__ lines, const uint32_t *__restrict__ super,
-                                            uint32_t q, HalfLine &hl) {
-    const uint32_t j = qr_line_of32(q);
-    const uint32_t p = q - j * (uint32_t)QR_DATA_BASES + QR_HDR;
-    hl.up = p >= QR_MID;
-    hl.t = hl.up ? p - QR_MID : p;
-    const uint4 *L = lines + (uint64_t)j * 8;
-    const uint4 *H = L + (hl.up ? 4 : 0);
-    const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
-    hl.w[0] = a.x, hl.w[1] = a.y, hl.w[2] = a.z, hl.w[3] = a.w;
-    hl.w[4] = b.x, hl.w[5] = b.y, hl.w[6] = b.z, hl.w[7] = b.w;
-    hl.w[8] = c.x, hl.w[9] = c.y, hl.w[10] = c.z, hl.w[11] = c.w;
-    hl.w[12] = d.x, hl.w[13] = d.y, hl.w[14] = d.z, hl.w[15] = d.w;
-    if (hl.up) {
-        const uint4 h0 = L[0];
-        hl.dAC = h0.x, hl.dGT = h0.z;
-    } else {
-        hl.dAC = a.x, hl.dGT = a.z;
-    }
-    hl.s = reinterpret_cast<const uint4 *>(super)[j / QR_LINES_PER_SB];
-}
-
 // v.{x,y,z,w}[c] by mask arithmetic: a runtime-indexed select chain would be lowered to a
 // stack array (scratch memory) once several queries are unrolled per lane.
 __device__ __forceinline__ uint32_t sel4(const uint4 &v, uint32_t c) {
@@ -70,87 +14,11 @@ __device__ __forceinline__ uint32_t sel4(const uint4 &v, uint32_t c) {
     return (lo & ~m2) | (hi & m2);
 }
 
-__device__ __forceinline__ uint32_t delta_of(const HalfLine &hl, uint32_t c) {
-    const uint32_t m2 = 0u - ((c >> 1) & 1u);
-    const uint32_t d = (hl.dAC & ~m2) | (hl.dGT & m2);
-    return (d >> (16u * (c & 1u))) & 0xffffu;
-}
-
-// Occurrences of c in the counted range of the half: slots [0, t) if up, else [t, 256).
-__device__ __forceinline__ uint32_t half_count1(const HalfLine &hl, uint32_t c) {
-    const uint32_t inv = hl.up ? 0u : 0xffffffffu;
-    const uint32_t xl = (c & 1) ? 0u : 0xffffffffu, xh = (c & 2) ? 0u : 0xffffffffu;
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-            const uint32_t lo = hl.w[4 * k + sub], hi = hl.w[4 * k + 2 + sub];
-            const uint32_t m = prefix_mask32(hl.t, 2 * k + sub) ^ inv;
-            cnt += __popc((lo ^ xl) & (hi ^ xh) & m);
-        }
-    }
-    return cnt;
-}
-
-__device__ __forceinline__ uint64_t rank1_from_half(const HalfLine &hl, uint32_t c) {
-    const uint64_t mid = ((uint64_t)sel4(hl.s, c) << QR_SHIFT) + delta_of(hl, c);
-    const uint32_t cnt = half_count1(hl, c);
-    return hl.up ? mid + cnt : mid - cnt;
-}
-
-// rank1_from_half in 32-bit arithmetic, for structures whose every rank is below 2^32 (then the
-// shifted offset, the mid-line rank and the result all fit).
-__device__ __forceinline__ uint32_t rank1_from_half32(const HalfLine &hl, uint32_t c) {
-    const uint32_t mid = (sel4(hl.s, c) << QR_SHIFT) + delta_of(hl, c);
-    const uint32_t cnt = half_count1(hl, c);
-    return hl.up ? mid + cnt : mid - cnt;
-}
-
-// The symbol stored at the slot of q (the half line's slot t), picked with masks.
-__device__ __forceinline__ uint32_t symbol_from_half(const HalfLine &hl) {
-    const uint32_t word = hl.t >> 5;  // 32-slot word of the half: pair word >> 1, its low/high u32 word & 1
-    uint32_t lo = 0, hi = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < 4; ++k) {
-#pragma unroll
-        for (uint32_t sub = 0; sub < 2; ++sub) {
-            const uint32_t m = (word == 2 * k + sub) ? 0xffffffffu : 0u;
-            lo |= hl.w[4 * k + sub] & m;
-            hi |= hl.w[4 * k + 2 + sub] & m;
-        }
-    }
-    const uint32_t b = hl.t & 31u;
-    return ((lo >> b) & 1u) | (((hi >> b) & 1u) << 1);
-}
-
-__device__ __forceinline__ void rank4_from_half(const HalfLine &hl, uint64_t (&r)[4]) {
-    const uint32_t inv = hl.up ? 0u : 0xffffffffu;
-    uint32_t cT = 0, cL = 0, cH = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-            const uint32_t m = prefix_mask32(hl.t, 2 * k + sub) ^ inv;
-            const uint32_t lo = hl.w[4 * k + sub] & m, hi = hl.w[4 * k + 2 + sub] & m;
-            cT += __popc(lo & hi);
-            cL += __popc(lo);
-            cH += __popc(hi);
-        }
-    }
-    const uint32_t len = hl.up ? hl.t : QR_MID - hl.t;
-    const uint32_t cnt[4] = {len - cL - cH + cT, cL - cT, cH - cT, cT};
-#pragma unroll
-    for (uint32_t c = 0; c < 4; ++c) {
-        const uint64_t mid = ((uint64_t)sel4(hl.s, c) << QR_SHIFT) + delta_of(hl, c);
-        r[c] = hl.up ? mid + cnt[c] : mid - cnt[c];
-    }
-}
-
 // ---- layouts -------------------------------------------------------------------------------------
 // Each layout gives HDR (header slots at the line start), DATA (bases per line), MID (slot 256, the
 // 64-byte half boundary), WORDS (packed input words per line), the offset-array geometry
-// (SB_LINES, SB_LOG, SHIFT, Super), the exact division by DATA (MAGIC, MAGIC_T), and
+// (SB_LINES, SB_LOG, SHIFT, Super), the exact division by DATA (MAGIC, MAGIC_T; and LINE32_SHIFT,
+// LINE32_MAGIC for 32-bit positions), and
 //   MULTI    false: a query counts between its slot p and the middle (within p's 64-byte half);
 //            true:  between p and the nearest of three anchors, within p's 64-slot pair (24_8);
 //   offset1(s, j, c) / offset4 + delta(a, b, c, p, j) = rank(anchor of p, c), where a and b hold the
@@ -171,6 +39,7 @@ struct QR16 {
     static constexpr uint32_t SB_LOG = 7, SHIFT = 12;
     static constexpr uint64_t MAGIC = QR_MAGIC;
     static constexpr uint32_t MAGIC_T = QR_MAGIC_T;
+    static constexpr uint32_t LINE32_SHIFT = 5, LINE32_MAGIC = 0x11111112u;  // 480 = 2^5 * 15
     static constexpr uint64_t MAX_N = (1ull << 44) - 1;
     using Super = uint32_t;
     __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &, uint32_t c, uint32_t, uint64_t) {
@@ -204,6 +73,7 @@ struct QR16P {
     static constexpr uint64_t BIAS = 128 * 480 - 224;
     static constexpr uint64_t MAGIC = QR_MAGIC;
     static constexpr uint32_t MAGIC_T = QR_MAGIC_T;
+    static constexpr uint32_t LINE32_SHIFT = QR16::LINE32_SHIFT, LINE32_MAGIC = QR16::LINE32_MAGIC;
     static constexpr uint64_t MAX_N = (1ull << 44) - 1;
     using Super = uint32_t;
     __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &b, uint32_t c, uint32_t p, uint64_t j) {
@@ -227,6 +97,7 @@ struct QR32 {
     static constexpr uint32_t SB_LOG = 23, SHIFT = 0;
     static constexpr uint64_t MAGIC = 0x924924924924924aull;  // ceil(2^72 / 448)
     static constexpr uint32_t MAGIC_T = 8;
+    static constexpr uint32_t LINE32_SHIFT = 6, LINE32_MAGIC = 0x24924925u;  // 448 = 2^6 * 7
     static constexpr uint64_t MAX_N = (1ull << 48) - 1;
     using Super = uint64_t;
     __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &, uint32_t c, uint32_t, uint64_t) {
@@ -262,6 +133,7 @@ struct QR64 {
     static constexpr uint32_t SB_LOG = 0, SHIFT = 0;
     static constexpr uint64_t MAGIC = 0xaaaaaaaaaaaaaaabull;  // ceil(2^72 / 384)
     static constexpr uint32_t MAGIC_T = 8;
+    static constexpr uint32_t LINE32_SHIFT = 7, LINE32_MAGIC = 0x55555556u;  // 384 = 2^7 * 3
     static constexpr uint64_t MAX_N = (1ull << 48) - 1;
     using Super = uint64_t;
     __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &b, uint32_t c, uint32_t, uint64_t) {
@@ -288,6 +160,7 @@ struct QR24_8 {
     static constexpr uint32_t SB_LOG = 15, SHIFT = 0;
     static constexpr uint64_t MAGIC = QR64::MAGIC;
     static constexpr uint32_t MAGIC_T = QR64::MAGIC_T;
+    static constexpr uint32_t LINE32_SHIFT = QR64::LINE32_SHIFT, LINE32_MAGIC = QR64::LINE32_MAGIC;
     static constexpr uint64_t MAX_N = (1ull << 48) - 1;
     using Super = uint64_t;
     __device__ __forceinline__ static uint64_t delta(const uint4 &a, const uint4 &b, uint32_t c, uint32_t p, uint64_t) {
@@ -307,6 +180,15 @@ struct QR24_8 {
 template <class L>
 __host__ __device__ __forceinline__ uint64_t qline_of(uint64_t q) {
     return mulhi64(q, L::MAGIC) >> L::MAGIC_T;
+}
+
+// floor(q / DATA) for every 32-bit q with one 32-bit multiply-high.  DATA = 2^s d with d odd
+// (480 = 2^5 * 15, 448 = 2^6 * 7, 384 = 2^7 * 3) and m = ceil(2^32 / d) has e = m d - 2^32 = 14, 3
+// and 2, so floor(y m / 2^32) = floor(y / d) wherever y e < 2^32, which covers y = q >> s < 2^27.
+// (Checked against division for all 2^32 values of q.)
+template <class L>
+__host__ __device__ __forceinline__ uint32_t qline_of32(uint32_t q) {
+    return (uint32_t)(((uint64_t)(q >> L::LINE32_SHIFT) * L::LINE32_MAGIC) >> 32);
 }
 
 // ---- lane-pair form: lane hf (0/1) of a pair holds half hf of the line -------------------------
@@ -497,6 +379,107 @@ __device__ __forceinline__ void count4(const PairHalf &ph, uint32_t hf, uint32_t
         fwd = ph.up;
         pair_count4(ph, hf, cnt);
     }
+}
+
+// ---- one lane per query, 32-bit positions (the FM-index search) ---------------------------------
+// Every rank of an FM-index is below 2^32 (its BWT has fewer than 2^32 rows), so the offsets and
+// deltas are summed modulo 2^32: the low words of the 64-bit sums, hence exact.
+
+// The 64-byte half line that holds a position, read by one lane, with the line's header (its first
+// 32 bytes, which hold the deltas of every layout) and its offsets.
+struct LaneHalf {
+    uint32_t w[16];  // the half: pair k (0..3) = lo_k (w[4k], w[4k+1]), hi_k (w[4k+2], w[4k+3])
+    uint4 h0, h1;    // line bytes [0, 16) and [16, 32)
+    uint32_t off[4]; // offsets of A, C, G, T (low 32 bits)
+    uint32_t j;      // line index
+};
+
+// Slot of position q in its line (header slots first).
+template <class L>
+__device__ __forceinline__ uint32_t lane_slot(uint32_t q, uint32_t j) {
+    return q - j * L::DATA + L::HDR;
+}
+
+// Load the half line of q.  For q in the upper half the header words are loaded on their own (the
+// second 16 bytes only where the layout's header is wider than 64 slots); in the lower half they
+// are the half's first words.
+template <class L>
+__device__ __forceinline__ void load_lane_half(const uint4 *__restrict__ lines, const typename L::Super *__restrict__ super,
+                                               uint32_t q, LaneHalf &hl) {
+    hl.j = qline_of32<L>(q);
+    const bool up = lane_slot<L>(q, hl.j) >= L::MID;
+    const uint4 *Ln = lines + (uint64_t)hl.j * 8;
+    const uint4 *H = Ln + (up ? 4 : 0);
+    const uint4 a = H[0], b = H[1], c = H[2], d = H[3];
+    hl.w[0] = a.x, hl.w[1] = a.y, hl.w[2] = a.z, hl.w[3] = a.w;
+    hl.w[4] = b.x, hl.w[5] = b.y, hl.w[6] = b.z, hl.w[7] = b.w;
+    hl.w[8] = c.x, hl.w[9] = c.y, hl.w[10] = c.z, hl.w[11] = c.w;
+    hl.w[12] = d.x, hl.w[13] = d.y, hl.w[14] = d.z, hl.w[15] = d.w;
+    if (up) {
+        hl.h0 = Ln[0];
+        if constexpr (L::HDR > 64) hl.h1 = Ln[1];
+        else hl.h1 = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        hl.h0 = a;
+        hl.h1 = b;
+    }
+    if constexpr (L::SB_LINES == 0) {
+        hl.off[0] = hl.off[1] = hl.off[2] = hl.off[3] = 0u;
+    } else {
+        uint64_t o[4];
+        L::offset4(super, hl.j, o);
+        hl.off[0] = (uint32_t)o[0], hl.off[1] = (uint32_t)o[1], hl.off[2] = (uint32_t)o[2], hl.off[3] = (uint32_t)o[3];
+    }
+}
+
+// rank(q, c) (modulo 2^32) for a position q whose half line hl holds, given q's line slot p.  The
+// count runs from p to the half's boundary with the middle, or (multi-anchor layouts) to the nearest
+// anchor within p's 64-slot pair.
+template <class L>
+__device__ __forceinline__ uint32_t lane_rank(const LaneHalf &hl, uint32_t p, uint32_t c) {
+    const bool up = p >= L::MID;
+    const uint32_t t = up ? p - L::MID : p;
+    const uint32_t anchor =
+        sel4(make_uint4(hl.off[0], hl.off[1], hl.off[2], hl.off[3]), c) + (uint32_t)L::delta(hl.h0, hl.h1, c, p, hl.j);
+    const uint32_t xl = (c & 1) ? 0u : 0xffffffffu, xh = (c & 2) ? 0u : 0xffffffffu;
+    bool fwd;
+    uint32_t cnt = 0;
+    if constexpr (L::MULTI) {
+        uint32_t m0, m1, v[4];
+        fwd = multi_masks(t, m0, m1);
+        pick_pair(hl.w, t >> 6, v);
+        cnt = __popc((v[0] ^ xl) & (v[2] ^ xh) & m0) + __popc((v[1] ^ xl) & (v[3] ^ xh) & m1);
+    } else {
+        fwd = up;
+        const uint32_t inv = up ? 0u : 0xffffffffu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int sub = 0; sub < 2; ++sub) {
+                const uint32_t m = prefix_mask32(t, 2 * k + sub) ^ inv;
+                cnt += __popc((hl.w[4 * k + sub] ^ xl) & (hl.w[4 * k + 2 + sub] ^ xh) & m);
+            }
+        }
+    }
+    return fwd ? anchor + cnt : anchor - cnt;
+}
+
+// The symbol at line slot p of the half line hl, picked with masks.
+__device__ __forceinline__ uint32_t lane_symbol(const LaneHalf &hl, uint32_t p) {
+    const uint32_t t = p & 255u;
+    const uint32_t word = t >> 5;  // 32-slot word of the half: pair word >> 1, its low/high u32 word & 1
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+#pragma unroll
+        for (uint32_t sub = 0; sub < 2; ++sub) {
+            const uint32_t m = (word == 2 * k + sub) ? 0xffffffffu : 0u;
+            lo |= hl.w[4 * k + sub] & m;
+            hi |= hl.w[4 * k + 2 + sub] & m;
+        }
+    }
+    const uint32_t b = t & 31u;
+    return ((lo >> b) & 1u) | (((hi >> b) & 1u) << 1);
 }
 
 }  // namespace qr

@@ -139,8 +139,10 @@ def test_fm_config3_full():
     locate sample) is prepared on the device; its suffix array is handed out and checked by the
     oracle directly (a permutation whose neighbouring suffixes increase).  Every one of the 10^7
     persistent-kernel counts then equals the oracle's suffix-array binary search over the text, and
-    so does every per-batch count.  200 sampled patterns are also recounted by the oracle's direct
-    scan of the text.  Intervals and locate (SA sampled at rate 32) are checked on the same index."""
+    so does every per-batch count and every count of the same index over the other QuadRank layouts
+    (16-bit paired, 32-bit, 64-bit and 24/8, with the 12-mer start table).  200 sampled patterns are
+    also recounted by the oracle's direct scan of the text.  Intervals and locate (SA sampled at rate
+    32) are checked on the same index."""
     qr = require_gpu()
     n = 1 << 28
     codes = datagen.dna_codes(2028, n)
@@ -151,11 +153,18 @@ def test_fm_config3_full():
     bwt, dollar, marks, samples = qr.quadfm_index_device(torch.from_numpy(codes).cuda(), 32, sa=d_sa)
     fm = qr.QuadFm(bwt, n + 1, dollar)
     fm.attach_locate(marks, samples, 32)
+    dp, do = to_dev(pat), to_dev(off)
+    got_layouts = {}
+    for name in ("16p", "32", "64", "24_8"):  # the same index over the other QuadRank layouts
+        announce("fm-config3 count, layout", name)
+        other = qr.QuadFm(bwt, n + 1, dollar, kmer=12, layout=qr.LAYOUT_BY_NAME[name])
+        got_layouts[name] = other.count(dp, do).cpu().numpy().view(np.uint32)
+        other.check()
+        other.free()
     del bwt, marks, samples
     sa = d_sa.cpu().numpy().view(np.uint32).astype(np.int64)
     del d_sa
     announce("fm-config3 count")
-    dp, do = to_dev(pat), to_dev(off)
     got = fm.count(dp, do).cpu().numpy().view(np.uint32)
     got_b = fm.count_batched(dp, do, 1 << 20).cpu().numpy().view(np.uint32)
     fm.check()
@@ -164,6 +173,8 @@ def test_fm_config3_full():
     want_all = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
     assert np.array_equal(got, want_all)
     assert np.array_equal(got_b, want_all)
+    for name, g in got_layouts.items():
+        assert np.array_equal(g, want_all), name
     assert sa[dollar] == 0                       # the '$' row of the BWT is the row of suffix 0
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(10 ** 7, 200, replace=False))

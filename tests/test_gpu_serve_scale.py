@@ -1,11 +1,12 @@
-"""Serving at full size: the 2^30-base index (uniform ACGT with 1000 planted 10-kb segments x20 at
-1 % substitutions), built on the device with the 12-character start table, served by the native
-loop in the launch configuration the benchmark times (4 slots, 256 MiB arena, batches of up to
-2^18 patterns, live free-memory check) at 10^7 patterns/s.  The suffix array behind the index is
-handed out by the device input preparation and checked by the oracle directly; every served count
-then equals the oracle's suffix-array binary search over the text, one direct count of all
-patterns, and each sampled request counted alone; sampled patterns are also recounted by the
-oracle's direct scan of the text."""
+"""Serving at full size: the 2^30-base index (uniform ACGT with 1000 planted 10-kb segments x20 at 1 %
+substitutions), built on the device with the 12-character start table, served by the native loop in
+the launch configuration the benchmark times (4 slots, 256 MiB arena, batches of up to 2^18
+patterns, live free-memory check) at 10^7 patterns/s. The suffix array behind the index is handed
+out by the device input preparation and checked by the oracle directly; every served count then
+equals the oracle's suffix-array binary search over the text, one direct count of all patterns, and
+each sampled request counted alone, and so does the direct count of every pattern by the same index
+over each other QuadRank layout (16-bit paired, 32-bit, 64-bit, 24/8); sampled patterns are also
+recounted by the oracle's direct scan of the text."""
 import numpy as np
 import pytest
 import torch
@@ -28,10 +29,19 @@ def test_native_serve_2e30_sampled():
     bwt, dollar, _, _ = qr.quadfm_index_device(torch.from_numpy(text).cuda(), 0, sa=d_sa)
     fm = qr.QuadFm(bwt, n + 1, dollar, kmer=12)
     sa = d_sa.cpu().numpy().view(np.uint32)
-    del bwt, d_sa
-    torch.cuda.empty_cache()
+    del d_sa
     fm.set_tuning(block=64, refill=32, waves_per_cu=8)
     w = make_workload(5003, text, 1e7, 0.02, max_requests=200_000)
+    # the same index over the other QuadRank layouts, counting every pattern directly
+    by_layout = {}
+    for name in ("16p", "32", "64", "24_8"):
+        announce("serve-2^30 layout", name)
+        other = qr.QuadFm(bwt, n + 1, dollar, kmer=12, layout=qr.LAYOUT_BY_NAME[name])
+        by_layout[name] = other.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
+        other.check()
+        other.free()
+    del bwt
+    torch.cuda.empty_cache()
     announce("serve-2^30 run", w.nreq, int(w.req_off[-1]))
     srv = NativeServer(fm, slots=4, budget_bytes=256 << 20, max_batch_patterns=1 << 18, check_free_memory=True)
     st = srv.run(w, deadline_s=120.0)
@@ -53,7 +63,10 @@ def test_native_serve_2e30_sampled():
     announce("serve-2^30 oracle: suffix-array check and every served count")
     sa = sa.astype(np.int64)
     assert oracle.check_sa(text, sa) == 0
-    assert np.array_equal(served, oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
+    want_all = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
+    assert np.array_equal(served, want_all)
+    for name, got in by_layout.items():
+        assert np.array_equal(got, want_all), name
     del sa
     # oracle on sampled patterns (direct substring counting over the whole text)
     idx = np.sort(rng.choice(npat, 32, replace=False))

@@ -45,39 +45,45 @@ def test_line_division_is_exact():
 
 
 def test_fm_line_division_32_bit():
-    """The FM search's 32-bit line index: the library's form on boundaries and samples, and its
-    constant exhaustively over every 32-bit position (a small C program)."""
+    """The FM search's 32-bit line index of every layout it runs on (480, 448 and 384 bases per
+    line): the library's form on boundaries and samples, and each constant exhaustively over every
+    32-bit position (a small C program)."""
     import shutil
     import tempfile
     import paper_2602_04103_amd as qr
     rng = np.random.default_rng(2)
-    xs = list(range(0, 4000)) + [int(x) for x in rng.integers(0, 1 << 32, 50_000, dtype=np.int64)]
-    for k in (1, 2, 15, 16, 1 << 20, (1 << 32) // 480 - 1, (1 << 32) // 480):
-        xs += [k * 480 - 1, k * 480, k * 480 + 1]
-    xs += [(1 << 32) - 1]
-    for x in xs:
-        if x < (1 << 32):
-            assert qr.qr_line_of(x, 4) == x // 480, x
-    assert qr.qr_line_of(1 << 32, 4) == (1 << 64) - 1
+    forms = ((4, 480, 5, 0x11111112), (7, 448, 6, 0x24924925), (8, 384, 7, 0x55555556))
+    for which, d, _, _ in forms:
+        xs = list(range(0, 4000)) + [int(x) for x in rng.integers(0, 1 << 32, 50_000, dtype=np.int64)]
+        for k in (1, 2, 15, 16, 1 << 20, (1 << 32) // d - 1, (1 << 32) // d):
+            xs += [k * d - 1, k * d, k * d + 1]
+        xs += [(1 << 32) - 1]
+        for x in xs:
+            if x < (1 << 32):
+                assert qr.qr_line_of(x, which) == x // d, (d, x)
+        assert qr.qr_line_of(1 << 32, which) == (1 << 64) - 1
     if shutil.which("gcc") is None:
         pytest.skip("no host compiler for the exhaustive check")
-    src = r"""
+    checks = "\n".join(
+        "        if ((uint32_t)((((uint64_t)((uint32_t)x >> %d)) * 0x%xull) >> 32) != (uint32_t)(x / %d)) {\n"
+        "            printf(\"%d %%llu\\n\", (unsigned long long)x);\n"
+        "            return 1;\n"
+        "        }" % (s, m, d, d) for _, d, s, m in forms)
+    src = """
 #include <stdint.h>
 #include <stdio.h>
 int main(void) {
-    for (uint64_t x = 0; x < (1ull << 32); ++x)
-        if ((uint32_t)((((uint64_t)((uint32_t)x >> 5)) * 0x11111112ull) >> 32) != (uint32_t)(x / 480)) {
-            printf("%llu\n", (unsigned long long)x);
-            return 1;
-        }
+    for (uint64_t x = 0; x < (1ull << 32); ++x) {
+%s
+    }
     return 0;
 }
-"""
+""" % checks
     with tempfile.TemporaryDirectory() as d:
         c, exe = os.path.join(d, "div.c"), os.path.join(d, "div")
         open(c, "w").write(src)
         subprocess.run(["gcc", "-O2", "-o", exe, c], check=True)
-        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
         assert r.returncode == 0, r.stdout
 
 
