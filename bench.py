@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--no-fm-hbm", action="store_true",
                     help="skip the FM count measurement on the served (HBM-resident) index")
     ap.add_argument("--fm-hbm-patterns", type=int, default=4 * 10 ** 6)
+    ap.add_argument("--no-fm-hbm-k8", action="store_true",
+                    help="skip the 8-mer start table in the HBM-resident FM row (the served index's k only)")
     ap.add_argument("--fm-layouts", default="16p,32,64,24_8",
                     help="QuadRank layouts besides the 16-bit one to build the FM rows' indexes over (empty: none)")
     ap.add_argument("--serve-python", action="store_true",
@@ -228,6 +230,15 @@ def main():
         fixed = {r: v.get("tuning") for r, v in prev.get("rows", {}).items()}
         fixed["_fm"] = (prev.get("fm") or {}).get("tuning")
         args.fm_tuning = fixed["_fm"]
+        # the FM rows' other launch settings, by index size, start table and layout
+        fm_prev, hbm_prev = prev.get("fm") or {}, ((prev.get("serve") or {}).get("fm_count_hbm") or {})
+        args.fm_fixed = {}
+        for name, r in (fm_prev.get("by_layout") or {}).items():
+            args.fm_fixed["2^28|layout|" + name] = r.get("tuning")
+        for k, r in (hbm_prev.get("by_kmer") or {}).items():
+            args.fm_fixed["2^30|k|" + k] = r.get("tuning")
+        for name, r in (hbm_prev.get("by_layout") or {}).items():
+            args.fm_fixed["2^30|layout|" + name] = r.get("tuning")
     for row in rows:
         if fixed and isinstance(fixed.get(row), dict):
             t = dict(fixed[row])
@@ -683,14 +694,14 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
                        "10%% iid" % (int(np.log2(n)), npat),
            "line_bytes": line_bytes, "line_gather_ceiling_lines_per_s": ceil_lps, "by_kmer": {}}
     fms = {args.serve_kmer: fm_serve}
-    if args.serve_kmer != 8:
+    if args.serve_kmer != 8 and not args.no_fm_hbm_k8:
         fms[8] = qr.QuadFm(bwt, n + 1, dollar, kmer=8, layout=qr.LAYOUT_BY_NAME[args.serve_layout])
     for k, fm in sorted(fms.items()):
         # the persistent kernel's launch settings tuned on this index (an HBM-resident index wants
         # more patterns in flight than the cache-resident one), on the first 10^6 patterns
         sub = min(npat, 1_000_000)
-        best, _ = autotune.tune("quadfm-hbm-k%d" % k, n, fm.set_tuning, lambda f=fm: f.count(dp, do[:sub + 1], cnt[:sub]),
-                                autotune.FM_CANDIDATES, reps=2, use_cache=False)
+        best = fm_tune(args, autotune, "2^%d|k|%d" % (int(np.log2(n)), k), n, fm,
+                       lambda f=fm: f.count(dp, do[:sub + 1], cnt[:sub]))
         t_p = autotune.time_launch(lambda f=fm: f.count(dp, do, cnt), reps=args.fm_reps)
         row = {"index_bytes": fm.nbytes, "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3,
                "tuning": best}
@@ -733,6 +744,17 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
     return res
 
 
+def fm_tune(args, autotune, key, n, fm, run):
+    """The FM count's launch settings: those of --tuning-from's run for this key if it has them, else
+    tuned now on the caller's run."""
+    t = (getattr(args, "fm_fixed", None) or {}).get(key)
+    if isinstance(t, dict):
+        fm.set_tuning(**t)
+        return t
+    best, _ = autotune.tune("quadfm|" + key, n, fm.set_tuning, run, autotune.FM_CANDIDATES, reps=2, use_cache=False)
+    return best
+
+
 # bases per line and header slots of each QuadRank layout the FM-index runs on, and its trait's name
 FM_GEOMETRY = {"16": (480, 32), "16p": (480, 32), "32": (448, 64), "64": (384, 128), "24_8": (384, 128)}
 FM_TRAIT = {"16": "QR16", "16p": "QR16P", "32": "QR32", "64": "QR64", "24_8": "QR24_8"}
@@ -749,9 +771,8 @@ def fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, fms, ref, dp, do,
     few per cent."""
     rows, rates = {}, {name: [] for name in fms}
     for name, fm in fms.items():
-        best, _ = autotune.tune("quadfm-%s-2^%d" % (name, int(np.log2(n))), n, fm.set_tuning,
-                                lambda f=fm: f.count(dp, do[:tune_sub + 1], cnt[:tune_sub]), autotune.FM_CANDIDATES,
-                                reps=2, use_cache=False)
+        best = fm_tune(args, autotune, "2^%d|layout|%s" % (int(np.log2(n)), name), n, fm,
+                       lambda f=fm: f.count(dp, do[:tune_sub + 1], cnt[:tune_sub]))
         rows[name] = {"tuning": best}
     for order in (list(fms), list(fms)[::-1]):
         for name in order:
@@ -872,7 +893,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     ns0.run(w0, deadline_s=60.0)
     ns0.free()
     res["loop"] = "python" if args.serve_python else "native"
-    for k, load in enumerate(float(x) for x in args.serve_loads.split(",")):
+    for k, load in enumerate(float(x) for x in args.serve_loads.split(",") if x):
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
         if args.serve_python:
             ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)
