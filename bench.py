@@ -73,8 +73,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-log-n", type=int, default=30, help="log2 of the served text length")
-    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8,2e8,4e8",
+    ap.add_argument("--serve-loads", default="1e4,1e5,1e6,3e6,1e7,3e7,1e8,2e8,4e8,6e8,8e8,1e9",
                     help="offered loads, patterns/s (past 10^8 the 200 000-request cap shortens the run)")
+    ap.add_argument("--serve-bytes", action="store_true",
+                    help="send the served patterns one byte per base (default: 2-bit packed words); the native "
+                         "loop's top load is also run the other way for comparison")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--serve-kmer", type=int, default=12, help="start-table size of the served index")
     ap.add_argument("--serve-layout", default="32",
@@ -888,6 +891,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
            "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "layout": args.serve_layout,
+           "patterns": "bytes" if args.serve_bytes else "packed",
            "device_free_bytes_at_start": int(free),
            "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": [],
            "fm_count_hbm": hbm_row}
@@ -908,7 +912,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                          free_bytes_fn=lambda: torch.cuda.mem_get_info()[0])
         else:
             ex = srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
-                                    check_free_memory=True)
+                                    check_free_memory=True, packed=not args.serve_bytes)
         st = srv.run(w, deadline_s=120.0)
         summ = st.summary()
         summ["offered_patterns_per_s"] = load
@@ -925,6 +929,23 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                summ.get("batch_patterns_of_p99_requests_median", 0), summ["max_inflight_batches"],
                summ["equal_to_direct_count"]))
         del ex, srv
+    if not args.serve_python and res["loads"]:
+        # the top load again with the patterns sent the other way (bytes against packed words)
+        load = res["loads"][-1]["offered_patterns_per_s"]
+        k = len(res["loads"]) - 1
+        w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
+        srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18, check_free_memory=True,
+                           packed=args.serve_bytes)
+        summ = srv.run(w, deadline_s=120.0).summary()
+        summ["offered_patterns_per_s"] = load
+        summ["patterns"] = "packed" if args.serve_bytes else "bytes"
+        d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
+        summ["equal_to_direct_count"] = bool(np.array_equal(srv.counts(0, int(w.req_off[-1])), d_all))
+        srv.free()
+        res["top_load_other_form"] = summ
+        log("serve load %.0e with %s patterns: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, equal=%s" % (
+            load, summ["patterns"], summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6,
+            summ["equal_to_direct_count"]))
     fm.free()
     return res
 

@@ -259,6 +259,16 @@ int quadfm_count_noalloc(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, 
  * overlap). */
 int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
                     uint32_t flags, uint32_t *d_count, void *d_workspace, hipStream_t stream);
+/* quadfm_count_ex over 2-bit packed patterns (Appendix D's count; the input packing of this
+ * header): the patterns form one stream of bases, base i being bits [2 (i mod 32), +2) of u64 word
+ * i/32 at d_pat2 (8-byte aligned), and pattern p is bases [d_off[p], d_off[p+1]) of it.  pat_bases
+ * is the number of valid bases of the stream (d_pat2 holds ceil(pat_bases/32) words; NULL only with
+ * pat_bases = 0); a pattern running past it is treated like a decreasing offset pair.  Every code
+ * is a base, so a pattern counts 0 only by not occurring.  A quarter of the bytes of the byte form,
+ * for callers whose patterns cross a slow link (a host-fed server).  flags, d_workspace and errors
+ * as for quadfm_count_ex. */
+int quadfm_count_packed(qr_quadfm h, const uint64_t *d_pat2, uint64_t pat_bases, const uint64_t *d_off, uint64_t npat,
+                        uint32_t flags, uint32_t *d_count, void *d_workspace, hipStream_t stream);
 /* Same result with one plain launch per batch of `batch` patterns, one lane per pattern
  * (batch = 0: a single launch over all patterns).  The baseline for the work-queue kernel. */
 int quadfm_count_batched(qr_quadfm h, const uint8_t *d_pat, const uint64_t *d_off, uint64_t npat, uint64_t batch,
@@ -350,6 +360,8 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
  * ---------------------------------------------------------------------------------------------- */
 typedef struct qr_server_s *qr_server;
 #define QR_SERVE_CHECK_FREE_MEMORY 1u
+#define QR_SERVE_PACKED_PATTERNS 2u /* h_pat holds 2-bit packed u64 words and h_off counts bases (the
+                                       stream of quadfm_count_packed); batches copy whole words */
 typedef struct {
     uint64_t batches;            /* batches launched */
     uint64_t max_inflight;       /* most batches in flight at once */

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libquadrank.so")
 QR_OK, QR_EINVAL, QR_ENOMEM, QR_EHIP, QR_ERANGE, QR_EDEVICE = 0, -1, -2, -3, -4, -5
 QUADFM_BOTH_STRANDS = 1
 QR_SERVE_CHECK_FREE_MEMORY = 1
+QR_SERVE_PACKED_PATTERNS = 2
 QR_LAYOUT_16, QR_LAYOUT_32, QR_LAYOUT_16P, QR_LAYOUT_64, QR_LAYOUT_16X2, QR_LAYOUT_24_8 = 0, 1, 2, 3, 4, 5
 LAYOUT_NAMES = {QR_LAYOUT_16: "16", QR_LAYOUT_32: "32", QR_LAYOUT_16P: "16p", QR_LAYOUT_64: "64",
                 QR_LAYOUT_16X2: "16x2", QR_LAYOUT_24_8: "24_8"}
@@ -118,6 +119,7 @@ def lib():
             "quadfm_count_ws": (ci, [vp, vp, vp, u64, vp, vp, vp]),
             "quadfm_count_ex": (ci, [vp, vp, u64, vp, u64, C.c_uint32, vp, vp, vp]),
             "quadfm_count_noalloc": (ci, [vp, vp, u64, vp, u64, C.c_uint32, vp, vp]),
+            "quadfm_count_packed": (ci, [vp, vp, u64, vp, u64, C.c_uint32, vp, vp, vp]),
             "quadfm_count_batched_ex": (ci, [vp, vp, u64, vp, u64, u64, C.c_uint32, vp, vp]),
             "quadfm_check": (ci, [vp, vp]),
             "quadfm_free": (ci, [vp]),
@@ -344,6 +346,18 @@ def quadfm_count_ex(h: int, pat: torch.Tensor, off: torch.Tensor, count: torch.T
     pp, pn = _pat(pat)
     _check(lib().quadfm_count_ex(h, pp, pn, _dev(off, "off", W64), npat, flags, _dev(count, "count", W32, npat), ws,
                                  _stream(stream)), "quadfm_count_ex")
+    return count
+
+
+def quadfm_count_packed(h: int, pat2: torch.Tensor, nbases: int, off: torch.Tensor, count: torch.Tensor,
+                        flags: int = 0, workspace: torch.Tensor | None = None, stream=None):
+    """quadfm_count_ex over 2-bit packed patterns: pat2 holds the stream's u64 words (at least
+    ceil(nbases / 32)), off counts bases."""
+    npat = off.numel() - 1
+    ws = _dev(workspace, "workspace", W64, 1) if workspace is not None else None
+    pp = _dev(pat2, "pat2", W64, (nbases + 31) // 32) if nbases else None
+    _check(lib().quadfm_count_packed(h, pp, nbases, _dev(off, "off", W64), npat, flags,
+                                     _dev(count, "count", W32, npat), ws, _stream(stream)), "quadfm_count_packed")
     return count
 
 
@@ -632,6 +646,14 @@ class QuadFm(_Handle):
         if both_strands:
             return quadfm_count_ex(self.h, pat, off, out, QUADFM_BOTH_STRANDS, None, stream)
         return quadfm_count(self.h, pat, off, out, stream)
+
+    def count_packed(self, pat2: torch.Tensor, nbases: int, off: torch.Tensor, out: torch.Tensor | None = None,
+                     stream=None, both_strands: bool = False):
+        """count over 2-bit packed patterns (pat2: u64 words of the base stream; off counts bases)."""
+        if out is None:
+            out = torch.empty(off.numel() - 1, dtype=torch.int32, device=off.device)
+        return quadfm_count_packed(self.h, pat2, nbases, off, out, QUADFM_BOTH_STRANDS if both_strands else 0, None,
+                                   stream)
 
     def count_batched(self, pat: torch.Tensor, off: torch.Tensor, batch: int = 0, out: torch.Tensor | None = None,
                       stream=None, both_strands: bool = False):

@@ -156,17 +156,22 @@ __global__ void fm_totals_kernel(FmDev f, unsigned long long *__restrict__ out4)
 
 // Per-lane search state.  The backward search over a pattern P reads P from its end; over the
 // reverse complement of P it reads P from its start and complements every code (c -> 3 - c).
+//
+// Patterns come as one byte per code, or (PACKED) as 2-bit codes in a stream of u64 words: base i of
+// the stream is bits [2 (i mod 32), +2) of word i / 32, and a pattern is a range of stream bases.
 struct Search {
     uint32_t sp, ep;   // the current BWT interval (every row index is below 2^32)
-    const uint8_t *P;  // pattern start
+    const uint8_t *P;  // pattern start (PACKED: the stream's first word)
+    uint64_t base;     // PACKED: stream index of the pattern's first base
     uint32_t m;        // pattern length
     uint32_t left;     // characters still to process
     uint32_t pos;      // index in P of the next character to read
     uint32_t rc;       // 0: P itself, 1: its reverse complement
     uint32_t acc;      // count of the first strand, when counting both
-    uint64_t buf;      // pattern bytes [win, win + wlen) (8 of them, or 1 near the pattern ends)
+    uint64_t buf;      // pattern bytes [win, win + wlen) (8 of them, or 1 near the pattern ends);
+                       // PACKED: stream word win (32 bases), valid when wlen != 0
     uint32_t win;      // index in P of buf's first byte; ~0u before the first fetch
-    uint32_t wlen;     // 8 or 1
+    uint32_t wlen;     // 8 or 1 (PACKED: 32, or 0 before the first fetch)
 };
 
 __device__ __forceinline__ uint32_t strand_code(uint32_t c, uint32_t rc) { return (rc && c <= 3u) ? 3u - c : c; }
@@ -179,8 +184,24 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
 
 // Next character of the current strand.  Characters are fetched 8 at a time with one aligned load
 // when the whole aligned 8-byte window lies inside the pattern [P, P + m), else one byte at a time.
+// Packed characters are fetched 32 at a time, one stream word: a word that holds a base of the
+// pattern lies inside the stream.  (Words of one pattern differ by less than 2^27, so the low 32
+// bits of a word index tell them apart.)
+template <bool PACKED>
 __device__ __forceinline__ uint32_t next_char(Search &s) {
     const uint32_t i = s.pos;
+    if constexpr (PACKED) {
+        const uint64_t a = s.base + i;
+        const uint32_t w = (uint32_t)(a >> 5);
+        if (s.wlen == 0 || w != s.win) {
+            s.buf = reinterpret_cast<const uint64_t *>(s.P)[a >> 5];
+            s.win = w;
+            s.wlen = 32;
+        }
+        s.pos = s.rc ? i + 1 : i - 1;
+        const uint32_t c = (uint32_t)(s.buf >> (2 * (a & 31u))) & 3u;
+        return s.rc ? 3u - c : c;
+    }
     if (s.win == ~0u || i < s.win || i - s.win >= s.wlen) {
         const uintptr_t lo = (uintptr_t)s.P, a = lo + i;
         const uintptr_t w = a & ~(uintptr_t)7;
@@ -200,9 +221,11 @@ __device__ __forceinline__ uint32_t next_char(Search &s) {
 }
 
 // Start the search of one strand; returns true if its count is already known (written to cnt).
+template <bool PACKED>
 __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc, uint32_t &cnt) {
     s.rc = rc;
     s.win = ~0u;
+    s.wlen = 0;
     const uint32_t m = s.m;
     const uint32_t K = f.kmer;
     if (m >= K) {
@@ -214,7 +237,7 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
         uint32_t w = 0;
         bool bad = false;
         for (uint32_t j = 0; j < K; ++j) {
-            const uint32_t c = next_char(s);
+            const uint32_t c = next_char<PACKED>(s);
             bad |= c > 3;
             w |= (c & 3u) << (2 * j);
         }
@@ -240,7 +263,8 @@ __device__ __forceinline__ bool fm_start(const FmDev &f, Search &s, uint32_t rc,
 }
 
 // Initialise the search for a pattern; returns true if its count is already known (written to cnt).
-template <bool BOTH>
+// The offsets count bytes, or (PACKED) stream bases; f.pat_len is the buffer's length in the same unit.
+template <bool BOTH, bool PACKED>
 __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restrict__ pat, const uint64_t *__restrict__ off,
                                         uint64_t p, Search &s, uint32_t &cnt) {
     const uint64_t o = off[p], e = off[p + 1];
@@ -251,25 +275,26 @@ __device__ __forceinline__ bool fm_init(const FmDev &f, const uint8_t *__restric
         return true;
     }
     const uint64_t m = e - o;
-    s.P = pat + o;
+    s.P = PACKED ? pat : pat + o;
+    s.base = o;
     s.m = (uint32_t)m;
     s.acc = 0;
     if (m == 0) {  // the empty pattern matches at every position 0..n (counted once)
         cnt = (uint32_t)f.n1;
         return true;
     }
-    if (!fm_start(f, s, 0, cnt)) return false;
+    if (!fm_start<PACKED>(f, s, 0, cnt)) return false;
     if (!BOTH) return true;
     s.acc = cnt;  // forward strand finished at once: go on with the reverse complement
-    if (!fm_start(f, s, 1, cnt)) return false;
+    if (!fm_start<PACKED>(f, s, 1, cnt)) return false;
     cnt = sat_add(cnt, s.acc);
     return true;
 }
 
 // Advance one character; returns true when the pattern's count is final (in cnt).
-template <class L, bool BOTH>
+template <class L, bool BOTH, bool PACKED>
 __device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &cnt) {
-    const uint32_t c = next_char(s);
+    const uint32_t c = next_char<PACKED>(s);
     bool fin;
     if (c > 3) {
         cnt = 0;
@@ -286,7 +311,7 @@ __device__ __forceinline__ bool fm_advance(const FmDev &f, Search &s, uint32_t &
         return true;
     }
     s.acc = cnt;  // forward strand done: start the reverse complement
-    if (!fm_start(f, s, 1, cnt)) return false;
+    if (!fm_start<PACKED>(f, s, 1, cnt)) return false;
     cnt = sat_add(cnt, s.acc);
     return true;
 }
@@ -313,15 +338,15 @@ __global__ __launch_bounds__(256) void fm_batch_kernel(FmDev f, const uint8_t *_
     const uint64_t p = p0 + k;
     Search s;
     uint32_t cnt = 0;
-    if (!fm_init<BOTH>(f, pat, off, p, s, cnt))
-        while (!fm_advance<L, BOTH>(f, s, cnt)) {
+    if (!fm_init<BOTH, false>(f, pat, off, p, s, cnt))
+        while (!fm_advance<L, BOTH, false>(f, s, cnt)) {
         }
     emit<IV>(f, out, p, s, cnt);
 }
 
 __global__ void fill_zero_u64(unsigned long long *p) { *p = 0ull; }
 
-template <class L, bool BOTH, bool IV>
+template <class L, bool BOTH, bool IV, bool PACKED>
 __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8_t *__restrict__ pat,
                                                             const uint64_t *__restrict__ off, uint64_t npat,
                                                             uint32_t *__restrict__ out,
@@ -332,6 +357,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
     Search s;
     s.sp = s.ep = 0;
     s.P = pat;
+    s.base = 0;
     s.m = s.left = s.pos = s.rc = s.acc = 0;
     s.buf = 0;
     s.win = ~0u;
@@ -352,7 +378,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
                     if (mine < npat) {
                         p = mine;
                         uint32_t cnt = 0;
-                        if (fm_init<BOTH>(f, pat, off, p, s, cnt)) emit<IV>(f, out, p, s, cnt);
+                        if (fm_init<BOTH, PACKED>(f, pat, off, p, s, cnt)) emit<IV>(f, out, p, s, cnt);
                         else active = true;
                     }
                 }
@@ -364,7 +390,7 @@ __global__ __launch_bounds__(256) void fm_persistent_kernel(FmDev f, const uint8
         }
         if (active) {
             uint32_t cnt = 0;
-            if (fm_advance<L, BOTH>(f, s, cnt)) {
+            if (fm_advance<L, BOTH, PACKED>(f, s, cnt)) {
                 emit<IV>(f, out, p, s, cnt);
                 active = false;
             }
@@ -689,9 +715,11 @@ int quadfm_build(const uint64_t *d_bwt_packed2, uint64_t n_plus_1, uint64_t doll
 
 int quadfm_layout_kind(qr_quadfm h) { return h ? h->layout : -1; }
 
-// flags: QUADFM_BOTH_STRANDS; iv: write intervals (uint2 per pattern) instead of counts
+// flags: QUADFM_BOTH_STRANDS; iv: write intervals (uint2 per pattern) instead of counts; packed: the
+// patterns are 2-bit codes in a stream of u64 words at d_pat, pat_bytes and the offsets count bases
 static int count_persistent(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,
-                            uint32_t *d_count, unsigned long long *head, uint32_t flags, bool iv, hipStream_t stream) {
+                            uint32_t *d_count, unsigned long long *head, uint32_t flags, bool iv, hipStream_t stream,
+                            bool packed = false) {
     const int block = h->tune.block ? h->tune.block : 256;
     const uint32_t refill = h->tune.per_lane > 0 ? (uint32_t)h->tune.per_lane : 16u;
     const int wpc = h->tune.grid_waves > 0 ? h->tune.grid_waves : 16;
@@ -706,14 +734,20 @@ static int count_persistent(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_byte
     fm_layout(h->layout, [&](auto tag) {
         using L = decltype(tag);
         if (iv)
-            hipLaunchKernelGGL((fm_persistent_kernel<L, false, true>), g, b, 0, stream, f, d_pat, d_off, npat, d_count,
-                               head, refill);
+            hipLaunchKernelGGL((fm_persistent_kernel<L, false, true, false>), g, b, 0, stream, f, d_pat, d_off, npat,
+                               d_count, head, refill);
+        else if (packed && (flags & QUADFM_BOTH_STRANDS))
+            hipLaunchKernelGGL((fm_persistent_kernel<L, true, false, true>), g, b, 0, stream, f, d_pat, d_off, npat,
+                               d_count, head, refill);
+        else if (packed)
+            hipLaunchKernelGGL((fm_persistent_kernel<L, false, false, true>), g, b, 0, stream, f, d_pat, d_off, npat,
+                               d_count, head, refill);
         else if (flags & QUADFM_BOTH_STRANDS)
-            hipLaunchKernelGGL((fm_persistent_kernel<L, true, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count,
-                               head, refill);
+            hipLaunchKernelGGL((fm_persistent_kernel<L, true, false, false>), g, b, 0, stream, f, d_pat, d_off, npat,
+                               d_count, head, refill);
         else
-            hipLaunchKernelGGL((fm_persistent_kernel<L, false, false>), g, b, 0, stream, f, d_pat, d_off, npat, d_count,
-                               head, refill);
+            hipLaunchKernelGGL((fm_persistent_kernel<L, false, false, false>), g, b, 0, stream, f, d_pat, d_off, npat,
+                               d_count, head, refill);
         return 0;
     });
     QR_HIP(hipGetLastError());
@@ -735,6 +769,25 @@ int quadfm_count_ex(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const
     if (!npat) return QR_OK;
     unsigned long long *head = d_workspace ? reinterpret_cast<unsigned long long *>(d_workspace) : h->head;
     return count_persistent(h, d_pat, pat_bytes, d_off, npat, d_count, head, flags, false, stream);
+}
+
+int quadfm_count_packed(qr_quadfm h, const uint64_t *d_pat2, uint64_t pat_bases, const uint64_t *d_off, uint64_t npat,
+                        uint32_t flags, uint32_t *d_count, void *d_workspace, hipStream_t stream) {
+    int rc = count_args(h, reinterpret_cast<const uint8_t *>(d_pat2), pat_bases, d_off, npat, d_count,
+                        "quadfm_count_packed");
+    if (rc) return rc;
+    if (flags & ~QUADFM_BOTH_STRANDS) {
+        set_error("quadfm_count_packed: unknown flag bits 0x%x", flags);
+        return QR_EINVAL;
+    }
+    if (((uintptr_t)d_pat2 & 7) || (d_workspace && ((uintptr_t)d_workspace & 7))) {
+        set_error("quadfm_count_packed: d_pat2 and d_workspace must be 8-byte aligned");
+        return QR_EINVAL;
+    }
+    if (!npat) return QR_OK;
+    unsigned long long *head = d_workspace ? reinterpret_cast<unsigned long long *>(d_workspace) : h->head;
+    return count_persistent(h, reinterpret_cast<const uint8_t *>(d_pat2), pat_bases, d_off, npat, d_count, head, flags,
+                            false, stream, true);
 }
 
 int quadfm_intervals(qr_quadfm h, const uint8_t *d_pat, uint64_t pat_bytes, const uint64_t *d_off, uint64_t npat,

@@ -5,7 +5,7 @@
 // patterns.  Whenever a slot (a stream with its own work-queue head) is free, every request that has
 // arrived is admitted FIFO as one batch, as large as the pattern cap and the device arena allow; an
 // optional live free-memory check can also hold admission back.  A batch copies its pattern bytes
-// and offsets into the arena, rebases the offsets on the device, runs the persistent count kernel
+// (one per base, or 2-bit packed words) and offsets into the arena, rebases the offsets on the device, runs the persistent count kernel
 // on the slot's stream, copies the counts back and records an event.  Up to `slots` batches are in
 // flight at once, so batches that arrive while others run overlap on the device.  A request
 // finishes when the host sees its batch's event complete.
@@ -68,6 +68,7 @@ struct Arena {
 };
 
 // off[i] -= base for i < n: the batch's offsets, copied as they are, made relative to its first byte
+// (packed patterns: to the first base of its first word)
 __global__ void rebase_offsets(uint64_t *__restrict__ off, uint64_t n, uint64_t base) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) off[i] -= base;
@@ -118,7 +119,7 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     if (!out) return QR_EINVAL;
     *out = nullptr;
     if (!fm || slots < 1 || slots > 64 || budget_bytes < 4 * ALIGN || max_batch_patterns == 0 ||
-        (flags & ~QR_SERVE_CHECK_FREE_MEMORY)) {
+        (flags & ~(QR_SERVE_CHECK_FREE_MEMORY | QR_SERVE_PACKED_PATTERNS))) {
         set_error("qr_server_create: need an index, 1..64 slots, a budget of at least 1 KiB and a batch cap");
         return QR_EINVAL;
     }
@@ -188,9 +189,16 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
         set_error("qr_server_run: h_pat is NULL");
         return QR_EINVAL;
     }
+    const bool packed = s->flags & QR_SERVE_PACKED_PATTERNS;
+    // a batch's pattern bytes at h_pat, from stream unit c0 (a byte, or a base of packed words) to c1:
+    // packed, the whole words holding bases [c0, c1), starting at word c0 / 32
+    auto pat_bytes = [&](uint64_t c0, uint64_t c1) -> uint64_t {
+        if (!packed) return c1 - c0;
+        return c1 > c0 ? 8 * ((c1 + 31) / 32 - c0 / 32) : 0;
+    };
     auto batch_bytes = [&](uint64_t r0, uint64_t r1) {
         const uint64_t p0 = h_req_off[r0], p1 = h_req_off[r1];
-        return pad(h_off[p1] - h_off[p0]) + pad(8 * (p1 - p0 + 1)) + pad(4 * (p1 - p0)) + ALIGN;
+        return pad(pat_bytes(h_off[p0], h_off[p1])) + pad(8 * (p1 - p0 + 1)) + pad(4 * (p1 - p0)) + ALIGN;
     };
     Arena arena;
     arena.reset(s->budget);
@@ -253,17 +261,19 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             const int k = free_slots.back();
             free_slots.pop_back();
             const uint64_t p0 = h_req_off[nxt], p1 = h_req_off[r1], npat = p1 - p0;
-            const uint64_t c0 = h_off[p0], chars = h_off[p1] - c0;
+            const uint64_t c0 = h_off[p0], chars = pat_bytes(c0, h_off[p1]);
+            const uint64_t first = packed ? c0 / 32 * 8 : c0;  // first byte of h_pat the batch copies
+            const uint64_t rebase = packed ? c0 / 32 * 32 : c0;  // stream unit of that byte
             uint8_t *d_pat = s->arena_dev + base;
             uint64_t *d_off = reinterpret_cast<uint64_t *>(s->arena_dev + base + pad(chars));
             uint32_t *d_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(d_off) + pad(8 * (npat + 1)));
             hipStream_t st = s->streams[k];
             hipError_t e = hipSuccess;
-            if (chars) e = hipMemcpyAsync(d_pat, h_pat + c0, chars, hipMemcpyHostToDevice, st);
+            if (chars) e = hipMemcpyAsync(d_pat, h_pat + first, chars, hipMemcpyHostToDevice, st);
             if (e == hipSuccess) e = hipMemcpyAsync(d_off, h_off + p0, 8 * (npat + 1), hipMemcpyHostToDevice, st);
             if (e == hipSuccess) {
                 hipLaunchKernelGGL(rebase_offsets, dim3((uint32_t)((npat + 1 + 255) / 256)), dim3(256), 0, st, d_off, npat + 1,
-                                   c0);
+                                   rebase);
                 e = hipGetLastError();
             }
             if (e != hipSuccess) {
@@ -271,7 +281,9 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 err = QR_EHIP;
                 break;
             }
-            rc = quadfm_count_ex(s->fm, d_pat, chars, d_off, npat, 0u, d_cnt, s->heads + k, st);
+            rc = packed ? quadfm_count_packed(s->fm, reinterpret_cast<const uint64_t *>(d_pat), chars / 8 * 32, d_off, npat,
+                                              0u, d_cnt, s->heads + k, st)
+                        : quadfm_count_ex(s->fm, d_pat, chars, d_off, npat, 0u, d_cnt, s->heads + k, st);
             if (rc) {
                 err = rc;
                 break;

@@ -77,6 +77,14 @@ class Workload:
     def nreq(self) -> int:
         return self.arrival.size
 
+    def packed(self) -> np.ndarray:
+        """The patterns as one stream of 2-bit codes in u64 words (base i at bits [2 (i mod 32), +2)
+        of word i / 32); off then counts bases.  Computed once and kept."""
+        if getattr(self, "_pat2", None) is None:
+            import datagen
+            self._pat2 = datagen.pack2(self.pat)
+        return self._pat2
+
     def batch_bytes(self, r0: int, r1: int) -> int:
         p0, p1 = int(self.req_off[r0]), int(self.req_off[r1])
         chars = int(self.off[p1] - self.off[p0])
@@ -164,13 +172,14 @@ class NativeServer:
     and the optional free-memory check; host buffers are pinned once per workload."""
 
     def __init__(self, fm, slots: int, budget_bytes: int, max_batch_patterns: int = 1 << 18,
-                 check_free_memory: bool = False):
+                 check_free_memory: bool = False, packed: bool = False):
         import ctypes as C
 
         import paper_2602_04103_amd as qr
-        self.qr, self.fm = qr, fm
+        self.qr, self.fm, self.packed = qr, fm, packed
         h = C.c_void_p()
-        flags = qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0
+        flags = (qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0) | (qr.QR_SERVE_PACKED_PATTERNS if packed
+                                                                                else 0)
         qr._check(qr.lib().qr_server_create(fm.h, slots, int(budget_bytes), int(max_batch_patterns), flags,
                                             C.byref(h)), "qr_server_create")
         self.h = h.value
@@ -181,7 +190,10 @@ class NativeServer:
 
         import torch
         qr = self.qr
-        h_pat = torch.from_numpy(w.pat if w.pat.size else np.zeros(1, np.uint8)).pin_memory()
+        if self.packed:  # 2-bit words: a quarter of the bytes to copy
+            h_pat = torch.from_numpy(w.packed().view(np.int64)).pin_memory()
+        else:
+            h_pat = torch.from_numpy(w.pat if w.pat.size else np.zeros(1, np.uint8)).pin_memory()
         h_off = torch.from_numpy(np.ascontiguousarray(w.off, dtype=np.uint64).view(np.int64)).pin_memory()
         h_cnt = torch.zeros(max(1, int(w.off.size - 1)), dtype=torch.int32).pin_memory()
         req_off = np.ascontiguousarray(w.req_off, dtype=np.uint64)

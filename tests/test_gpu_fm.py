@@ -139,7 +139,7 @@ def test_fm_config3_full():
     locate sample) is prepared on the device; its suffix array is handed out and checked by the
     oracle directly (a permutation whose neighbouring suffixes increase).  Every one of the 10^7
     persistent-kernel counts then equals the oracle's suffix-array binary search over the text, and
-    so does every per-batch count and every count of the same index over the other QuadRank layouts
+    so does every per-batch count, every count of the 2-bit packed patterns and every count of the same index over the other QuadRank layouts
     (16-bit paired, 32-bit, 64-bit and 24/8, with the 12-mer start table).  200 sampled patterns are
     also recounted by the oracle's direct scan of the text.  Intervals and locate (SA sampled at rate
     32) are checked on the same index."""
@@ -167,12 +167,14 @@ def test_fm_config3_full():
     announce("fm-config3 count")
     got = fm.count(dp, do).cpu().numpy().view(np.uint32)
     got_b = fm.count_batched(dp, do, 1 << 20).cpu().numpy().view(np.uint32)
+    got_p = fm.count_packed(to_dev(datagen.pack2(pat)), int(off[-1]), do).cpu().numpy().view(np.uint32)
     fm.check()
     announce("fm-config3 oracle: suffix-array check and 10^7 counts")
     assert oracle.check_sa(codes, sa) == 0
     want_all = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
     assert np.array_equal(got, want_all)
     assert np.array_equal(got_b, want_all)
+    assert np.array_equal(got_p, want_all)
     for name, g in got_layouts.items():
         assert np.array_equal(g, want_all), name
     assert sa[dollar] == 0                       # the '$' row of the BWT is the row of suffix 0
@@ -364,3 +366,44 @@ def test_fm_rejects_bad_kmer():
     for k in (0, 13):
         with pytest.raises(qr.QRError):
             qr.QuadFm.from_text(codes, kmer=k)
+
+
+@pytest.mark.parametrize("layout", ["16", "32"])
+@pytest.mark.parametrize("n", [1, 1000, 200_000])
+def test_fm_count_packed(layout, n):
+    """Counts over 2-bit packed patterns (one stream of u64 words, offsets in bases) equal the
+    byte-pattern counts and the oracle's, one strand and both: patterns start at every place of a
+    word (a filler of k bases precedes them), span several words, are empty or shorter than the
+    start table, and the stream's last word carries garbage past its last base.  A pattern whose
+    offsets run past the stream's length counts 0 and is reported."""
+    qr = require_gpu()
+    codes = make_text(900 + n, n)
+    pats = [p for p in edge_patterns(codes, 19 * n) if p.size == 0 or p.max() <= 3]
+    sp, so, _ = datagen.patterns(n + 13, codes, 3000, minlen=1, maxlen=120, frac_sampled=0.8, sub=0.02)
+    pats += [sp[int(so[i]):int(so[i + 1])] for i in range(so.size - 1)]
+    pats += [oracle.revcomp(p) for p in pats[:40]]
+    pat, off = csr(pats)
+    announce("fm-packed", layout, n, len(pats))
+    fm = qr.QuadFm.from_text(codes, kmer=8, layout=qr.LAYOUT_BY_NAME[layout])
+    sa = oracle.suffix_array(codes)
+    want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
+    both = oracle.count_both_strands(codes, sa, pat, off).astype(np.uint32)
+    total = int(off[-1])
+    for k in (0, 1, 17, 31, 32, 45):  # filler bases before the first pattern
+        stream = np.concatenate([datagen.dna_codes(7 + k, k), pat[:total]]).astype(np.uint8)
+        words = to_dev(datagen.pack2(stream, tail_garbage=True, seed=k + 1))
+        o = to_dev((off + np.uint64(k)).astype(np.uint64))
+        got = fm.count_packed(words, stream.size, o).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want), k
+        got2 = fm.count_packed(words, stream.size, o, both_strands=True).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got2, both), k
+        fm.check()
+    # offsets past the stream: counted 0, reported, nothing read beyond it
+    words = to_dev(datagen.pack2(pat[:total] if total else np.zeros(1, np.uint8)))
+    bad = off.copy()
+    bad[-1] = total + 64
+    got = fm.count_packed(words, total, to_dev(bad)).cpu().numpy().view(np.uint32)
+    assert got[-1] == 0 and np.array_equal(got[:-1], want[:-1])
+    with pytest.raises(qr.QRError):
+        fm.check()
+    fm.free()

@@ -83,20 +83,23 @@ def test_serve_tight_budget_still_exact(index):
 
 
 # ------------------------------------------------------------------------------ native serving loop
-def native(qr, fm, w, slots, budget, max_batch, check_free=False):
+def native(qr, fm, w, slots, budget, max_batch, check_free=False, packed=False):
     from paper_2602_04103_amd.serve import NativeServer
     srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=max_batch,
-                       check_free_memory=check_free)
+                       check_free_memory=check_free, packed=packed)
     st = srv.run(w, deadline_s=120.0)
     return srv, st
 
 
-def test_native_poisson_mix_equals_alone_and_oracle(index):
+@pytest.mark.parametrize("packed", [False, True])
+def test_native_poisson_mix_equals_alone_and_oracle(index, packed):
+    """Patterns sent one byte per base, or as 2-bit packed words (batches then copy the whole words
+    around their bases, and their first pattern starts inside a word)."""
     qr, text, fm, sa = index
     from paper_2602_04103_amd.serve import make_workload
     w = make_workload(87, text, rate_patterns_per_s=4e6, duration_s=0.25, max_size=4096)
-    announce("native serve poisson", w.nreq)
-    srv, st = native(qr, fm, w, slots=4, budget=32 << 20, max_batch=1 << 15, check_free=True)
+    announce("native serve poisson", w.nreq, "packed" if packed else "bytes")
+    srv, st = native(qr, fm, w, slots=4, budget=32 << 20, max_batch=1 << 15, check_free=True, packed=packed)
     assert not np.isnan(st.finish_s).any()
     assert np.all(st.finish_s >= w.arrival)                 # nothing finishes before it arrives
     served = srv.counts(0, int(w.req_off[-1]))
@@ -108,13 +111,14 @@ def test_native_poisson_mix_equals_alone_and_oracle(index):
     srv.free()
 
 
-def test_native_burst_overlaps_and_tight_budget(index):
+@pytest.mark.parametrize("packed", [False, True])
+def test_native_burst_overlaps_and_tight_budget(index, packed):
     qr, text, fm, sa = index
     from paper_2602_04103_amd.serve import make_workload
     w = make_workload(88, text, rate_patterns_per_s=1e8, duration_s=0.01, max_size=512)
     w.arrival[:] = 0.0
-    announce("native serve burst", w.nreq)
-    srv, st = native(qr, fm, w, slots=4, budget=16 << 20, max_batch=2048)
+    announce("native serve burst", w.nreq, "packed" if packed else "bytes")
+    srv, st = native(qr, fm, w, slots=4, budget=16 << 20, max_batch=2048, packed=packed)
     assert st.max_inflight >= 2 and st.max_inflight <= 4
     assert st.max_reserved_bytes <= 16 << 20
     want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
@@ -122,7 +126,7 @@ def test_native_burst_overlaps_and_tight_budget(index):
     srv.free()
     one = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
     announce("native serve tight budget", 2 * one)
-    srv, st = native(qr, fm, w, slots=4, budget=2 * one, max_batch=256)
+    srv, st = native(qr, fm, w, slots=4, budget=2 * one, max_batch=256, packed=packed)
     assert st.max_reserved_bytes <= 2 * one
     assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
     srv.free()
