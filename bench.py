@@ -891,7 +891,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
            "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "layout": args.serve_layout,
-           "patterns": "bytes" if args.serve_bytes else "packed",
+           "pattern_form": "bytes" if args.serve_bytes else "packed",
            "device_free_bytes_at_start": int(free),
            "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": [],
            "fm_count_hbm": hbm_row}
@@ -938,13 +938,13 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                            packed=args.serve_bytes)
         summ = srv.run(w, deadline_s=120.0).summary()
         summ["offered_patterns_per_s"] = load
-        summ["patterns"] = "packed" if args.serve_bytes else "bytes"
+        summ["pattern_form"] = "packed" if args.serve_bytes else "bytes"
         d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
         summ["equal_to_direct_count"] = bool(np.array_equal(srv.counts(0, int(w.req_off[-1])), d_all))
         srv.free()
         res["top_load_other_form"] = summ
         log("serve load %.0e with %s patterns: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, equal=%s" % (
-            load, summ["patterns"], summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6,
+            load, summ["pattern_form"], summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6,
             summ["equal_to_direct_count"]))
     fm.free()
     return res
