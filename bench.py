@@ -613,6 +613,15 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     res["both_strands_patterns_per_s"] = npat / t_2
     res["both_strands_ms"] = t_2 * 1e3
     log("fm both strands %.1f M patterns/s (%.2f ms)" % (npat / t_2 / 1e6, t_2 * 1e3))
+    # the same count over 2-bit packed patterns (a quarter of the pattern bytes)
+    dp2 = to_dev(datagen.pack2(pat))
+    cnt3 = torch.empty(npat, dtype=torch.int32, device=dev)
+    t_k = autotune.time_launch(lambda: fm.count_packed(dp2, int(off[-1]), do, cnt3), reps=args.fm_reps)
+    res["packed_patterns_per_s"] = npat / t_k
+    res["packed_equals_bytes"] = bool(torch.equal(cnt3, cnt))
+    del dp2, cnt3
+    log("fm packed patterns %.1f M patterns/s (%.2f ms), equal=%s" % (npat / t_k / 1e6, t_k * 1e3,
+                                                                     res["packed_equals_bytes"]))
     # roofline of the persistent kernel: algorithmic lines (128 B each) per pattern from a sample
     work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=kbest)
     achieved = npat / t_p * work["lines_per_pattern"] * 128 / 1e9
@@ -620,14 +629,17 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     line_bytes = ((n + 1) // 480 + 1) * 128
     ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
     lps = npat / t_p * work["lines_per_pattern"]
-    res["roofline"] = {"bound": "cache", "kernel": "fm_persistent_kernel<QR16, false, false>",
+    plps = res["packed_patterns_per_s"] * work["lines_per_pattern"]
+    res["roofline"] = {"bound": "cache", "kernel": "fm_persistent_kernel<QR16, false, false, false>",
                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
                        "lines_per_s": lps, "line_gather_ceiling_lines_per_s": ceil_lps,
                        "frac": round(lps / ceil_lps, 4),
+                       "packed_patterns_lines_per_s": plps, "packed_patterns_frac": round(plps / ceil_lps, 4),
                        "note": "algorithmic 128-byte lines; the %.0f MB of lines fit the 256 MB memory-side cache, "
                                "so the fraction is taken against the measured random-line gather rate over an "
-                               "allocation of the same size, not against HBM" % (line_bytes / 1e6)}
+                               "allocation of the same size, not against HBM (which a cache-resident count with "
+                               "packed patterns can exceed)" % (line_bytes / 1e6)}
     log("fm work: %.1f steps, %.1f lines, %.1f half lines per pattern -> %.0f GB/s of lines (%.0f%% of HBM), "
         "%.2f G lines/s against a gather ceiling of %.2f G lines/s over %.0f MB (%.0f%%)" % (
             work["steps_per_pattern"], work["lines_per_pattern"], work["half_lines_per_pattern"], achieved,
@@ -715,6 +727,11 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
         t_p = autotune.time_launch(lambda f=fm: f.count(dp, do, cnt), reps=args.fm_reps)
         row = {"index_bytes": fm.nbytes, "persistent_patterns_per_s": npat / t_p, "persistent_ms": t_p * 1e3,
                "tuning": best}
+        dp2, cnt3 = to_dev(datagen.pack2(pat)), torch.empty(npat, dtype=torch.int32, device=dev)
+        t_k = autotune.time_launch(lambda f=fm: f.count_packed(dp2, int(off[-1]), do, cnt3), reps=args.fm_reps)
+        row["packed_patterns_per_s"] = npat / t_k
+        row["packed_equals_bytes"] = bool(torch.equal(cnt3, cnt))
+        del dp2, cnt3
         for batch in (1 << 16, 1 << 20, 0):
             t_b = autotune.time_launch(lambda f=fm: f.count_batched(dp, do, batch, cnt_b), reps=args.fm_reps)
             row["batched_%s_patterns_per_s" % (batch or "all")] = npat / t_b
@@ -725,16 +742,18 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
         lps = npat / t_p * work["lines_per_pattern"]
         row["work"] = work
         row["roofline"] = {"bound": "hbm",
-                           "kernel": "fm_persistent_kernel<%s, false, false>" % FM_TRAIT[args.serve_layout],
+                           "kernel": "fm_persistent_kernel<%s, false, false, false>" % FM_TRAIT[args.serve_layout],
                            "achieved": round(lps * 128 / 1e9, 1),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(lps * 128 / 1e9 / HBM_PEAK_GBS, 4),
                            "lines_per_s": lps, "frac_of_line_gather_ceiling": round(lps / ceil_lps, 4)}
         res["by_kmer"][str(k)] = row
-        log("fm 2^%d k=%d: persistent %.1f M patterns/s, best batched %.1f M (gain %.2fx), %.1f lines/pattern, "
-            "%.0f GB/s of lines = %.1f%% of HBM, %.0f%% of the gather ceiling (%.2f G lines/s), equal=%s" % (
-                int(np.log2(n)), k, npat / t_p / 1e6, best_b / 1e6, row["gain_vs_best_batched"],
-                work["lines_per_pattern"], lps * 128 / 1e9, 100 * lps * 128 / 1e9 / HBM_PEAK_GBS,
-                100 * lps / ceil_lps, ceil_lps / 1e9, row["persistent_equals_batched"]))
+        log("fm 2^%d k=%d: persistent %.1f M patterns/s (packed patterns %.1f M), best batched %.1f M (gain %.2fx), "
+            "%.1f lines/pattern, %.0f GB/s of lines = %.1f%% of HBM, %.0f%% of the gather ceiling (%.2f G lines/s), "
+            "equal=%s" % (
+                int(np.log2(n)), k, npat / t_p / 1e6, row["packed_patterns_per_s"] / 1e6, best_b / 1e6,
+                row["gain_vs_best_batched"], work["lines_per_pattern"], lps * 128 / 1e9,
+                100 * lps * 128 / 1e9 / HBM_PEAK_GBS, 100 * lps / ceil_lps, ceil_lps / 1e9,
+                row["persistent_equals_batched"] and row["packed_equals_bytes"]))
         if k != args.serve_kmer:
             fm.free()
         else:
@@ -746,8 +765,8 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
         ref = cnt.clone()
         others = {name: qr.QuadFm(bwt, n + 1, dollar, kmer=k, layout=qr.LAYOUT_BY_NAME[name])
                   for name in ["16"] + names}
-        res["by_layout"] = fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, others, ref, dp, do, cnt, pat, off,
-                                          npat, n, k, min(npat, 1_000_000))
+        res["by_layout"] = fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, others, ref, dp, do, cnt, pat,
+                                          off, npat, n, k, min(npat, 1_000_000))
         res["best_layout"], res["roofline"] = fm_best_layout(res["by_layout"])
         for f in others.values():
             f.free()
@@ -773,13 +792,16 @@ FM_TRAIT = {"16": "QR16", "16p": "QR16P", "32": "QR32", "64": "QR64", "24_8": "Q
 def fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, fms, ref, dp, do, cnt, pat, off, npat, n, kmer,
                    tune_sub):
     """The persistent count of the same BWT's index over each QuadRank layout (size against
-    throughput, as the paper compares QuadFm over each rank structure): tuned launch settings, rate,
-    counts equal to the reference counts, lines per pattern in the layout's geometry and the
-    fraction of the random-line gather ceiling over an allocation of the layout's line bytes.  All
-    indexes are built before any is timed, and the rates are timed twice, in opposite orders (the
-    best of the two is reported): where an allocation lands in HBM moves a random-line rate by a
-    few per cent."""
-    rows, rates = {}, {name: [] for name in fms}
+    throughput, as the paper compares QuadFm over each rank structure): tuned launch settings, rate
+    with byte patterns and with 2-bit packed ones, counts equal to the reference counts, lines per
+    pattern in the layout's geometry and the fraction of the random-line gather ceiling over an
+    allocation of the layout's line bytes.  All indexes are built before any is timed, and the rates
+    are timed twice, in opposite orders (the best of the two is reported): where an allocation lands
+    in HBM moves a random-line rate by a few per cent."""
+    import datagen
+    rows, rates, prates = {}, {name: [] for name in fms}, {name: [] for name in fms}
+    dp2 = to_dev(datagen.pack2(pat))
+    nb = int(off[-1])
     for name, fm in fms.items():
         best = fm_tune(args, autotune, "2^%d|layout|%s" % (int(np.log2(n)), name), n, fm,
                        lambda f=fm: f.count(dp, do[:tune_sub + 1], cnt[:tune_sub]))
@@ -788,36 +810,46 @@ def fm_layout_rows(args, qr, autotune, np, torch, dev, to_dev, fms, ref, dp, do,
         for name in order:
             rates[name].append(npat / autotune.time_launch(lambda f=fms[name]: f.count(dp, do, cnt), reps=args.fm_reps))
             eq = bool(torch.equal(cnt, ref))
+            prates[name].append(npat / autotune.time_launch(lambda f=fms[name]: f.count_packed(dp2, nb, do, cnt),
+                                                            reps=args.fm_reps))
+            eq = eq and bool(torch.equal(cnt, ref))
             rows[name]["equal_to_reference"] = rows[name].get("equal_to_reference", True) and eq
+    del dp2
     for name, fm in fms.items():
-        rate = max(rates[name])
+        rate, prate = max(rates[name]), max(prates[name])
         work = fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=kmer, layout=name)
         data = FM_GEOMETRY[name][0]
         line_bytes = ((n + 1) // data + 1) * 128
         ceil_lps = gather_ceiling(qr, torch, dev, line_bytes)
-        lps = rate * work["lines_per_pattern"]
+        lps, plps = rate * work["lines_per_pattern"], prate * work["lines_per_pattern"]
         rows[name].update({"index_bytes": fm.nbytes, "bits_per_base": round(fm.nbytes * 8 / n, 3),
                            "persistent_patterns_per_s": rate, "passes_patterns_per_s": rates[name],
-                           "persistent_ms": npat / rate * 1e3, "lines_per_pattern": work["lines_per_pattern"],
+                           "persistent_ms": npat / rate * 1e3, "packed_patterns_per_s": prate,
+                           "packed_passes_patterns_per_s": prates[name],
+                           "lines_per_pattern": work["lines_per_pattern"],
                            "half_lines_per_pattern": work["half_lines_per_pattern"], "lines_per_s": lps,
-                           "line_gather_ceiling_lines_per_s": ceil_lps,
-                           "frac_of_line_gather_ceiling": round(lps / ceil_lps, 4)})
-        log("fm 2^%d k=%d layout %s: %.1f M patterns/s (passes %s), %.3f bits/base, %.1f lines/pattern, %.0f%% of the "
-            "gather ceiling (%.2f G lines/s), equal=%s" % (
-                int(np.log2(n)), kmer, name, rate / 1e6, " ".join("%.1f" % (r / 1e6) for r in rates[name]),
-                fm.nbytes * 8 / n, work["lines_per_pattern"], 100 * lps / ceil_lps, ceil_lps / 1e9,
-                rows[name]["equal_to_reference"]))
+                           "packed_lines_per_s": plps, "line_gather_ceiling_lines_per_s": ceil_lps,
+                           "frac_of_line_gather_ceiling": round(lps / ceil_lps, 4),
+                           "packed_frac_of_line_gather_ceiling": round(plps / ceil_lps, 4)})
+        log("fm 2^%d k=%d layout %s: %.1f M patterns/s, packed %.1f M (passes %s / %s), %.3f bits/base, "
+            "%.1f lines/pattern, %.0f%% / %.0f%% of the gather ceiling (%.2f G lines/s), equal=%s" % (
+                int(np.log2(n)), kmer, name, rate / 1e6, prate / 1e6,
+                " ".join("%.1f" % (r / 1e6) for r in rates[name]), " ".join("%.1f" % (r / 1e6) for r in prates[name]),
+                fm.nbytes * 8 / n, work["lines_per_pattern"], 100 * lps / ceil_lps, 100 * plps / ceil_lps,
+                ceil_lps / 1e9, rows[name]["equal_to_reference"]))
     return rows
 
 
 def fm_best_layout(rows):
-    """The layout with the highest count rate, and a roofline object for its kernel."""
-    name = max(rows, key=lambda k: rows[k]["persistent_patterns_per_s"])
+    """The layout with the highest count rate over packed patterns, and a roofline object for its
+    kernel (the served index's form)."""
+    name = max(rows, key=lambda k: rows[k]["packed_patterns_per_s"])
     r = rows[name]
-    return name, {"bound": "hbm", "kernel": "fm_persistent_kernel<%s, false, false>" % FM_TRAIT[name],
-                  "layout": name, "achieved": round(r["lines_per_s"] * 128 / 1e9, 1), "peak": HBM_PEAK_GBS,
-                  "unit": "GB/s", "frac": round(r["lines_per_s"] * 128 / 1e9 / HBM_PEAK_GBS, 4),
-                  "lines_per_s": r["lines_per_s"], "frac_of_line_gather_ceiling": r["frac_of_line_gather_ceiling"]}
+    achieved = r["packed_lines_per_s"] * 128 / 1e9
+    return name, {"bound": "hbm", "kernel": "fm_persistent_kernel<%s, false, false, true>" % FM_TRAIT[name],
+                  "layout": name, "patterns": "2-bit packed", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "lines_per_s": r["packed_lines_per_s"],
+                  "frac_of_line_gather_ceiling": r["packed_frac_of_line_gather_ceiling"]}
 
 
 def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=8, sample=2000, seed=11, layout="16"):
