@@ -175,7 +175,8 @@ def main():
             build_rate("quadrank%s" % L, n_qr // 4, structs["quadrank"][L].nbytes, time.time() - t0)
         del d
         if "quadrank_rank" in rows:
-            qsets["quadrank_rank"] = (to_dev(datagen.queries(3204, n_qr, TOTAL_Q)), to_dev(datagen.symbols(3205, TOTAL_Q)))
+            qsets["quadrank_rank"] = (to_dev(datagen.queries(3204, n_qr, TOTAL_Q)),
+                                      to_dev(datagen.symbols(3205, TOTAL_Q)))
         if "quadrank_rank4" in rows:
             qsets["quadrank_rank4"] = (to_dev(datagen.queries(3206, n_qr, TOTAL_Q)), None)
         if "quadrank_prefix_rank" in rows:  # optional row (not in the default step)
@@ -893,6 +894,57 @@ def fm_work_sample(fm, pat, off, npat, np, torch, to_dev, kmer=8, sample=2000, s
             "half_lines_per_pattern": halves / n}
 
 
+def serve_light_load(qr, np, torch, to_dev, fm, text, slots, budget, packed):
+    """Where a lightly loaded server's latency goes.  Device time of one count of a single pattern
+    against its length: the patterns are substrings of the text, so each search takes every step, one
+    dependent half-line load per base beyond the start table, and the slope is the latency of one
+    step.  Then the native loop on requests of one such pattern arriving once per millisecond (no
+    queueing): its latency less the device time is the loop's own cost (copies, launches, polling)."""
+    from paper_2602_04103_amd.serve import NativeServer, Workload
+    rng = np.random.default_rng(6060)
+    n = text.size
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+    lens = (20, 80, 160, 250)
+    dev_us = {}
+    for L in lens:
+        pat = np.concatenate([text[p:p + L] for p in rng.integers(0, n - L, 16)])
+        dp = to_dev(pat)
+        ts = []
+        for i in range(16):
+            do = to_dev(np.array([i * L, (i + 1) * L], np.uint64))
+            fm.count(dp, do, cnt)
+            for _ in range(3):
+                s.record()
+                fm.count(dp, do, cnt)
+                e.record()
+                e.synchronize()
+                ts.append(s.elapsed_time(e) * 1e3)
+        dev_us[L] = statistics.median(ts)
+    k = fm.kmer
+    res = {"single_pattern_device_us": {str(L): round(dev_us[L], 1) for L in lens},
+           "us_per_step": round((dev_us[lens[-1]] - dev_us[lens[0]]) / (lens[-1] - lens[0]), 3),
+           "start_table_k": k, "one_pattern_requests": {}}
+    for L in (20, 250):
+        nreq = 200
+        pat = np.concatenate([text[p:p + L] for p in rng.integers(0, n - L, nreq)])
+        w = Workload(pat=pat, off=np.arange(nreq + 1, dtype=np.uint64) * L, req_off=np.arange(nreq + 1, dtype=np.int64),
+                     arrival=np.arange(nreq, dtype=np.float64) * 1e-3)
+        srv = NativeServer(fm, slots=slots, budget_bytes=budget, packed=packed)
+        srv.run(w, deadline_s=60.0)
+        lat = srv.run(w, deadline_s=60.0).latency_s * 1e6
+        direct = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
+        res["one_pattern_requests"][str(L)] = {
+            "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+            "loop_us_over_device": round(float(np.percentile(lat, 50)) - dev_us[L], 1),
+            "equal_to_direct_count": bool(np.array_equal(srv.counts(0, nreq), direct))}
+        srv.free()
+    log("serve light load: one pattern %s us (%.2f us per step); one-pattern requests p50 %s" % (
+        res["single_pattern_device_us"], res["us_per_step"],
+        {L: v["p50_us"] for L, v in res["one_pattern_requests"].items()}))
+    return res
+
+
 def bench_serve(args, qr, datagen, np, torch, to_dev):
     """Poisson request arrivals against a device-resident index; each request holds 1..4096 patterns
     (log-uniform), lengths 20..250; offered loads swept; latency from arrival to counts on the host."""
@@ -936,6 +988,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     ns0.run(w0, deadline_s=60.0)
     ns0.free()
     res["loop"] = "python" if args.serve_python else "native"
+    res["light_load"] = serve_light_load(qr, np, torch, to_dev, fm, text, slots, budget, not args.serve_bytes)
     for k, load in enumerate(float(x) for x in args.serve_loads.split(",") if x):
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
         if args.serve_python:
