@@ -361,7 +361,9 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
 typedef struct qr_server_s *qr_server;
 #define QR_SERVE_CHECK_FREE_MEMORY 1u
 #define QR_SERVE_PACKED_PATTERNS 2u /* h_pat holds 2-bit packed u64 words and h_off counts bases (the
-                                       stream of quadfm_count_packed); batches copy whole words */
+                                       stream of quadfm_count_packed); batches copy whole words, so
+                                       h_pat must hold ceil(h_off[h_req_off[nreq]] / 32) words (without
+                                       the flag: h_off[h_req_off[nreq]] bytes) */
 typedef struct {
     uint64_t batches;            /* batches launched */
     uint64_t max_inflight;       /* most batches in flight at once */
