@@ -45,6 +45,21 @@ STREAM_BYTES_PER_QUERY = {
 }
 
 
+# The paper's own measurements, quoted as context (CPU only; it reports no GPU number): its hardware,
+# the memory bounds it measured there, and the rank rate they imply (§5 and the appendix on EPYC).
+PAPER_CPU_CONTEXT = {
+    "hardware": "Intel Core i7-10750H, 6 cores / 12 threads pinned at 3.0 GHz, dual-channel DDR4-3200 "
+                "(controller at 2933 MHz); the paper names its random-access throughput as the limit",
+    "ram_latency_ns": 80,
+    "one_thread_ns_per_random_line": 7.5,
+    "all_threads_ns_per_random_line": 2.5,
+    "birank16_prefetch_ns_per_query": {"one_thread": 8, "all_threads": 2.5},
+    "derived_all_threads_rank_queries_per_s": 4.0e8,
+    "quadrank16": "one query per cache line with prefetching; rank4 costs about as much as rank(q,c)",
+    "also": "AMD EPYC 9684X (96 cores, 12-channel DDR5): the same trends, 130 ns RAM latency",
+}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -525,6 +540,7 @@ def main():
         "fm": fm_res,
         "serve": serve_res,
         "cpu_baseline": cpu,
+        "paper_cpu_context": PAPER_CPU_CONTEXT,
         "setup_s": round(time.time() - t_setup, 1),
     }
     line = json.dumps(out)
