@@ -990,7 +990,8 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     res = {"workload": "QuadFm serving: 2^%d-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs); "
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
-           "slots": slots, "hbm_budget_bytes": budget, "kmer": args.serve_kmer, "layout": args.serve_layout,
+           "slots": slots, "hbm_budget_bytes": budget, "arena": "grows from free HBM (native loop)",
+           "kmer": args.serve_kmer, "layout": args.serve_layout,
            "pattern_form": "bytes" if args.serve_bytes else "packed",
            "device_free_bytes_at_start": int(free),
            "text_sa_bwt_s": t1 - t0, "sa_bwt_on": "host" if args.host_sa else "device", "loads": [],
@@ -1013,10 +1014,12 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                          free_bytes_fn=lambda: torch.cuda.mem_get_info()[0])
         else:
             ex = srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
-                                    check_free_memory=True, packed=not args.serve_bytes)
+                                    check_free_memory=True, packed=not args.serve_bytes, grow=True)
         st = srv.run(w, deadline_s=120.0)
         summ = st.summary()
         summ["offered_patterns_per_s"] = load
+        if not args.serve_python:
+            summ["arena_bytes"] = srv.arena_bytes
         # every served count equals one direct count of all patterns of the run
         d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
         summ["equal_to_direct_count"] = bool(np.array_equal(ex.counts(0, int(w.req_off[-1])), d_all))
@@ -1036,7 +1039,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         k = len(res["loads"]) - 1
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
         srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18, check_free_memory=True,
-                           packed=args.serve_bytes)
+                           packed=args.serve_bytes, grow=True)
         summ = srv.run(w, deadline_s=120.0).summary()
         summ["offered_patterns_per_s"] = load
         summ["pattern_form"] = "packed" if args.serve_bytes else "bytes"

@@ -350,13 +350,20 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
  * streams is free, every request that has arrived is admitted first-in first-out as one batch of at
  * most max_batch_patterns patterns (a larger single request is still admitted alone) whose device
  * bytes fit the budget's first-fit arena; with QR_SERVE_CHECK_FREE_MEMORY, a batch larger than the
- * device's free memory also waits.  Each batch copies its patterns in, counts them with the
- * persistent kernel on its slot's stream and copies the counts to h_counts[h_req_off[r]..].
+ * device's free memory also waits.  With QR_SERVE_GROW_FROM_FREE_HBM the budget is the arena's first
+ * chunk and admission follows the device's free memory: a batch that finds no room adds a chunk of
+ * max(its bytes, budget_bytes), rounded up to 2 MiB, when hipMemGetInfo shows that much free with at
+ * least max(1 GiB, 1/64 of the device's memory) left over, and waits for earlier batches otherwise;
+ * batches are still cut to the budget where their requests allow, so the arena stays within about
+ * `slots` chunks.  Chunks are kept until qr_server_free; qr_server_arena_bytes gives the arena's
+ * size.  Each batch copies its patterns in, counts them with the persistent kernel on its slot's
+ * stream and copies the counts to h_counts[h_req_off[r]..].
  * h_finish_s[r] receives the time at which the host saw request r's batch complete.  For
  * asynchronous copies, h_pat, h_off and h_counts should be pinned host memory (hipHostMalloc);
  * pageable memory works but serialises the copies.  The server owns its arena, streams and queue
  * heads; the index must outlive it.  run returns once every request is done (QR_ERANGE if
- * deadline_s passes first or a request alone exceeds the budget), with no copy in flight.
+ * deadline_s passes first or a request alone exceeds the budget, or with QR_SERVE_GROW_FROM_FREE_HBM
+ * every chunk and the free memory), with no copy in flight.
  * ---------------------------------------------------------------------------------------------- */
 typedef struct qr_server_s *qr_server;
 #define QR_SERVE_CHECK_FREE_MEMORY 1u
@@ -364,6 +371,7 @@ typedef struct qr_server_s *qr_server;
                                        stream of quadfm_count_packed); batches copy whole words, so
                                        h_pat must hold ceil(h_off[h_req_off[nreq]] / 32) words (without
                                        the flag: h_off[h_req_off[nreq]] bytes) */
+#define QR_SERVE_GROW_FROM_FREE_HBM 4u /* the arena grows from the device's free memory (above) */
 typedef struct {
     uint64_t batches;            /* batches launched */
     uint64_t max_inflight;       /* most batches in flight at once */
@@ -376,6 +384,7 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
 int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, const uint64_t *h_req_off, uint64_t nreq,
                   const double *h_arrival_s, uint32_t *h_counts, double *h_finish_s, double deadline_s,
                   qr_serve_stats *stats);
+uint64_t qr_server_arena_bytes(qr_server s); /* bytes of the arena's chunks (0 for NULL) */
 int qr_server_free(qr_server s);
 
 /* ------------------------------------------------------------------------------------------------

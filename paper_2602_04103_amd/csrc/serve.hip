@@ -4,11 +4,13 @@
 // Requests arrive over time (their arrival times are given), each holding a contiguous block of
 // patterns.  Whenever a slot (a stream with its own work-queue head) is free, every request that has
 // arrived is admitted FIFO as one batch, as large as the pattern cap and the device arena allow; an
-// optional live free-memory check can also hold admission back.  A batch copies its pattern bytes
-// (one per base, or 2-bit packed words) and offsets into the arena, rebases the offsets on the device, runs the persistent count kernel
-// on the slot's stream, copies the counts back and records an event.  Up to `slots` batches are in
-// flight at once, so batches that arrive while others run overlap on the device.  A request
-// finishes when the host sees its batch's event complete.
+// optional live free-memory check can also hold admission back, and the arena can grow from the
+// device's free memory (chunks of at least the budget, kept above a headroom).  A batch copies its
+// pattern bytes (one per base, or 2-bit packed words) and offsets into the arena, rebases the
+// offsets on the device, runs the persistent count kernel on the slot's stream, copies the counts
+// back and records an event.  Up to `slots` batches are in flight at once, so batches that arrive
+// while others run overlap on the device.  A request finishes when the host sees its batch's event
+// complete.
 //
 // The policy (FIFO batches, first-fit arena of 256-byte aligned blocks, batch byte budget) is the
 // same as the scheduler the Python tests exercise with a CPU stand-in.
@@ -28,42 +30,49 @@ constexpr uint64_t ALIGN = 256;
 
 uint64_t pad(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-// First-fit allocator over [0, size): sorted, disjoint, coalesced free ranges.
+// First-fit allocator over a list of chunks, each [0, size): per chunk sorted, disjoint, coalesced
+// free ranges; a block never spans two chunks.
 struct Arena {
-    uint64_t size = 0;
-    std::vector<std::pair<uint64_t, uint64_t>> free_;
+    std::vector<uint64_t> size;
+    std::vector<std::vector<std::pair<uint64_t, uint64_t>>> free_;
 
-    void reset(uint64_t s) {
-        size = s;
-        free_.assign(1, {0, s});
+    void add(uint64_t s) {
+        size.push_back(s);
+        free_.push_back({{0, s}});
     }
-    bool alloc(uint64_t nbytes, uint64_t &at) {
-        for (size_t k = 0; k < free_.size(); ++k) {
-            const uint64_t a = free_[k].first, b = free_[k].second;
-            const uint64_t s = (a + ALIGN - 1) / ALIGN * ALIGN;
-            if (s + nbytes <= b) {
-                std::vector<std::pair<uint64_t, uint64_t>> pieces;
-                if (s > a) pieces.push_back({a, s});
-                if (s + nbytes < b) pieces.push_back({s + nbytes, b});
-                free_.erase(free_.begin() + k);
-                free_.insert(free_.begin() + k, pieces.begin(), pieces.end());
-                at = s;
-                return true;
+    uint64_t largest() const { return size.empty() ? 0 : *std::max_element(size.begin(), size.end()); }
+    bool alloc(uint64_t nbytes, uint32_t &chunk, uint64_t &at) {
+        for (size_t c = 0; c < free_.size(); ++c) {
+            auto &fr = free_[c];
+            for (size_t k = 0; k < fr.size(); ++k) {
+                const uint64_t a = fr[k].first, b = fr[k].second;
+                const uint64_t s = (a + ALIGN - 1) / ALIGN * ALIGN;
+                if (s + nbytes <= b) {
+                    std::vector<std::pair<uint64_t, uint64_t>> pieces;
+                    if (s > a) pieces.push_back({a, s});
+                    if (s + nbytes < b) pieces.push_back({s + nbytes, b});
+                    fr.erase(fr.begin() + k);
+                    fr.insert(fr.begin() + k, pieces.begin(), pieces.end());
+                    chunk = (uint32_t)c;
+                    at = s;
+                    return true;
+                }
             }
         }
         return false;
     }
-    void release(uint64_t start, uint64_t nbytes) {
+    void release(uint32_t chunk, uint64_t start, uint64_t nbytes) {
+        auto &fr = free_[chunk];
         const std::pair<uint64_t, uint64_t> blk{start, start + nbytes};
-        free_.insert(std::lower_bound(free_.begin(), free_.end(), blk), blk);
+        fr.insert(std::lower_bound(fr.begin(), fr.end(), blk), blk);
         std::vector<std::pair<uint64_t, uint64_t>> merged;
-        for (const auto &r : free_) {
+        for (const auto &r : fr) {
             if (!merged.empty() && merged.back().second >= r.first)
                 merged.back().second = std::max(merged.back().second, r.second);
             else
                 merged.push_back(r);
         }
-        free_.swap(merged);
+        fr.swap(merged);
     }
 };
 
@@ -77,7 +86,13 @@ __global__ void rebase_offsets(uint64_t *__restrict__ off, uint64_t n, uint64_t 
 struct Inflight {
     bool busy = false;
     uint64_t r0 = 0, r1 = 0, base = 0, nbytes = 0;
+    uint32_t chunk = 0;
 };
+
+// Growth of the arena from the device's free memory: a new chunk holds max(need, budget) bytes,
+// rounded up to 2 MiB, and is taken only while the free memory left after it stays at or above
+// max(1 GiB, 1/64 of the device's memory).
+constexpr uint64_t GROW_ROUND = 2ull << 20, GROW_MIN_HEADROOM = 1ull << 30;
 
 }  // namespace
 
@@ -87,8 +102,8 @@ struct qr_server_s {
     int slots;
     uint64_t budget, max_batch_patterns;
     uint32_t flags;
-    uint8_t *arena_dev;
-    unsigned long long *heads;  // one work-queue head per slot
+    std::vector<std::pair<uint8_t *, uint64_t>> chunks;  // the arena's device memory: the budget, then growth
+    unsigned long long *heads;                            // one work-queue head per slot
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
 };
@@ -101,13 +116,34 @@ void release_server(qr_server_s *s) {
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);
-    if (s->arena_dev) (void)hipFree(s->arena_dev);
+    for (const auto &c : s->chunks) (void)hipFree(c.first);
     if (s->heads) (void)hipFree(s->heads);
     delete s;
 }
 
 void drain(qr_server_s *s) {
     for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+}
+
+// Adds a chunk of at least `need` bytes to the server and to the run's arena, if the device's free
+// memory allows it (GROW_ROUND, GROW_MIN_HEADROOM); false leaves both unchanged.
+bool grow_arena(qr_server_s *s, Arena &arena, uint64_t need) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uint64_t chunk = (std::max(need, s->budget) + GROW_ROUND - 1) / GROW_ROUND * GROW_ROUND;
+    const uint64_t headroom = std::max<uint64_t>(GROW_MIN_HEADROOM, (uint64_t)tot / 64);
+    if ((uint64_t)fr < chunk || (uint64_t)fr - chunk < headroom) return false;
+    void *p = nullptr;
+    if (hipMalloc(&p, chunk) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    s->chunks.push_back({reinterpret_cast<uint8_t *>(p), chunk});
+    arena.add(chunk);
+    return true;
 }
 
 }  // namespace
@@ -119,7 +155,7 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     if (!out) return QR_EINVAL;
     *out = nullptr;
     if (!fm || slots < 1 || slots > 64 || budget_bytes < 4 * ALIGN || max_batch_patterns == 0 ||
-        (flags & ~(QR_SERVE_CHECK_FREE_MEMORY | QR_SERVE_PACKED_PATTERNS))) {
+        (flags & ~(QR_SERVE_CHECK_FREE_MEMORY | QR_SERVE_PACKED_PATTERNS | QR_SERVE_GROW_FROM_FREE_HBM))) {
         set_error("qr_server_create: need an index, 1..64 slots, a budget of at least 1 KiB and a batch cap");
         return QR_EINVAL;
     }
@@ -136,7 +172,10 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     s->flags = flags;
     s->streams.assign(slots, nullptr);
     s->events.assign(slots, nullptr);
-    if (hipMalloc(&s->arena_dev, budget_bytes) != hipSuccess || hipMalloc(&s->heads, 8 * (size_t)slots) != hipSuccess) {
+    void *first = nullptr;
+    const bool got = hipMalloc(&first, budget_bytes) == hipSuccess;
+    if (got) s->chunks.push_back({reinterpret_cast<uint8_t *>(first), budget_bytes});
+    if (!got || hipMalloc(&s->heads, 8 * (size_t)slots) != hipSuccess) {
         (void)hipGetLastError();
         release_server(s);
         set_error("qr_server_create: device allocation of %llu bytes failed", (unsigned long long)budget_bytes);
@@ -153,6 +192,13 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     }
     *out = s;
     return QR_OK;
+}
+
+uint64_t qr_server_arena_bytes(qr_server s) {
+    uint64_t b = 0;
+    if (s)
+        for (const auto &c : s->chunks) b += c.second;
+    return b;
 }
 
 int qr_server_free(qr_server s) {
@@ -200,8 +246,9 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
         const uint64_t p0 = h_req_off[r0], p1 = h_req_off[r1];
         return pad(pat_bytes(h_off[p0], h_off[p1])) + pad(8 * (p1 - p0 + 1)) + pad(4 * (p1 - p0)) + ALIGN;
     };
+    const bool grow = s->flags & QR_SERVE_GROW_FROM_FREE_HBM;
     Arena arena;
-    arena.reset(s->budget);
+    for (const auto &c : s->chunks) arena.add(c.second);
     std::vector<Inflight> fl(s->slots);
     std::vector<int> free_slots;
     for (int k = s->slots - 1; k >= 0; --k) free_slots.push_back(k);
@@ -231,7 +278,7 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             const double t = elapsed();
             for (uint64_t r = fl[k].r0; r < fl[k].r1; ++r) h_finish_s[r] = t;
             done += fl[k].r1 - fl[k].r0;
-            arena.release(fl[k].base, fl[k].nbytes);
+            arena.release(fl[k].chunk, fl[k].base, fl[k].nbytes);
             reserved -= fl[k].nbytes;
             fl[k].busy = false;
             --inflight;
@@ -246,9 +293,14 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             while (r1 < arrived && h_req_off[r1 + 1] - h_req_off[nxt] <= s->max_batch_patterns) ++r1;
             uint64_t nb = batch_bytes(nxt, r1);
             while (r1 > nxt + 1 && nb > s->budget) nb = batch_bytes(nxt, --r1);
-            if (nb > s->budget) {
-                set_error("qr_server_run: request %llu needs %llu bytes, more than the budget %llu", (unsigned long long)nxt,
-                          (unsigned long long)nb, (unsigned long long)s->budget);
+            if (nb > arena.largest() && !(grow && grow_arena(s, arena, nb))) {
+                if (grow)
+                    set_error("qr_server_run: request %llu needs %llu bytes, more than the arena's largest chunk %llu, "
+                              "and the device's free memory leaves no room for a chunk that large",
+                              (unsigned long long)nxt, (unsigned long long)nb, (unsigned long long)arena.largest());
+                else
+                    set_error("qr_server_run: request %llu needs %llu bytes, more than the budget %llu",
+                              (unsigned long long)nxt, (unsigned long long)nb, (unsigned long long)s->budget);
                 err = QR_ERANGE;
                 break;
             }
@@ -256,16 +308,18 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 size_t fr = 0, tot = 0;
                 if (hipMemGetInfo(&fr, &tot) != hipSuccess || nb > fr) break;
             }
+            uint32_t ck = 0;
             uint64_t base = 0;
-            if (!arena.alloc(nb, base)) break;  // wait for a batch to finish
+            // no room: grow the arena if allowed, else wait for a batch to finish
+            if (!arena.alloc(nb, ck, base) && !(grow && grow_arena(s, arena, nb) && arena.alloc(nb, ck, base))) break;
             const int k = free_slots.back();
             free_slots.pop_back();
             const uint64_t p0 = h_req_off[nxt], p1 = h_req_off[r1], npat = p1 - p0;
             const uint64_t c0 = h_off[p0], chars = pat_bytes(c0, h_off[p1]);
             const uint64_t first = packed ? c0 / 32 * 8 : c0;  // first byte of h_pat the batch copies
             const uint64_t rebase = packed ? c0 / 32 * 32 : c0;  // stream unit of that byte
-            uint8_t *d_pat = s->arena_dev + base;
-            uint64_t *d_off = reinterpret_cast<uint64_t *>(s->arena_dev + base + pad(chars));
+            uint8_t *d_pat = s->chunks[ck].first + base;
+            uint64_t *d_off = reinterpret_cast<uint64_t *>(d_pat + pad(chars));
             uint32_t *d_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(d_off) + pad(8 * (npat + 1)));
             hipStream_t st = s->streams[k];
             hipError_t e = hipSuccess;
@@ -295,7 +349,7 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 err = QR_EHIP;
                 break;
             }
-            fl[k] = Inflight{true, nxt, r1, base, nb};
+            fl[k] = Inflight{true, nxt, r1, base, nb, ck};
             reserved += nb;
             max_reserved = std::max(max_reserved, reserved);
             ++inflight;

@@ -168,18 +168,19 @@ class GpuExecutor:
 
 # ------------------------------------------------------------------------------------------ native loop
 class NativeServer:
-    """The same policy run by the library's native loop (qr_server_*): slots, arena budget, batch cap
-    and the optional free-memory check; host buffers are pinned once per workload."""
+    """The same policy run by the library's native loop (qr_server_*): slots, arena budget, batch cap,
+    the optional free-memory check and the optional growth of the arena from free device memory
+    (`grow`); host buffers are pinned once per workload."""
 
     def __init__(self, fm, slots: int, budget_bytes: int, max_batch_patterns: int = 1 << 18,
-                 check_free_memory: bool = False, packed: bool = False):
+                 check_free_memory: bool = False, packed: bool = False, grow: bool = False):
         import ctypes as C
 
         import paper_2602_04103_amd as qr
         self.qr, self.fm, self.packed = qr, fm, packed
         h = C.c_void_p()
-        flags = (qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0) | (qr.QR_SERVE_PACKED_PATTERNS if packed
-                                                                                else 0)
+        flags = ((qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0)
+                 | (qr.QR_SERVE_PACKED_PATTERNS if packed else 0) | (qr.QR_SERVE_GROW_FROM_FREE_HBM if grow else 0))
         qr._check(qr.lib().qr_server_create(fm.h, slots, int(budget_bytes), int(max_batch_patterns), flags,
                                             C.byref(h)), "qr_server_create")
         self.h = h.value
@@ -211,6 +212,11 @@ class NativeServer:
 
     def counts(self, p0: int, p1: int) -> np.ndarray:
         return self.counts_host[p0:p1]
+
+    @property
+    def arena_bytes(self) -> int:
+        """Device bytes of the arena: the budget, plus the chunks growth has added."""
+        return int(self.qr.lib().qr_server_arena_bytes(self.h)) if self.h else 0
 
     def free(self):
         if self.h:

@@ -158,3 +158,46 @@ def test_native_rejects_decreasing_pattern_offsets(index):
     with pytest.raises(qr.QRError):
         srv.run(w, deadline_s=30.0)
     srv.free()
+
+
+@pytest.mark.parametrize("packed", [False, True])
+def test_native_arena_grows_from_free_memory(index, packed):
+    """With QR_SERVE_GROW_FROM_FREE_HBM a burst no longer waits on a budget of one batch: the arena
+    adds chunks from free device memory until the four slots' batches fit (at most three chunks,
+    since a batch is cut to the budget and an empty chunk always holds one), every count equals the
+    oracle's, and a second run reuses the chunks."""
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import NativeServer, make_workload
+    w = make_workload(91, text, rate_patterns_per_s=1e8, duration_s=0.01, max_size=512)
+    w.arrival[:] = 0.0
+    budget = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
+    announce("native serve growing arena", w.nreq, budget, "packed" if packed else "bytes")
+    srv = NativeServer(fm, slots=4, budget_bytes=budget, max_batch_patterns=1 << 15, packed=packed, grow=True)
+    assert srv.arena_bytes == budget
+    want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
+    st = srv.run(w, deadline_s=120.0)
+    assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
+    chunk = (budget + (2 << 20) - 1) // (2 << 20) * (2 << 20)
+    grown = srv.arena_bytes
+    assert st.max_inflight == 4
+    assert budget < grown <= budget + 3 * chunk and (grown - budget) % chunk == 0
+    assert st.max_reserved_bytes > budget
+    st = srv.run(w, deadline_s=120.0)
+    assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
+    assert srv.arena_bytes == grown
+    srv.free()
+
+
+def test_native_growing_arena_admits_a_request_over_the_budget(index):
+    """The request that a fixed 4 KiB budget refuses is admitted once the arena may grow: it gets a
+    chunk of its own (2 MiB, the growth unit), and its counts equal the oracle's."""
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import NativeServer, make_workload
+    w = make_workload(89, text, rate_patterns_per_s=1e6, duration_s=0.01, max_size=4096)
+    assert max(w.batch_bytes(r, r + 1) for r in range(w.nreq)) > 4096
+    announce("native serve over budget, growing arena")
+    srv = NativeServer(fm, slots=2, budget_bytes=4096, max_batch_patterns=1 << 15, grow=True)
+    srv.run(w, deadline_s=30.0)
+    assert np.array_equal(srv.counts(0, int(w.req_off[-1])), oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
+    assert srv.arena_bytes >= 4096 + (2 << 20)
+    srv.free()
