@@ -54,16 +54,18 @@ def test_quadrank_random(n, nq, tune, l32, s):
 @settings(max_examples=15, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(st.one_of(st.integers(1, 300), st.integers(3_000, 20_000)), st.integers(1, 600), st.integers(1, 9),
-       st.sampled_from([1, 4, 8, 12]),
+       st.sampled_from([1, 4, 8, 12]), st.sampled_from(["16", "16p", "32", "64", "24_8"]), st.integers(0, 63),
        st.integers(0, 2 ** 31))
-def test_fm_random(n, npat, maxlen_div, kmer, s):
+def test_fm_random(n, npat, maxlen_div, kmer, layout, lead, s):
+    """Any layout with one-lane queries; patterns also as 2-bit packed words, the stream starting
+    `lead` filler bases before the first pattern (so patterns start anywhere inside a word)."""
     qr = require_gpu()
     text = datagen.dna_codes(s, n)
     if n > 2000:
         datagen.plant_repeats(s + 1, text, nseg=3, seglen=min(500, n // 4), copies=4, sub=0.01)
     maxlen = max(2, 250 // maxlen_div)
     pat, off, _ = datagen.patterns(s + 2, text, npat, minlen=1, maxlen=min(maxlen, max(1, n)))
-    fm = qr.QuadFm.from_text(text, kmer=kmer)
+    fm = qr.QuadFm.from_text(text, kmer=kmer, layout=qr.LAYOUT_BY_NAME[layout])
     sa = oracle.suffix_array(text)
     dp, do = to_dev(pat), to_dev(off)
     want = oracle.count_sa(text, sa, pat, off).astype(np.uint32)
@@ -71,4 +73,10 @@ def test_fm_random(n, npat, maxlen_div, kmer, s):
     assert np.array_equal(fm.count_batched(dp, do, 97).cpu().numpy().view(np.uint32), want)
     both = oracle.count_both_strands(text, sa, pat, off).astype(np.uint32)
     assert np.array_equal(fm.count(dp, do, both_strands=True).cpu().numpy().view(np.uint32), both)
+    stream = np.concatenate([datagen.dna_codes(s + 3, lead), pat])
+    p2, o2 = to_dev(datagen.pack2(stream)), to_dev(off + np.uint64(lead))
+    got = fm.count_packed(p2, stream.size, o2).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+    got = fm.count_packed(p2, stream.size, o2, both_strands=True).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, both)
     fm.check()
