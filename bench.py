@@ -1020,6 +1020,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         summ["offered_patterns_per_s"] = load
         if not args.serve_python:
             summ["arena_bytes"] = srv.arena_bytes
+            summ["batches_staged_by_kernels"] = srv.last_run_direct == 1
         # every served count equals one direct count of all patterns of the run
         d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
         summ["equal_to_direct_count"] = bool(np.array_equal(ex.counts(0, int(w.req_off[-1])), d_all))
@@ -1034,6 +1035,23 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
                summ["equal_to_direct_count"]))
         del ex, srv
     if not args.serve_python and res["loads"]:
+        # a mid load again with the batches copied by hipMemcpyAsync instead of staged by kernels
+        mids = [i for i, l in enumerate(res["loads"]) if 1e7 <= l["offered_patterns_per_s"] <= 1e8]
+        if mids:
+            k = mids[len(mids) // 2]
+            load = res["loads"][k]["offered_patterns_per_s"]
+            w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
+            srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18, check_free_memory=True,
+                               packed=not args.serve_bytes, grow=True, copy_engine=True)
+            summ = srv.run(w, deadline_s=120.0).summary()
+            summ["offered_patterns_per_s"] = load
+            d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
+            summ["equal_to_direct_count"] = bool(np.array_equal(srv.counts(0, int(w.req_off[-1])), d_all))
+            srv.free()
+            res["mid_load_copy_engine"] = summ
+            log("serve load %.0e with hipMemcpyAsync batches: p50 %.2f ms p99 %.2f ms, %.2f M patterns/s, equal=%s"
+                % (load, summ["p50_ms"], summ["p99_ms"], (summ["patterns_per_s"] or 0) / 1e6,
+                   summ["equal_to_direct_count"]))
         # the top load again with the patterns sent the other way (bytes against packed words)
         load = res["loads"][-1]["offered_patterns_per_s"]
         k = len(res["loads"]) - 1

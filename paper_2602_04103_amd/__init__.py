@@ -24,6 +24,7 @@ QUADFM_BOTH_STRANDS = 1
 QR_SERVE_CHECK_FREE_MEMORY = 1
 QR_SERVE_PACKED_PATTERNS = 2
 QR_SERVE_GROW_FROM_FREE_HBM = 4
+QR_SERVE_COPY_ENGINE = 8
 QR_LAYOUT_16, QR_LAYOUT_32, QR_LAYOUT_16P, QR_LAYOUT_64, QR_LAYOUT_16X2, QR_LAYOUT_24_8 = 0, 1, 2, 3, 4, 5
 LAYOUT_NAMES = {QR_LAYOUT_16: "16", QR_LAYOUT_32: "32", QR_LAYOUT_16P: "16p", QR_LAYOUT_64: "64",
                 QR_LAYOUT_16X2: "16x2", QR_LAYOUT_24_8: "24_8"}
@@ -98,6 +99,7 @@ def lib():
             "qr_server_create": (ci, [vp, ci, u64, u64, C.c_uint32, C.POINTER(vp)]),
             "qr_server_run": (ci, [vp, vp, vp, vp, u64, vp, vp, vp, C.c_double, C.POINTER(qr_serve_stats)]),
             "qr_server_arena_bytes": (u64, [vp]),
+            "qr_server_last_run_direct": (ci, [vp]),
             "qr_server_free": (ci, [vp]),
             "qr_graph_begin": (ci, [vp]),
             "qr_graph_end": (ci, [vp, C.POINTER(vp)]),

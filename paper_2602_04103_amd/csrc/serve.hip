@@ -83,6 +83,54 @@ __global__ void rebase_offsets(uint64_t *__restrict__ off, uint64_t n, uint64_t 
     if (i < n) off[i] -= base;
 }
 
+// Direct batches (pinned, device-mapped host buffers): the GPU reads the batch's pattern bytes and
+// offsets from host memory into the arena, rebasing the offsets, and writes the counts back, so a
+// batch is launches only (no DMA copies).  src and dst of the pattern copy are both 8-byte aligned
+// when src is (dst is an arena block); the copy then moves u64 words and the tail bytes.
+__global__ void stage_in(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src, uint64_t nbytes,
+                         uint64_t *__restrict__ doff, const uint64_t *__restrict__ soff, uint64_t noff, uint64_t base) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t head = 0;
+    if (((uintptr_t)src & 7) == 0) {
+        head = nbytes / 8 * 8;
+        const uint64_t *s8 = reinterpret_cast<const uint64_t *>(src);
+        uint64_t *d8 = reinterpret_cast<uint64_t *>(dst);
+        for (uint64_t i = t; i < nbytes / 8; i += stride) d8[i] = s8[i];
+    }
+    for (uint64_t i = head + t; i < nbytes; i += stride) dst[i] = src[i];
+    for (uint64_t i = t; i < noff; i += stride) doff[i] = soff[i] - base;
+}
+
+__global__ void stage_out(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src, uint64_t n) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = t; i < n; i += stride) dst[i] = src[i];
+}
+
+uint32_t stage_blocks(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)); }
+
+// Device address of the host range [p, p + len) if the GPU can access it directly: pinned host
+// memory mapped for the device (hipMemoryTypeHost with a device pointer) whose allocation holds the
+// whole range.  nullptr otherwise (pageable memory, or a range past its allocation); len 0 asks
+// nothing and gives nullptr.
+uint8_t *mapped_host_range(const void *p, uint64_t len) {
+    if (!p || !len) return nullptr;
+    hipPointerAttribute_t a{};
+    uint64_t start = 0, size = 0;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess || a.type != hipMemoryTypeHost || !a.devicePointer ||
+        hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, (hipDeviceptr_t)p) != hipSuccess ||
+        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    const uint64_t lo = (uint64_t)(uintptr_t)p;
+    if (lo < start || len > size || lo - start > size - len) return nullptr;
+    return reinterpret_cast<uint8_t *>(a.devicePointer);
+}
+
+// The live free-memory reading is refreshed at most this often (a hipMemGetInfo call has been seen
+// to block the loop for milliseconds).
+constexpr double FREE_MEMORY_REFRESH_S = 5e-3;
+
 struct Inflight {
     bool busy = false;
     uint64_t r0 = 0, r1 = 0, base = 0, nbytes = 0;
@@ -102,6 +150,7 @@ struct qr_server_s {
     int slots;
     uint64_t budget, max_batch_patterns;
     uint32_t flags;
+    int last_direct = -1;  // whether the last run staged its batches on the GPU (1) or copied them (0)
     std::vector<std::pair<uint8_t *, uint64_t>> chunks;  // the arena's device memory: the budget, then growth
     unsigned long long *heads;                            // one work-queue head per slot
     std::vector<hipStream_t> streams;
@@ -155,7 +204,8 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     if (!out) return QR_EINVAL;
     *out = nullptr;
     if (!fm || slots < 1 || slots > 64 || budget_bytes < 4 * ALIGN || max_batch_patterns == 0 ||
-        (flags & ~(QR_SERVE_CHECK_FREE_MEMORY | QR_SERVE_PACKED_PATTERNS | QR_SERVE_GROW_FROM_FREE_HBM))) {
+        (flags & ~(QR_SERVE_CHECK_FREE_MEMORY | QR_SERVE_PACKED_PATTERNS | QR_SERVE_GROW_FROM_FREE_HBM |
+                   QR_SERVE_COPY_ENGINE))) {
         set_error("qr_server_create: need an index, 1..64 slots, a budget of at least 1 KiB and a batch cap");
         return QR_EINVAL;
     }
@@ -193,6 +243,8 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     *out = s;
     return QR_OK;
 }
+
+int qr_server_last_run_direct(qr_server s) { return s ? s->last_direct : -1; }
 
 uint64_t qr_server_arena_bytes(qr_server s) {
     uint64_t b = 0;
@@ -237,9 +289,9 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
     }
     const bool packed = s->flags & QR_SERVE_PACKED_PATTERNS;
     // a batch's pattern bytes at h_pat, from stream unit c0 (a byte, or a base of packed words) to c1:
-    // packed, the whole words holding bases [c0, c1), starting at word c0 / 32
+    // bytes [c0 rounded down to 8, c1); packed, the whole words holding bases [c0, c1), from word c0 / 32
     auto pat_bytes = [&](uint64_t c0, uint64_t c1) -> uint64_t {
-        if (!packed) return c1 - c0;
+        if (!packed) return c1 > c0 ? c1 - c0 / 8 * 8 : 0;
         return c1 > c0 ? 8 * ((c1 + 31) / 32 - c0 / 32) : 0;
     };
     auto batch_bytes = [&](uint64_t r0, uint64_t r1) {
@@ -247,6 +299,23 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
         return pad(pat_bytes(h_off[p0], h_off[p1])) + pad(8 * (p1 - p0 + 1)) + pad(4 * (p1 - p0)) + ALIGN;
     };
     const bool grow = s->flags & QR_SERVE_GROW_FROM_FREE_HBM;
+    // Direct batches need every host range the run touches in pinned, device-mapped memory: h_pat
+    // from byte 0 to the end of the last pattern (whole words when packed), the offsets and the counts.
+    const uint8_t *dev_pat = nullptr, *dev_off = nullptr;
+    uint8_t *dev_cnt = nullptr;
+    uint64_t pat_end = 0;
+    bool direct = false;
+    if (nreq && !(s->flags & QR_SERVE_COPY_ENGINE)) {
+        const uint64_t q0 = h_req_off[0], q1 = h_req_off[nreq], e = h_off[q1];
+        pat_end = packed ? (e + 31) / 32 * 8 : e;
+        dev_pat = mapped_host_range(h_pat, pat_end);
+        dev_off = mapped_host_range(h_off + q0, 8 * (q1 - q0 + 1));
+        dev_cnt = mapped_host_range(h_counts + q0, 4 * (q1 - q0));
+        direct = (dev_pat || !pat_end) && dev_off && (dev_cnt || q1 == q0);
+    }
+    s->last_direct = direct ? 1 : 0;
+    double free_at = -1.0;  // time of the last free-memory reading
+    size_t free_now = 0;
     Arena arena;
     for (const auto &c : s->chunks) arena.add(c.second);
     std::vector<Inflight> fl(s->slots);
@@ -305,8 +374,15 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 break;
             }
             if (s->flags & QR_SERVE_CHECK_FREE_MEMORY) {
-                size_t fr = 0, tot = 0;
-                if (hipMemGetInfo(&fr, &tot) != hipSuccess || nb > fr) break;
+                if (free_at < 0 || now - free_at > FREE_MEMORY_REFRESH_S) {
+                    size_t tot = 0;
+                    if (hipMemGetInfo(&free_now, &tot) != hipSuccess) {
+                        (void)hipGetLastError();
+                        free_now = 0;
+                    }
+                    free_at = now;
+                }
+                if (nb > free_now) break;
             }
             uint32_t ck = 0;
             uint64_t base = 0;
@@ -316,19 +392,31 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             free_slots.pop_back();
             const uint64_t p0 = h_req_off[nxt], p1 = h_req_off[r1], npat = p1 - p0;
             const uint64_t c0 = h_off[p0], chars = pat_bytes(c0, h_off[p1]);
-            const uint64_t first = packed ? c0 / 32 * 8 : c0;  // first byte of h_pat the batch copies
-            const uint64_t rebase = packed ? c0 / 32 * 32 : c0;  // stream unit of that byte
+            const uint64_t first = packed ? c0 / 32 * 8 : c0 / 8 * 8;     // first byte of h_pat the batch copies
+            const uint64_t rebase = packed ? c0 / 32 * 32 : c0 / 8 * 8;  // stream unit of that byte
             uint8_t *d_pat = s->chunks[ck].first + base;
             uint64_t *d_off = reinterpret_cast<uint64_t *>(d_pat + pad(chars));
             uint32_t *d_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(d_off) + pad(8 * (npat + 1)));
             hipStream_t st = s->streams[k];
             hipError_t e = hipSuccess;
-            if (chars) e = hipMemcpyAsync(d_pat, h_pat + first, chars, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(d_off, h_off + p0, 8 * (npat + 1), hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) {
-                hipLaunchKernelGGL(rebase_offsets, dim3((uint32_t)((npat + 1 + 255) / 256)), dim3(256), 0, st, d_off, npat + 1,
-                                   rebase);
+            if (direct) {
+                if (chars && first + chars > pat_end) {  // cannot happen: offsets are non-decreasing
+                    set_error("qr_server_run: batch pattern bytes beyond the checked host range");
+                    err = QR_EINVAL;
+                    break;
+                }
+                const uint64_t *so = reinterpret_cast<const uint64_t *>(dev_off) + (p0 - h_req_off[0]);
+                hipLaunchKernelGGL(stage_in, dim3(stage_blocks(std::max(chars / 8, npat + 1))), dim3(256), 0, st, d_pat,
+                                   chars ? dev_pat + first : nullptr, chars, d_off, so, npat + 1, rebase);
                 e = hipGetLastError();
+            } else {
+                if (chars) e = hipMemcpyAsync(d_pat, h_pat + first, chars, hipMemcpyHostToDevice, st);
+                if (e == hipSuccess) e = hipMemcpyAsync(d_off, h_off + p0, 8 * (npat + 1), hipMemcpyHostToDevice, st);
+                if (e == hipSuccess) {
+                    hipLaunchKernelGGL(rebase_offsets, dim3((uint32_t)((npat + 1 + 255) / 256)), dim3(256), 0, st, d_off,
+                                       npat + 1, rebase);
+                    e = hipGetLastError();
+                }
             }
             if (e != hipSuccess) {
                 set_error("qr_server_run: %s", hipGetErrorString(e));
@@ -342,7 +430,15 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 err = rc;
                 break;
             }
-            e = hipMemcpyAsync(h_counts + p0, d_cnt, 4 * npat, hipMemcpyDeviceToHost, st);
+            if (direct) {
+                if (npat) {
+                    uint32_t *dc = reinterpret_cast<uint32_t *>(dev_cnt) + (p0 - h_req_off[0]);
+                    hipLaunchKernelGGL(stage_out, dim3(stage_blocks(npat)), dim3(256), 0, st, dc, d_cnt, npat);
+                }
+                e = hipGetLastError();
+            } else {
+                e = hipMemcpyAsync(h_counts + p0, d_cnt, 4 * npat, hipMemcpyDeviceToHost, st);
+            }
             if (e == hipSuccess) e = hipEventRecord(s->events[k], st);
             if (e != hipSuccess) {
                 set_error("qr_server_run: %s", hipGetErrorString(e));

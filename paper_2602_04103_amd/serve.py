@@ -86,8 +86,11 @@ class Workload:
         return self._pat2
 
     def batch_bytes(self, r0: int, r1: int) -> int:
+        """Arena bytes of a batch of requests [r0, r1) with byte patterns: the pattern bytes from the
+        first one's start rounded down to 8, the offsets and the counts, each padded to 256."""
         p0, p1 = int(self.req_off[r0]), int(self.req_off[r1])
-        chars = int(self.off[p1] - self.off[p0])
+        c0, c1 = int(self.off[p0]), int(self.off[p1])
+        chars = c1 - c0 // 8 * 8 if c1 > c0 else 0
         return _pad(chars) + _pad(8 * (p1 - p0 + 1)) + _pad(4 * (p1 - p0)) + 256
 
 
@@ -173,30 +176,38 @@ class NativeServer:
     (`grow`); host buffers are pinned once per workload."""
 
     def __init__(self, fm, slots: int, budget_bytes: int, max_batch_patterns: int = 1 << 18,
-                 check_free_memory: bool = False, packed: bool = False, grow: bool = False):
+                 check_free_memory: bool = False, packed: bool = False, grow: bool = False,
+                 copy_engine: bool = False):
         import ctypes as C
 
         import paper_2602_04103_amd as qr
         self.qr, self.fm, self.packed = qr, fm, packed
         h = C.c_void_p()
         flags = ((qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0)
-                 | (qr.QR_SERVE_PACKED_PATTERNS if packed else 0) | (qr.QR_SERVE_GROW_FROM_FREE_HBM if grow else 0))
+                 | (qr.QR_SERVE_PACKED_PATTERNS if packed else 0) | (qr.QR_SERVE_GROW_FROM_FREE_HBM if grow else 0)
+                 | (qr.QR_SERVE_COPY_ENGINE if copy_engine else 0))
         qr._check(qr.lib().qr_server_create(fm.h, slots, int(budget_bytes), int(max_batch_patterns), flags,
                                             C.byref(h)), "qr_server_create")
         self.h = h.value
         self.counts_host = None
 
-    def run(self, w: Workload, deadline_s: float = 600.0) -> "ServeStats":
+    def run(self, w: Workload, deadline_s: float = 600.0, pin: bool = True) -> "ServeStats":
+        """Serve the workload.  The host buffers are pinned (so batches are staged by kernels) unless
+        pin is False, which leaves them pageable and the loop copying."""
         import ctypes as C
 
         import torch
         qr = self.qr
-        if self.packed:  # 2-bit words: a quarter of the bytes to copy
-            h_pat = torch.from_numpy(w.packed().view(np.int64)).pin_memory()
+
+        def host(a):
+            t = torch.from_numpy(a)
+            return t.pin_memory() if pin else t.clone()
+        if self.packed:  # 2-bit words: a quarter of the bytes to move
+            h_pat = host(w.packed().view(np.int64))
         else:
-            h_pat = torch.from_numpy(w.pat if w.pat.size else np.zeros(1, np.uint8)).pin_memory()
-        h_off = torch.from_numpy(np.ascontiguousarray(w.off, dtype=np.uint64).view(np.int64)).pin_memory()
-        h_cnt = torch.zeros(max(1, int(w.off.size - 1)), dtype=torch.int32).pin_memory()
+            h_pat = host(w.pat if w.pat.size else np.zeros(1, np.uint8))
+        h_off = host(np.ascontiguousarray(w.off, dtype=np.uint64).view(np.int64))
+        h_cnt = host(np.zeros(max(1, int(w.off.size - 1)), dtype=np.int32))
         req_off = np.ascontiguousarray(w.req_off, dtype=np.uint64)
         arrival = np.ascontiguousarray(w.arrival, dtype=np.float64)
         finish = np.full(w.nreq, np.nan)
@@ -212,6 +223,11 @@ class NativeServer:
 
     def counts(self, p0: int, p1: int) -> np.ndarray:
         return self.counts_host[p0:p1]
+
+    @property
+    def last_run_direct(self) -> int:
+        """1 if the last run's batches were staged by kernels from host memory, 0 if copied."""
+        return int(self.qr.lib().qr_server_last_run_direct(self.h)) if self.h else -1
 
     @property
     def arena_bytes(self) -> int:

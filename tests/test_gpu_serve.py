@@ -83,23 +83,28 @@ def test_serve_tight_budget_still_exact(index):
 
 
 # ------------------------------------------------------------------------------ native serving loop
-def native(qr, fm, w, slots, budget, max_batch, check_free=False, packed=False):
+def native(qr, fm, w, slots, budget, max_batch, check_free=False, packed=False, copy_engine=False, pin=True):
     from paper_2602_04103_amd.serve import NativeServer
     srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=max_batch,
-                       check_free_memory=check_free, packed=packed)
-    st = srv.run(w, deadline_s=120.0)
+                       check_free_memory=check_free, packed=packed, copy_engine=copy_engine)
+    st = srv.run(w, deadline_s=120.0, pin=pin)
+    assert srv.last_run_direct == (1 if pin and not copy_engine else 0)
     return srv, st
 
 
+@pytest.mark.parametrize("mode", ["direct", "copy_engine", "pageable"])
 @pytest.mark.parametrize("packed", [False, True])
-def test_native_poisson_mix_equals_alone_and_oracle(index, packed):
-    """Patterns sent one byte per base, or as 2-bit packed words (batches then copy the whole words
-    around their bases, and their first pattern starts inside a word)."""
+def test_native_poisson_mix_equals_alone_and_oracle(index, packed, mode):
+    """Patterns sent one byte per base, or as 2-bit packed words (batches then move the whole words
+    around their bases, and their first pattern starts inside a word); batches staged by kernels
+    from pinned host memory (direct), copied by hipMemcpyAsync from pinned memory (copy_engine) or
+    from pageable memory (pageable)."""
     qr, text, fm, sa = index
     from paper_2602_04103_amd.serve import make_workload
     w = make_workload(87, text, rate_patterns_per_s=4e6, duration_s=0.25, max_size=4096)
-    announce("native serve poisson", w.nreq, "packed" if packed else "bytes")
-    srv, st = native(qr, fm, w, slots=4, budget=32 << 20, max_batch=1 << 15, check_free=True, packed=packed)
+    announce("native serve poisson", w.nreq, "packed" if packed else "bytes", mode)
+    srv, st = native(qr, fm, w, slots=4, budget=32 << 20, max_batch=1 << 15, check_free=True, packed=packed,
+                     copy_engine=mode == "copy_engine", pin=mode != "pageable")
     assert not np.isnan(st.finish_s).any()
     assert np.all(st.finish_s >= w.arrival)                 # nothing finishes before it arrives
     served = srv.counts(0, int(w.req_off[-1]))
@@ -173,7 +178,7 @@ def test_native_arena_grows_from_free_memory(index, packed):
     budget = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
     announce("native serve growing arena", w.nreq, budget, "packed" if packed else "bytes")
     srv = NativeServer(fm, slots=4, budget_bytes=budget, max_batch_patterns=1 << 15, packed=packed, grow=True)
-    assert srv.arena_bytes == budget
+    assert srv.arena_bytes == budget and srv.last_run_direct == -1
     want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
     st = srv.run(w, deadline_s=120.0)
     assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
