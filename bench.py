@@ -1020,7 +1020,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         summ["offered_patterns_per_s"] = load
         if not args.serve_python:
             summ["arena_bytes"] = srv.arena_bytes
-            summ["batches_staged_by_kernels"] = srv.last_run_direct == 1
+            summ["batches_staged_by_kernels"] = srv.last_run_staged
         # every served count equals one direct count of all patterns of the run
         d_all = fm.count(to_dev(w.pat), to_dev(w.off)).cpu().numpy().view(np.uint32)
         summ["equal_to_direct_count"] = bool(np.array_equal(ex.counts(0, int(w.req_off[-1])), d_all))

@@ -360,11 +360,11 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
  * stream and copies the counts to h_counts[h_req_off[r]..].
  * h_finish_s[r] receives the time at which the host saw request r's batch complete.  When h_pat
  * (from byte 0 to the end of the last pattern), the run's offsets and its counts all lie in pinned,
- * device-mapped host memory (hipHostMalloc; one allocation each), every batch is launches only: a
- * kernel reads the batch's patterns and offsets from host memory into the arena and another writes
- * the counts back (qr_server_last_run_direct then returns 1).  Otherwise, or with
- * QR_SERVE_COPY_ENGINE, the batches are copied with hipMemcpyAsync (pageable memory works but
- * serialises the copies).  With QR_SERVE_CHECK_FREE_MEMORY the free-memory reading is refreshed at
+ * device-mapped host memory (hipHostMalloc; one allocation each), every batch that moves at most
+ * 4 MiB of host bytes is launches only: a kernel reads the batch's patterns and offsets from host
+ * memory into the arena and another writes the counts back (qr_server_last_run_staged counts such
+ * batches).  Larger batches, and every batch with pageable arrays or QR_SERVE_COPY_ENGINE, are
+ * copied with hipMemcpyAsync (pageable memory works but serialises the copies).  With QR_SERVE_CHECK_FREE_MEMORY the free-memory reading is refreshed at
  * most every 5 ms.  The server owns its arena, streams and queue
  * heads; the index must outlive it.  run returns once every request is done (QR_ERANGE if
  * deadline_s passes first or a request alone exceeds the budget, or with QR_SERVE_GROW_FROM_FREE_HBM
@@ -391,8 +391,8 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                   const double *h_arrival_s, uint32_t *h_counts, double *h_finish_s, double deadline_s,
                   qr_serve_stats *stats);
 uint64_t qr_server_arena_bytes(qr_server s); /* bytes of the arena's chunks (0 for NULL) */
-int qr_server_last_run_direct(qr_server s);  /* 1: the last run's batches were staged by kernels from
-                                                host memory; 0: copied; -1: no run yet (or NULL) */
+int64_t qr_server_last_run_staged(qr_server s); /* batches of the last run staged by kernels from host
+                                                   memory (the others were copied); -1: no run yet */
 int qr_server_free(qr_server s);
 
 /* ------------------------------------------------------------------------------------------------

@@ -99,7 +99,7 @@ def lib():
             "qr_server_create": (ci, [vp, ci, u64, u64, C.c_uint32, C.POINTER(vp)]),
             "qr_server_run": (ci, [vp, vp, vp, vp, u64, vp, vp, vp, C.c_double, C.POINTER(qr_serve_stats)]),
             "qr_server_arena_bytes": (u64, [vp]),
-            "qr_server_last_run_direct": (ci, [vp]),
+            "qr_server_last_run_staged": (C.c_int64, [vp]),
             "qr_server_free": (ci, [vp]),
             "qr_graph_begin": (ci, [vp]),
             "qr_graph_end": (ci, [vp, C.POINTER(vp)]),

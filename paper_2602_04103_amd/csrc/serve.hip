@@ -109,23 +109,34 @@ __global__ void stage_out(uint32_t *__restrict__ dst, const uint32_t *__restrict
 uint32_t stage_blocks(uint64_t n) { return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024)); }
 
 // Device address of the host range [p, p + len) if the GPU can access it directly: pinned host
-// memory mapped for the device (hipMemoryTypeHost with a device pointer) whose allocation holds the
-// whole range.  nullptr otherwise (pageable memory, or a range past its allocation); len 0 asks
-// nothing and gives nullptr.
+// memory mapped for the device (hipMemoryTypeHost with a device pointer) whose first and last bytes
+// belong to the same allocation (the same range start; the runtime reports no range size above
+// 2 GiB, so the last byte is asked instead) at consecutive device addresses.  nullptr otherwise
+// (pageable memory, or a range past its allocation); len 0 asks nothing and gives nullptr.
 uint8_t *mapped_host_range(const void *p, uint64_t len) {
     if (!p || !len) return nullptr;
-    hipPointerAttribute_t a{};
-    uint64_t start = 0, size = 0;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess || a.type != hipMemoryTypeHost || !a.devicePointer ||
-        hipPointerGetAttribute(&start, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, (hipDeviceptr_t)p) != hipSuccess ||
-        hipPointerGetAttribute(&size, HIP_POINTER_ATTRIBUTE_RANGE_SIZE, (hipDeviceptr_t)p) != hipSuccess) {
+    const void *last = static_cast<const uint8_t *>(p) + (len - 1);
+    hipPointerAttribute_t a{}, b{};
+    uint64_t start_a = 0, start_b = 0;
+    const bool ok = hipPointerGetAttributes(&a, p) == hipSuccess && a.type == hipMemoryTypeHost && a.devicePointer &&
+                    hipPointerGetAttributes(&b, last) == hipSuccess && b.type == hipMemoryTypeHost && b.devicePointer &&
+                    hipPointerGetAttribute(&start_a, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, (hipDeviceptr_t)p) ==
+                        hipSuccess &&
+                    hipPointerGetAttribute(&start_b, HIP_POINTER_ATTRIBUTE_RANGE_START_ADDR, (hipDeviceptr_t)last) ==
+                        hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
         return nullptr;
     }
-    const uint64_t lo = (uint64_t)(uintptr_t)p;
-    if (lo < start || len > size || lo - start > size - len) return nullptr;
-    return reinterpret_cast<uint8_t *>(a.devicePointer);
+    uint8_t *dev = reinterpret_cast<uint8_t *>(a.devicePointer);
+    if (start_a != start_b || reinterpret_cast<uint8_t *>(b.devicePointer) != dev + (len - 1)) return nullptr;
+    return dev;
 }
+
+// Batches that move more host bytes than this (patterns, offsets and counts) are copied by the DMA
+// engines even when they could be staged: at that size the copies' bandwidth wins, and staging
+// kernels would take compute units from the counts in flight.
+constexpr uint64_t STAGE_MAX_BYTES = 4ull << 20;
 
 // The live free-memory reading is refreshed at most this often (a hipMemGetInfo call has been seen
 // to block the loop for milliseconds).
@@ -150,7 +161,7 @@ struct qr_server_s {
     int slots;
     uint64_t budget, max_batch_patterns;
     uint32_t flags;
-    int last_direct = -1;  // whether the last run staged its batches on the GPU (1) or copied them (0)
+    int64_t last_staged = -1;  // batches of the last run staged by kernels (the rest were copied)
     std::vector<std::pair<uint8_t *, uint64_t>> chunks;  // the arena's device memory: the budget, then growth
     unsigned long long *heads;                            // one work-queue head per slot
     std::vector<hipStream_t> streams;
@@ -244,7 +255,7 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     return QR_OK;
 }
 
-int qr_server_last_run_direct(qr_server s) { return s ? s->last_direct : -1; }
+int64_t qr_server_last_run_staged(qr_server s) { return s ? s->last_staged : -1; }
 
 uint64_t qr_server_arena_bytes(qr_server s) {
     uint64_t b = 0;
@@ -313,7 +324,7 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
         dev_cnt = mapped_host_range(h_counts + q0, 4 * (q1 - q0));
         direct = (dev_pat || !pat_end) && dev_off && (dev_cnt || q1 == q0);
     }
-    s->last_direct = direct ? 1 : 0;
+    uint64_t staged = 0;
     double free_at = -1.0;  // time of the last free-memory reading
     size_t free_now = 0;
     Arena arena;
@@ -357,7 +368,8 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
         if (err) break;
         // admissions: every arrived request, FIFO, in one batch per free slot
         while (!free_slots.empty() && nxt < nreq && h_arrival_s[nxt] <= now) {
-            const uint64_t arrived = (uint64_t)(std::upper_bound(h_arrival_s + nxt, h_arrival_s + nreq, now) - h_arrival_s);
+            const uint64_t arrived =
+                (uint64_t)(std::upper_bound(h_arrival_s + nxt, h_arrival_s + nreq, now) - h_arrival_s);
             uint64_t r1 = nxt + 1;
             while (r1 < arrived && h_req_off[r1 + 1] - h_req_off[nxt] <= s->max_batch_patterns) ++r1;
             uint64_t nb = batch_bytes(nxt, r1);
@@ -399,7 +411,9 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             uint32_t *d_cnt = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(d_off) + pad(8 * (npat + 1)));
             hipStream_t st = s->streams[k];
             hipError_t e = hipSuccess;
-            if (direct) {
+            const bool stage = direct && chars + 12 * npat + 8 <= STAGE_MAX_BYTES;
+            staged += stage;
+            if (stage) {
                 if (chars && first + chars > pat_end) {  // cannot happen: offsets are non-decreasing
                     set_error("qr_server_run: batch pattern bytes beyond the checked host range");
                     err = QR_EINVAL;
@@ -413,8 +427,8 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 if (chars) e = hipMemcpyAsync(d_pat, h_pat + first, chars, hipMemcpyHostToDevice, st);
                 if (e == hipSuccess) e = hipMemcpyAsync(d_off, h_off + p0, 8 * (npat + 1), hipMemcpyHostToDevice, st);
                 if (e == hipSuccess) {
-                    hipLaunchKernelGGL(rebase_offsets, dim3((uint32_t)((npat + 1 + 255) / 256)), dim3(256), 0, st, d_off,
-                                       npat + 1, rebase);
+                    hipLaunchKernelGGL(rebase_offsets, dim3((uint32_t)((npat + 1 + 255) / 256)), dim3(256), 0, st,
+                                       d_off, npat + 1, rebase);
                     e = hipGetLastError();
                 }
             }
@@ -423,14 +437,14 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 err = QR_EHIP;
                 break;
             }
-            rc = packed ? quadfm_count_packed(s->fm, reinterpret_cast<const uint64_t *>(d_pat), chars / 8 * 32, d_off, npat,
-                                              0u, d_cnt, s->heads + k, st)
+            rc = packed ? quadfm_count_packed(s->fm, reinterpret_cast<const uint64_t *>(d_pat), chars / 8 * 32, d_off,
+                                              npat, 0u, d_cnt, s->heads + k, st)
                         : quadfm_count_ex(s->fm, d_pat, chars, d_off, npat, 0u, d_cnt, s->heads + k, st);
             if (rc) {
                 err = rc;
                 break;
             }
-            if (direct) {
+            if (stage) {
                 if (npat) {
                     uint32_t *dc = reinterpret_cast<uint32_t *>(dev_cnt) + (p0 - h_req_off[0]);
                     hipLaunchKernelGGL(stage_out, dim3(stage_blocks(npat)), dim3(256), 0, st, dc, d_cnt, npat);
@@ -462,6 +476,7 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
             }
         }
     }
+    s->last_staged = (int64_t)staged;
     drain(s);  // no copy may still target the caller's buffers on return
     if (stats) {
         stats->batches = batches;

@@ -192,8 +192,8 @@ class NativeServer:
         self.counts_host = None
 
     def run(self, w: Workload, deadline_s: float = 600.0, pin: bool = True) -> "ServeStats":
-        """Serve the workload.  The host buffers are pinned (so batches are staged by kernels) unless
-        pin is False, which leaves them pageable and the loop copying."""
+        """Serve the workload.  The host buffers are pinned (so batches of up to 4 MiB are staged by
+        kernels) unless pin is False, which leaves them pageable and the loop copying."""
         import ctypes as C
 
         import torch
@@ -225,9 +225,10 @@ class NativeServer:
         return self.counts_host[p0:p1]
 
     @property
-    def last_run_direct(self) -> int:
-        """1 if the last run's batches were staged by kernels from host memory, 0 if copied."""
-        return int(self.qr.lib().qr_server_last_run_direct(self.h)) if self.h else -1
+    def last_run_staged(self) -> int:
+        """Batches of the last run staged by kernels from pinned host memory (the others were
+        copied); -1 before the first run."""
+        return int(self.qr.lib().qr_server_last_run_staged(self.h)) if self.h else -1
 
     @property
     def arena_bytes(self) -> int:

@@ -88,7 +88,10 @@ def native(qr, fm, w, slots, budget, max_batch, check_free=False, packed=False, 
     srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=max_batch,
                        check_free_memory=check_free, packed=packed, copy_engine=copy_engine)
     st = srv.run(w, deadline_s=120.0, pin=pin)
-    assert srv.last_run_direct == (1 if pin and not copy_engine else 0)
+    if pin and not copy_engine:
+        assert srv.last_run_staged > 0  # these workloads' batches stay below the 4 MiB staging limit
+    else:
+        assert srv.last_run_staged == 0
     return srv, st
 
 
@@ -178,7 +181,7 @@ def test_native_arena_grows_from_free_memory(index, packed):
     budget = max(w.batch_bytes(r, r + 1) for r in range(w.nreq))
     announce("native serve growing arena", w.nreq, budget, "packed" if packed else "bytes")
     srv = NativeServer(fm, slots=4, budget_bytes=budget, max_batch_patterns=1 << 15, packed=packed, grow=True)
-    assert srv.arena_bytes == budget and srv.last_run_direct == -1
+    assert srv.arena_bytes == budget and srv.last_run_staged == -1
     want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
     st = srv.run(w, deadline_s=120.0)
     assert np.array_equal(srv.counts(0, int(w.req_off[-1])), want)
@@ -205,4 +208,43 @@ def test_native_growing_arena_admits_a_request_over_the_budget(index):
     srv.run(w, deadline_s=30.0)
     assert np.array_equal(srv.counts(0, int(w.req_off[-1])), oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32))
     assert srv.arena_bytes >= 4096 + (2 << 20)
+    srv.free()
+
+
+def test_native_direct_batches_inside_a_large_pinned_allocation(index):
+    """Host arrays that lie inside a pinned allocation of more than 2 GiB (the runtime reports no
+    range size there, so the check compares the range's first and last bytes) are still staged by
+    kernels, and the counts equal the oracle's; with a pageable counts array the run copies."""
+    import ctypes as C
+
+    import torch
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import NativeServer, make_workload
+    w = make_workload(92, text, rate_patterns_per_s=4e6, duration_s=0.05, max_size=1024)
+    npat, nreq = int(w.req_off[-1]), w.nreq
+    announce("native serve, arrays inside a 2.5 GiB pinned allocation", nreq, npat)
+    big = torch.empty(5 << 29, dtype=torch.uint8).pin_memory()
+    big[:w.pat.size].copy_(torch.from_numpy(w.pat))
+    h_off = torch.from_numpy(np.ascontiguousarray(w.off, dtype=np.uint64).view(np.int64)).pin_memory()
+    h_cnt = torch.zeros(npat, dtype=torch.int32).pin_memory()
+    req_off = np.ascontiguousarray(w.req_off, dtype=np.uint64)
+    arrival = np.ascontiguousarray(w.arrival, dtype=np.float64)
+    finish = np.full(nreq, np.nan)
+    srv = NativeServer(fm, slots=4, budget_bytes=32 << 20)
+    st = qr.qr_serve_stats()
+    qr._check(qr.lib().qr_server_run(srv.h, big.data_ptr(), h_off.data_ptr(), req_off.ctypes.data, nreq,
+                                     arrival.ctypes.data, h_cnt.data_ptr(), finish.ctypes.data, 60.0, C.byref(st)),
+              "qr_server_run")
+    assert srv.last_run_staged > 0
+    want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
+    assert np.array_equal(h_cnt.numpy().view(np.uint32), want)
+    del big
+    # pinned patterns and offsets but a pageable counts array: not every range is mapped, so the run copies
+    small_pat = torch.from_numpy(w.pat).pin_memory()
+    h_cnt2 = np.zeros(npat, dtype=np.uint32)
+    qr._check(qr.lib().qr_server_run(srv.h, small_pat.data_ptr(), h_off.data_ptr(), req_off.ctypes.data, nreq,
+                                     arrival.ctypes.data, h_cnt2.ctypes.data, finish.ctypes.data, 60.0, C.byref(st)),
+              "qr_server_run")
+    assert srv.last_run_staged == 0  # pageable counts array: copied
+    assert np.array_equal(h_cnt2, want)
     srv.free()

@@ -45,6 +45,7 @@ def test_native_serve_2e30_sampled():
     announce("serve-2^30 run", w.nreq, int(w.req_off[-1]))
     srv = NativeServer(fm, slots=4, budget_bytes=256 << 20, max_batch_patterns=1 << 18, check_free_memory=True)
     st = srv.run(w, deadline_s=120.0)
+    assert srv.last_run_staged > 0  # pinned host arrays: batches staged by kernels
     assert not np.isnan(st.finish_s).any()
     assert np.all(st.finish_s >= w.arrival)
     npat = int(w.req_off[-1])
