@@ -356,8 +356,8 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
  * least max(1 GiB, 1/64 of the device's memory) left over, and waits for earlier batches otherwise;
  * batches are still cut to the budget where their requests allow, so the arena stays within about
  * `slots` chunks.  Chunks are kept until qr_server_free; qr_server_arena_bytes gives the arena's
- * size.  Each batch copies its patterns in, counts them with the persistent kernel on its slot's
- * stream and copies the counts to h_counts[h_req_off[r]..].
+ * size.  Each batch moves its patterns in, counts them with the persistent kernel on its slot's
+ * stream and moves the counts to h_counts[h_req_off[r]..].
  * h_finish_s[r] receives the time at which the host saw request r's batch complete.  When h_pat
  * (from byte 0 to the end of the last pattern), the run's offsets and its counts all lie in pinned,
  * device-mapped host memory (hipHostMalloc; one allocation each), every batch that moves at most

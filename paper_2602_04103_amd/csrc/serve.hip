@@ -5,10 +5,12 @@
 // patterns.  Whenever a slot (a stream with its own work-queue head) is free, every request that has
 // arrived is admitted FIFO as one batch, as large as the pattern cap and the device arena allow; an
 // optional live free-memory check can also hold admission back, and the arena can grow from the
-// device's free memory (chunks of at least the budget, kept above a headroom).  A batch copies its
-// pattern bytes (one per base, or 2-bit packed words) and offsets into the arena, rebases the
-// offsets on the device, runs the persistent count kernel on the slot's stream, copies the counts
-// back and records an event.  Up to `slots` batches are in flight at once, so batches that arrive
+// device's free memory (chunks of at least the budget, kept above a headroom).  A batch moves its
+// pattern bytes (one per base, or 2-bit packed words) and offsets into the arena, rebasing the
+// offsets, runs the persistent count kernel on the slot's stream, moves the counts back and records
+// an event.  The moves are kernels that read and write the caller's pinned host memory when the
+// batch is small (no copy call, whose rare multi-millisecond pauses would hold up the whole loop)
+// and DMA copies otherwise.  Up to `slots` batches are in flight at once, so batches that arrive
 // while others run overlap on the device.  A request finishes when the host sees its batch's event
 // complete.
 //

@@ -3,10 +3,11 @@
 Continuous batching.  Requests arrive over time, each carrying a block of patterns.  Whenever a
 slot is free and device memory allows, every request that has arrived (FIFO, up to a batch limit)
 is admitted as one batch:
-  - the batch's patterns are copied to device memory taken from an arena of fixed size (the HBM
-    budget),
+  - the batch's patterns are moved to device memory taken from an arena (the HBM budget; the native
+    loop can grow it from free device memory),
   - the persistent count kernel runs on the slot's own stream with the slot's own queue head,
-  - the counts come back to pinned host memory.
+  - the counts come back to pinned host memory (the native loop stages small batches with kernels
+    that read and write the pinned host arrays, and copies larger ones).
 Up to `slots` batches are in flight at once, so batches that arrive while others run overlap on the
 device.  A request completes when the host observes its batch's completion event; its latency is
 completion time minus arrival time.
