@@ -214,7 +214,8 @@ def test_native_growing_arena_admits_a_request_over_the_budget(index):
 def test_native_direct_batches_inside_a_large_pinned_allocation(index):
     """Host arrays that lie inside a pinned allocation of more than 2 GiB (the runtime reports no
     range size there, so the check compares the range's first and last bytes) are still staged by
-    kernels, and the counts equal the oracle's; with a pageable counts array the run copies."""
+    kernels, also from an address that is not 8-byte aligned, and the counts equal the oracle's; with
+    a pageable counts array the run copies."""
     import ctypes as C
 
     import torch
@@ -237,6 +238,15 @@ def test_native_direct_batches_inside_a_large_pinned_allocation(index):
               "qr_server_run")
     assert srv.last_run_staged > 0
     want = oracle.count_sa(text, sa, w.pat, w.off).astype(np.uint32)
+    assert np.array_equal(h_cnt.numpy().view(np.uint32), want)
+    # the same patterns 3 bytes into the allocation: h_pat is not 8-byte aligned, so the staging
+    # kernel moves every byte singly
+    big[3:3 + w.pat.size].copy_(torch.from_numpy(w.pat))
+    h_cnt.zero_()
+    qr._check(qr.lib().qr_server_run(srv.h, big.data_ptr() + 3, h_off.data_ptr(), req_off.ctypes.data, nreq,
+                                     arrival.ctypes.data, h_cnt.data_ptr(), finish.ctypes.data, 60.0, C.byref(st)),
+              "qr_server_run")
+    assert srv.last_run_staged > 0
     assert np.array_equal(h_cnt.numpy().view(np.uint32), want)
     del big
     # pinned patterns and offsets but a pageable counts array: not every range is mapped, so the run copies
