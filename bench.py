@@ -495,6 +495,7 @@ def main():
     fm_res = None
     if not args.no_fm:
         fm_res = bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev)
+    fm_cpu_inputs = fm_res.pop("_cpu_inputs", None) if fm_res else None
 
     # ------------------------------------------------------------------ serving sweep
     serve_res = None
@@ -504,11 +505,14 @@ def main():
     # ------------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
     if not args.no_cpu_baseline and packed_q is not None and "quadrank_rank" in qsets:
-        cpu = cpu_baseline(packed_q, n_qr, datagen, np, with_birank="birank_rank_p0.5" in rows)
-        log("cpu baseline (oracle, %d threads, %s): rank %.1f M q/s (one thread %.1f), rank4 %.1f M q/s%s" % (
+        cpu = cpu_baseline(packed_q, n_qr, datagen, np, with_birank="birank_rank_p0.5" in rows, fm_inputs=fm_cpu_inputs)
+        log("cpu baseline (oracle, %d threads, %s): rank %.1f M q/s (one thread %.1f), rank4 %.1f M q/s%s%s" % (
             cpu["cores"], cpu["cpu_model"], cpu["value"] / 1e6, cpu["one_thread_queries_per_s"] / 1e6,
             cpu["rank4_queries_per_s"] / 1e6,
-            ", BiRank %.1f M q/s" % (cpu["birank_queries_per_s"] / 1e6) if "birank_queries_per_s" in cpu else ""))
+            ", BiRank %.1f M q/s" % (cpu["birank_queries_per_s"] / 1e6) if "birank_queries_per_s" in cpu else "",
+            ", FM count %.2f M patterns/s" % (cpu["fm_count_patterns_per_s"] / 1e6)
+            if "fm_count_patterns_per_s" in cpu else ""))
+    del fm_cpu_inputs
 
     out = {
         "metric": "rank queries/s + % HBM random-line roofline; FM count patterns/s, p99 latency",
@@ -566,9 +570,11 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
         bwt = to_dev(bwt)
     else:
         d_text = torch.from_numpy(codes).to(dev)
+        # the suffix array is handed out only for the CPU baseline's oracle search (outside the timings)
+        d_sa = None if args.no_cpu_baseline else torch.empty(n + 1, dtype=torch.int32, device=dev)
         torch.cuda.synchronize()
         t1 = time.time()
-        bwt, dollar, marks, samples = qr.quadfm_index_device(d_text, rate)
+        bwt, dollar, marks, samples = qr.quadfm_index_device(d_text, rate, sa=d_sa)
         del d_text
     t2 = time.time()
     kmers = [int(x) for x in args.fm_kmers.split(",") if x]
@@ -576,6 +582,12 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
     torch.cuda.synchronize()
     t3 = time.time()
     pat, off, kind = datagen.patterns(2830, codes, args.fm_patterns)
+    cpu_inputs = None
+    if not args.no_cpu_baseline and not args.host_sa:
+        sample = min(args.fm_patterns, 3 * 10 ** 6)  # the oracle's sample: the first 3*10^6 patterns
+        cpu_inputs = (codes, d_sa.cpu().numpy().view(np.uint32).astype(np.int64), pat[:int(off[sample])],
+                      off[:sample + 1].copy())
+        del d_sa
     del codes
     dp, do = to_dev(pat), to_dev(off)
     npat = args.fm_patterns
@@ -688,6 +700,7 @@ def bench_fm(args, qr, autotune, datagen, np, torch, dev, to_dev):
         log("fm locate (rate %d): %d positions, %.1f M positions/s; intervals %.2f ms, offsets %.2f ms, walks %.2f ms"
             % (rate, total, total / t_loc / 1e6, t_iv * 1e3, t_off * 1e3, t_loc * 1e3))
     fm.free()
+    res["_cpu_inputs"] = cpu_inputs  # taken out by main() for the CPU baseline, not reported
     return res
 
 
@@ -1108,7 +1121,7 @@ def host_threads():
     return aff, os.cpu_count()
 
 
-def cpu_baseline(packed, n, datagen, np, with_birank=True):
+def cpu_baseline(packed, n, datagen, np, with_birank=True, fm_inputs=None):
     """The oracle (plain C, OpenMP over queries) on the host cores, on bounded samples of the same
     workloads.  Every oracle call first builds its prefix table over the whole structure (serially),
     which the GPU timing has no counterpart of, so each rate is differential: one call on a sample
@@ -1164,6 +1177,23 @@ def cpu_baseline(packed, n, datagen, np, with_birank=True):
         res["birank_sample"] = ("2*10^8 uniform BiRank queries on a 2^36-bit vector of density 0.5 vs their "
                                 "first 5*10^7 (%.2f s vs %.2f s)" % (tbb, tsb))
         del bits, qb
+    if fm_inputs is not None:
+        # FM count: the oracle's suffix-array binary search over the FM row's 2^28-base text (its suffix
+        # array from the device input preparation), on the first 3*10^6 of the row's patterns; the
+        # search has no per-call table, so this is a plain rate, taken against its first quarter too
+        text, sa, pat, off = fm_inputs
+        m = off.size - 1
+        q = m // 4
+        t0 = time.perf_counter()
+        oracle.count_sa(text, sa, pat[:int(off[q])], off[:q + 1])
+        tq = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.count_sa(text, sa, pat, off)
+        tm = time.perf_counter() - t0
+        res["fm_count_patterns_per_s"] = (m - q) / max(tm - tq, 1e-9)
+        res["fm_count_sample"] = ("the first %d of the FM row's 10^7 patterns (lengths 20..250) on its 2^28-base "
+                                  "text by suffix-array binary search, timed against their first quarter "
+                                  "(%.2f s vs %.2f s)" % (m, tm, tq))
     return res
 
 
