@@ -350,25 +350,30 @@ int quadfm_set_tuning(qr_quadfm h, const qr_tuning *t);
  * streams is free, every request that has arrived is admitted first-in first-out as one batch of at
  * most max_batch_patterns patterns (a larger single request is still admitted alone) whose device
  * bytes fit the budget's first-fit arena; with QR_SERVE_CHECK_FREE_MEMORY, a batch larger than the
- * device's free memory also waits.  With QR_SERVE_GROW_FROM_FREE_HBM the budget is the arena's first
- * chunk and admission follows the device's free memory: a batch that finds no room adds a chunk of
- * max(its bytes, budget_bytes), rounded up to 2 MiB, when hipMemGetInfo shows that much free with at
- * least max(1 GiB, 1/64 of the device's memory) left over, and waits for earlier batches otherwise;
- * batches are still cut to the budget where their requests allow, so the arena stays within about
- * `slots` chunks.  Chunks are kept until qr_server_free; qr_server_arena_bytes gives the arena's
- * size.  Each batch moves its patterns in, counts them with the persistent kernel on its slot's
- * stream and moves the counts to h_counts[h_req_off[r]..].
- * h_finish_s[r] receives the time at which the host saw request r's batch complete.  When h_pat
- * (from byte 0 to the end of the last pattern), the run's offsets and its counts all lie in pinned,
- * device-mapped host memory (hipHostMalloc; one allocation each), every batch that moves at most
- * 4 MiB of host bytes is launches only: a kernel reads the batch's patterns and offsets from host
- * memory into the arena and another writes the counts back (qr_server_last_run_staged counts such
- * batches).  Larger batches, and every batch with pageable arrays or QR_SERVE_COPY_ENGINE, are
- * copied with hipMemcpyAsync (pageable memory works but serialises the copies).  With QR_SERVE_CHECK_FREE_MEMORY the free-memory reading is refreshed at
- * most every 5 ms.  The server owns its arena, streams and queue
- * heads; the index must outlive it.  run returns once every request is done (QR_ERANGE if
- * deadline_s passes first or a request alone exceeds the budget, or with QR_SERVE_GROW_FROM_FREE_HBM
- * every chunk and the free memory), with no copy in flight.
+ * device's free memory also waits (the reading is refreshed at most every 5 ms).
+ *
+ * With QR_SERVE_GROW_FROM_FREE_HBM the budget is the arena's first chunk and admission follows the
+ * device's free memory: a batch that finds no room adds a chunk of max(its bytes, budget_bytes),
+ * rounded up to 2 MiB, when hipMemGetInfo shows that much free with at least max(1 GiB, 1/64 of
+ * the device's memory) left over, and waits for earlier batches otherwise.  Batches are still cut
+ * to the budget where their requests allow, so the arena stays within about `slots` chunks.
+ * Chunks are kept until qr_server_free; qr_server_arena_bytes gives the arena's size.
+ *
+ * Each batch moves its patterns in, counts them with the persistent kernel on its slot's stream
+ * and moves the counts to h_counts[h_req_off[r]..]; h_finish_s[r] receives the time at which the
+ * host saw request r's batch complete.  When h_pat (from byte 0 to the end of the last pattern),
+ * the run's offsets and its counts all lie in pinned, device-mapped host memory (hipHostMalloc;
+ * one allocation each), every batch that moves at most 4 MiB of host bytes is launches only: a
+ * kernel reads the batch's patterns and offsets from host memory into the arena and another writes
+ * the counts back (qr_server_last_run_staged counts such batches).  Larger batches, and every batch
+ * with pageable arrays or QR_SERVE_COPY_ENGINE, are copied with hipMemcpyAsync (pageable memory
+ * works but serialises the copies).
+ *
+ * The server owns its arena, streams and queue heads; the index must outlive it.  A server runs one
+ * qr_server_run at a time (its slots, arena and queue heads serve that run's batches); distinct
+ * servers may run concurrently on one index.  run returns once every request is done (QR_ERANGE if
+ * deadline_s passes first, or a request alone exceeds the budget, or with
+ * QR_SERVE_GROW_FROM_FREE_HBM every chunk and what free memory allows), with no copy in flight.
  * ---------------------------------------------------------------------------------------------- */
 typedef struct qr_server_s *qr_server;
 #define QR_SERVE_CHECK_FREE_MEMORY 1u
