@@ -95,6 +95,8 @@ def main():
                          "loop's top load is also run the other way for comparison")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival span per load point")
     ap.add_argument("--serve-kmer", type=int, default=12, help="start-table size of the served index")
+    ap.add_argument("--serve-batch-cap-log", type=int, default=20,
+                    help="log2 of the most patterns one served batch takes")
     ap.add_argument("--serve-layout", default="32",
                     help="QuadRank layout of the served index (32: the fastest count over the 2^30-base index)")
     ap.add_argument("--no-fm-hbm", action="store_true",
@@ -998,12 +1000,13 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
     torch.cuda.empty_cache()
     fm.set_tuning(block=64, refill=32, waves_per_cu=8)
     log("serve index 2^%d: text + %s SA+BWT %.1fs" % (args.serve_log_n, "host" if args.host_sa else "device", t1 - t0))
-    slots, budget = 4, 256 << 20
+    slots, budget, cap = 4, 256 << 20, 1 << args.serve_batch_cap_log
     free, total = torch.cuda.mem_get_info()
     res = {"workload": "QuadFm serving: 2^%d-base text (uniform ACGT, 1000 planted 10-kb segments x20, 1%% subs); "
                        "Poisson arrivals, request size log-uniform 1..4096 patterns, lengths 20..250"
                        % args.serve_log_n,
            "slots": slots, "hbm_budget_bytes": budget, "arena": "grows from free HBM (native loop)",
+           "batch_cap_patterns": cap,
            "kmer": args.serve_kmer, "layout": args.serve_layout,
            "pattern_form": "bytes" if args.serve_bytes else "packed",
            "device_free_bytes_at_start": int(free),
@@ -1023,10 +1026,10 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
         if args.serve_python:
             ex = GpuExecutor(fm, w, slots=slots, budget_bytes=budget)
-            srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
+            srv = Server(ex, slots=slots, budget_bytes=budget, max_batch_patterns=cap,
                          free_bytes_fn=lambda: torch.cuda.mem_get_info()[0])
         else:
-            ex = srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18,
+            ex = srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=cap,
                                     check_free_memory=True, packed=not args.serve_bytes, grow=True)
         st = srv.run(w, deadline_s=120.0)
         summ = st.summary()
@@ -1054,7 +1057,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
             k = mids[len(mids) // 2]
             load = res["loads"][k]["offered_patterns_per_s"]
             w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
-            srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18, check_free_memory=True,
+            srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=cap, check_free_memory=True,
                                packed=not args.serve_bytes, grow=True, copy_engine=True)
             summ = srv.run(w, deadline_s=120.0).summary()
             summ["offered_patterns_per_s"] = load
@@ -1069,7 +1072,7 @@ def bench_serve(args, qr, datagen, np, torch, to_dev):
         load = res["loads"][-1]["offered_patterns_per_s"]
         k = len(res["loads"]) - 1
         w = make_workload(5000 + k, text, load, args.serve_seconds, max_requests=200_000)
-        srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=1 << 18, check_free_memory=True,
+        srv = NativeServer(fm, slots=slots, budget_bytes=budget, max_batch_patterns=cap, check_free_memory=True,
                            packed=args.serve_bytes, grow=True)
         summ = srv.run(w, deadline_s=120.0).summary()
         summ["offered_patterns_per_s"] = load
