@@ -802,7 +802,41 @@ def bench_fm_hbm(args, qr, autotune, datagen, np, torch, dev, to_dev, text, bwt,
         res["best_layout"], res["roofline"] = fm_best_layout(res["by_layout"])
         for f in others.values():
             f.free()
+    res["reads_150"] = fm_reads_row(args, autotune, datagen, np, torch, dev, to_dev, text, fm_serve,
+                                    res["by_kmer"].get(str(args.serve_kmer), {}).get("tuning"))
+    fm_serve.set_tuning(block=64, refill=32, waves_per_cu=8)  # back to the serving loop's settings
     return res
+
+
+def fm_reads_row(args, autotune, datagen, np, torch, dev, to_dev, text, fm, tuning):
+    """The paper's read-counting shape on the served index: 10^6 reads of 150 bases with 1 %
+    substitutions, every other one taken from the reverse strand, counted on both strands (and on
+    the forward strand alone), with byte and with 2-bit packed reads."""
+    nr, rl = 10 ** 6, 150
+    rpat, roff, _ = datagen.patterns(4141, text, nr, minlen=rl, maxlen=rl, frac_sampled=1.0, sub=0.01)
+    rows = rpat.reshape(nr, rl)
+    rows[1::2] = 3 - rows[1::2, ::-1]  # reverse complements
+    drp, dro, dr2 = to_dev(rpat), to_dev(roff), to_dev(datagen.pack2(rpat))
+    if tuning:
+        fm.set_tuning(**tuning)
+    c_b = torch.empty(nr, dtype=torch.int32, device=dev)
+    c_p = torch.empty(nr, dtype=torch.int32, device=dev)
+    t_b = autotune.time_launch(lambda: fm.count(drp, dro, c_b, both_strands=True), reps=args.fm_reps)
+    t_p = autotune.time_launch(lambda: fm.count_packed(dr2, nr * rl, dro, c_p, both_strands=True), reps=args.fm_reps)
+    both = c_p.cpu().numpy()
+    equal = bool(torch.equal(c_b, c_p))
+    t_f = autotune.time_launch(lambda: fm.count_packed(dr2, nr * rl, dro, c_p), reps=args.fm_reps)
+    fwd = c_p.cpu().numpy()
+    row = {"workload": "10^6 reads of 150 bases sampled from the served text with 1% substitutions, every other "
+                       "one reverse-complemented",
+           "both_strands_reads_per_s": nr / t_b, "both_strands_packed_reads_per_s": nr / t_p,
+           "forward_packed_reads_per_s": nr / t_f, "packed_equals_bytes": equal,
+           "reads_matched_both_strands": float((both > 0).mean()), "reads_matched_forward": float((fwd > 0).mean())}
+    log("fm reads (150 bases, 1%% subs, half reverse strand): both strands %.1f M reads/s (packed %.1f M), forward "
+        "only %.1f M; %.1f%% of the reads occur exactly (%.1f%% on the forward strand), equal=%s" % (
+            nr / t_b / 1e6, nr / t_p / 1e6, nr / t_f / 1e6, 100 * row["reads_matched_both_strands"],
+            100 * row["reads_matched_forward"], equal))
+    return row
 
 
 def fm_tune(args, autotune, key, n, fm, run):

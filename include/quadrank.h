@@ -383,6 +383,8 @@ typedef struct qr_server_s *qr_server;
                                        the flag: h_off[h_req_off[nreq]] bytes) */
 #define QR_SERVE_GROW_FROM_FREE_HBM 4u /* the arena grows from the device's free memory (above) */
 #define QR_SERVE_COPY_ENGINE 8u        /* copy batches with hipMemcpyAsync even from pinned memory */
+#define QR_SERVE_BOTH_STRANDS 16u      /* each count covers the pattern and its reverse complement
+                                          (QUADFM_BOTH_STRANDS) */
 typedef struct {
     uint64_t batches;            /* batches launched */
     uint64_t max_inflight;       /* most batches in flight at once */

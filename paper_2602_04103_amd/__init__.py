@@ -25,6 +25,7 @@ QR_SERVE_CHECK_FREE_MEMORY = 1
 QR_SERVE_PACKED_PATTERNS = 2
 QR_SERVE_GROW_FROM_FREE_HBM = 4
 QR_SERVE_COPY_ENGINE = 8
+QR_SERVE_BOTH_STRANDS = 16
 QR_LAYOUT_16, QR_LAYOUT_32, QR_LAYOUT_16P, QR_LAYOUT_64, QR_LAYOUT_16X2, QR_LAYOUT_24_8 = 0, 1, 2, 3, 4, 5
 LAYOUT_NAMES = {QR_LAYOUT_16: "16", QR_LAYOUT_32: "32", QR_LAYOUT_16P: "16p", QR_LAYOUT_64: "64",
                 QR_LAYOUT_16X2: "16x2", QR_LAYOUT_24_8: "24_8"}

@@ -218,7 +218,7 @@ int qr_server_create(qr_quadfm fm, int slots, uint64_t budget_bytes, uint64_t ma
     *out = nullptr;
     if (!fm || slots < 1 || slots > 64 || budget_bytes < 4 * ALIGN || max_batch_patterns == 0 ||
         (flags & ~(QR_SERVE_CHECK_FREE_MEMORY | QR_SERVE_PACKED_PATTERNS | QR_SERVE_GROW_FROM_FREE_HBM |
-                   QR_SERVE_COPY_ENGINE))) {
+                   QR_SERVE_COPY_ENGINE | QR_SERVE_BOTH_STRANDS))) {
         set_error("qr_server_create: need an index, 1..64 slots, a budget of at least 1 KiB and a batch cap");
         return QR_EINVAL;
     }
@@ -301,6 +301,7 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
         return QR_EINVAL;
     }
     const bool packed = s->flags & QR_SERVE_PACKED_PATTERNS;
+    const uint32_t cflags = (s->flags & QR_SERVE_BOTH_STRANDS) ? QUADFM_BOTH_STRANDS : 0u;
     // a batch's pattern bytes at h_pat, from stream unit c0 (a byte, or a base of packed words) to c1:
     // bytes [c0 rounded down to 8, c1); packed, the whole words holding bases [c0, c1), from word c0 / 32
     auto pat_bytes = [&](uint64_t c0, uint64_t c1) -> uint64_t {
@@ -440,8 +441,8 @@ int qr_server_run(qr_server s, const uint8_t *h_pat, const uint64_t *h_off, cons
                 break;
             }
             rc = packed ? quadfm_count_packed(s->fm, reinterpret_cast<const uint64_t *>(d_pat), chars / 8 * 32, d_off,
-                                              npat, 0u, d_cnt, s->heads + k, st)
-                        : quadfm_count_ex(s->fm, d_pat, chars, d_off, npat, 0u, d_cnt, s->heads + k, st);
+                                              npat, cflags, d_cnt, s->heads + k, st)
+                        : quadfm_count_ex(s->fm, d_pat, chars, d_off, npat, cflags, d_cnt, s->heads + k, st);
             if (rc) {
                 err = rc;
                 break;

@@ -173,12 +173,12 @@ class GpuExecutor:
 # ------------------------------------------------------------------------------------------ native loop
 class NativeServer:
     """The same policy run by the library's native loop (qr_server_*): slots, arena budget, batch cap,
-    the optional free-memory check and the optional growth of the arena from free device memory
-    (`grow`); host buffers are pinned once per workload."""
+    the optional free-memory check, the optional growth of the arena from free device memory
+    (`grow`) and optional counts over both strands; host buffers are pinned once per workload."""
 
     def __init__(self, fm, slots: int, budget_bytes: int, max_batch_patterns: int = 1 << 18,
                  check_free_memory: bool = False, packed: bool = False, grow: bool = False,
-                 copy_engine: bool = False):
+                 copy_engine: bool = False, both_strands: bool = False):
         import ctypes as C
 
         import paper_2602_04103_amd as qr
@@ -186,7 +186,7 @@ class NativeServer:
         h = C.c_void_p()
         flags = ((qr.QR_SERVE_CHECK_FREE_MEMORY if check_free_memory else 0)
                  | (qr.QR_SERVE_PACKED_PATTERNS if packed else 0) | (qr.QR_SERVE_GROW_FROM_FREE_HBM if grow else 0)
-                 | (qr.QR_SERVE_COPY_ENGINE if copy_engine else 0))
+                 | (qr.QR_SERVE_COPY_ENGINE if copy_engine else 0) | (qr.QR_SERVE_BOTH_STRANDS if both_strands else 0))
         qr._check(qr.lib().qr_server_create(fm.h, slots, int(budget_bytes), int(max_batch_patterns), flags,
                                             C.byref(h)), "qr_server_create")
         self.h = h.value

@@ -258,3 +258,24 @@ def test_native_direct_batches_inside_a_large_pinned_allocation(index):
     assert srv.last_run_staged == 0  # pageable counts array: copied
     assert np.array_equal(h_cnt2, want)
     srv.free()
+
+
+@pytest.mark.parametrize("packed", [False, True])
+def test_native_both_strands_equals_oracle(index, packed):
+    """With QR_SERVE_BOTH_STRANDS every served count covers the pattern and its reverse complement:
+    reads of 150 bases, every other one reverse-complemented, against the oracle's two-strand count."""
+    qr, text, fm, sa = index
+    from paper_2602_04103_amd.serve import NativeServer, make_workload
+    w = make_workload(93, text, rate_patterns_per_s=4e6, duration_s=0.05, max_size=512)
+    npat = int(w.req_off[-1])
+    pat, off, _ = datagen.patterns(94, text, npat, minlen=150, maxlen=150, frac_sampled=1.0, sub=0.01)
+    rows = pat.reshape(npat, 150)
+    rows[1::2] = 3 - rows[1::2, ::-1]
+    w.pat, w.off = pat, off
+    announce("native serve both strands", w.nreq, npat, "packed" if packed else "bytes")
+    srv = NativeServer(fm, slots=4, budget_bytes=32 << 20, packed=packed, both_strands=True)
+    srv.run(w, deadline_s=60.0)
+    want = oracle.count_both_strands(text, sa, pat, off).astype(np.uint32)
+    assert np.array_equal(srv.counts(0, npat), want)
+    assert want.max() > 0 and np.count_nonzero(want[1::2]) > 0  # reverse-strand reads occur
+    srv.free()
