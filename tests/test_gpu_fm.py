@@ -139,8 +139,10 @@ def test_fm_config3_full():
     locate sample) is prepared on the device; its suffix array is handed out and checked by the
     oracle directly (a permutation whose neighbouring suffixes increase).  Every one of the 10^7
     persistent-kernel counts then equals the oracle's suffix-array binary search over the text, and
-    so does every per-batch count, every count of the 2-bit packed patterns and every count of the same index over the other QuadRank layouts
-    (16-bit paired, 32-bit, 64-bit and 24/8, with the 12-mer start table).  200 sampled patterns are
+    so does every per-batch count, every count of the 2-bit packed patterns and every count of the
+    same index over the other QuadRank layouts (16-bit paired, 32-bit, 64-bit and 24/8, with the
+    12-mer start table); 10^5 150-base reads, half of them reverse-complemented, are counted on both
+    strands as the oracle does.  200 sampled patterns are
     also recounted by the oracle's direct scan of the text.  Intervals and locate (SA sampled at rate
     32) are checked on the same index."""
     qr = require_gpu()
@@ -168,6 +170,13 @@ def test_fm_config3_full():
     got = fm.count(dp, do).cpu().numpy().view(np.uint32)
     got_b = fm.count_batched(dp, do, 1 << 20).cpu().numpy().view(np.uint32)
     got_p = fm.count_packed(to_dev(datagen.pack2(pat)), int(off[-1]), do).cpu().numpy().view(np.uint32)
+    # 10^5 reads of 150 bases with 1 % substitutions, every other one reverse-complemented, on both
+    # strands from packed words (the shape of the paper's read-counting experiment)
+    rpat, roff, _ = datagen.patterns(2831, codes, 100_000, minlen=150, maxlen=150, frac_sampled=1.0, sub=0.01)
+    rrows = rpat.reshape(-1, 150)
+    rrows[1::2] = 3 - rrows[1::2, ::-1]
+    got_r = fm.count_packed(to_dev(datagen.pack2(rpat)), rpat.size, to_dev(roff),
+                            both_strands=True).cpu().numpy().view(np.uint32)
     fm.check()
     announce("fm-config3 oracle: suffix-array check and 10^7 counts")
     assert oracle.check_sa(codes, sa) == 0
@@ -177,6 +186,9 @@ def test_fm_config3_full():
     assert np.array_equal(got_p, want_all)
     for name, g in got_layouts.items():
         assert np.array_equal(g, want_all), name
+    want_r = oracle.count_both_strands(codes, sa, rpat, roff).astype(np.uint32)
+    assert np.array_equal(got_r, want_r)
+    assert np.count_nonzero(want_r[1::2]) > 0  # reverse-strand reads are found
     assert sa[dollar] == 0                       # the '$' row of the BWT is the row of suffix 0
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(10 ** 7, 200, replace=False))

@@ -78,7 +78,8 @@ def test_fm_layouts_2e24_with_repeats():
     """One BWT of 2^24 bases (200 planted 10-kb segments x 20 copies, 1% substitutions), prepared on
     the device with its suffix array handed out and checked by the oracle; every layout's index
     counts 10^5 patterns (lengths 20..250) exactly as the oracle's suffix-array search, with both
-    kernels and both strands, and sizes its intervals as counted."""
+    kernels and both strands, sizes its intervals as counted, and counts 2*10^4 150-base reads (half
+    reverse-complemented) on both strands from packed words as the oracle does."""
     qr = require_gpu()
     n = 1 << 24
     codes = datagen.dna_codes(2424, n)
@@ -93,6 +94,14 @@ def test_fm_layouts_2e24_with_repeats():
     want = oracle.count_sa(codes, sa, pat, off).astype(np.uint32)
     both = oracle.count_both_strands(codes, sa, pat[:int(off[10_000])], off[:10_001]).astype(np.uint32)
     dp, do = to_dev(pat), to_dev(off)
+    # reads in the shape of the paper's experiment: 150 bases, 1 % substitutions, every other one
+    # reverse-complemented, counted on both strands from 2-bit packed words
+    rpat, roff, _ = datagen.patterns(2427, codes, 20_000, minlen=150, maxlen=150, frac_sampled=1.0, sub=0.01)
+    rrows = rpat.reshape(-1, 150)
+    rrows[1::2] = 3 - rrows[1::2, ::-1]
+    rwant = oracle.count_both_strands(codes, sa, rpat, roff).astype(np.uint32)
+    assert np.count_nonzero(rwant[0::2]) and np.count_nonzero(rwant[1::2])
+    drp2, dro = to_dev(datagen.pack2(rpat)), to_dev(roff)
     sizes = {}
     for name in LAYOUT_NAMES:
         announce("fm-layouts 2^24", name)
@@ -102,6 +111,8 @@ def test_fm_layouts_2e24_with_repeats():
         assert np.array_equal(fm.count_batched(dp, do, 1 << 16).cpu().numpy().view(np.uint32), want), name
         g2 = fm.count(dp, do[:10_001], both_strands=True).cpu().numpy().view(np.uint32)
         assert np.array_equal(g2, both), name
+        gr = fm.count_packed(drp2, rpat.size, dro, both_strands=True).cpu().numpy().view(np.uint32)
+        assert np.array_equal(gr, rwant), name
         iv = fm.intervals(dp, do).cpu().numpy().view(np.uint32).astype(np.int64)
         assert np.array_equal((iv[:, 1] - iv[:, 0]).astype(np.uint32), want), name
         fm.check()
